@@ -1,0 +1,217 @@
+/*
+ * im.h -- C ABI of the MI355X (gfx950) library for sketch-based influence
+ * maximisation with hash-based fused sampling and error-adaptive rebuild
+ * (Gokturk & Kaya, arXiv 2105.04023, "HyperFuseR").
+ *
+ * Conventions for every call:
+ *  - Plain pointers and sizes only.  A pointer is a host pointer unless the
+ *    argument or struct field says it is a device pointer.
+ *  - Inputs are borrowed for the duration of the call and never retained.
+ *  - Handles own their device memory until the matching *_free call.
+ *  - Errors are returned as im_status; im_last_error() gives a thread-local
+ *    message.  Validation errors leave existing handles unchanged.  A device
+ *    error (IM_ERR_DEVICE) poisons the handle it happened on: later calls on
+ *    it return IM_ERR_STATE.  The library never aborts the process.
+ *  - Work is enqueued on the context's HIP stream; a call returns after the
+ *    stream work it needs for its outputs has completed.
+ *  - Calls on one handle are not thread-safe; distinct handles may be used from
+ *    distinct threads when they belong to distinct contexts.
+ */
+#ifndef IM_H
+#define IM_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum im_status {
+    IM_OK = 0,
+    IM_ERR_INVALID_ARG = -1,   /* a scalar argument or pointer is invalid */
+    IM_ERR_INVALID_GRAPH = -2, /* the CSR is malformed (offsets or ids out of range) */
+    IM_ERR_OUT_OF_BUDGET = -3, /* the request exceeds the context's device-memory budget */
+    IM_ERR_DEVICE = -4,        /* a HIP call failed */
+    IM_ERR_STATE = -5          /* the handle is poisoned or in the wrong state */
+} im_status;
+
+/* Edge-probability model (Sec. 2.1): independent cascade with one constant
+ * probability, weighted cascade w_uv = 1/d_v with d_v the in-degree of v, or
+ * independent cascade with one binary32 probability per edge. */
+typedef enum im_prob_kind {
+    IM_PROB_CONSTANT = 0,
+    IM_PROB_WEIGHTED_CASCADE = 1,
+    IM_PROB_PER_EDGE = 2
+} im_prob_kind;
+
+/* Directed graph in compressed sparse rows over OUT-neighbours (Sec. 3.3):
+ * the out-neighbours of vertex u are adj[xadj[u] .. xadj[u+1]-1].
+ * Requirements: n >= 1, xadj[0] = 0, xadj nondecreasing, xadj[n] = m,
+ * 0 <= adj[e] < n, n < 2^31.  Duplicate edges and self-loops are accepted
+ * (they do not change the registers; they do count towards in-degrees for the
+ * weighted cascade). */
+typedef struct im_csr {
+    int64_t n;
+    int64_t m;
+    const int64_t* xadj; /* n+1 offsets */
+    const int32_t* adj;  /* m vertex ids */
+    int32_t on_device;   /* 0: xadj/adj are host pointers; 1: device pointers on the context's device */
+} im_csr;
+
+/* Edge probabilities w_uv in [0, 1] (Sec. 2.1).  per_edge (kind PER_EDGE)
+ * holds m binary32 values aligned with adj, resident where the CSR is. */
+typedef struct im_probs {
+    im_prob_kind kind;
+    float p;
+    const float* per_edge;
+} im_probs;
+
+/* Options of the sketch build.  eps_c is the early-exit ratio of Alg. 2:
+ * sweeping stops once |L| <= eps_c * n (0 = run to the fixed point).  The
+ * tuning fields select the work decomposition only; results do not depend on
+ * them.  Zero means "library default". */
+typedef struct im_build_opts {
+    double eps_c;
+    int32_t heavy_degree; /* rows with more out-edges are split across waves */
+    int32_t piece_edges;  /* edges per piece of a split row */
+    int32_t rows_per_wave_chunk; /* multiple of 32: consecutive rows per wave chunk */
+    int32_t reserved;
+} im_build_opts;
+
+/* Thresholds of the error-adaptive rebuild (Sec. 3.2.1): the sketches are
+ * kept when err_l < eps_l or err_g < eps_g, otherwise rebuilt.  The paper
+ * uses eps_l = 0.3 and eps_g = 0.01. */
+typedef struct im_select_opts {
+    double eps_g;
+    double eps_l;
+} im_select_opts;
+
+/* One greedy step of Alg. 1. */
+typedef struct im_step {
+    int32_t seed;    /* vertex added to S at this step */
+    int32_t rebuilt; /* 1 if the sketches were rebuilt after this step */
+    int32_t fresh;   /* 1 if err_l < eps_l or err_g < eps_g */
+    int32_t sweeps;  /* sweeps of the rebuild (0 if none) */
+    int64_t score;   /* integer register sum of Merge(M_S', M_s) */
+    int64_t reach;   /* blocked (vertex, simulation) pairs after this step = sigma * R */
+    double e;        /* Estimate(Merge(M_S', M_s)) */
+    double sigma;    /* Monte-Carlo influence of S over the R samples */
+    double delta;    /* sigma minus sigma at the last rebuild */
+    double err_l;    /* |(e - delta) / delta| (+inf if delta = 0) */
+    double err_g;    /* |(e - delta) / sigma| */
+    int64_t visits;  /* edge visits (edges with a live head, summed over sweeps) of the rebuild */
+} im_step;
+
+typedef struct im_sketch_info {
+    int64_t n;
+    int64_t m;
+    int32_t R;
+    int32_t sweeps;        /* sweeps of the build */
+    int64_t visits;        /* edges with a live head, summed over the build's sweeps */
+    double build_ms;       /* device time of the build's Simulate (init + sweeps) */
+    double prep_ms;        /* device time of graph upload, hashing and thresholds */
+    size_t device_bytes;   /* device memory held by the sketch */
+    int64_t heavy_rows;    /* rows split across waves */
+    int64_t heavy_pieces;
+} im_sketch_info;
+
+typedef struct im_select_stats {
+    int32_t rebuilds;
+    int32_t reserved;
+    int64_t rebuild_sweeps;
+    int64_t rebuild_visits;
+    int64_t bfs_levels;
+    double device_ms; /* device time of im_select_seeds (events on the context stream) */
+    double wall_ms;   /* host wall time of im_select_seeds */
+} im_select_stats;
+
+typedef struct im_ctx im_ctx;
+typedef struct im_sketch im_sketch;
+
+/* Device allocator hooks; both NULL selects hipMalloc/hipFree.  alloc returns a
+ * device pointer aligned to 256 bytes, or NULL on failure. */
+typedef void* (*im_alloc_fn)(size_t bytes, void* user);
+typedef void (*im_free_fn)(void* ptr, void* user);
+
+/* Creates a context on HIP device `device`.  `stream` is a hipStream_t (NULL =
+ * the null stream) that must outlive the context.  hbm_budget bounds the
+ * device bytes all sketches of this context may hold (0 = no bound). */
+im_status im_ctx_create(int32_t device, void* stream, size_t hbm_budget, im_alloc_fn alloc, im_free_fn dealloc,
+                        void* user, im_ctx** out);
+void im_ctx_free(im_ctx* ctx);
+/* Device bytes currently held by sketches of the context. */
+size_t im_ctx_bytes_in_use(const im_ctx* ctx);
+
+/* Device bytes a sketch of this shape would hold (for admission by budget). */
+size_t im_sketch_bytes_needed(int64_t n, int64_t m, int32_t R, im_prob_kind kind);
+
+/*
+ * Builds the per-vertex sketches (Alg. 1 initialisation and Alg. 2 Simulate).
+ * Uploads or copies the graph, computes the 31-bit Murmur3 edge hashes
+ * (Eq. hash), the per-simulation words X_j and the integer live thresholds of
+ * Eq. (hash_prob), initialises M_v[j] = clz(hash(v) xor hash(j)), and runs
+ * synchronous pull sweeps until |L| <= eps_c * n.
+ * R: registers (= simulations) per vertex, a multiple of 4 in [4, 1024].
+ * hash_seed: seed of every hash.  opts may be NULL.
+ * On success *out owns the graph copy and the registers.
+ */
+im_status im_build_sketches(im_ctx* ctx, const im_csr* graph, const im_probs* probs, int32_t R, uint32_t hash_seed,
+                            const im_build_opts* opts, im_sketch** out);
+
+/*
+ * Estimate (Eq. sketch-estimate, with the merge of Eq. sketch-merge) of the
+ * union of the sketches of `count` vertices, from the registers of the build:
+ * e = 2^(mean_j max_v M_v[j]) / 0.77351, returned as binary32.  verts is a host
+ * array of ids in [0, n); count >= 1.
+ */
+im_status im_estimate(im_sketch* sk, const int32_t* verts, int64_t count, float* out_estimate);
+
+/* Per-vertex estimates of the build's registers: out[v] = Estimate(M_v) as
+ * binary32.  out holds n floats; out_on_device selects a device pointer. */
+im_status im_estimate_all(im_sketch* sk, float* out, int32_t out_on_device);
+
+/*
+ * Greedy seed selection with error-adaptive rebuild (Alg. 1).  Starts from the
+ * build's registers every time it is called (the build is kept), so repeated
+ * calls with different K return consistent prefixes.  K in [1, n].
+ * out_seeds: K ids.  out_steps: K records or NULL.  stats may be NULL.
+ * opts NULL selects eps_g = 0.01, eps_l = 0.3.
+ */
+im_status im_select_seeds(im_sketch* sk, int32_t K, const im_select_opts* opts, int32_t* out_seeds,
+                          im_step* out_steps, im_select_stats* stats);
+
+/* Build information; trace of the build: live_counts[t] = |L_t| (t = 0..sweeps)
+ * and edge_visits[t] = edges with a live head in sweep t (t < sweeps); cap
+ * bounds both arrays; *written receives sweeps+1. */
+im_status im_sketch_get_info(const im_sketch* sk, im_sketch_info* info);
+im_status im_sketch_get_trace(const im_sketch* sk, int64_t* live_counts, int64_t* edge_visits, int32_t cap,
+                              int32_t* written);
+
+/* Device time (ms) of the non-split-row sweep kernel of every sweep of the
+ * build, recorded only when the build was asked to time sweeps
+ * (im_build_opts.reserved != 0).  Returns the number of values written. */
+int32_t im_sketch_get_sweep_kernel_ms(const im_sketch* sk, float* out, int32_t cap);
+
+/* Copies registers to the host, n*R bytes, vertex-major (R registers of a
+ * vertex adjacent).  which = 0: registers of the build; which = 1: registers
+ * in force at the end of the last im_select_seeds. */
+im_status im_sketch_get_registers(const im_sketch* sk, int32_t which, uint8_t* out);
+
+/* Copies the blocked pairs of the last im_select_seeds (the reach of S in
+ * every sample) to the host as n*R bytes (1 = blocked). */
+im_status im_sketch_get_blocked(const im_sketch* sk, uint8_t* out);
+
+void im_sketch_free(im_sketch* sk);
+
+/* Thread-local message of the last failed call on this thread ("" if none). */
+const char* im_last_error(void);
+
+/* Library version string. */
+const char* im_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* IM_H */

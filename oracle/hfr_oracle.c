@@ -30,6 +30,8 @@
  *   R8  e is the estimate of Merge(M_S', M_s) taken before M_S' is merged.
  *   R9  No rebuild after the K-th seed (it cannot change S).
  *   R10 delta = 0 gives err_l = +inf.
+ *   R11 The edge-visit count of a sweep is the number of edges (u, v) with v
+ *       in L and u not blocked in every simulation (such a row cannot change).
  */
 #include <math.h>
 #include <stdint.h>
@@ -228,6 +230,13 @@ int64_t orc_simulate(int64_t n, const int64_t* xadj, const int32_t* adj, const u
         memcpy(Mn, M, (size_t)(n * J));
         int64_t edges = 0;
         for (int64_t u = 0; u < n; ++u) {
+            /* R11: a row blocked in every simulation can never change; its
+             * edges are not visited (and not counted). */
+            if (blk) {
+                int32_t j = 0;
+                while (j < J && blk[u * J + j]) ++j;
+                if (j == J) continue;
+            }
             for (int64_t e = xadj[u]; e < xadj[u + 1]; ++e) {
                 int32_t v = adj[e];
                 if (!L[v]) continue;

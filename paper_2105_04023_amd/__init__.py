@@ -1,0 +1,213 @@
+"""MI355X (gfx950) library for sketch-based influence maximisation (arXiv 2105.04023).
+
+Python names mirror the C ABI of include/im.h: ``im_build_sketches``, ``im_estimate``,
+``im_estimate_all`` and ``im_select_seeds``.  This module only marshals arguments; the
+sampling, register propagation, estimates, reach and greedy decisions all run in the HIP
+library.  PyTorch provides the device, the stream and (by default) the device allocator.
+"""
+from __future__ import annotations
+
+import ctypes
+from dataclasses import dataclass
+
+import numpy as np
+
+from . import _binding as B
+
+__all__ = ["Context", "Sketch", "im_build_sketches", "im_estimate", "im_estimate_all", "im_select_seeds",
+           "ImError"]
+
+ImError = B.ImError
+_KIND = {"const": B.IM_PROB_CONSTANT, "wc": B.IM_PROB_WEIGHTED_CASCADE, "edge": B.IM_PROB_PER_EDGE}
+
+
+def _torch():
+    import torch
+
+    return torch
+
+
+class Context:
+    """A device, a HIP stream and an optional device-memory budget (bytes, 0 = none)."""
+
+    def __init__(self, device: int = 0, hbm_budget: int = 0, stream=None, torch_allocator: bool = True):
+        torch = _torch()
+        self.lib = B.load()
+        torch.cuda.set_device(device)
+        self.device = device
+        self.stream = stream if stream is not None else torch.cuda.current_stream(device)
+        self._keep = []
+        if torch_allocator:
+            dev, st = device, self.stream
+
+            def _alloc(nbytes, _user):
+                try:
+                    return torch.cuda.caching_allocator_alloc(int(nbytes), dev, st)
+                except Exception:  # out of memory: the library reports IM_ERR_OUT_OF_BUDGET
+                    return None
+
+            def _free(ptr, _user):
+                torch.cuda.caching_allocator_delete(ptr)
+
+            af, ff = B.ALLOC_FN(_alloc), B.FREE_FN(_free)
+        else:
+            af, ff = B.ALLOC_FN(), B.FREE_FN()
+        self._keep += [af, ff]
+        h = ctypes.c_void_p()
+        B.check(self.lib.im_ctx_create(device, ctypes.c_void_p(self.stream.cuda_stream), hbm_budget, af, ff, None,
+                                       ctypes.byref(h)))
+        self.handle = h
+
+    def bytes_in_use(self) -> int:
+        return int(self.lib.im_ctx_bytes_in_use(self.handle))
+
+    def bytes_needed(self, n: int, m: int, R: int, model: str = "const") -> int:
+        return int(self.lib.im_sketch_bytes_needed(n, m, R, _KIND[model]))
+
+    def close(self):
+        if self.handle:
+            self.lib.im_ctx_free(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+@dataclass
+class Step:
+    seed: int
+    rebuilt: int
+    fresh: int
+    sweeps: int
+    score: int
+    reach: int
+    e: float
+    sigma: float
+    delta: float
+    err_l: float
+    err_g: float
+    visits: int
+
+
+class Sketch:
+    """Handle of a built sketch (graph copy + registers) on the device."""
+
+    def __init__(self, ctx: Context, handle, n: int, R: int):
+        self.ctx, self.handle, self.n, self.R = ctx, handle, n, R
+        self.lib = ctx.lib
+
+    def info(self) -> dict:
+        i = B.im_sketch_info()
+        B.check(self.lib.im_sketch_get_info(self.handle, ctypes.byref(i)))
+        return {f: getattr(i, f) for f, _ in B.im_sketch_info._fields_}
+
+    def trace(self):
+        """(|L_t| for t = 0..sweeps, edges with a live head per sweep)."""
+        cap = self.info()["sweeps"] + 1
+        live = np.zeros(cap, dtype=np.int64)
+        vis = np.zeros(cap, dtype=np.int64)
+        w = ctypes.c_int32()
+        B.check(self.lib.im_sketch_get_trace(self.handle, live.ctypes.data, vis.ctypes.data, cap, ctypes.byref(w)))
+        return live[: w.value], vis[: w.value - 1]
+
+    def sweep_kernel_ms(self) -> np.ndarray:
+        out = np.zeros(4096, dtype=np.float32)
+        k = self.lib.im_sketch_get_sweep_kernel_ms(self.handle, out.ctypes.data, len(out))
+        return out[:k].copy()
+
+    def registers(self, which: int = 0) -> np.ndarray:
+        out = np.empty((self.n, self.R), dtype=np.uint8)
+        B.check(self.lib.im_sketch_get_registers(self.handle, which, out.ctypes.data))
+        return out
+
+    def blocked(self) -> np.ndarray:
+        out = np.empty((self.n, self.R), dtype=np.uint8)
+        B.check(self.lib.im_sketch_get_blocked(self.handle, out.ctypes.data))
+        return out
+
+    def free(self):
+        if self.handle:
+            self.lib.im_sketch_free(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.free()
+        except Exception:
+            pass
+
+
+def _ptr_and_residency(a, dtype):
+    """Returns (pointer, on_device, keepalive) for a numpy array or a torch tensor."""
+    torch = _torch()
+    if isinstance(a, torch.Tensor):
+        if a.dtype != dtype[1]:
+            raise TypeError(f"expected {dtype[1]}, got {a.dtype}")
+        a = a.contiguous()
+        return a.data_ptr(), int(a.is_cuda), a
+    arr = np.ascontiguousarray(a, dtype=dtype[0])
+    return arr.ctypes.data, 0, arr
+
+
+def im_build_sketches(ctx: Context, xadj, adj, n: int, R: int, model: str = "const", p: float = 0.0,
+                      per_edge=None, hash_seed: int = 0, eps_c: float = 0.0, heavy_degree: int = 0,
+                      piece_edges: int = 0, time_sweeps: bool = False) -> Sketch:
+    """Alg. 1 initialisation + Alg. 2: builds the per-vertex rank registers of R samples."""
+    torch = _torch()
+    xp, xdev, xk = _ptr_and_residency(xadj, (np.int64, torch.int64))
+    ap, adev, ak = _ptr_and_residency(adj, (np.int32, torch.int32))
+    if xdev != adev:
+        raise ValueError("xadj and adj must both be host arrays or both device tensors")
+    m = int(len(adj)) if not isinstance(adj, torch.Tensor) else int(adj.numel())
+    g = B.im_csr(n, m, xp, ap, xdev)
+    keep = [xk, ak]
+    pe_ptr = None
+    if model == "edge":
+        pp, pdev, pk = _ptr_and_residency(per_edge, (np.float32, torch.float32))
+        if pdev != xdev:
+            raise ValueError("per-edge probabilities must reside where the CSR resides")
+        pe_ptr = pp
+        keep.append(pk)
+    probs = B.im_probs(_KIND[model], float(p), pe_ptr)
+    opts = B.im_build_opts(eps_c, heavy_degree, piece_edges, 0, 1 if time_sweeps else 0)
+    h = ctypes.c_void_p()
+    B.check(ctx.lib.im_build_sketches(ctx.handle, ctypes.byref(g), ctypes.byref(probs), R, hash_seed & 0xFFFFFFFF,
+                                      ctypes.byref(opts), ctypes.byref(h)))
+    del keep
+    return Sketch(ctx, h, n, R)
+
+
+def im_estimate(sk: Sketch, verts) -> float:
+    """Eq. (sketch-estimate) of the merged sketch of a vertex set, as binary32."""
+    v = np.ascontiguousarray(verts, dtype=np.int32).ravel()
+    out = ctypes.c_float()
+    B.check(sk.lib.im_estimate(sk.handle, v.ctypes.data, len(v), ctypes.byref(out)))
+    return float(out.value)
+
+
+def im_estimate_all(sk: Sketch, out=None):
+    """Per-vertex estimates (binary32).  `out` may be a float32 CUDA tensor of n elements."""
+    torch = _torch()
+    if out is not None and isinstance(out, torch.Tensor):
+        if out.dtype != torch.float32 or out.numel() != sk.n or not out.is_cuda:
+            raise ValueError("out must be a float32 CUDA tensor of n elements")
+        B.check(sk.lib.im_estimate_all(sk.handle, out.data_ptr(), 1))
+        return out
+    res = np.empty(sk.n, dtype=np.float32)
+    B.check(sk.lib.im_estimate_all(sk.handle, res.ctypes.data, 0))
+    return res
+
+
+def im_select_seeds(sk: Sketch, K: int, eps_g: float = 0.01, eps_l: float = 0.3):
+    """Alg. 1 greedy loop with error-adaptive rebuild.  Returns (seeds, steps, stats)."""
+    seeds = np.zeros(K, dtype=np.int32)
+    steps = (B.im_step * K)()
+    stats = B.im_select_stats()
+    opts = B.im_select_opts(eps_g, eps_l)
+    B.check(sk.lib.im_select_seeds(sk.handle, K, ctypes.byref(opts), seeds.ctypes.data,
+                                   ctypes.cast(steps, ctypes.c_void_p), ctypes.byref(stats)))
+    st = [Step(**{f: getattr(s, f) for f, _ in B.im_step._fields_}) for s in steps]
+    return seeds, st, {f: getattr(stats, f) for f, _ in B.im_select_stats._fields_}

@@ -1,0 +1,118 @@
+"""ctypes binding of include/im.h: argument marshalling only, every step runs in the HIP library.
+
+The library is loaded from this package directory (libhipfuser.so, built in-tree by
+``build.py``).  If it is missing, loading raises: there is no CPU fallback.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libhipfuser.so")
+
+IM_OK = 0
+STATUS_NAMES = {0: "IM_OK", -1: "IM_ERR_INVALID_ARG", -2: "IM_ERR_INVALID_GRAPH", -3: "IM_ERR_OUT_OF_BUDGET",
+                -4: "IM_ERR_DEVICE", -5: "IM_ERR_STATE"}
+IM_PROB_CONSTANT, IM_PROB_WEIGHTED_CASCADE, IM_PROB_PER_EDGE = 0, 1, 2
+
+# Every symbol include/im.h declares (checked by the CPU test suite).
+EXPORTED = [
+    "im_ctx_create", "im_ctx_free", "im_ctx_bytes_in_use", "im_sketch_bytes_needed", "im_build_sketches",
+    "im_estimate", "im_estimate_all", "im_select_seeds", "im_sketch_get_info", "im_sketch_get_trace",
+    "im_sketch_get_registers", "im_sketch_get_blocked", "im_sketch_free", "im_last_error", "im_version",
+    "im_sketch_get_sweep_kernel_ms",
+]
+
+
+class ImError(RuntimeError):
+    def __init__(self, status: int, msg: str):
+        super().__init__(f"{STATUS_NAMES.get(status, status)}: {msg}")
+        self.status = status
+
+
+class im_csr(ctypes.Structure):
+    _fields_ = [("n", ctypes.c_int64), ("m", ctypes.c_int64), ("xadj", ctypes.c_void_p), ("adj", ctypes.c_void_p),
+                ("on_device", ctypes.c_int32)]
+
+
+class im_probs(ctypes.Structure):
+    _fields_ = [("kind", ctypes.c_int), ("p", ctypes.c_float), ("per_edge", ctypes.c_void_p)]
+
+
+class im_build_opts(ctypes.Structure):
+    _fields_ = [("eps_c", ctypes.c_double), ("heavy_degree", ctypes.c_int32), ("piece_edges", ctypes.c_int32),
+                ("rows_per_wave_chunk", ctypes.c_int32), ("reserved", ctypes.c_int32)]
+
+
+class im_select_opts(ctypes.Structure):
+    _fields_ = [("eps_g", ctypes.c_double), ("eps_l", ctypes.c_double)]
+
+
+class im_step(ctypes.Structure):
+    _fields_ = [("seed", ctypes.c_int32), ("rebuilt", ctypes.c_int32), ("fresh", ctypes.c_int32),
+                ("sweeps", ctypes.c_int32), ("score", ctypes.c_int64), ("reach", ctypes.c_int64),
+                ("e", ctypes.c_double), ("sigma", ctypes.c_double), ("delta", ctypes.c_double),
+                ("err_l", ctypes.c_double), ("err_g", ctypes.c_double), ("visits", ctypes.c_int64)]
+
+
+class im_sketch_info(ctypes.Structure):
+    _fields_ = [("n", ctypes.c_int64), ("m", ctypes.c_int64), ("R", ctypes.c_int32), ("sweeps", ctypes.c_int32),
+                ("visits", ctypes.c_int64), ("build_ms", ctypes.c_double), ("prep_ms", ctypes.c_double),
+                ("device_bytes", ctypes.c_size_t), ("heavy_rows", ctypes.c_int64),
+                ("heavy_pieces", ctypes.c_int64)]
+
+
+class im_select_stats(ctypes.Structure):
+    _fields_ = [("rebuilds", ctypes.c_int32), ("reserved", ctypes.c_int32), ("rebuild_sweeps", ctypes.c_int64),
+                ("rebuild_visits", ctypes.c_int64), ("bfs_levels", ctypes.c_int64), ("device_ms", ctypes.c_double),
+                ("wall_ms", ctypes.c_double)]
+
+
+ALLOC_FN = ctypes.CFUNCTYPE(ctypes.c_void_p, ctypes.c_size_t, ctypes.c_void_p)
+FREE_FN = ctypes.CFUNCTYPE(None, ctypes.c_void_p, ctypes.c_void_p)
+
+_lib = None
+
+
+def load(path: str = LIB_PATH):
+    """Loads libhipfuser.so; raises if it has not been built."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(path):
+        raise ImportError(f"{path} is missing: build it with paper_2105_04023_amd/build.py (no CPU fallback exists)")
+    lib = ctypes.CDLL(path)
+    p, i32, i64, sz = ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64, ctypes.c_size_t
+    sig = {
+        "im_ctx_create": ([i32, p, sz, ALLOC_FN, FREE_FN, p, ctypes.POINTER(p)], ctypes.c_int),
+        "im_ctx_free": ([p], None),
+        "im_ctx_bytes_in_use": ([p], sz),
+        "im_sketch_bytes_needed": ([i64, i64, i32, ctypes.c_int], sz),
+        "im_build_sketches": ([p, ctypes.POINTER(im_csr), ctypes.POINTER(im_probs), i32, ctypes.c_uint32,
+                               ctypes.POINTER(im_build_opts), ctypes.POINTER(p)], ctypes.c_int),
+        "im_estimate": ([p, p, i64, ctypes.POINTER(ctypes.c_float)], ctypes.c_int),
+        "im_estimate_all": ([p, p, i32], ctypes.c_int),
+        "im_select_seeds": ([p, i32, ctypes.POINTER(im_select_opts), p, p, ctypes.POINTER(im_select_stats)],
+                            ctypes.c_int),
+        "im_sketch_get_info": ([p, ctypes.POINTER(im_sketch_info)], ctypes.c_int),
+        "im_sketch_get_trace": ([p, p, p, i32, ctypes.POINTER(i32)], ctypes.c_int),
+        "im_sketch_get_registers": ([p, i32, p], ctypes.c_int),
+        "im_sketch_get_blocked": ([p, p], ctypes.c_int),
+        "im_sketch_free": ([p], None),
+        "im_last_error": ([], ctypes.c_char_p),
+        "im_version": ([], ctypes.c_char_p),
+        "im_sketch_get_sweep_kernel_ms": ([p, p, i32], i32),
+    }
+    for name, (args, res) in sig.items():
+        fn = getattr(lib, name)
+        fn.argtypes = args
+        fn.restype = res
+    _lib = lib
+    return lib
+
+
+def check(status: int):
+    if status != IM_OK:
+        msg = load().im_last_error().decode(errors="replace")
+        raise ImError(status, msg)

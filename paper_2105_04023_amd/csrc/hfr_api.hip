@@ -1,0 +1,850 @@
+// Host side of the library: the C ABI declared in include/im.h.
+//
+// Control flow per call:
+//  - im_build_sketches: upload/copy the CSR, validate it on the device, hash
+//    every edge, derive the integer live thresholds, split high-degree rows,
+//    then Simulate (Alg. 2): init + synchronous sweeps.  Sweeps are launched
+//    in batches; each sweep kernel reads the live count of the previous sweep
+//    from device memory and returns at once when the stopping rule holds, so
+//    the host only reads counts back once per batch, one batch ahead.
+//  - im_select_seeds: the greedy loop of Alg. 1 with device argmax, device
+//    multi-sample BFS for the Monte-Carlo reach, an FP64 decision kernel and a
+//    rebuild (init with blocked pairs + Simulate) when the decision asks.
+#include <hip/hip_runtime.h>
+#include <math.h>
+#include <stdarg.h>
+#include <stdio.h>
+#include <string.h>
+
+#include <algorithm>
+#include <chrono>
+#include <string>
+#include <vector>
+
+#include "../../include/im.h"
+#include "hfr_internal.h"
+
+using namespace hfr;
+
+namespace {
+
+thread_local std::string g_last_error;
+
+im_status fail(im_status st, const char* fmt, ...) {
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof(buf), fmt, ap);
+    va_end(ap);
+    g_last_error = buf;
+    return st;
+}
+
+constexpr int RING = 256;         // sweeps held by the counter ring
+constexpr int MAX_BATCH = 64;     // sweeps per batch
+constexpr int DEFAULT_HEAVY = 256;
+constexpr int DEFAULT_PIECE = 256;
+constexpr int BFS_CHUNK = 256;
+constexpr int SWEEP_TIMERS = 2 * RING;
+
+}  // namespace
+
+struct im_ctx {
+    int device = 0;
+    hipStream_t stream = nullptr;
+    size_t budget = 0;
+    size_t in_use = 0;
+    im_alloc_fn af = nullptr;
+    im_free_fn ff = nullptr;
+    void* user = nullptr;
+};
+
+struct DevBuf {
+    void* p;
+    size_t bytes;
+};
+
+struct im_sketch {
+    im_ctx* ctx = nullptr;
+    bool poisoned = false;
+    Layout L{};
+    DevGraph g{};
+    uint32_t seed = 0;
+    double eps_c = 0.0;
+    std::vector<DevBuf> bufs;
+    size_t bytes = 0;
+
+    uint32_t* X = nullptr;
+    uint32_t* HJ = nullptr;
+    double* T = nullptr;
+    uint32_t* M[3] = {nullptr, nullptr, nullptr};
+    int build_buf = 0;
+    int sel_buf = 0;
+    uint32_t* Lbm[2] = {nullptr, nullptr};
+    uint32_t* cnt_ring = nullptr;
+    unsigned long long* vis_ring = nullptr;
+    unsigned long long* gather = nullptr;  // device [2 * MAX_BATCH]
+    uint32_t* part = nullptr;
+    uint32_t* part_any = nullptr;
+    GreedyBufs gb{};
+    StepRec* d_steps = nullptr;
+    int32_t* d_seeds = nullptr;
+    int32_t* d_flag = nullptr;
+    uint32_t* d_err = nullptr;
+    unsigned long long* d_heavy_counts = nullptr;
+
+    // pinned host staging
+    unsigned long long* h_gather[2] = {nullptr, nullptr};
+    uint32_t* h_small = nullptr;  // 16 words
+
+    hipEvent_t ev_a = nullptr, ev_b = nullptr;
+    hipEvent_t ev_batch[2] = {nullptr, nullptr};
+    std::vector<hipEvent_t> sweep_ev;
+    bool time_sweeps = false;
+
+    // build statistics
+    int sweeps = 0;
+    int64_t visits = 0;
+    double build_ms = 0.0, prep_ms = 0.0;
+    std::vector<int64_t> trace_live, trace_vis;
+    std::vector<float> light_ms;
+    int32_t level_id = 1;
+    bool selected = false;
+};
+
+namespace {
+
+void* ctx_alloc(im_ctx* c, size_t bytes) {
+    bytes = (bytes + 255) & ~size_t(255);
+    if (bytes == 0) bytes = 256;
+    void* p = nullptr;
+    if (c->af) {
+        p = c->af(bytes, c->user);
+    } else if (hipMalloc(&p, bytes) != hipSuccess) {
+        (void)hipGetLastError();
+        p = nullptr;
+    }
+    return p;
+}
+
+void ctx_free(im_ctx* c, void* p) {
+    if (!p) return;
+    if (c->ff)
+        c->ff(p, c->user);
+    else
+        (void)hipFree(p);
+}
+
+template <typename T>
+bool sk_alloc(im_sketch* sk, T** out, size_t count) {
+    size_t bytes = sizeof(T) * (count ? count : 1);
+    void* p = ctx_alloc(sk->ctx, bytes);
+    if (!p) return false;
+    sk->bufs.push_back({p, bytes});
+    sk->bytes += bytes;
+    sk->ctx->in_use += bytes;
+    *out = reinterpret_cast<T*>(p);
+    return true;
+}
+
+void sk_release(im_sketch* sk) {
+    if (!sk) return;
+    if (sk->ctx) {
+        (void)hipStreamSynchronize(sk->ctx->stream);
+        for (auto& b : sk->bufs) {
+            ctx_free(sk->ctx, b.p);
+            sk->ctx->in_use -= b.bytes;
+        }
+    }
+    sk->bufs.clear();
+    if (sk->h_gather[0]) (void)hipHostFree(sk->h_gather[0]);
+    if (sk->h_gather[1]) (void)hipHostFree(sk->h_gather[1]);
+    if (sk->h_small) (void)hipHostFree(sk->h_small);
+    for (hipEvent_t e : {sk->ev_a, sk->ev_b, sk->ev_batch[0], sk->ev_batch[1]})
+        if (e) (void)hipEventDestroy(e);
+    for (hipEvent_t e : sk->sweep_ev) (void)hipEventDestroy(e);
+    delete sk;
+}
+
+#define HIP_TRY(expr)                                                                                 \
+    do {                                                                                              \
+        hipError_t _e = (expr);                                                                       \
+        if (_e != hipSuccess) {                                                                       \
+            if (sk) sk->poisoned = true;                                                              \
+            return fail(IM_ERR_DEVICE, "%s failed: %s (%s:%d)", #expr, hipGetErrorString(_e), __FILE__, \
+                        __LINE__);                                                                    \
+        }                                                                                             \
+    } while (0)
+
+struct Sizes {
+    int64_t n, m, J;
+    size_t total;
+};
+
+int64_t qcap_for(int64_t n, int64_t m) { return n + (m + BFS_CHUNK - 1) / BFS_CHUNK + 64; }
+
+size_t bytes_needed(int64_t n, int64_t m, int32_t R, im_prob_kind kind) {
+    const Layout L = make_layout(R);
+    auto al = [](size_t b) { return (std::max<size_t>(b, 1) + 255) & ~size_t(255); };
+    size_t t = 0;
+    t += al(8 * (n + 1)) + al(4 * m) + al(4 * m);  // xadj, adj, edge hashes
+    if (kind == IM_PROB_WEIGHTED_CASCADE) t += al(4 * n);
+    if (kind == IM_PROB_PER_EDGE) t += al(4 * m);
+    t += al(4 * R) * 2 + al(8 * R);               // X, HJ, T
+    t += 3 * al((size_t)n * L.P * 4);             // register buffers
+    const int64_t words = (n + 31) / 32 + 1;
+    t += 2 * al(4 * words);
+    t += al((size_t)RING * NSLOT * SLOT_U32 * 4) + al((size_t)RING * NSLOT * SLOT_U64 * 8) + al(16 * MAX_BATCH);
+    // split rows: bounded by m / heavy_degree rows and m / piece + rows pieces
+    const int64_t nh = m / DEFAULT_HEAVY + 1, np = m / DEFAULT_PIECE + nh + 1;
+    t += al(4 * nh) + al(8 * (nh + 1)) + al(8 * nh) + al(4 * np) + 2 * al(8 * np) + al((size_t)np * L.P * 4) +
+         al(4 * np);
+    // greedy
+    const size_t W = 4 * (size_t)L.PW;
+    t += 3 * al((size_t)n * W * 4);
+    t += 2 * al(8 * qcap_for(n, m)) + al(64) + al(4 * n) + al(n) + 2 * al(4 * L.P) + al(8) +
+         al(NSLOT * SLOT_U64 * 8) + al(8);
+    t += al(sizeof(StepRec) * 64) + al(4 * 64) + al(16) + al(16) + al(64);
+    return t;
+}
+
+// Sum of the live-count slots of sweeps [t0+1, t0+nb] and the visit slots of
+// sweeps [t0, t0+nb-1] into out[2i], out[2i+1].
+__global__ void k_gather_counts(const uint32_t* __restrict__ cnt, const unsigned long long* __restrict__ vis,
+                                int64_t t0, int nb, unsigned long long* out) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= nb) return;
+    const uint32_t* c = cnt + ((t0 + i + 1) % RING) * NSLOT * SLOT_U32;
+    const unsigned long long* v = vis + ((t0 + i) % RING) * NSLOT * SLOT_U64;
+    unsigned long long sc = 0, sv = 0;
+    for (int k = 0; k < NSLOT; ++k) {
+        sc += c[k * SLOT_U32];
+        sv += v[k * SLOT_U64];
+    }
+    out[2 * i] = sc;
+    out[2 * i + 1] = sv;
+}
+
+// Zeroes the live-count slots of sweeps [t0+1, t0+nb] and the visit slots of
+// sweeps [t0, t0+nb-1].
+__global__ void k_ring_zero(uint32_t* cnt, unsigned long long* vis, int64_t t0, int nb) {
+    const int i = blockIdx.x;  // sweep offset
+    if (i >= nb) return;
+    uint32_t* c = cnt + ((t0 + i + 1) % RING) * NSLOT * SLOT_U32;
+    unsigned long long* v = vis + ((t0 + i) % RING) * NSLOT * SLOT_U64;
+    for (int k = threadIdx.x; k < NSLOT * SLOT_U32; k += blockDim.x) c[k] = 0u;
+    for (int k = threadIdx.x; k < NSLOT * SLOT_U64; k += blockDim.x) v[k] = 0ull;
+}
+
+uint32_t* cnt_slots(im_sketch* sk, int64_t t) { return sk->cnt_ring + (t % RING) * NSLOT * SLOT_U32; }
+unsigned long long* vis_slots(im_sketch* sk, int64_t t) { return sk->vis_ring + (t % RING) * NSLOT * SLOT_U64; }
+
+struct SimResult {
+    int buf;
+    int sweeps;
+    int64_t visits;
+    double ms;
+    std::vector<int64_t> live, vis;
+    std::vector<float> light_ms;
+};
+
+// Simulate (Alg. 2) on buffers ia/ib: init (with blocked pairs if blk), then
+// synchronous sweeps until |L_t| <= floor(eps_c * n).
+im_status run_simulate(im_sketch* sk, int ia, int ib, const uint32_t* blk, SimResult* res) {
+    hipStream_t s = sk->ctx->stream;
+    const int64_t n = sk->g.n;
+    uint32_t* buf[2] = {sk->M[ia], sk->M[ib]};
+    const double lim = floor(sk->eps_c * (double)n);
+    const uint32_t thresh = lim >= (double)n ? (uint32_t)n : (uint32_t)lim;
+    res->live.assign(1, n);
+    res->vis.clear();
+    res->light_ms.clear();
+    HIP_TRY(hipEventRecord(sk->ev_a, s));
+    HIP_TRY(launch_init(sk->L, n, sk->HJ, sk->seed, blk, buf[0], buf[1], s));
+    int final_sweeps = -1;
+    if ((uint64_t)n <= thresh) final_sweeps = 0;
+    int64_t t = 0;
+    int nb = 8;
+    int inflight = 0;  // batches launched and not yet read
+    int64_t batch_t0[2] = {0, 0};
+    int batch_nb[2] = {0, 0};
+    int batch_slot = 0;
+    int timer_idx = 0;
+    std::vector<int> timer_of_sweep;
+    while (final_sweeps < 0) {
+        // synchronous sweeps reach the fixed point within n + 1 sweeps
+        if (t > n + 2 + 2 * MAX_BATCH) {
+            sk->poisoned = true;
+            return fail(IM_ERR_DEVICE, "sweep count exceeded n + 1 without convergence");
+        }
+        // launch one batch
+        hipLaunchKernelGGL(k_ring_zero, dim3(nb), dim3(256), 0, s, sk->cnt_ring, sk->vis_ring, t, nb);
+        HIP_TRY(hipGetLastError());
+        for (int64_t st = t; st < t + nb; ++st) {
+            SweepParams sp{};
+            sp.A = buf[st & 1];
+            sp.B = buf[(st + 1) & 1];
+            sp.Lcur = sk->Lbm[st & 1];
+            sp.Lnext = sk->Lbm[(st + 1) & 1];
+            sp.blk = blk;
+            sp.gate = st == 0 ? nullptr : cnt_slots(sk, st);
+            sp.gate_thresh = thresh;
+            sp.cnt_out = cnt_slots(sk, st + 1);
+            sp.vis_out = vis_slots(sk, st);
+            sp.part = sk->part;
+            sp.part_any = sk->part_any;
+            sp.first = st == 0;
+            hipEvent_t e0 = nullptr, e1 = nullptr;
+            if (sk->time_sweeps && timer_idx + 1 < (int)sk->sweep_ev.size()) {
+                e0 = sk->sweep_ev[timer_idx];
+                e1 = sk->sweep_ev[timer_idx + 1];
+                timer_idx += 2;
+            }
+            HIP_TRY(launch_sweep(sk->L, sk->g, sk->X, sp, 0, s, e0, e1));
+        }
+        hipLaunchKernelGGL(k_gather_counts, dim3(1), dim3(64), 0, s, sk->cnt_ring, sk->vis_ring, t, nb,
+                           sk->gather + 2 * MAX_BATCH * batch_slot);
+        HIP_TRY(hipGetLastError());
+        HIP_TRY(hipMemcpyAsync(sk->h_gather[batch_slot], sk->gather + 2 * MAX_BATCH * batch_slot,
+                               sizeof(unsigned long long) * 2 * nb, hipMemcpyDeviceToHost, s));
+        HIP_TRY(hipEventRecord(sk->ev_batch[batch_slot], s));
+        batch_t0[batch_slot] = t;
+        batch_nb[batch_slot] = nb;
+        batch_slot ^= 1;
+        ++inflight;
+        t += nb;
+        nb = std::min(nb * 2, MAX_BATCH);
+        if (inflight < 2) continue;
+        // read the older batch
+        const int rs = batch_slot;  // older slot (the one launched first)
+        HIP_TRY(hipEventSynchronize(sk->ev_batch[rs]));
+        --inflight;
+        for (int i = 0; i < batch_nb[rs]; ++i) {
+            const int64_t live = (int64_t)sk->h_gather[rs][2 * i];
+            const int64_t vis = (int64_t)sk->h_gather[rs][2 * i + 1];
+            res->vis.push_back(vis);
+            res->live.push_back(live);
+            if ((uint64_t)live <= thresh) {
+                final_sweeps = (int)(batch_t0[rs] + i + 1);
+                break;
+            }
+        }
+    }
+    HIP_TRY(hipEventRecord(sk->ev_b, s));
+    HIP_TRY(hipStreamSynchronize(s));
+    float ms = 0.f;
+    HIP_TRY(hipEventElapsedTime(&ms, sk->ev_a, sk->ev_b));
+    res->ms = ms;
+    res->sweeps = final_sweeps;
+    res->live.resize(final_sweeps + 1);
+    res->vis.resize(final_sweeps);
+    res->visits = 0;
+    for (int64_t v : res->vis) res->visits += v;
+    res->buf = (final_sweeps & 1) ? ib : ia;
+    if (sk->time_sweeps) {
+        for (int i = 0; i + 1 < timer_idx && i / 2 < final_sweeps; i += 2) {
+            float km = 0.f;
+            if (hipEventElapsedTime(&km, sk->sweep_ev[i], sk->sweep_ev[i + 1]) == hipSuccess) res->light_ms.push_back(km);
+        }
+    }
+    return IM_OK;
+}
+
+im_status check_sketch(const im_sketch* sk) {
+    if (!sk) return fail(IM_ERR_INVALID_ARG, "null sketch");
+    if (sk->poisoned) return fail(IM_ERR_STATE, "sketch is poisoned by an earlier device error");
+    return IM_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+const char* im_last_error(void) { return g_last_error.c_str(); }
+
+const char* im_version(void) { return "hipfuser 0.1 (gfx950)"; }
+
+im_status im_ctx_create(int32_t device, void* stream, size_t hbm_budget, im_alloc_fn alloc, im_free_fn dealloc,
+                        void* user, im_ctx** out) {
+    im_sketch* sk = nullptr;
+    if (!out) return fail(IM_ERR_INVALID_ARG, "out is null");
+    if ((alloc == nullptr) != (dealloc == nullptr)) return fail(IM_ERR_INVALID_ARG, "alloc and dealloc must both be set");
+    int ndev = 0;
+    HIP_TRY(hipGetDeviceCount(&ndev));
+    if (device < 0 || device >= ndev) return fail(IM_ERR_INVALID_ARG, "device %d out of range (%d devices)", device, ndev);
+    HIP_TRY(hipSetDevice(device));
+    im_ctx* c = new im_ctx;
+    c->device = device;
+    c->stream = (hipStream_t)stream;
+    c->budget = hbm_budget;
+    c->af = alloc;
+    c->ff = dealloc;
+    c->user = user;
+    *out = c;
+    return IM_OK;
+}
+
+void im_ctx_free(im_ctx* ctx) { delete ctx; }
+
+size_t im_ctx_bytes_in_use(const im_ctx* ctx) { return ctx ? ctx->in_use : 0; }
+
+size_t im_sketch_bytes_needed(int64_t n, int64_t m, int32_t R, im_prob_kind kind) {
+    if (n < 1 || m < 0 || R < 4 || R > 1024 || R % 4) return 0;
+    return bytes_needed(n, m, R, kind);
+}
+
+im_status im_build_sketches(im_ctx* ctx, const im_csr* graph, const im_probs* probs, int32_t R, uint32_t hash_seed,
+                            const im_build_opts* opts, im_sketch** out) {
+    im_sketch* sk = nullptr;
+    if (!ctx || !graph || !probs || !out) return fail(IM_ERR_INVALID_ARG, "null argument");
+    if (R < 4 || R > 1024 || R % 4) return fail(IM_ERR_INVALID_ARG, "R must be a multiple of 4 in [4, 1024] (got %d)", R);
+    const int64_t n = graph->n, m = graph->m;
+    if (n < 1 || n >= (1ll << 31)) return fail(IM_ERR_INVALID_GRAPH, "n must be in [1, 2^31) (got %lld)", (long long)n);
+    if (m < 0 || m >= (1ll << 40)) return fail(IM_ERR_INVALID_GRAPH, "m out of range (got %lld)", (long long)m);
+    if (!graph->xadj || (m > 0 && !graph->adj)) return fail(IM_ERR_INVALID_GRAPH, "null CSR array");
+    if (probs->kind != IM_PROB_CONSTANT && probs->kind != IM_PROB_WEIGHTED_CASCADE && probs->kind != IM_PROB_PER_EDGE)
+        return fail(IM_ERR_INVALID_ARG, "unknown probability kind %d", (int)probs->kind);
+    if (probs->kind == IM_PROB_CONSTANT && live_threshold(probs->p) == 0xFFFFFFFFu)
+        return fail(IM_ERR_INVALID_ARG, "probability must be in [0, 1]");
+    if (probs->kind == IM_PROB_PER_EDGE && m > 0 && !probs->per_edge)
+        return fail(IM_ERR_INVALID_ARG, "per-edge probabilities missing");
+    im_build_opts o{};
+    if (opts) o = *opts;
+    if (!(o.eps_c >= 0.0)) return fail(IM_ERR_INVALID_ARG, "eps_c must be >= 0");
+    if (o.heavy_degree < 0 || o.piece_edges < 0) return fail(IM_ERR_INVALID_ARG, "negative tuning value");
+    const size_t need = bytes_needed(n, m, R, probs->kind);
+    if (ctx->budget && ctx->in_use + need > ctx->budget)
+        return fail(IM_ERR_OUT_OF_BUDGET, "sketch needs %zu bytes, %zu of %zu in use", need, ctx->in_use, ctx->budget);
+
+    hipStream_t s = ctx->stream;
+    if (hipSetDevice(ctx->device) != hipSuccess) return fail(IM_ERR_DEVICE, "hipSetDevice failed");
+
+    // host-side offset checks that need no device pass
+    int64_t x0 = 0, xn = 0;
+    if (graph->on_device) {
+        if (hipMemcpy(&x0, graph->xadj, 8, hipMemcpyDeviceToHost) != hipSuccess ||
+            hipMemcpy(&xn, graph->xadj + n, 8, hipMemcpyDeviceToHost) != hipSuccess)
+            return fail(IM_ERR_DEVICE, "reading device xadj failed");
+    } else {
+        x0 = graph->xadj[0];
+        xn = graph->xadj[n];
+    }
+    if (x0 != 0 || xn != m) return fail(IM_ERR_INVALID_GRAPH, "xadj[0] must be 0 and xadj[n] must equal m");
+
+    sk = new im_sketch;
+    sk->ctx = ctx;
+    sk->L = make_layout(R);
+    sk->seed = hash_seed;
+    sk->eps_c = o.eps_c;
+    sk->time_sweeps = o.reserved != 0;
+    DevGraph& g = sk->g;
+    g.n = n;
+    g.m = m;
+    const Layout& L = sk->L;
+    bool ok = true;
+    ok = ok && sk_alloc(sk, &g.xadj, n + 1) && sk_alloc(sk, &g.adj, m) && sk_alloc(sk, &g.eh, m);
+    ok = ok && sk_alloc(sk, &sk->X, R) && sk_alloc(sk, &sk->HJ, R) && sk_alloc(sk, &sk->T, R);
+    for (int i = 0; i < 3 && ok; ++i) ok = sk_alloc(sk, &sk->M[i], (size_t)n * L.P);
+    const int64_t words = (n + 31) / 32 + 1;
+    ok = ok && sk_alloc(sk, &sk->Lbm[0], words) && sk_alloc(sk, &sk->Lbm[1], words);
+    ok = ok && sk_alloc(sk, &sk->cnt_ring, (size_t)RING * NSLOT * SLOT_U32) &&
+         sk_alloc(sk, &sk->vis_ring, (size_t)RING * NSLOT * SLOT_U64) && sk_alloc(sk, &sk->gather, 4 * MAX_BATCH);
+    ok = ok && sk_alloc(sk, &sk->d_err, 4) && sk_alloc(sk, &sk->d_heavy_counts, 4) && sk_alloc(sk, &sk->d_flag, 4);
+    if (probs->kind == IM_PROB_WEIGHTED_CASCADE) ok = ok && sk_alloc(sk, &g.thr, n);
+    if (probs->kind == IM_PROB_PER_EDGE) ok = ok && sk_alloc(sk, &g.thr, m);
+    if (!ok) {
+        sk_release(sk);
+        return fail(IM_ERR_OUT_OF_BUDGET, "device allocation failed");
+    }
+    if (hipHostMalloc((void**)&sk->h_gather[0], 16 * MAX_BATCH) != hipSuccess ||
+        hipHostMalloc((void**)&sk->h_gather[1], 16 * MAX_BATCH) != hipSuccess ||
+        hipHostMalloc((void**)&sk->h_small, 64) != hipSuccess) {
+        sk_release(sk);
+        return fail(IM_ERR_DEVICE, "pinned host allocation failed");
+    }
+    if (hipEventCreate(&sk->ev_a) != hipSuccess || hipEventCreate(&sk->ev_b) != hipSuccess ||
+        hipEventCreate(&sk->ev_batch[0]) != hipSuccess || hipEventCreate(&sk->ev_batch[1]) != hipSuccess) {
+        sk_release(sk);
+        return fail(IM_ERR_DEVICE, "event creation failed");
+    }
+    if (sk->time_sweeps) {
+        sk->sweep_ev.resize(SWEEP_TIMERS);
+        for (auto& e : sk->sweep_ev)
+            if (hipEventCreate(&e) != hipSuccess) {
+                sk_release(sk);
+                return fail(IM_ERR_DEVICE, "event creation failed");
+            }
+    }
+
+    im_status st = IM_OK;
+    auto body = [&]() -> im_status {
+        const hipMemcpyKind kind = graph->on_device ? hipMemcpyDeviceToDevice : hipMemcpyHostToDevice;
+        HIP_TRY(hipEventRecord(sk->ev_a, s));
+        HIP_TRY(hipMemcpyAsync(g.xadj, graph->xadj, 8 * (n + 1), kind, s));
+        if (m > 0) HIP_TRY(hipMemcpyAsync(g.adj, graph->adj, 4 * m, kind, s));
+        HIP_TRY(launch_fill_u32(sk->d_err, 0u, 1, s));
+        HIP_TRY(launch_validate(g, sk->d_err, s));
+        HIP_TRY(hipMemcpyAsync(sk->h_small, sk->d_err, 4, hipMemcpyDeviceToHost, s));
+        HIP_TRY(hipStreamSynchronize(s));
+        if (sk->h_small[0] & 1u) return fail(IM_ERR_INVALID_GRAPH, "xadj is not nondecreasing");
+        if (sk->h_small[0] & 2u) return fail(IM_ERR_INVALID_GRAPH, "adj holds an id outside [0, n)");
+
+        HIP_TRY(launch_edge_hash(g, hash_seed, s));
+        HIP_TRY(launch_sim_words(sk->X, sk->HJ, R, hash_seed, s));
+        // exp2(r/J) table for the estimate (host libm), uploaded once
+        std::vector<double> T(R);
+        for (int r = 0; r < R; ++r) T[r] = exp2((double)r / (double)R);
+        HIP_TRY(hipMemcpyAsync(sk->T, T.data(), 8 * R, hipMemcpyHostToDevice, s));
+        if (probs->kind == IM_PROB_CONSTANT) {
+            g.kind = THR_CONST;
+            g.thr_const = live_threshold(probs->p);
+        } else if (probs->kind == IM_PROB_WEIGHTED_CASCADE) {
+            g.kind = THR_TARGET;
+            uint32_t* indeg = nullptr;
+            void* p = ctx_alloc(ctx, 4 * n);
+            if (!p) return fail(IM_ERR_OUT_OF_BUDGET, "temporary allocation failed");
+            indeg = (uint32_t*)p;
+            HIP_TRY(launch_fill_u32(indeg, 0u, n, s));
+            HIP_TRY(launch_indegree(g, indeg, s));
+            HIP_TRY(launch_wc_thresholds(indeg, g.thr, n, s));
+            HIP_TRY(hipStreamSynchronize(s));
+            ctx_free(ctx, p);
+        } else {
+            g.kind = THR_EDGE;
+            if (m > 0) {
+                const float* w = probs->per_edge;
+                void* tmp = nullptr;
+                if (!graph->on_device) {
+                    tmp = ctx_alloc(ctx, 4 * m);
+                    if (!tmp) return fail(IM_ERR_OUT_OF_BUDGET, "temporary allocation failed");
+                    HIP_TRY(hipMemcpyAsync(tmp, probs->per_edge, 4 * m, hipMemcpyHostToDevice, s));
+                    w = (const float*)tmp;
+                }
+                HIP_TRY(launch_fill_u32(sk->d_err, 0u, 1, s));
+                HIP_TRY(launch_edge_thresholds(w, g.thr, m, sk->d_err, s));
+                HIP_TRY(hipMemcpyAsync(sk->h_small, sk->d_err, 4, hipMemcpyDeviceToHost, s));
+                HIP_TRY(hipStreamSynchronize(s));
+                if (tmp) ctx_free(ctx, tmp);
+                if (sk->h_small[0] & 4u) return fail(IM_ERR_INVALID_ARG, "a per-edge probability is outside [0, 1]");
+            }
+        }
+        // split rows
+        const int64_t heavy = o.heavy_degree > 0 ? o.heavy_degree : DEFAULT_HEAVY;
+        const int64_t piece = o.piece_edges > 0 ? o.piece_edges : DEFAULT_PIECE;
+        g.heavy_deg = heavy;
+        HIP_TRY(hipMemsetAsync(sk->d_heavy_counts, 0, 32, s));
+        HIP_TRY(launch_heavy_count(g, piece, sk->d_heavy_counts, s));
+        unsigned long long hc[2] = {0, 0};
+        HIP_TRY(hipMemcpyAsync(hc, sk->d_heavy_counts, 16, hipMemcpyDeviceToHost, s));
+        HIP_TRY(hipStreamSynchronize(s));
+        g.nheavy = (int64_t)hc[0];
+        g.npieces = (int64_t)hc[1];
+        if (g.nheavy > 0) {
+            bool ok2 = sk_alloc(sk, &g.hrow, g.nheavy) && sk_alloc(sk, &g.hpb, g.nheavy) &&
+                       sk_alloc(sk, &g.hpn, g.nheavy) && sk_alloc(sk, &g.prow, g.npieces) &&
+                       sk_alloc(sk, &g.pe0, g.npieces) && sk_alloc(sk, &g.pe1, g.npieces) &&
+                       sk_alloc(sk, &sk->part, (size_t)g.npieces * L.P) && sk_alloc(sk, &sk->part_any, g.npieces);
+            if (!ok2) return fail(IM_ERR_OUT_OF_BUDGET, "device allocation failed (split rows)");
+            HIP_TRY(launch_heavy_assign(g, piece, sk->d_heavy_counts, s));
+            HIP_TRY(launch_heavy_pieces(g, piece, s));
+        }
+        // greedy buffers
+        const size_t W = 4 * (size_t)L.PW;
+        GreedyBufs& b = sk->gb;
+        b.qcap = qcap_for(n, m);
+        b.bfs_chunk = BFS_CHUNK;
+        bool ok3 = sk_alloc(sk, &b.blk, n * W) && sk_alloc(sk, &b.F[0], n * W) && sk_alloc(sk, &b.F[1], n * W) &&
+                   sk_alloc(sk, &b.Q[0], b.qcap) && sk_alloc(sk, &b.Q[1], b.qcap) && sk_alloc(sk, &b.qsize, 16) &&
+                   sk_alloc(sk, &b.stamp, n) && sk_alloc(sk, &b.inS, n) && sk_alloc(sk, &b.MS, L.P) &&
+                   sk_alloc(sk, &b.merged, L.P) && sk_alloc(sk, &b.key, 1) &&
+                   sk_alloc(sk, &b.R, NSLOT * SLOT_U64) && sk_alloc(sk, &b.Rreb, 1);
+        if (!ok3) return fail(IM_ERR_OUT_OF_BUDGET, "device allocation failed (greedy buffers)");
+        b.T = sk->T;
+        HIP_TRY(hipMemsetAsync(b.stamp, 0, 4 * n, s));
+        HIP_TRY(hipMemsetAsync(b.F[0], 0, 4 * n * W, s));
+        HIP_TRY(hipMemsetAsync(b.F[1], 0, 4 * n * W, s));
+        HIP_TRY(hipEventRecord(sk->ev_b, s));
+        HIP_TRY(hipStreamSynchronize(s));
+        float pm = 0.f;
+        HIP_TRY(hipEventElapsedTime(&pm, sk->ev_a, sk->ev_b));
+        sk->prep_ms = pm;
+
+        SimResult r;
+        im_status rs = run_simulate(sk, 0, 1, nullptr, &r);
+        if (rs != IM_OK) return rs;
+        sk->build_buf = r.buf;
+        sk->sel_buf = r.buf;
+        sk->sweeps = r.sweeps;
+        sk->visits = r.visits;
+        sk->build_ms = r.ms;
+        sk->trace_live = r.live;
+        sk->trace_vis = r.vis;
+        sk->light_ms = r.light_ms;
+        return IM_OK;
+    };
+    st = body();
+    if (st != IM_OK) {
+        sk_release(sk);
+        return st;
+    }
+    *out = sk;
+    return IM_OK;
+}
+
+void im_sketch_free(im_sketch* sk) { sk_release(sk); }
+
+im_status im_sketch_get_info(const im_sketch* sk, im_sketch_info* info) {
+    im_status st = check_sketch(sk);
+    if (st != IM_OK) return st;
+    if (!info) return fail(IM_ERR_INVALID_ARG, "info is null");
+    info->n = sk->g.n;
+    info->m = sk->g.m;
+    info->R = sk->L.J;
+    info->sweeps = sk->sweeps;
+    info->visits = sk->visits;
+    info->build_ms = sk->build_ms;
+    info->prep_ms = sk->prep_ms;
+    info->device_bytes = sk->bytes;
+    info->heavy_rows = sk->g.nheavy;
+    info->heavy_pieces = sk->g.npieces;
+    return IM_OK;
+}
+
+im_status im_sketch_get_trace(const im_sketch* sk, int64_t* live_counts, int64_t* edge_visits, int32_t cap,
+                              int32_t* written) {
+    im_status st = check_sketch(sk);
+    if (st != IM_OK) return st;
+    const int32_t nl = (int32_t)sk->trace_live.size();
+    for (int32_t i = 0; i < nl && i < cap; ++i) {
+        if (live_counts) live_counts[i] = sk->trace_live[i];
+        if (edge_visits && i < (int32_t)sk->trace_vis.size()) edge_visits[i] = sk->trace_vis[i];
+    }
+    if (written) *written = nl;
+    return IM_OK;
+}
+
+// Per-sweep device time of the dominant (non-split-row) sweep kernel, in ms,
+// when the build was asked to time sweeps; returns the count written.
+int32_t im_sketch_get_sweep_kernel_ms(const im_sketch* sk, float* out, int32_t cap) {
+    if (!sk) return 0;
+    int32_t k = 0;
+    for (; k < cap && k < (int32_t)sk->light_ms.size(); ++k) out[k] = sk->light_ms[k];
+    return k;
+}
+
+im_status im_sketch_get_registers(const im_sketch* sk, int32_t which, uint8_t* out) {
+    im_status st = check_sketch(sk);
+    if (st != IM_OK) return st;
+    if (!out || (which != 0 && which != 1)) return fail(IM_ERR_INVALID_ARG, "bad arguments");
+    const uint32_t* M = sk->M[which == 0 ? sk->build_buf : sk->sel_buf];
+    if (hipMemcpy(out, M, (size_t)sk->g.n * sk->L.J, hipMemcpyDeviceToHost) != hipSuccess)
+        return fail(IM_ERR_DEVICE, "copy failed");
+    return IM_OK;
+}
+
+im_status im_sketch_get_blocked(const im_sketch* sk, uint8_t* out) {
+    im_status st = check_sketch(sk);
+    if (st != IM_OK) return st;
+    if (!out) return fail(IM_ERR_INVALID_ARG, "out is null");
+    if (!sk->selected) return fail(IM_ERR_STATE, "no seed selection has run on this sketch");
+    const size_t bytes = (size_t)sk->g.n * sk->L.J;
+    void* tmp = nullptr;
+    if (hipMalloc(&tmp, bytes) != hipSuccess) return fail(IM_ERR_OUT_OF_BUDGET, "temporary allocation failed");
+    hipStream_t s = sk->ctx->stream;
+    im_status rs = IM_OK;
+    if (launch_blocked_to_bytes(sk->L, sk->g.n, sk->gb.blk, (uint8_t*)tmp, s) != hipSuccess ||
+        hipMemcpyAsync(out, tmp, bytes, hipMemcpyDeviceToHost, s) != hipSuccess || hipStreamSynchronize(s) != hipSuccess)
+        rs = fail(IM_ERR_DEVICE, "blocked copy failed");
+    (void)hipFree(tmp);
+    return rs;
+}
+
+im_status im_estimate_all(im_sketch* sk, float* out, int32_t out_on_device) {
+    im_status st = check_sketch(sk);
+    if (st != IM_OK) return st;
+    if (!out) return fail(IM_ERR_INVALID_ARG, "out is null");
+    hipStream_t s = sk->ctx->stream;
+    const int64_t n = sk->g.n;
+    float* dst = out;
+    void* tmp = nullptr;
+    if (!out_on_device) {
+        tmp = ctx_alloc(sk->ctx, 4 * n);
+        if (!tmp) return fail(IM_ERR_OUT_OF_BUDGET, "temporary allocation failed");
+        dst = (float*)tmp;
+    }
+    im_status rs = IM_OK;
+    if (launch_estimate_all(sk->L, n, sk->M[sk->build_buf], sk->T, dst, s) != hipSuccess)
+        rs = fail(IM_ERR_DEVICE, "estimate kernel failed");
+    if (rs == IM_OK && tmp && hipMemcpyAsync(out, tmp, 4 * n, hipMemcpyDeviceToHost, s) != hipSuccess)
+        rs = fail(IM_ERR_DEVICE, "copy failed");
+    if (hipStreamSynchronize(s) != hipSuccess) rs = fail(IM_ERR_DEVICE, "synchronize failed");
+    if (tmp) ctx_free(sk->ctx, tmp);
+    return rs;
+}
+
+im_status im_estimate(im_sketch* sk, const int32_t* verts, int64_t count, float* out_estimate) {
+    im_status st = check_sketch(sk);
+    if (st != IM_OK) return st;
+    if (!verts || count < 1 || !out_estimate) return fail(IM_ERR_INVALID_ARG, "bad arguments");
+    for (int64_t i = 0; i < count; ++i)
+        if (verts[i] < 0 || verts[i] >= sk->g.n) return fail(IM_ERR_INVALID_ARG, "vertex id out of range");
+    hipStream_t s = sk->ctx->stream;
+    void* tmp = ctx_alloc(sk->ctx, 4 * count + 256);
+    if (!tmp) return fail(IM_ERR_OUT_OF_BUDGET, "temporary allocation failed");
+    float* dout = (float*)((char*)tmp + ((4 * count + 255) & ~int64_t(255)));
+    im_status rs = IM_OK;
+    float h = 0.f;
+    if (hipMemcpyAsync(tmp, verts, 4 * count, hipMemcpyHostToDevice, s) != hipSuccess ||
+        launch_estimate_set(sk->L, sk->M[sk->build_buf], (const int32_t*)tmp, count, sk->T, dout, s) != hipSuccess ||
+        hipMemcpyAsync(&h, dout, 4, hipMemcpyDeviceToHost, s) != hipSuccess || hipStreamSynchronize(s) != hipSuccess)
+        rs = fail(IM_ERR_DEVICE, "estimate failed");
+    ctx_free(sk->ctx, tmp);
+    if (rs == IM_OK) *out_estimate = h;
+    return rs;
+}
+
+im_status im_select_seeds(im_sketch* sk, int32_t K, const im_select_opts* opts, int32_t* out_seeds, im_step* out_steps,
+                          im_select_stats* stats) {
+    im_status st0 = check_sketch(sk);
+    if (st0 != IM_OK) return st0;
+    if (!out_seeds) return fail(IM_ERR_INVALID_ARG, "out_seeds is null");
+    if (K < 1 || K > sk->g.n) return fail(IM_ERR_INVALID_ARG, "K must be in [1, n] (got %d)", K);
+    double eps_g = 0.01, eps_l = 0.3;
+    if (opts) {
+        eps_g = opts->eps_g;
+        eps_l = opts->eps_l;
+    }
+    if (!(eps_g >= 0.0) || !(eps_l >= 0.0)) return fail(IM_ERR_INVALID_ARG, "thresholds must be >= 0");
+    const auto wall0 = std::chrono::steady_clock::now();
+    hipStream_t s = sk->ctx->stream;
+    const int64_t n = sk->g.n;
+    const Layout& L = sk->L;
+    GreedyBufs& b = sk->gb;
+    const size_t W = 4 * (size_t)L.PW;
+
+    // per-call buffers for K records and seeds
+    StepRec* d_steps = nullptr;
+    int32_t* d_seeds = nullptr;
+    {
+        void* p = ctx_alloc(sk->ctx, sizeof(StepRec) * K + 4 * (size_t)K + 512);
+        if (!p) return fail(IM_ERR_OUT_OF_BUDGET, "temporary allocation failed");
+        d_steps = (StepRec*)p;
+        d_seeds = (int32_t*)((char*)p + ((sizeof(StepRec) * K + 255) & ~size_t(255)));
+    }
+    std::vector<StepRec> h_steps(K);
+    int32_t rebuilds = 0;
+    int64_t rsweeps = 0, rvisits = 0, levels_total = 0;
+
+    auto body = [&]() -> im_status {
+        HIP_TRY(hipEventRecord(sk->ev_a, s));
+        HIP_TRY(hipMemsetAsync(b.blk, 0, 4 * n * W, s));
+        HIP_TRY(hipMemsetAsync(b.inS, 0, n, s));
+        HIP_TRY(hipMemsetAsync(b.MS, 0, 4 * L.P, s));
+        HIP_TRY(hipMemsetAsync(b.key, 0, 8, s));
+        HIP_TRY(hipMemsetAsync(b.R, 0, 8 * NSLOT * SLOT_U64, s));
+        HIP_TRY(hipMemsetAsync(b.Rreb, 0, 8, s));
+        HIP_TRY(hipMemsetAsync(d_steps, 0, sizeof(StepRec) * K, s));
+        int cur = sk->build_buf;
+        for (int k = 1; k <= K; ++k) {
+            HIP_TRY(launch_argmax(L, n, sk->M[cur], b, s));
+            HIP_TRY(hipMemsetAsync(b.qsize, 0, 16, s));
+            const int32_t lvl0 = sk->level_id;
+            HIP_TRY(launch_select(L, sk->g, sk->M[cur], b, d_steps + (k - 1), d_seeds, k - 1, lvl0, s));
+            // BFS levels in batches; the decision kernel is enqueued after every
+            // batch and reports -1 while the frontier is not empty.
+            int level = 0, nb = 4;
+            int32_t flag = -1;
+            while (true) {
+                const int64_t bfs_grid = 2048;
+                for (int i = 0; i < nb; ++i, ++level)
+                    HIP_TRY(launch_bfs_level(L, sk->g, sk->X, b, level, lvl0 + level + 1, (int)bfs_grid, s));
+                HIP_TRY(hipMemcpyAsync(sk->h_small, b.qsize, 16, hipMemcpyDeviceToHost, s));
+                HIP_TRY(hipStreamSynchronize(s));
+                if ((sk->h_small[0] | sk->h_small[1] | sk->h_small[2]) == 0u) break;
+                if (level > n + 2) {
+                    sk->poisoned = true;
+                    return fail(IM_ERR_DEVICE, "reach search exceeded n levels");
+                }
+                nb = std::min(nb * 2, 64);
+            }
+            levels_total += sk->h_small[3];
+            sk->level_id = lvl0 + level + 2;
+            {
+                int32_t chosen = 0;
+                HIP_TRY(hipMemcpyAsync(&chosen, d_seeds + (k - 1), 4, hipMemcpyDeviceToHost, s));
+                HIP_TRY(hipStreamSynchronize(s));
+                if (chosen < 0) {
+                    sk->poisoned = true;
+                    return fail(IM_ERR_DEVICE, "argmax found no candidate at step %d", k);
+                }
+            }
+            HIP_TRY(launch_decide(L, b, d_steps + (k - 1), k, K, eps_g, eps_l, sk->d_flag, s));
+            HIP_TRY(hipMemcpyAsync(&flag, sk->d_flag, 4, hipMemcpyDeviceToHost, s));
+            HIP_TRY(hipStreamSynchronize(s));
+            if (flag == 1) {
+                int ia = (cur + 1) % 3, ib = (cur + 2) % 3;
+                if (ia == sk->build_buf) ia = (ia + 1) % 3;
+                if (ib == sk->build_buf || ib == ia) ib = 3 - sk->build_buf - ia;
+                SimResult r;
+                im_status rs = run_simulate(sk, ia, ib, b.blk, &r);
+                if (rs != IM_OK) return rs;
+                cur = r.buf;
+                ++rebuilds;
+                rsweeps += r.sweeps;
+                rvisits += r.visits;
+                h_steps[k - 1].sweeps = r.sweeps;
+                h_steps[k - 1].visits = r.visits;
+            }
+        }
+        HIP_TRY(hipEventRecord(sk->ev_b, s));
+        std::vector<StepRec> dev(K);
+        HIP_TRY(hipMemcpyAsync(dev.data(), d_steps, sizeof(StepRec) * K, hipMemcpyDeviceToHost, s));
+        HIP_TRY(hipMemcpyAsync(out_seeds, d_seeds, 4 * (size_t)K, hipMemcpyDeviceToHost, s));
+        HIP_TRY(hipStreamSynchronize(s));
+        for (int k = 0; k < K; ++k) {
+            const int32_t sw = h_steps[k].sweeps;
+            const int64_t vi = h_steps[k].visits;
+            h_steps[k] = dev[k];
+            h_steps[k].sweeps = sw;
+            h_steps[k].visits = vi;
+        }
+        sk->sel_buf = cur;
+        sk->selected = true;
+        float ms = 0.f;
+        HIP_TRY(hipEventElapsedTime(&ms, sk->ev_a, sk->ev_b));
+        if (stats) stats->device_ms = ms;
+        return IM_OK;
+    };
+    im_status st = body();
+    ctx_free(sk->ctx, d_steps);
+    if (st != IM_OK) return st;
+    if (out_steps) {
+        for (int k = 0; k < K; ++k) {
+            const StepRec& r = h_steps[k];
+            im_step& o = out_steps[k];
+            o.seed = r.seed;
+            o.rebuilt = r.rebuilt;
+            o.fresh = r.fresh;
+            o.sweeps = r.sweeps;
+            o.score = r.score;
+            o.reach = r.reach;
+            o.e = r.e;
+            o.sigma = r.sigma;
+            o.delta = r.delta;
+            o.err_l = r.err_l;
+            o.err_g = r.err_g;
+            o.visits = r.visits;
+        }
+    }
+    if (stats) {
+        stats->rebuilds = rebuilds;
+        stats->reserved = 0;
+        stats->rebuild_sweeps = rsweeps;
+        stats->rebuild_visits = rvisits;
+        stats->bfs_levels = levels_total;
+        stats->wall_ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - wall0).count();
+    }
+    return IM_OK;
+}
+
+}  // extern "C"

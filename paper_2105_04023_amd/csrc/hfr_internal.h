@@ -1,0 +1,141 @@
+// Internal interface between the host side of the library (hfr_api.hip) and
+// its gfx950 kernels (hfr_kernels.hip).  Not part of the public ABI.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace hfr {
+
+// Spread counters: atomics from many blocks land on NSLOT distinct 128-byte
+// lines instead of one address; readers sum the slots.
+constexpr int NSLOT = 32;
+constexpr int SLOT_U32 = 32;  // u32 stride between slots (128 B)
+constexpr int SLOT_U64 = 16;  // u64 stride between slots (128 B)
+
+// Register layout: a vertex row holds J one-byte registers = P = J/4 dwords.
+// A wave serves 64/G rows at once (G lanes per row, DW dwords per lane, lane p
+// of a row owns dwords q = i*G + p, i < DW).  The blocked bits of a vertex are
+// 4 planes of PW dwords: plane k holds bit q for register 4q+k.
+struct Layout {
+    int J;
+    int P;   // dwords per row
+    int PW;  // dwords per blocked-bit plane
+    int G;   // lanes per row
+    int DW;  // dwords per lane
+};
+
+Layout make_layout(int J);
+
+enum ThrKind { THR_CONST = 0, THR_TARGET = 1, THR_EDGE = 2 };
+
+struct DevGraph {
+    int64_t n = 0, m = 0;
+    int64_t* xadj = nullptr;
+    int32_t* adj = nullptr;
+    uint32_t* eh = nullptr;   // 31-bit edge hash per edge
+    uint32_t* thr = nullptr;  // per target vertex (WC) or per edge
+    uint32_t thr_const = 0;
+    int kind = THR_CONST;
+    // rows split across waves
+    int64_t heavy_deg = 0;
+    int64_t nheavy = 0, npieces = 0;
+    int32_t* hrow = nullptr;    // heavy row ids [nheavy]
+    int64_t* hpb = nullptr;     // first piece of each heavy row [nheavy]
+    int64_t* hpn = nullptr;     // number of pieces of each heavy row [nheavy]
+    int32_t* prow = nullptr;    // row of each piece [npieces]
+    int64_t* pe0 = nullptr;     // first edge of each piece
+    int64_t* pe1 = nullptr;     // one past the last edge of each piece
+};
+
+// Per-sweep launch parameters.
+struct SweepParams {
+    const uint32_t* A;  // registers M^t
+    uint32_t* B;        // registers M^{t+1}
+    const uint32_t* Lcur;
+    uint32_t* Lnext;
+    const uint32_t* blk;       // nullptr when no pair is blocked
+    const uint32_t* gate;      // live-count slots of L_t (nullptr on the first sweep)
+    uint32_t gate_thresh;      // sweep runs iff |L_t| > gate_thresh
+    uint32_t* cnt_out;         // slots of |L_{t+1}|
+    unsigned long long* vis_out;  // slots of edges with a live head in this sweep
+    uint32_t* part;            // partial rows of split-row pieces [npieces * P]
+    uint32_t* part_any;        // per piece: 1 if some live edge was merged
+    int first;
+};
+
+struct GreedyBufs {
+    uint32_t* blk;     // n * 4 * PW
+    uint32_t* F[2];    // frontier bits, same shape as blk
+    int2* Q[2];        // queue entries (vertex, chunk)
+    uint32_t* qsize;   // 3 ring counters (+ level counter at [3])
+    int32_t* stamp;    // last level a vertex was queued for
+    uint8_t* inS;      // n
+    uint32_t* MS;      // P dwords: M_S'
+    uint32_t* merged;  // P dwords: Merge(M_S', M_s)
+    unsigned long long* key;   // argmax key
+    unsigned long long* R;     // reach slots
+    unsigned long long* Rreb;  // reach at the last rebuild
+    double* T;         // exp2(r/J), r < J
+    int64_t qcap;
+    int32_t bfs_chunk;
+};
+
+// Device-side record of one greedy step (mirrors im_step).
+struct StepRec {
+    int32_t seed, rebuilt, fresh, sweeps;
+    int64_t score, reach;
+    double e, sigma, delta, err_l, err_g;
+    int64_t visits;
+};
+
+// ---- launchers (hfr_kernels.hip) ----
+hipError_t launch_fill_u32(uint32_t* p, uint32_t v, int64_t count, hipStream_t s);
+hipError_t launch_validate(const DevGraph& g, uint32_t* err, hipStream_t s);
+hipError_t launch_edge_hash(const DevGraph& g, uint32_t seed, hipStream_t s);
+hipError_t launch_indegree(const DevGraph& g, uint32_t* indeg, hipStream_t s);
+hipError_t launch_wc_thresholds(const uint32_t* indeg, uint32_t* thr, int64_t n, hipStream_t s);
+hipError_t launch_edge_thresholds(const float* w, uint32_t* thr, int64_t m, uint32_t* err, hipStream_t s);
+hipError_t launch_sim_words(uint32_t* X, uint32_t* HJ, int J, uint32_t seed, hipStream_t s);
+hipError_t launch_heavy_count(const DevGraph& g, int64_t piece_edges, unsigned long long* counts, hipStream_t s);
+hipError_t launch_heavy_assign(const DevGraph& g, int64_t piece_edges, unsigned long long* counts, hipStream_t s);
+hipError_t launch_heavy_pieces(const DevGraph& g, int64_t piece_edges, hipStream_t s);
+hipError_t launch_init(const Layout& L, int64_t n, const uint32_t* HJ, uint32_t seed, const uint32_t* blk,
+                       uint32_t* A, uint32_t* B, hipStream_t s);
+hipError_t launch_sweep(const Layout& L, const DevGraph& g, const uint32_t* X, const SweepParams& sp, int grid,
+                        hipStream_t s, hipEvent_t ev_light_begin, hipEvent_t ev_light_end);
+hipError_t launch_argmax(const Layout& L, int64_t n, const uint32_t* M, const GreedyBufs& b, hipStream_t s);
+hipError_t launch_select(const Layout& L, const DevGraph& g, const uint32_t* M, const GreedyBufs& b,
+                         StepRec* rec, int32_t* seeds_dev, int k, int32_t level_id, hipStream_t s);
+hipError_t launch_bfs_level(const Layout& L, const DevGraph& g, const uint32_t* X, const GreedyBufs& b, int level,
+                            int32_t level_id_next, int grid, hipStream_t s);
+hipError_t launch_decide(const Layout& L, const GreedyBufs& b, StepRec* rec, int k, int K, double eps_g,
+                         double eps_l, int32_t* rebuild_flag, hipStream_t s);
+hipError_t launch_estimate_all(const Layout& L, int64_t n, const uint32_t* M, const double* T, float* out,
+                               hipStream_t s);
+hipError_t launch_estimate_set(const Layout& L, const uint32_t* M, const int32_t* verts, int64_t count,
+                               const double* T, float* out, hipStream_t s);
+hipError_t launch_blocked_to_bytes(const Layout& L, int64_t n, const uint32_t* blk, uint8_t* out, hipStream_t s);
+
+// Integer live threshold of a binary32 weight: the number of 31-bit integers
+// x with x < w * (2^31 - 1); 0xFFFFFFFF when w is not in [0, 1].
+__host__ __device__ inline uint32_t live_threshold(float w) {
+    if (!(w >= 0.0f && w <= 1.0f)) return 0xFFFFFFFFu;
+    uint32_t bits = __builtin_bit_cast(uint32_t, w);
+    uint32_t ex = (bits >> 23) & 0xFFu;
+    uint64_t mant = bits & 0x7FFFFFu;
+    int sh;
+    if (ex == 0) {
+        sh = 149;
+    } else {
+        mant |= 1ull << 23;
+        sh = 150 - (int)ex;
+    }
+    if (mant == 0) return 0u;
+    uint64_t prod = mant * 2147483647ull;  // < 2^55
+    if (sh >= 64) return 1u;
+    uint64_t q = prod >> sh;
+    return (uint32_t)(q + ((prod & ((1ull << sh) - 1)) != 0));
+}
+
+}  // namespace hfr
