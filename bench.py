@@ -1,0 +1,185 @@
+"""Benchmark of the sketch-based influence-maximisation path on one MI355X.
+
+One step = the whole path on one synthetic graph already resident in HBM: build the
+sketches (edge hashing, thresholds, register init, synchronous sweeps to the fixed point)
+and select K seeds with error-adaptive rebuild.  The headline value is edge*simulation
+visits per second of sketch build (visits = R * edges with a live head, summed over the
+build's sweeps); the K-seed IM time is reported beside it.
+
+Prints one JSON line.  `--gpus N` with N > 1 is refused: this path runs on one GPU.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import platform
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0  # MI355X published HBM3E bandwidth
+
+
+def log(*a):
+    print("[bench]", *a, file=sys.stderr, flush=True)
+
+
+WORKLOADS = {
+    "rmat24_wc_J256_K50": lambda s: s.workload_rmat24_wc(),
+    "rmat20_p0.01_J256_K50": lambda s: s.workload_rmat20(),
+    "er_n1000_m10000_p0.1_J64_K10": lambda s: s.workload_er_small(),
+}
+
+
+def sweep_bytes(rec, n, m_light, J, wc):
+    """Algorithmic HBM bytes of one row-kernel sweep launch.
+
+    Reads xadj (8(n+1)), the out-edge ids of the rows it owns (4 m_light), the live
+    bitmap L_t (n/8), per visited edge the neighbour row (J) plus its hash (4) and, for the
+    weighted cascade, the target threshold (4); writes L_{t+1} (n/8); reads and writes
+    every changed row (2J).  A launch past the stopping rule moves nothing.
+    """
+    if not rec["ran"]:
+        return 0
+    per_edge = J + 4 + (4 if wc else 0)
+    return 8 * (n + 1) + 4 * m_light + n // 4 + rec["light_visits"] * per_edge + 2 * J * rec["live_next"]
+
+
+def cpu_baseline(seconds_hint: float = 15.0):
+    """The oracle's Simulate, single-threaded, on a bounded sample: the same R-MAT recipe at scale 16."""
+    import oracle
+    import synth
+
+    g = synth.rmat(16, 16 << 16, seed=3)
+    thr = oracle.edge_thresholds(g, "wc")
+    t0 = time.perf_counter()
+    M, sweeps, tl, te = oracle.simulate(g, thr, 256)
+    dt = time.perf_counter() - t0
+    visits = int(te.sum()) * 256
+    return {"value": visits / dt, "unit": "edge*sim visits/s", "cores": 1, "kind": "oracle",
+            "sample": f"R-MAT scale 16 (n=65536, m={g.m}), weighted cascade, R=256: full Simulate to the fixed "
+                      f"point ({sweeps} sweeps, {visits} visits) in {dt:.1f} s on one host core",
+            "host_cpu": platform.processor() or platform.machine(), "host_nproc": os.cpu_count()}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=3)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--workload", default="rmat24_wc_J256_K50", choices=sorted(WORKLOADS))
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--K", type=int, default=0, help="override K")
+    ap.add_argument("--sparse-div", type=int, default=0)
+    ap.add_argument("--heavy-degree", type=int, default=0)
+    ap.add_argument("--dump-sweeps", default="", help="write the sweep log of the last step to this JSON file")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(json.dumps({"error": "this path runs on one GPU; multi-GPU runs are not part of this build",
+                          "n_gpus": args.gpus}))
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+
+    import paper_2105_04023_amd as hf
+    import synth
+
+    t = time.perf_counter()
+    w = WORKLOADS[args.workload](synth)
+    g = w.graph
+    K = args.K or w.K
+    log(f"workload {w.name}: n={g.n} m={g.m} generated in {time.perf_counter() - t:.1f} s")
+    deg = np.diff(g.xadj)
+    heavy_deg = args.heavy_degree or 32
+    m_light = int(deg[deg <= heavy_deg].sum())
+    xd = torch.from_numpy(g.xadj).cuda()
+    ad = torch.from_numpy(g.adj).cuda()
+    torch.cuda.synchronize()
+    ctx = hf.Context(0)
+
+    def step(timed):
+        t0 = time.perf_counter()
+        sk = hf.im_build_sketches(ctx, xd, ad, g.n, w.J, model=w.model, p=w.p, eps_c=w.eps_c,
+                                  sparse_div=args.sparse_div, heavy_degree=args.heavy_degree,
+                                  time_sweeps=timed)
+        t1 = time.perf_counter()
+        seeds, steps, stats = hf.im_select_seeds(sk, K, eps_g=w.eps_g, eps_l=w.eps_l)
+        t2 = time.perf_counter()
+        info = sk.info()
+        swl = sk.sweep_log() if timed else []
+        sk.free()
+        return {"build_s": t1 - t0, "select_s": t2 - t1, "info": info, "stats": stats, "seeds": list(map(int, seeds)),
+                "sweep_log": swl, "sigma": steps[-1].sigma}
+
+    for i in range(args.warmup):
+        r = step(False)
+        log(f"warmup {i}: build {r['build_s'] * 1e3:.1f} ms select {r['select_s'] * 1e3:.1f} ms "
+            f"sweeps {r['info']['sweeps']} rebuilds {r['stats']['rebuilds']}")
+    torch.cuda.synchronize()
+    results = []
+    tstart = time.perf_counter()
+    for i in range(args.steps):
+        r = step(True)
+        results.append(r)
+        log(f"step {i}: build {r['build_s'] * 1e3:.1f} ms select {r['select_s'] * 1e3:.1f} ms "
+            f"sweeps {r['info']['sweeps']} rebuilds {r['stats']['rebuilds']} sigma {r['sigma']:.1f}")
+    torch.cuda.synchronize()
+    total_s = time.perf_counter() - tstart
+
+    J = w.J
+    visits = sum(r["info"]["visits"] for r in results) * J
+    build_s = sum(r["build_s"] for r in results)
+    select_s = sum(r["select_s"] for r in results)
+    sim_ms = sum(r["info"]["build_ms"] for r in results)
+    # roofline of the row sweep kernel over every timed launch (build and rebuilds)
+    recs = [rec for r in results for rec in r["sweep_log"]]
+    wc = w.model == "wc"
+    tot_bytes = sum(sweep_bytes(rec, g.n, m_light, J, wc) for rec in recs)
+    tot_ms = sum(rec["kernel_ms"] for rec in recs)
+    nlaunch = len(recs)
+    achieved = tot_bytes / (tot_ms * 1e-3) / 1e9 if tot_ms > 0 else 0.0
+    out = {
+        "metric": "edge*simulation visits/s in sketch build (+ K-seed IM time)",
+        "value": visits / build_s,
+        "unit": "edge*sim visits/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": total_s * 1e3 / args.steps,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "u8",
+        "data": "synthetic",
+        "config": {"workload": w.name, "n": g.n, "m": g.m, "R": J, "K": K, "model": w.model, "p": w.p,
+                   "eps_g": w.eps_g, "eps_l": w.eps_l, "eps_c": w.eps_c, "hash_seed": w.hash_seed},
+        "im_time_ms": select_s * 1e3 / args.steps,
+        "build_ms": build_s * 1e3 / args.steps,
+        "simulate_device_ms": sim_ms / args.steps,
+        "visits_per_step": visits // args.steps,
+        "sweeps": results[-1]["info"]["sweeps"],
+        "rebuilds": results[-1]["stats"]["rebuilds"],
+        "rebuild_sweeps": results[-1]["stats"]["rebuild_sweeps"],
+        "bfs_levels": results[-1]["stats"]["bfs_levels"],
+        "sigma": results[-1]["sigma"],
+        "seeds_head": results[-1]["seeds"][:8],
+        "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": achieved / HBM_PEAK_GBS, "traffic": None, "kernel": "k_sweep_light",
+                     "launches": nlaunch, "avg_launch_ms": tot_ms / max(nlaunch, 1),
+                     "algorithmic_bytes_per_launch": tot_bytes / max(nlaunch, 1)},
+    }
+    if args.dump_sweeps:
+        with open(args.dump_sweeps, "w") as fh:
+            json.dump(results[-1]["sweep_log"], fh)
+    if not args.no_cpu_baseline:
+        log("timing the oracle on the CPU sample")
+        out["cpu_baseline"] = cpu_baseline()
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

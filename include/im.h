@@ -75,7 +75,9 @@ typedef struct im_build_opts {
     double eps_c;
     int32_t heavy_degree; /* rows with more out-edges are split across waves */
     int32_t piece_edges;  /* edges per piece of a split row */
-    int32_t rows_per_wave_chunk; /* multiple of 32: consecutive rows per wave chunk */
+    int32_t sparse_div;   /* sweep t > 0 visits only the rows next to L_t when the
+                             in-degrees of L_t sum to at most m / sparse_div
+                             (0: 16; < 0: never) */
     int32_t reserved;
 } im_build_opts;
 
@@ -188,10 +190,30 @@ im_status im_sketch_get_info(const im_sketch* sk, im_sketch_info* info);
 im_status im_sketch_get_trace(const im_sketch* sk, int64_t* live_counts, int64_t* edge_visits, int32_t cap,
                               int32_t* written);
 
-/* Device time (ms) of the non-split-row sweep kernel of every sweep of the
- * build, recorded only when the build was asked to time sweeps
- * (im_build_opts.reserved != 0).  Returns the number of values written. */
-int32_t im_sketch_get_sweep_kernel_ms(const im_sketch* sk, float* out, int32_t cap);
+/* One launch of the row (non-split-row) sweep kernel, recorded when the build
+ * was asked to time sweeps (im_build_opts.reserved != 0): kernel_ms is its
+ * device time from HIP events on the context stream (sweep_ms: all kernels
+ * of the sweep); light_visits the edges
+ * with a live head it visited, visits those of the whole sweep, live_next
+ * |L_{t+1}|.  ran = 0 marks a launch past the stopping rule (it returned at
+ * once).  simulate numbers the Simulate calls of the sketch (0 = build,
+ * later ones are rebuilds inside im_select_seeds). */
+typedef struct im_sweep_rec {
+    int32_t simulate;
+    int32_t sweep;
+    int32_t ran;
+    float kernel_ms;  /* row kernel */
+    float sweep_ms;   /* every kernel of the sweep */
+    int32_t reserved;
+    int64_t light_visits;
+    int64_t visits;
+    int64_t live;      /* |L_t| */
+    int64_t live_next; /* |L_{t+1}| */
+} im_sweep_rec;
+
+/* Copies up to cap records of the sweep log; returns the number copied. */
+int32_t im_sketch_get_sweep_log(const im_sketch* sk, im_sweep_rec* out, int32_t cap);
+void im_sketch_clear_sweep_log(im_sketch* sk);
 
 /* Copies registers to the host, n*R bytes, vertex-major (R registers of a
  * vertex adjacent).  which = 0: registers of the build; which = 1: registers

@@ -113,10 +113,15 @@ class Sketch:
         B.check(self.lib.im_sketch_get_trace(self.handle, live.ctypes.data, vis.ctypes.data, cap, ctypes.byref(w)))
         return live[: w.value], vis[: w.value - 1]
 
-    def sweep_kernel_ms(self) -> np.ndarray:
-        out = np.zeros(4096, dtype=np.float32)
-        k = self.lib.im_sketch_get_sweep_kernel_ms(self.handle, out.ctypes.data, len(out))
-        return out[:k].copy()
+    def sweep_log(self, clear: bool = False) -> list:
+        """Timed launches of the row sweep kernel (needs time_sweeps=True at build)."""
+        cap = 1 << 16
+        buf = (B.im_sweep_rec * cap)()
+        k = self.lib.im_sketch_get_sweep_log(self.handle, ctypes.cast(buf, ctypes.c_void_p), cap)
+        out = [{f: getattr(buf[i], f) for f, _ in B.im_sweep_rec._fields_} for i in range(k)]
+        if clear:
+            self.lib.im_sketch_clear_sweep_log(self.handle)
+        return out
 
     def registers(self, which: int = 0) -> np.ndarray:
         out = np.empty((self.n, self.R), dtype=np.uint8)
@@ -154,7 +159,7 @@ def _ptr_and_residency(a, dtype):
 
 def im_build_sketches(ctx: Context, xadj, adj, n: int, R: int, model: str = "const", p: float = 0.0,
                       per_edge=None, hash_seed: int = 0, eps_c: float = 0.0, heavy_degree: int = 0,
-                      piece_edges: int = 0, time_sweeps: bool = False) -> Sketch:
+                      piece_edges: int = 0, sparse_div: int = 0, time_sweeps: bool = False) -> Sketch:
     """Alg. 1 initialisation + Alg. 2: builds the per-vertex rank registers of R samples."""
     torch = _torch()
     xp, xdev, xk = _ptr_and_residency(xadj, (np.int64, torch.int64))
@@ -172,7 +177,7 @@ def im_build_sketches(ctx: Context, xadj, adj, n: int, R: int, model: str = "con
         pe_ptr = pp
         keep.append(pk)
     probs = B.im_probs(_KIND[model], float(p), pe_ptr)
-    opts = B.im_build_opts(eps_c, heavy_degree, piece_edges, 0, 1 if time_sweeps else 0)
+    opts = B.im_build_opts(eps_c, heavy_degree, piece_edges, sparse_div, 1 if time_sweeps else 0)
     h = ctypes.c_void_p()
     B.check(ctx.lib.im_build_sketches(ctx.handle, ctypes.byref(g), ctypes.byref(probs), R, hash_seed & 0xFFFFFFFF,
                                       ctypes.byref(opts), ctypes.byref(h)))

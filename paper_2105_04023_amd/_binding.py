@@ -21,7 +21,7 @@ EXPORTED = [
     "im_ctx_create", "im_ctx_free", "im_ctx_bytes_in_use", "im_sketch_bytes_needed", "im_build_sketches",
     "im_estimate", "im_estimate_all", "im_select_seeds", "im_sketch_get_info", "im_sketch_get_trace",
     "im_sketch_get_registers", "im_sketch_get_blocked", "im_sketch_free", "im_last_error", "im_version",
-    "im_sketch_get_sweep_kernel_ms",
+    "im_sketch_get_sweep_log", "im_sketch_clear_sweep_log",
 ]
 
 
@@ -42,7 +42,7 @@ class im_probs(ctypes.Structure):
 
 class im_build_opts(ctypes.Structure):
     _fields_ = [("eps_c", ctypes.c_double), ("heavy_degree", ctypes.c_int32), ("piece_edges", ctypes.c_int32),
-                ("rows_per_wave_chunk", ctypes.c_int32), ("reserved", ctypes.c_int32)]
+                ("sparse_div", ctypes.c_int32), ("reserved", ctypes.c_int32)]
 
 
 class im_select_opts(ctypes.Structure):
@@ -61,6 +61,13 @@ class im_sketch_info(ctypes.Structure):
                 ("visits", ctypes.c_int64), ("build_ms", ctypes.c_double), ("prep_ms", ctypes.c_double),
                 ("device_bytes", ctypes.c_size_t), ("heavy_rows", ctypes.c_int64),
                 ("heavy_pieces", ctypes.c_int64)]
+
+
+class im_sweep_rec(ctypes.Structure):
+    _fields_ = [("simulate", ctypes.c_int32), ("sweep", ctypes.c_int32), ("ran", ctypes.c_int32),
+                ("kernel_ms", ctypes.c_float), ("sweep_ms", ctypes.c_float), ("reserved", ctypes.c_int32),
+                ("light_visits", ctypes.c_int64), ("visits", ctypes.c_int64), ("live", ctypes.c_int64),
+                ("live_next", ctypes.c_int64)]
 
 
 class im_select_stats(ctypes.Structure):
@@ -102,7 +109,8 @@ def load(path: str = LIB_PATH):
         "im_sketch_free": ([p], None),
         "im_last_error": ([], ctypes.c_char_p),
         "im_version": ([], ctypes.c_char_p),
-        "im_sketch_get_sweep_kernel_ms": ([p, p, i32], i32),
+        "im_sketch_get_sweep_log": ([p, p, i32], i32),
+        "im_sketch_clear_sweep_log": ([p], None),
     }
     for name, (args, res) in sig.items():
         fn = getattr(lib, name)

@@ -42,10 +42,10 @@ im_status fail(im_status st, const char* fmt, ...) {
 
 constexpr int RING = 256;         // sweeps held by the counter ring
 constexpr int MAX_BATCH = 64;     // sweeps per batch
-constexpr int DEFAULT_HEAVY = 256;
+constexpr int DEFAULT_HEAVY = 32;
 constexpr int DEFAULT_PIECE = 256;
 constexpr int BFS_CHUNK = 256;
-constexpr int SWEEP_TIMERS = 2 * RING;
+constexpr int SWEEP_TIMERS = 4 * RING;
 
 }  // namespace
 
@@ -80,10 +80,11 @@ struct im_sketch {
     uint32_t* M[3] = {nullptr, nullptr, nullptr};
     int build_buf = 0;
     int sel_buf = 0;
-    uint32_t* Lbm[2] = {nullptr, nullptr};
+    uint32_t* Lbm[3] = {nullptr, nullptr, nullptr};
+    Frontier fr{};
     uint32_t* cnt_ring = nullptr;
     unsigned long long* vis_ring = nullptr;
-    unsigned long long* gather = nullptr;  // device [2 * MAX_BATCH]
+    unsigned long long* gather = nullptr;  // device [2][3 * MAX_BATCH]
     uint32_t* part = nullptr;
     uint32_t* part_any = nullptr;
     GreedyBufs gb{};
@@ -107,7 +108,8 @@ struct im_sketch {
     int64_t visits = 0;
     double build_ms = 0.0, prep_ms = 0.0;
     std::vector<int64_t> trace_live, trace_vis;
-    std::vector<float> light_ms;
+    std::vector<im_sweep_rec> sweep_log;
+    int32_t simulate_count = 0;
     int32_t level_id = 1;
     bool selected = false;
 };
@@ -188,17 +190,19 @@ size_t bytes_needed(int64_t n, int64_t m, int32_t R, im_prob_kind kind) {
     auto al = [](size_t b) { return (std::max<size_t>(b, 1) + 255) & ~size_t(255); };
     size_t t = 0;
     t += al(8 * (n + 1)) + al(4 * m) + al(4 * m);  // xadj, adj, edge hashes
+    t += al(8 * (n + 1)) + al(4 * m) + al(4 * n);  // reverse CSR, heavy slots
+    t += al(4 * ((n + 31) / 32 + 1)) + al(8 * (n + m / 256 + 64)) + al(4 * n) + al(32);  // sparse lists
     if (kind == IM_PROB_WEIGHTED_CASCADE) t += al(4 * n);
     if (kind == IM_PROB_PER_EDGE) t += al(4 * m);
     t += al(4 * R) * 2 + al(8 * R);               // X, HJ, T
     t += 3 * al((size_t)n * L.P * 4);             // register buffers
     const int64_t words = (n + 31) / 32 + 1;
-    t += 2 * al(4 * words);
-    t += al((size_t)RING * NSLOT * SLOT_U32 * 4) + al((size_t)RING * NSLOT * SLOT_U64 * 8) + al(16 * MAX_BATCH);
+    t += 3 * al(4 * words);
+    t += al((size_t)RING * NSLOT * SLOT_U32 * 4) + al((size_t)3 * RING * NSLOT * SLOT_U64 * 8) + al(48 * MAX_BATCH);
     // split rows: bounded by m / heavy_degree rows and m / piece + rows pieces
     const int64_t nh = m / DEFAULT_HEAVY + 1, np = m / DEFAULT_PIECE + nh + 1;
     t += al(4 * nh) + al(8 * (nh + 1)) + al(8 * nh) + al(4 * np) + 2 * al(8 * np) + al((size_t)np * L.P * 4) +
-         al(4 * np);
+         al(4 * np) + al(4 * nh) + al(4 * np);
     // greedy
     const size_t W = 4 * (size_t)L.PW;
     t += 3 * al((size_t)n * W * 4);
@@ -208,21 +212,25 @@ size_t bytes_needed(int64_t n, int64_t m, int32_t R, im_prob_kind kind) {
     return t;
 }
 
-// Sum of the live-count slots of sweeps [t0+1, t0+nb] and the visit slots of
-// sweeps [t0, t0+nb-1] into out[2i], out[2i+1].
+// Sums of the live-count slots of sweeps [t0+1, t0+nb] and of the row-kernel
+// and split-row-kernel visit slots of sweeps [t0, t0+nb-1] into out[3i..3i+2].
+// The visit ring holds RING row-kernel entries followed by RING split-row ones.
 __global__ void k_gather_counts(const uint32_t* __restrict__ cnt, const unsigned long long* __restrict__ vis,
                                 int64_t t0, int nb, unsigned long long* out) {
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= nb) return;
     const uint32_t* c = cnt + ((t0 + i + 1) % RING) * NSLOT * SLOT_U32;
     const unsigned long long* v = vis + ((t0 + i) % RING) * NSLOT * SLOT_U64;
-    unsigned long long sc = 0, sv = 0;
+    const unsigned long long* vh = v + (size_t)RING * NSLOT * SLOT_U64;
+    unsigned long long sc = 0, sv = 0, sh = 0;  // the third ring region (S_t) is not gathered
     for (int k = 0; k < NSLOT; ++k) {
         sc += c[k * SLOT_U32];
         sv += v[k * SLOT_U64];
+        sh += vh[k * SLOT_U64];
     }
-    out[2 * i] = sc;
-    out[2 * i + 1] = sv;
+    out[3 * i] = sc;
+    out[3 * i + 1] = sv;
+    out[3 * i + 2] = sh;
 }
 
 // Zeroes the live-count slots of sweeps [t0+1, t0+nb] and the visit slots of
@@ -232,20 +240,32 @@ __global__ void k_ring_zero(uint32_t* cnt, unsigned long long* vis, int64_t t0, 
     if (i >= nb) return;
     uint32_t* c = cnt + ((t0 + i + 1) % RING) * NSLOT * SLOT_U32;
     unsigned long long* v = vis + ((t0 + i) % RING) * NSLOT * SLOT_U64;
+    unsigned long long* vh = v + (size_t)RING * NSLOT * SLOT_U64;
+    unsigned long long* sm = vis + (2 * (size_t)RING + (t0 + i + 1) % RING) * NSLOT * SLOT_U64;
     for (int k = threadIdx.x; k < NSLOT * SLOT_U32; k += blockDim.x) c[k] = 0u;
-    for (int k = threadIdx.x; k < NSLOT * SLOT_U64; k += blockDim.x) v[k] = 0ull;
+    for (int k = threadIdx.x; k < NSLOT * SLOT_U64; k += blockDim.x) {
+        v[k] = 0ull;
+        vh[k] = 0ull;
+        sm[k] = 0ull;
+    }
 }
 
 uint32_t* cnt_slots(im_sketch* sk, int64_t t) { return sk->cnt_ring + (t % RING) * NSLOT * SLOT_U32; }
 unsigned long long* vis_slots(im_sketch* sk, int64_t t) { return sk->vis_ring + (t % RING) * NSLOT * SLOT_U64; }
+unsigned long long* vis_heavy_slots(im_sketch* sk, int64_t t) {
+    return sk->vis_ring + (RING + t % RING) * NSLOT * SLOT_U64;
+}
+// S_t: sum of the in-degrees of L_t, produced by sweep t-1
+unsigned long long* sum_slots(im_sketch* sk, int64_t t) {
+    return sk->vis_ring + (2 * RING + t % RING) * NSLOT * SLOT_U64;
+}
 
 struct SimResult {
     int buf;
     int sweeps;
     int64_t visits;
     double ms;
-    std::vector<int64_t> live, vis;
-    std::vector<float> light_ms;
+    std::vector<int64_t> live, vis, vis_light;
 };
 
 // Simulate (Alg. 2) on buffers ia/ib: init (with blocked pairs if blk), then
@@ -258,9 +278,12 @@ im_status run_simulate(im_sketch* sk, int ia, int ib, const uint32_t* blk, SimRe
     const uint32_t thresh = lim >= (double)n ? (uint32_t)n : (uint32_t)lim;
     res->live.assign(1, n);
     res->vis.clear();
-    res->light_ms.clear();
+    res->vis_light.clear();
+    const int32_t sim_id = sk->simulate_count++;
     HIP_TRY(hipEventRecord(sk->ev_a, s));
     HIP_TRY(launch_init(sk->L, n, sk->HJ, sk->seed, blk, buf[0], buf[1], s));
+    HIP_TRY(launch_fill_u32(sk->fr.mark, 0u, (n + 31) / 32 + 1, s));
+    HIP_TRY(launch_fill_u32(sk->fr.counts, 0u, 8, s));
     int final_sweeps = -1;
     if ((uint64_t)n <= thresh) final_sweeps = 0;
     int64_t t = 0;
@@ -284,29 +307,39 @@ im_status run_simulate(im_sketch* sk, int ia, int ib, const uint32_t* blk, SimRe
             SweepParams sp{};
             sp.A = buf[st & 1];
             sp.B = buf[(st + 1) & 1];
-            sp.Lcur = sk->Lbm[st & 1];
-            sp.Lnext = sk->Lbm[(st + 1) & 1];
+            sp.Lcur = sk->Lbm[st % 3];
+            sp.Lnext = sk->Lbm[(st + 1) % 3];
+            sp.Lclear = sk->Lbm[(st + 2) % 3];
+            sp.fr = sk->fr;
+            sp.parity = (int)(st & 1);
             sp.blk = blk;
             sp.gate = st == 0 ? nullptr : cnt_slots(sk, st);
             sp.gate_thresh = thresh;
             sp.cnt_out = cnt_slots(sk, st + 1);
             sp.vis_out = vis_slots(sk, st);
+            sp.vis_heavy_out = vis_heavy_slots(sk, st);
+            sp.sgate = st == 0 ? nullptr : sum_slots(sk, st);
+            sp.sum_out = sum_slots(sk, st + 1);
             sp.part = sk->part;
             sp.part_any = sk->part_any;
             sp.first = st == 0;
-            hipEvent_t e0 = nullptr, e1 = nullptr;
-            if (sk->time_sweeps && timer_idx + 1 < (int)sk->sweep_ev.size()) {
+            hipEvent_t e0 = nullptr, e1 = nullptr, ea = nullptr, eb = nullptr;
+            if (sk->time_sweeps && timer_idx + 3 < (int)sk->sweep_ev.size()) {
                 e0 = sk->sweep_ev[timer_idx];
                 e1 = sk->sweep_ev[timer_idx + 1];
-                timer_idx += 2;
+                ea = sk->sweep_ev[timer_idx + 2];
+                eb = sk->sweep_ev[timer_idx + 3];
+                timer_idx += 4;
             }
+            if (ea) HIP_TRY(hipEventRecord(ea, s));
             HIP_TRY(launch_sweep(sk->L, sk->g, sk->X, sp, 0, s, e0, e1));
+            if (eb) HIP_TRY(hipEventRecord(eb, s));
         }
         hipLaunchKernelGGL(k_gather_counts, dim3(1), dim3(64), 0, s, sk->cnt_ring, sk->vis_ring, t, nb,
-                           sk->gather + 2 * MAX_BATCH * batch_slot);
+                           sk->gather + 3 * MAX_BATCH * batch_slot);
         HIP_TRY(hipGetLastError());
-        HIP_TRY(hipMemcpyAsync(sk->h_gather[batch_slot], sk->gather + 2 * MAX_BATCH * batch_slot,
-                               sizeof(unsigned long long) * 2 * nb, hipMemcpyDeviceToHost, s));
+        HIP_TRY(hipMemcpyAsync(sk->h_gather[batch_slot], sk->gather + 3 * MAX_BATCH * batch_slot,
+                               sizeof(unsigned long long) * 3 * nb, hipMemcpyDeviceToHost, s));
         HIP_TRY(hipEventRecord(sk->ev_batch[batch_slot], s));
         batch_t0[batch_slot] = t;
         batch_nb[batch_slot] = nb;
@@ -320,9 +353,11 @@ im_status run_simulate(im_sketch* sk, int ia, int ib, const uint32_t* blk, SimRe
         HIP_TRY(hipEventSynchronize(sk->ev_batch[rs]));
         --inflight;
         for (int i = 0; i < batch_nb[rs]; ++i) {
-            const int64_t live = (int64_t)sk->h_gather[rs][2 * i];
-            const int64_t vis = (int64_t)sk->h_gather[rs][2 * i + 1];
+            const int64_t live = (int64_t)sk->h_gather[rs][3 * i];
+            const int64_t vis_l = (int64_t)sk->h_gather[rs][3 * i + 1];
+            const int64_t vis = vis_l + (int64_t)sk->h_gather[rs][3 * i + 2];
             res->vis.push_back(vis);
+            res->vis_light.push_back(vis_l);
             res->live.push_back(live);
             if ((uint64_t)live <= thresh) {
                 final_sweeps = (int)(batch_t0[rs] + i + 1);
@@ -338,13 +373,31 @@ im_status run_simulate(im_sketch* sk, int ia, int ib, const uint32_t* blk, SimRe
     res->sweeps = final_sweeps;
     res->live.resize(final_sweeps + 1);
     res->vis.resize(final_sweeps);
+    res->vis_light.resize(final_sweeps);
     res->visits = 0;
     for (int64_t v : res->vis) res->visits += v;
     res->buf = (final_sweeps & 1) ? ib : ia;
     if (sk->time_sweeps) {
-        for (int i = 0; i + 1 < timer_idx && i / 2 < final_sweeps; i += 2) {
-            float km = 0.f;
-            if (hipEventElapsedTime(&km, sk->sweep_ev[i], sk->sweep_ev[i + 1]) == hipSuccess) res->light_ms.push_back(km);
+        // every timed launch of the row kernel, including the ones past the
+        // stopping rule that returned at once
+        for (int i = 0; i + 3 < timer_idx; i += 4) {
+            float km = 0.f, wm = 0.f;
+            HIP_TRY(hipEventElapsedTime(&km, sk->sweep_ev[i], sk->sweep_ev[i + 1]));
+            HIP_TRY(hipEventElapsedTime(&wm, sk->sweep_ev[i + 2], sk->sweep_ev[i + 3]));
+            const int t = i / 4;
+            im_sweep_rec rec{};
+            rec.simulate = sim_id;
+            rec.sweep = t;
+            rec.ran = t < final_sweeps;
+            rec.kernel_ms = km;
+            rec.sweep_ms = wm;
+            if (rec.ran) {
+                rec.light_visits = res->vis_light[t];
+                rec.visits = res->vis[t];
+                rec.live = res->live[t];
+                rec.live_next = res->live[t + 1];
+            }
+            sk->sweep_log.push_back(rec);
         }
     }
     return IM_OK;
@@ -446,18 +499,24 @@ im_status im_build_sketches(im_ctx* ctx, const im_csr* graph, const im_probs* pr
     ok = ok && sk_alloc(sk, &sk->X, R) && sk_alloc(sk, &sk->HJ, R) && sk_alloc(sk, &sk->T, R);
     for (int i = 0; i < 3 && ok; ++i) ok = sk_alloc(sk, &sk->M[i], (size_t)n * L.P);
     const int64_t words = (n + 31) / 32 + 1;
-    ok = ok && sk_alloc(sk, &sk->Lbm[0], words) && sk_alloc(sk, &sk->Lbm[1], words);
+    ok = ok && sk_alloc(sk, &sk->Lbm[0], words) && sk_alloc(sk, &sk->Lbm[1], words) &&
+         sk_alloc(sk, &sk->Lbm[2], words);
+    ok = ok && sk_alloc(sk, &g.rxadj, n + 1) && sk_alloc(sk, &g.radj, m) && sk_alloc(sk, &g.hslot, n);
+    ok = ok && sk_alloc(sk, &sk->fr.mark, words) && sk_alloc(sk, &sk->fr.items, n + m / 256 + 64) &&
+         sk_alloc(sk, &sk->fr.W, n) && sk_alloc(sk, &sk->fr.counts, 8);
     ok = ok && sk_alloc(sk, &sk->cnt_ring, (size_t)RING * NSLOT * SLOT_U32) &&
-         sk_alloc(sk, &sk->vis_ring, (size_t)RING * NSLOT * SLOT_U64) && sk_alloc(sk, &sk->gather, 4 * MAX_BATCH);
+         sk_alloc(sk, &sk->vis_ring, (size_t)3 * RING * NSLOT * SLOT_U64) && sk_alloc(sk, &sk->gather, 6 * MAX_BATCH);
     ok = ok && sk_alloc(sk, &sk->d_err, 4) && sk_alloc(sk, &sk->d_heavy_counts, 4) && sk_alloc(sk, &sk->d_flag, 4);
+    sk->fr.chunk = 256;
+    sk->fr.sparse_div = o.sparse_div < 0 ? 0u : (o.sparse_div == 0 ? 16u : (uint32_t)o.sparse_div);
     if (probs->kind == IM_PROB_WEIGHTED_CASCADE) ok = ok && sk_alloc(sk, &g.thr, n);
     if (probs->kind == IM_PROB_PER_EDGE) ok = ok && sk_alloc(sk, &g.thr, m);
     if (!ok) {
         sk_release(sk);
         return fail(IM_ERR_OUT_OF_BUDGET, "device allocation failed");
     }
-    if (hipHostMalloc((void**)&sk->h_gather[0], 16 * MAX_BATCH) != hipSuccess ||
-        hipHostMalloc((void**)&sk->h_gather[1], 16 * MAX_BATCH) != hipSuccess ||
+    if (hipHostMalloc((void**)&sk->h_gather[0], 24 * MAX_BATCH) != hipSuccess ||
+        hipHostMalloc((void**)&sk->h_gather[1], 24 * MAX_BATCH) != hipSuccess ||
         hipHostMalloc((void**)&sk->h_small, 64) != hipSuccess) {
         sk_release(sk);
         return fail(IM_ERR_DEVICE, "pinned host allocation failed");
@@ -500,15 +559,6 @@ im_status im_build_sketches(im_ctx* ctx, const im_csr* graph, const im_probs* pr
             g.thr_const = live_threshold(probs->p);
         } else if (probs->kind == IM_PROB_WEIGHTED_CASCADE) {
             g.kind = THR_TARGET;
-            uint32_t* indeg = nullptr;
-            void* p = ctx_alloc(ctx, 4 * n);
-            if (!p) return fail(IM_ERR_OUT_OF_BUDGET, "temporary allocation failed");
-            indeg = (uint32_t*)p;
-            HIP_TRY(launch_fill_u32(indeg, 0u, n, s));
-            HIP_TRY(launch_indegree(g, indeg, s));
-            HIP_TRY(launch_wc_thresholds(indeg, g.thr, n, s));
-            HIP_TRY(hipStreamSynchronize(s));
-            ctx_free(ctx, p);
         } else {
             g.kind = THR_EDGE;
             if (m > 0) {
@@ -527,6 +577,21 @@ im_status im_build_sketches(im_ctx* ctx, const im_csr* graph, const im_probs* pr
                 if (tmp) ctx_free(ctx, tmp);
                 if (sk->h_small[0] & 4u) return fail(IM_ERR_INVALID_ARG, "a per-edge probability is outside [0, 1]");
             }
+        }
+        // in-degrees: weighted-cascade thresholds and the reverse CSR
+        {
+            const int64_t nb = (n + 1023) / 1024;
+            void* p = ctx_alloc(ctx, 4 * n + 8 * (n + 1) + 8 * (nb + 2) + 512);
+            if (!p) return fail(IM_ERR_OUT_OF_BUDGET, "temporary allocation failed");
+            uint32_t* indeg = (uint32_t*)p;
+            int64_t* cursor = (int64_t*)((char*)p + ((4 * n + 255) & ~int64_t(255)));
+            uint32_t* scan_tmp = (uint32_t*)((char*)cursor + ((8 * (n + 1) + 255) & ~int64_t(255)));
+            HIP_TRY(launch_fill_u32(indeg, 0u, n, s));
+            HIP_TRY(launch_indegree(g, indeg, s));
+            if (g.kind == THR_TARGET) HIP_TRY(launch_wc_thresholds(indeg, g.thr, n, s));
+            HIP_TRY(launch_reverse_csr(g, indeg, cursor, scan_tmp, s));
+            HIP_TRY(hipStreamSynchronize(s));
+            ctx_free(ctx, p);
         }
         // split rows
         const int64_t heavy = o.heavy_degree > 0 ? o.heavy_degree : DEFAULT_HEAVY;
@@ -547,7 +612,10 @@ im_status im_build_sketches(im_ctx* ctx, const im_csr* graph, const im_probs* pr
             if (!ok2) return fail(IM_ERR_OUT_OF_BUDGET, "device allocation failed (split rows)");
             HIP_TRY(launch_heavy_assign(g, piece, sk->d_heavy_counts, s));
             HIP_TRY(launch_heavy_pieces(g, piece, s));
+            if (!sk_alloc(sk, &sk->fr.HW, g.nheavy) || !sk_alloc(sk, &sk->fr.HP, g.npieces))
+                return fail(IM_ERR_OUT_OF_BUDGET, "device allocation failed (sparse lists)");
         }
+        HIP_TRY(launch_heavy_slots(g, s));
         // greedy buffers
         const size_t W = 4 * (size_t)L.PW;
         GreedyBufs& b = sk->gb;
@@ -579,7 +647,6 @@ im_status im_build_sketches(im_ctx* ctx, const im_csr* graph, const im_probs* pr
         sk->build_ms = r.ms;
         sk->trace_live = r.live;
         sk->trace_vis = r.vis;
-        sk->light_ms = r.light_ms;
         return IM_OK;
     };
     st = body();
@@ -623,13 +690,15 @@ im_status im_sketch_get_trace(const im_sketch* sk, int64_t* live_counts, int64_t
     return IM_OK;
 }
 
-// Per-sweep device time of the dominant (non-split-row) sweep kernel, in ms,
-// when the build was asked to time sweeps; returns the count written.
-int32_t im_sketch_get_sweep_kernel_ms(const im_sketch* sk, float* out, int32_t cap) {
+int32_t im_sketch_get_sweep_log(const im_sketch* sk, im_sweep_rec* out, int32_t cap) {
     if (!sk) return 0;
     int32_t k = 0;
-    for (; k < cap && k < (int32_t)sk->light_ms.size(); ++k) out[k] = sk->light_ms[k];
-    return k;
+    for (; k < cap && k < (int32_t)sk->sweep_log.size(); ++k) out[k] = sk->sweep_log[k];
+    return (int32_t)sk->sweep_log.size() < cap ? (int32_t)sk->sweep_log.size() : cap;
+}
+
+void im_sketch_clear_sweep_log(im_sketch* sk) {
+    if (sk) sk->sweep_log.clear();
 }
 
 im_status im_sketch_get_registers(const im_sketch* sk, int32_t which, uint8_t* out) {

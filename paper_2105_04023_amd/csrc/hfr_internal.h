@@ -46,6 +46,23 @@ struct DevGraph {
     int32_t* prow = nullptr;    // row of each piece [npieces]
     int64_t* pe0 = nullptr;     // first edge of each piece
     int64_t* pe1 = nullptr;     // one past the last edge of each piece
+    // in-edges (reverse CSR), for sweeps that start from the live vertices
+    int64_t* rxadj = nullptr;   // [n + 1]
+    int32_t* radj = nullptr;    // [m]
+    int32_t* hslot = nullptr;   // heavy slot of each row, -1 for rows processed whole [n]
+};
+
+// Work lists of a sparse sweep.  Counters come in two sets selected by the
+// sweep parity; a sweep zeroes the other set for the next sweep.
+struct Frontier {
+    uint32_t* mark = nullptr;   // n bits: row already listed in this sweep
+    int2* items = nullptr;      // (live vertex, chunk of its in-edges)
+    int32_t* W = nullptr;       // rows processed whole
+    int32_t* HW = nullptr;      // heavy row slots
+    int32_t* HP = nullptr;      // pieces of listed heavy rows
+    uint32_t* counts = nullptr; // [2][4]: items, W, HW, HP
+    int32_t chunk = 256;        // in-edges per item
+    uint32_t sparse_div = 8;    // sweep t > 0 is sparse iff S_t * sparse_div <= m (0: never)
 };
 
 // Per-sweep launch parameters.
@@ -58,9 +75,15 @@ struct SweepParams {
     const uint32_t* gate;      // live-count slots of L_t (nullptr on the first sweep)
     uint32_t gate_thresh;      // sweep runs iff |L_t| > gate_thresh
     uint32_t* cnt_out;         // slots of |L_{t+1}|
-    unsigned long long* vis_out;  // slots of edges with a live head in this sweep
+    unsigned long long* vis_out;        // slots: edges with a live head visited by the row kernel
+    unsigned long long* vis_heavy_out;  // slots: edges with a live head visited by the split-row kernel
     uint32_t* part;            // partial rows of split-row pieces [npieces * P]
     uint32_t* part_any;        // per piece: 1 if some live edge was merged
+    uint32_t* Lclear;          // bitmap of L_{t-1}, zeroed during this sweep for L_{t+2}
+    const unsigned long long* sgate;  // slots of S_t = sum of in-degrees over L_t (nullptr on the first sweep)
+    unsigned long long* sum_out;      // slots of S_{t+1}
+    Frontier fr;
+    int parity;                // t & 1
     int first;
 };
 
@@ -104,6 +127,9 @@ hipError_t launch_init(const Layout& L, int64_t n, const uint32_t* HJ, uint32_t 
                        uint32_t* A, uint32_t* B, hipStream_t s);
 hipError_t launch_sweep(const Layout& L, const DevGraph& g, const uint32_t* X, const SweepParams& sp, int grid,
                         hipStream_t s, hipEvent_t ev_light_begin, hipEvent_t ev_light_end);
+hipError_t launch_reverse_csr(const DevGraph& g, const uint32_t* indeg, int64_t* cursor, uint32_t* scan_tmp,
+                              hipStream_t s);
+hipError_t launch_heavy_slots(const DevGraph& g, hipStream_t s);
 hipError_t launch_argmax(const Layout& L, int64_t n, const uint32_t* M, const GreedyBufs& b, hipStream_t s);
 hipError_t launch_select(const Layout& L, const DevGraph& g, const uint32_t* M, const GreedyBufs& b,
                          StepRec* rec, int32_t* seeds_dev, int k, int32_t level_id, hipStream_t s);

@@ -101,6 +101,12 @@ DEVI uint32_t unblocked_mask(const uint32_t* __restrict__ blk, int64_t u, int q,
     return m;
 }
 
+DEVI uint32_t plane_valid_mask(int w, int P, int PW) {
+    const int ww = w % PW;  // word within the plane
+    const int left = P - 32 * ww;
+    return left >= 32 ? 0xFFFFFFFFu : (left <= 0 ? 0u : ((1u << left) - 1u));
+}
+
 template <typename T>
 DEVI T wave_sum(T v) {
 #pragma unroll
@@ -441,11 +447,16 @@ hipError_t launch_init(const Layout& L, int64_t n, const uint32_t* HJ, uint32_t 
 // Invariant before sweep t: B[u] = A[u] for every u not in L_t (for t = 0 the
 // init kernel wrote both buffers).  Row u merges the rows of its out-
 // neighbours v in L_t over the live samples; it is written to B iff it
-// changed or u is in L_t (then B still holds M^{t-1}[u]).  Rows with more
-// than heavy_deg out-edges are handled by k_sweep_heavy / k_sweep_heavy_fix.
+// changed or u is in L_t (then B still holds M^{t-1}[u]).
 //
-// A wave owns 32 consecutive rows per chunk and stores the chunk's L_{t+1}
-// bitmap word with a plain store.
+// Dense sweep: every row is visited; a wave owns 32 consecutive rows per chunk
+// and stores the chunk's L_{t+1} bitmap word with a plain store.  Sparse sweep
+// (few live vertices): only the rows that can change are visited -- the
+// in-neighbours of L_t, found through the reverse CSR, and L_t itself (for the
+// copy rule); their L_{t+1} bits are set atomically.  Both visit exactly the
+// rows with a live out-neighbour, so registers, traces and counts are the same.
+// Rows with more than heavy_deg out-edges are split into pieces
+// (k_sweep_heavy) and combined by k_sweep_heavy_fix.
 // ----------------------------------------------------------------------------
 
 // Copies a wave-uniform value into a VGPR, so that v_xad_u32 can take the
@@ -468,51 +479,54 @@ DEVI uint32_t merge_edges64(int64_t eb, int64_t ee, const int32_t* __restrict__ 
                             const uint32_t* __restrict__ Lcur, int first, int P, int lane,
                             const uint32_t (&x)[DW][4], Acc (&acc)[DW]) {
     uint32_t vis = 0;
+    // the next window's edge ids are loaded while the current one is merged
+    bool in_n = eb + lane < ee;
+    int32_t v_n = in_n ? adj[eb + lane] : 0;
     for (int64_t w0 = eb; w0 < ee; w0 += 64) {
         const int64_t e = w0 + lane;
-        const bool in = e < ee;
-        const int32_t v = in ? adj[e] : 0;
+        const bool in = in_n;
+        const int32_t v = v_n;
+        in_n = w0 + 64 + lane < ee;
+        v_n = in_n ? adj[w0 + 64 + lane] : 0;
         const bool lv = in && (first || bit_of(Lcur, v) != 0u);
-        uint64_t mask = __ballot(lv);
-        if (mask == 0) continue;
-        vis += (uint32_t)__builtin_popcountll(mask);
-        const uint32_t hh = lv ? eh[e] : 0u;
+        const uint32_t hh = in ? eh[e] : 0u;
         uint32_t tt = 0u;
-        if constexpr (KIND == THR_TARGET) tt = lv ? thr[v] : 0u;
-        if constexpr (KIND == THR_EDGE) tt = lv ? thr[e] : 0u;
+        if constexpr (KIND == THR_TARGET) tt = in ? thr[v] : 0u;
+        if constexpr (KIND == THR_EDGE) tt = in ? thr[e] : 0u;
+        uint64_t mask = __ballot(lv);
+        vis += (uint32_t)__builtin_popcountll(mask);
         while (mask) {
-            const int pc = __builtin_popcountll(mask);
-            const int cnt = pc < UB ? pc : UB;
+            // up to UB live edges; unused slots repeat the last one (max-merge is
+            // idempotent), so every load is issued without a branch
             int idx[UB];
+            int last = __builtin_ctzll(mask);
 #pragma unroll
             for (int b = 0; b < UB; ++b) {
-                idx[b] = mask ? __builtin_ctzll(mask) : 0;
+                if (mask) last = __builtin_ctzll(mask);
+                idx[b] = last;
                 mask &= mask - 1;
             }
+            // lanes past the row (q >= P) load a valid dword of it instead; their
+            // results are never stored
             uint32_t d[UB][DW];
 #pragma unroll
             for (int b = 0; b < UB; ++b) {
+                const int64_t vb = __builtin_amdgcn_readlane(v, idx[b]);
+                const uint32_t* __restrict__ row = A + vb * P;
 #pragma unroll
-                for (int i = 0; i < DW; ++i) d[b][i] = 0u;
-                if (b < cnt) {
-                    const int64_t vb = __builtin_amdgcn_readlane(v, idx[b]);
-                    const uint32_t* __restrict__ row = A + vb * P;
-#pragma unroll
-                    for (int i = 0; i < DW; ++i) {
-                        const int q = i * 64 + lane;
-                        if (q < P) d[b][i] = row[q];
-                    }
+                for (int i = 0; i < DW; ++i) {
+                    const int q = i * 64 + lane;
+                    d[b][i] = row[q < P ? q : P - 1];
                 }
             }
+            __builtin_amdgcn_sched_barrier(0);
 #pragma unroll
             for (int b = 0; b < UB; ++b) {
-                if (b < cnt) {
-                    const uint32_t hb = (uint32_t)__builtin_amdgcn_readlane((int)hh, idx[b]);
-                    uint32_t nt = ntv;
-                    if constexpr (KIND != THR_CONST) nt = 0u - (uint32_t)__builtin_amdgcn_readlane((int)tt, idx[b]);
+                const uint32_t hb = (uint32_t)__builtin_amdgcn_readlane((int)hh, idx[b]);
+                uint32_t nt = ntv;
+                if constexpr (KIND != THR_CONST) nt = 0u - (uint32_t)__builtin_amdgcn_readlane((int)tt, idx[b]);
 #pragma unroll
-                    for (int i = 0; i < DW; ++i) merge_live(acc[i], d[b][i], x[i][0], x[i][1], x[i][2], x[i][3], hb, nt);
-                }
+                for (int i = 0; i < DW; ++i) merge_live(acc[i], d[b][i], x[i][0], x[i][1], x[i][2], x[i][3], hb, nt);
             }
         }
     }
@@ -565,17 +579,242 @@ DEVI void load_sim_words(const uint32_t* __restrict__ X, int P, int p, uint32_t 
     }
 }
 
+// Live count |L_t| of a running sweep, or 0 when the sweep is past the
+// stopping rule (the kernel then returns).
+DEVI uint32_t sweep_live(const uint32_t* __restrict__ gate, uint32_t gate_thresh, int first, int64_t n) {
+    if (first) return (uint32_t)n;
+    const uint32_t live = gate_sum(gate);
+    return live > gate_thresh ? live : 0u;
+}
+
+// A sweep after the first is sparse when the in-degrees of L_t sum to at most
+// m / div: then listing the in-neighbours of L_t costs less than visiting
+// every row.  The sum S_t is accumulated by the previous sweep.
+DEVI bool sweep_sparse(const unsigned long long* __restrict__ sgate, int first, int64_t m, uint32_t div) {
+    if (first || div == 0) return false;
+    unsigned long long s = 0;
+#pragma unroll
+    for (int i = 0; i < NSLOT; ++i) s += sgate[i * SLOT_U64];
+    return s * div <= (unsigned long long)m;
+}
+
+// Exclusive prefix of c over the wave and the wave total.
+DEVI uint32_t wave_excl_scan(uint32_t c, uint32_t* total) {
+    const int lane = threadIdx.x & 63;
+    uint32_t x = c;
+#pragma unroll
+    for (int off = 1; off < 64; off <<= 1) {
+        const uint32_t y = __shfl_up(x, off, 64);
+        if (lane >= off) x += y;
+    }
+    *total = __shfl(x, 63, 64);
+    return x - c;
+}
+
+// Appends heavy slot r and its pieces to the sparse lists (one thread).
+DEVI void list_heavy(Frontier& fr, uint32_t* cnt, int32_t r, const int64_t* __restrict__ hpb,
+                     const int64_t* __restrict__ hpn) {
+    const uint32_t hw = atomicAdd(&cnt[2], 1u);
+    fr.HW[hw] = r;
+    const int64_t np = hpn[r], pb = hpb[r];
+    const uint32_t hp = atomicAdd(&cnt[3], (uint32_t)np);
+    for (int64_t i = 0; i < np; ++i) fr.HP[hp + i] = (int32_t)(pb + i);
+}
+
+// First kernel of every sweep.  Zeroes the bitmap that will hold L_{t+2}; in a
+// sparse sweep also lists L_t (marked, for the copy rule) and the in-edge
+// chunks of every vertex of L_t.
+__global__ __launch_bounds__(256) void k_sweep_frontier(const uint32_t* __restrict__ gate, uint32_t gate_thresh,
+                                                        const unsigned long long* __restrict__ sgate, int64_t m,
+                                                        int first, int64_t n, const uint32_t* __restrict__ Lcur,
+                                                        uint32_t* __restrict__ Lclear, Frontier fr, int parity,
+                                                        const int64_t* __restrict__ rxadj,
+                                                        const int32_t* __restrict__ hslot,
+                                                        const int64_t* __restrict__ hpb,
+                                                        const int64_t* __restrict__ hpn) {
+    const uint32_t live = sweep_live(gate, gate_thresh, first, n);
+    if (!live) return;
+    const int64_t nwords = (n + 31) >> 5;
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    const int64_t tid = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    for (int64_t w = tid; w < nwords + 1; w += stride) Lclear[w] = 0u;
+    if (!sweep_sparse(sgate, first, m, fr.sparse_div)) return;
+    uint32_t* cnt = fr.counts + 4 * parity;
+    const int lane = threadIdx.x & 63;
+    // uniform trip count per wave so that every lane takes part in the scans
+    const int64_t span = ((nwords + stride - 1) / stride) * stride;
+    for (int64_t w0 = tid - lane; w0 < span; w0 += stride) {
+        const int64_t w = w0 + lane;
+        const uint32_t bits = w < nwords ? Lcur[w] : 0u;
+        uint32_t nlight = 0, nitems = 0;
+        for (uint32_t b = bits; b; b &= b - 1) {
+            const int64_t v = w * 32 + __builtin_ctz(b);
+            if (hslot[v] < 0) ++nlight;
+            nitems += (uint32_t)((rxadj[v + 1] - rxadj[v] + fr.chunk - 1) / fr.chunk);
+        }
+        uint32_t tl, ti;
+        const uint32_t ol = wave_excl_scan(nlight, &tl);
+        const uint32_t oi = wave_excl_scan(nitems, &ti);
+        uint32_t bl = 0, bi = 0;
+        if (lane == 0) {
+            if (tl) bl = atomicAdd(&cnt[1], tl);
+            if (ti) bi = atomicAdd(&cnt[0], ti);
+        }
+        bl = __shfl(bl, 0, 64) + ol;
+        bi = __shfl(bi, 0, 64) + oi;
+        if (bits) {
+            fr.mark[w] = bits;
+            for (uint32_t b = bits; b; b &= b - 1) {
+                const int64_t v = w * 32 + __builtin_ctz(b);
+                const int32_t r = hslot[v];
+                if (r < 0)
+                    fr.W[bl++] = (int32_t)v;
+                else
+                    list_heavy(fr, cnt, r, hpb, hpn);
+                const int64_t nc = (rxadj[v + 1] - rxadj[v] + fr.chunk - 1) / fr.chunk;
+                for (int64_t c = 0; c < nc; ++c) fr.items[bi++] = make_int2((int)v, (int)c);
+            }
+        }
+    }
+}
+
+// Sparse sweep: marks the in-neighbours of L_t and lists the new ones.
+__global__ __launch_bounds__(256) void k_sweep_expand(const uint32_t* __restrict__ gate, uint32_t gate_thresh,
+                                                      const unsigned long long* __restrict__ sgate, int64_t m,
+                                                      int first, int64_t n, Frontier fr, int parity,
+                                                      const int64_t* __restrict__ rxadj,
+                                                      const int32_t* __restrict__ radj,
+                                                      const int32_t* __restrict__ hslot,
+                                                      const int64_t* __restrict__ hpb,
+                                                      const int64_t* __restrict__ hpn) {
+    const uint32_t live = sweep_live(gate, gate_thresh, first, n);
+    if (!live || !sweep_sparse(sgate, first, m, fr.sparse_div)) return;
+    uint32_t* cnt = fr.counts + 4 * parity;
+    const uint32_t nitems = cnt[0];
+    const int lane = threadIdx.x & 63;
+    for (int64_t it = wave_index(); it < (int64_t)nitems; it += wave_count()) {
+        const int2 item = fr.items[it];
+        const int64_t vb = rxadj[item.x], ve = rxadj[item.x + 1];
+        const int64_t e0 = vb + (int64_t)item.y * fr.chunk;
+        const int64_t e1 = e0 + fr.chunk < ve ? e0 + fr.chunk : ve;
+        for (int64_t w0 = e0; w0 < e1; w0 += 64) {
+            const int64_t e = w0 + lane;
+            bool fresh = false;
+            int32_t u = 0, r = -1;
+            if (e < e1) {
+                u = radj[e];
+                const uint32_t bit = 1u << (u & 31);
+                // most in-neighbours are reached from several live vertices: test
+                // before paying for the atomic
+                if ((fr.mark[u >> 5] & bit) == 0u) fresh = (atomicOr(&fr.mark[u >> 5], bit) & bit) == 0u;
+                if (fresh) r = hslot[u];
+            }
+            const bool lt = fresh && r < 0;
+            const uint64_t bal = __ballot(lt);
+            if (bal) {
+                uint32_t base = 0;
+                if (lane == 0) base = atomicAdd(&cnt[1], (uint32_t)__builtin_popcountll(bal));
+                base = __shfl(base, 0, 64);
+                if (lt) fr.W[base + (uint32_t)__builtin_popcountll(bal & ((1ull << lane) - 1ull))] = u;
+            }
+            if (fresh && r >= 0) list_heavy(fr, cnt, r, hpb, hpn);
+        }
+    }
+}
+
+// Last kernel of every sweep: unmarks the rows listed in a sparse sweep and
+// zeroes the list counters of the next sweep.
+__global__ __launch_bounds__(256) void k_sweep_cleanup(const uint32_t* __restrict__ gate, uint32_t gate_thresh,
+                                                       const unsigned long long* __restrict__ sgate, int64_t m,
+                                                       int first, int64_t n, Frontier fr, int parity,
+                                                       const int32_t* __restrict__ hrow) {
+    const uint32_t live = sweep_live(gate, gate_thresh, first, n);
+    if (!live) return;
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    const int64_t tid = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (tid < 4) fr.counts[4 * (parity ^ 1) + tid] = 0u;
+    if (!sweep_sparse(sgate, first, m, fr.sparse_div)) return;
+    const uint32_t* cnt = fr.counts + 4 * parity;
+    const int64_t nw = cnt[1], nh = cnt[2];
+    for (int64_t i = tid; i < nw; i += stride) fr.mark[fr.W[i] >> 5] = 0u;
+    for (int64_t i = tid; i < nh; i += stride) fr.mark[hrow[fr.HW[i]] >> 5] = 0u;
+}
+
+// Merge of one whole row (one G-lane group): returns true if it changed.
+// dense_word: the caller stores L_{t+1} words itself; otherwise the bit is set
+// atomically.
+template <int G, int DW, int KIND>
+DEVI bool sweep_row(int64_t u, const int64_t* __restrict__ xadj, const int32_t* __restrict__ adj,
+                    const uint32_t* __restrict__ eh, const uint32_t* __restrict__ thr, uint32_t ntv,
+                    const uint32_t (&x)[DW][4], const uint32_t* __restrict__ A, uint32_t* __restrict__ B,
+                    const uint32_t* __restrict__ Lcur, uint32_t* __restrict__ Lnext, const uint32_t* __restrict__ blk,
+                    int64_t heavy_deg, int P, int PW, int first, bool dense_word, int lane, int p,
+                    unsigned long long& my_vis) {
+    const int64_t eb = xadj[u], ee = xadj[u + 1];
+    const bool inL = first ? false : bit_of(Lcur, u) != 0;
+    bool active = ee - eb <= heavy_deg && (ee > eb || inL);
+    uint32_t ub[DW];
+#pragma unroll
+    for (int i = 0; i < DW; ++i) ub[i] = 0xFFFFFFFFu;
+    if (active && blk) {
+        bool none = true;
+#pragma unroll
+        for (int i = 0; i < DW; ++i) {
+            const int q = i * G + p;
+            if (q < P) {
+                ub[i] = unblocked_mask(blk, u, q, PW);
+                none = none && ub[i] == 0u;
+            }
+        }
+        active = !group_all<G>(none);
+    }
+    if (!active) return false;
+    Acc acc[DW];
+#pragma unroll
+    for (int i = 0; i < DW; ++i) acc[i].e = acc[i].o = 0u;
+    const uint32_t vis = merge_edges<G, DW, KIND>(eb, ee, adj, eh, thr, ntv, A, Lcur, first, P, lane, p, x, acc);
+    if (p == 0) my_vis += vis;
+    if (vis == 0 && !inL) return false;
+    bool ch = false;
+    uint32_t nw[DW];
+#pragma unroll
+    for (int i = 0; i < DW; ++i) {
+        const int q = i * G + p;
+        nw[i] = 0;
+        if (q < P) {
+            const uint32_t a = A[u * P + q];
+            nw[i] = acc_max(a, acc[i]) & ub[i];
+            ch = ch || nw[i] != a;
+        }
+    }
+    const bool changed = group_any<G>(ch);
+    if (changed || inL) {
+#pragma unroll
+        for (int i = 0; i < DW; ++i) {
+            const int q = i * G + p;
+            if (q < P) B[u * P + q] = nw[i];
+        }
+    }
+    if (changed && !dense_word && p == 0) atomicOr(&Lnext[u >> 5], 1u << (u & 31));
+    return changed;
+}
+
 template <int G, int DW, int KIND>
 __global__ __launch_bounds__(256) void k_sweep_light(
     const int64_t* __restrict__ xadj, const int32_t* __restrict__ adj, const uint32_t* __restrict__ eh,
     const uint32_t* __restrict__ thr, uint32_t thr_const, const uint32_t* __restrict__ X,
     const uint32_t* __restrict__ A, uint32_t* __restrict__ B, const uint32_t* __restrict__ Lcur,
     uint32_t* __restrict__ Lnext, const uint32_t* __restrict__ blk, const uint32_t* __restrict__ gate,
-    uint32_t gate_thresh, uint32_t* __restrict__ cnt_out, unsigned long long* __restrict__ vis_out, int64_t n,
-    int P, int PW, int64_t heavy_deg, int first) {
+    uint32_t gate_thresh, uint32_t* __restrict__ cnt_out, unsigned long long* __restrict__ vis_out,
+    const unsigned long long* __restrict__ sgate, unsigned long long* __restrict__ sum_out,
+    const int64_t* __restrict__ rxadj, int64_t n, int64_t m, int P, int PW, int64_t heavy_deg, int first, Frontier fr,
+    int parity) {
     __shared__ unsigned long long sh64[4];
     __shared__ uint32_t sh32[4];
-    if (!first && gate_sum(gate) <= gate_thresh) return;
+    const uint32_t live = sweep_live(gate, gate_thresh, first, n);
+    if (!live) return;
+    const bool sparse = sweep_sparse(sgate, first, m, fr.sparse_div);
+    unsigned long long my_sum = 0;
     constexpr int RPW = 64 / G;
     const int lane = threadIdx.x & 63, grp = lane / G, p = lane % G;
     uint32_t x[DW][4];
@@ -583,78 +822,282 @@ __global__ __launch_bounds__(256) void k_sweep_light(
     const uint32_t ntv = to_vgpr(0u - thr_const);
     uint32_t my_cnt = 0;
     unsigned long long my_vis = 0;
-    const int64_t nwords = (n + 31) >> 5;
-    for (int64_t c = wave_index(); c < nwords; c += wave_count()) {
-        uint32_t word = 0;
-        for (int rr = 0; rr < 32; rr += RPW) {
-            const int64_t u = c * 32 + rr + grp;
-            bool changed = false;
-            if (u < n) {
-                const int64_t eb = xadj[u], ee = xadj[u + 1];
-                const bool inL = first ? false : bit_of(Lcur, u) != 0;
-                bool active = ee - eb <= heavy_deg && (ee > eb || inL);
-                uint32_t ub[DW];
+    if (!sparse) {
+        const int64_t nwords = (n + 31) >> 5;
+        for (int64_t c = wave_index(); c < nwords; c += wave_count()) {
+            uint32_t word = 0;
+            for (int rr = 0; rr < 32; rr += RPW) {
+                const int64_t u = c * 32 + rr + grp;
+                bool changed = false;
+                if (u < n)
+                    changed = sweep_row<G, DW, KIND>(u, xadj, adj, eh, thr, ntv, x, A, B, Lcur, Lnext, blk, heavy_deg,
+                                                     P, PW, first, true, lane, p, my_vis);
+                if (changed && p == 0) my_sum += (unsigned long long)(rxadj[u + 1] - rxadj[u]);
+                const uint64_t bal = __ballot(changed && p == 0);
 #pragma unroll
-                for (int i = 0; i < DW; ++i) ub[i] = 0xFFFFFFFFu;
-                if (active && blk) {
-                    bool none = true;
-#pragma unroll
-                    for (int i = 0; i < DW; ++i) {
-                        const int q = i * G + p;
-                        if (q < P) {
-                            ub[i] = unblocked_mask(blk, u, q, PW);
-                            none = none && ub[i] == 0u;
-                        }
-                    }
-                    active = !group_all<G>(none);
-                }
-                if (active) {
-                    Acc acc[DW];
-#pragma unroll
-                    for (int i = 0; i < DW; ++i) acc[i].e = acc[i].o = 0u;
-                    const uint32_t vis =
-                        merge_edges<G, DW, KIND>(eb, ee, adj, eh, thr, ntv, A, Lcur, first, P, lane, p, x, acc);
-                    if (p == 0) my_vis += vis;
-                    if (vis > 0 || inL) {
-                        bool ch = false;
-                        uint32_t nw[DW];
-#pragma unroll
-                        for (int i = 0; i < DW; ++i) {
-                            const int q = i * G + p;
-                            nw[i] = 0;
-                            if (q < P) {
-                                const uint32_t a = A[u * P + q];
-                                nw[i] = acc_max(a, acc[i]) & ub[i];
-                                ch = ch || nw[i] != a;
-                            }
-                        }
-                        changed = group_any<G>(ch);
-                        if (changed || inL) {
-#pragma unroll
-                            for (int i = 0; i < DW; ++i) {
-                                const int q = i * G + p;
-                                if (q < P) B[u * P + q] = nw[i];
-                            }
-                        }
-                    }
-                }
+                for (int g = 0; g < RPW; ++g) word |= (uint32_t)((bal >> (g * G)) & 1ull) << (rr + g);
             }
-            const uint64_t bal = __ballot(changed && p == 0);
-#pragma unroll
-            for (int g = 0; g < RPW; ++g) word |= (uint32_t)((bal >> (g * G)) & 1ull) << (rr + g);
+            if (lane == 0) {
+                Lnext[c] = word;
+                my_cnt += __builtin_popcount(word);
+            }
         }
-        if (lane == 0) Lnext[c] = word;
-        my_cnt += __builtin_popcount(word);
+    } else {
+        const int64_t nw = fr.counts[4 * parity + 1];
+        for (int64_t base = wave_index() * RPW; base < nw; base += wave_count() * RPW) {
+            const int64_t i = base + grp;
+            bool changed = false;
+            if (i < nw)
+                changed = sweep_row<G, DW, KIND>(fr.W[i], xadj, adj, eh, thr, ntv, x, A, B, Lcur, Lnext, blk,
+                                                 heavy_deg, P, PW, first, false, lane, p, my_vis);
+            if (changed && p == 0) {
+                my_cnt += 1;
+                my_sum += (unsigned long long)(rxadj[fr.W[i] + 1] - rxadj[fr.W[i]]);
+            }
+        }
     }
-    if (lane != 0) my_cnt = 0;
     const uint32_t bc = block_sum256(my_cnt, sh32);
     const unsigned long long bv = block_sum256(my_vis, sh64);
+    const unsigned long long bs = block_sum256(my_sum, sh64);
     if (threadIdx.x == 0) {
         const int slot = blockIdx.x % NSLOT;
         if (bc) atomicAdd(&cnt_out[slot * SLOT_U32], bc);
         if (bv) atomicAdd(&vis_out[slot * SLOT_U64], bv);
+        if (bs) atomicAdd(&sum_out[slot * SLOT_U64], bs);
     }
 }
+
+// Row kernel for one row per wave (R > 128): a wave takes 32 rows at a time
+// (dense: 32 consecutive rows, one L_{t+1} word; sparse: 32 listed rows).
+// Lane i < 32 reads the offsets of row i; the rows' out-edges are then read as
+// one flat sequence, 64 per window, each lane finding its row by binary search
+// over the rows' prefix offsets in LDS.  Live heads are merged in batches of UB
+// row loads; the first load of a row also fetches the row itself (and its
+// blocked bits), so finishing a row needs no extra round trip.
+template <int DW, int KIND, bool BLK>
+__global__ __launch_bounds__(256) void k_sweep_rows64(
+    const int64_t* __restrict__ xadj, const int32_t* __restrict__ adj, const uint32_t* __restrict__ eh,
+    const uint32_t* __restrict__ thr, uint32_t thr_const, const uint32_t* __restrict__ X,
+    const uint32_t* __restrict__ A, uint32_t* __restrict__ B, const uint32_t* __restrict__ Lcur,
+    uint32_t* __restrict__ Lnext, const uint32_t* __restrict__ blk, const uint32_t* __restrict__ gate,
+    uint32_t gate_thresh, uint32_t* __restrict__ cnt_out, unsigned long long* __restrict__ vis_out,
+    const unsigned long long* __restrict__ sgate, unsigned long long* __restrict__ sum_out,
+    const int64_t* __restrict__ rxadj, int64_t n, int64_t m, int P, int PW, int64_t heavy_deg, int first, Frontier fr,
+    int parity) {
+    __shared__ unsigned long long sh64[4];
+    __shared__ uint32_t sh32[4];
+    __shared__ uint32_t s_off[4][33];
+    __shared__ int64_t s_x[4][32];
+    const uint32_t live = sweep_live(gate, gate_thresh, first, n);
+    if (!live) return;
+    const bool sparse = sweep_sparse(sgate, first, m, fr.sparse_div);
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    uint32_t x[DW][4];
+    load_sim_words<64, DW>(X, P, lane, x);
+    const uint32_t ntv = to_vgpr(0u - thr_const);
+    uint32_t my_cnt = 0;
+    unsigned long long my_vis = 0, my_sum = 0;
+    const int64_t nrows = sparse ? (int64_t)fr.counts[4 * parity + 1] : n;
+    const int64_t nbatch = (nrows + 31) >> 5;
+    for (int64_t c = wave_index(); c < nbatch; c += wave_count()) {
+        // ---- the batch's rows: one per lane i < 32
+        int64_t u = -1;
+        if (lane < 32) {
+            const int64_t idx = c * 32 + lane;
+            if (idx < nrows) u = sparse ? (int64_t)fr.W[idx] : idx;
+        }
+        int64_t eb = 0, ee = 0;
+        bool inL = false;
+        if (u >= 0) {
+            eb = xadj[u];
+            ee = xadj[u + 1];
+            if (ee - eb > heavy_deg) {
+                ee = eb;  // split row: handled by the piece kernels
+            } else {
+                inL = !first && bit_of(Lcur, u) != 0u;
+                if (BLK && ee > eb) {
+                    bool all = true;
+                    for (int w = 0; w < 4 * PW; ++w) all = all && (blk[u * 4 * PW + w] | ~plane_valid_mask(w, P, PW)) == 0xFFFFFFFFu;
+                    if (all) ee = eb;  // blocked in every sample: cannot change, never in L
+                }
+            }
+        }
+        uint32_t total;
+        const uint32_t off = wave_excl_scan((uint32_t)(ee - eb), &total);
+        if (lane < 32) {
+            s_off[wv][lane] = off;
+            s_x[wv][lane] = eb;
+        }
+        if (lane == 32) s_off[wv][32] = total;
+        __builtin_amdgcn_wave_barrier();
+        const uint64_t inl_mask = __ballot(inL);
+        uint32_t word = 0, touched = 0;
+        int cur = -1;
+        int64_t cur_u = 0;
+        uint32_t cur_a[DW], cur_ub[DW];
+        Acc acc[DW];
+#pragma unroll
+        for (int i = 0; i < DW; ++i) {
+            cur_a[i] = 0u;
+            cur_ub[i] = 0xFFFFFFFFu;
+            acc[i].e = acc[i].o = 0u;
+        }
+        uint32_t vis = 0;
+        // flat edge f of the batch -> (row r, edge id e); the next window's ids
+        // are fetched while the current window is merged
+        auto locate = [&](uint32_t f, int& r, int64_t& e) {
+            int lo = 0, hi = 32;  // largest r with s_off[r] <= f
+            while (lo < hi) {
+                const int mid = (lo + hi + 1) >> 1;
+                if (s_off[wv][mid] <= f) lo = mid; else hi = mid - 1;
+            }
+            r = lo < 31 ? lo : 31;  // lo = 32 only for lanes past the last edge
+            e = s_x[wv][r] + (int64_t)(f - s_off[wv][r]);
+        };
+        int r_n;
+        int64_t e_n;
+        locate((uint32_t)lane, r_n, e_n);
+        bool in_n = (uint32_t)lane < total;
+        int32_t v_n = in_n ? adj[e_n] : 0;
+        for (uint32_t f0 = 0; f0 < total; f0 += 64) {
+            const int r = r_n;
+            const int64_t e = e_n;
+            const bool valid = in_n;
+            const int32_t v = v_n;
+            const uint32_t fn = f0 + 64 + lane;
+            locate(fn, r_n, e_n);
+            in_n = fn < total;
+            v_n = in_n ? adj[e_n] : 0;
+            const bool lv = valid && (first || bit_of(Lcur, v) != 0u);
+            const uint32_t hh = valid ? eh[e] : 0u;
+            uint32_t tt = 0u;
+            if constexpr (KIND == THR_TARGET) tt = valid ? thr[v] : 0u;
+            if constexpr (KIND == THR_EDGE) tt = valid ? thr[e] : 0u;
+            uint64_t mask = __ballot(lv);
+            vis += (uint32_t)__builtin_popcountll(mask);
+            while (mask) {
+                // up to UB live edges; unused slots repeat the last one (max-merge
+                // is idempotent), so every load is issued without a branch
+                int idx[UB], rb[UB];
+                int last = __builtin_ctzll(mask);
+#pragma unroll
+                for (int b = 0; b < UB; ++b) {
+                    if (mask) last = __builtin_ctzll(mask);
+                    idx[b] = last;
+                    mask &= mask - 1;
+                    rb[b] = __builtin_amdgcn_readlane(r, idx[b]);
+                }
+                uint32_t d[UB][DW], own[UB][DW], oub[UB][DW];
+#pragma unroll
+                for (int b = 0; b < UB; ++b) {
+                    const int64_t vb = __builtin_amdgcn_readlane(v, idx[b]);
+                    const int64_t ub_ = __builtin_amdgcn_readlane((int)u, rb[b]);
+                    const uint32_t* __restrict__ row = A + vb * P;
+#pragma unroll
+                    for (int i = 0; i < DW; ++i) {
+                        // lanes past the row (q >= P) read a valid dword of it; their
+                        // results are masked from the change test and never stored
+                        const int q = i * 64 + lane;
+                        const int qc = q < P ? q : P - 1;
+                        d[b][i] = row[qc];
+                        own[b][i] = A[ub_ * P + qc];
+                        oub[b][i] = BLK ? unblocked_mask(blk, ub_, qc, PW) : 0xFFFFFFFFu;
+                    }
+                }
+                // keep the batch's loads ahead of the merges (no sinking to the uses)
+                __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+                for (int b = 0; b < UB; ++b) {
+                    if (rb[b] != cur) {
+                        if (cur >= 0) {
+                            bool ch = false;
+#pragma unroll
+                            for (int i = 0; i < DW; ++i) {
+                                const uint32_t nw = acc_max(cur_a[i], acc[i]) & cur_ub[i];
+                                ch = ch || (i * 64 + lane < P && nw != cur_a[i]);
+                                cur_a[i] = nw;
+                            }
+                            const bool changed = __ballot(ch) != 0;
+                            const bool il = (inl_mask >> cur) & 1ull;
+                            if (changed || il) {
+#pragma unroll
+                                for (int i = 0; i < DW; ++i) {
+                                    const int q = i * 64 + lane;
+                                    if (q < P) B[cur_u * P + q] = cur_a[i];
+                                }
+                            }
+                            if (changed) word |= 1u << cur;
+                        }
+                        cur = rb[b];
+                        cur_u = __builtin_amdgcn_readlane((int)u, cur);
+                        touched |= 1u << cur;
+#pragma unroll
+                        for (int i = 0; i < DW; ++i) {
+                            cur_a[i] = own[b][i];
+                            cur_ub[i] = oub[b][i];
+                            acc[i].e = acc[i].o = 0u;
+                        }
+                    }
+                    const uint32_t hb = (uint32_t)__builtin_amdgcn_readlane((int)hh, idx[b]);
+                    uint32_t nt = ntv;
+                    if constexpr (KIND != THR_CONST) nt = 0u - (uint32_t)__builtin_amdgcn_readlane((int)tt, idx[b]);
+#pragma unroll
+                    for (int i = 0; i < DW; ++i)
+                        merge_live(acc[i], d[b][i], x[i][0], x[i][1], x[i][2], x[i][3], hb, nt);
+                }
+            }
+        }
+        if (cur >= 0) {
+            bool ch = false;
+#pragma unroll
+            for (int i = 0; i < DW; ++i) {
+                const uint32_t nw = acc_max(cur_a[i], acc[i]) & cur_ub[i];
+                ch = ch || (i * 64 + lane < P && nw != cur_a[i]);
+                cur_a[i] = nw;
+            }
+            const bool changed = __ballot(ch) != 0;
+            const bool il = (inl_mask >> cur) & 1ull;
+            if (changed || il) {
+#pragma unroll
+                for (int i = 0; i < DW; ++i) {
+                    const int q = i * 64 + lane;
+                    if (q < P) B[cur_u * P + q] = cur_a[i];
+                }
+            }
+            if (changed) word |= 1u << cur;
+        }
+        // rows of L_t without a live out-neighbour: B still holds M^{t-1}; copy M^t
+        for (uint32_t cp = (uint32_t)inl_mask & ~touched; cp; cp &= cp - 1) {
+            const int rr = __builtin_ctz(cp);
+            const int64_t uu = __builtin_amdgcn_readlane((int)u, rr);
+#pragma unroll
+            for (int i = 0; i < DW; ++i) {
+                const int q = i * 64 + lane;
+                if (q < P) B[uu * P + q] = A[uu * P + q];
+            }
+        }
+        if (!sparse) {
+            if (lane == 0) Lnext[c] = word;
+        } else if (lane < 32 && ((word >> lane) & 1u)) {
+            atomicOr(&Lnext[u >> 5], 1u << (u & 31));
+        }
+        if (lane < 32 && ((word >> lane) & 1u)) my_sum += (unsigned long long)(rxadj[u + 1] - rxadj[u]);
+        if (lane == 0) {
+            my_cnt += __builtin_popcount(word);
+            my_vis += vis;
+        }
+    }
+    const uint32_t bc = block_sum256(my_cnt, sh32);
+    const unsigned long long bv = block_sum256(my_vis, sh64);
+    const unsigned long long bs = block_sum256(my_sum, sh64);
+    if (threadIdx.x == 0) {
+        const int slot = blockIdx.x % NSLOT;
+        if (bc) atomicAdd(&cnt_out[slot * SLOT_U32], bc);
+        if (bv) atomicAdd(&vis_out[slot * SLOT_U64], bv);
+        if (bs) atomicAdd(&sum_out[slot * SLOT_U64], bs);
+    }
+}
+
 
 // One G-lane group per piece of a split row: merge of the live rows of the
 // piece's out-neighbours in L_t, written to part[piece].
@@ -665,38 +1108,43 @@ __global__ __launch_bounds__(256) void k_sweep_heavy(
     const uint32_t* __restrict__ Lcur, const uint32_t* __restrict__ blk, const uint32_t* __restrict__ gate,
     uint32_t gate_thresh, unsigned long long* __restrict__ vis_out, const int32_t* __restrict__ hrow,
     const int32_t* __restrict__ prow, const int64_t* __restrict__ pe0, const int64_t* __restrict__ pe1,
-    uint32_t* __restrict__ part, uint32_t* __restrict__ part_any, int64_t npieces, int P, int PW, int first) {
+    uint32_t* __restrict__ part, uint32_t* __restrict__ part_any, int64_t npieces, int64_t n, int P, int PW,
+    int first, Frontier fr, int parity, const unsigned long long* __restrict__ sgate, int64_t m) {
     __shared__ unsigned long long sh64[4];
-    if (!first && gate_sum(gate) <= gate_thresh) return;
+    const uint32_t live = sweep_live(gate, gate_thresh, first, n);
+    if (!live) return;
+    const bool sparse = sweep_sparse(sgate, first, m, fr.sparse_div);
+    const int64_t count = sparse ? (int64_t)fr.counts[4 * parity + 3] : npieces;
     constexpr int RPW = 64 / G;
     const int lane = threadIdx.x & 63, grp = lane / G, p = lane % G;
     uint32_t x[DW][4];
     load_sim_words<G, DW>(X, P, p, x);
     const uint32_t ntv = to_vgpr(0u - thr_const);
     unsigned long long my_vis = 0;
-    for (int64_t base = wave_index() * RPW; base < npieces; base += wave_count() * RPW) {
-        const int64_t pc = base + grp;
-        if (pc >= npieces) continue;
+    for (int64_t base = wave_index() * RPW; base < count; base += wave_count() * RPW) {
+        const int64_t i = base + grp;
+        if (i >= count) continue;
+        const int64_t pc = sparse ? (int64_t)fr.HP[i] : i;
         const int64_t u = hrow[prow[pc]];
         bool skip = false;
         if (blk) {
             bool none = true;
 #pragma unroll
-            for (int i = 0; i < DW; ++i) {
-                const int q = i * G + p;
+            for (int k = 0; k < DW; ++k) {
+                const int q = k * G + p;
                 if (q < P) none = none && unblocked_mask(blk, u, q, PW) == 0u;
             }
             skip = group_all<G>(none);
         }
         Acc acc[DW];
 #pragma unroll
-        for (int i = 0; i < DW; ++i) acc[i].e = acc[i].o = 0u;
+        for (int k = 0; k < DW; ++k) acc[k].e = acc[k].o = 0u;
         uint32_t vis = 0;
         if (!skip) vis = merge_edges<G, DW, KIND>(pe0[pc], pe1[pc], adj, eh, thr, ntv, A, Lcur, first, P, lane, p, x, acc);
 #pragma unroll
-        for (int i = 0; i < DW; ++i) {
-            const int q = i * G + p;
-            if (q < P) part[pc * P + q] = acc[i].e | acc[i].o;
+        for (int k = 0; k < DW; ++k) {
+            const int q = k * G + p;
+            if (q < P) part[pc * P + q] = acc[k].e | acc[k].o;
         }
         if (p == 0) {
             part_any[pc] = vis > 0 ? 1u : 0u;
@@ -714,75 +1162,96 @@ __global__ __launch_bounds__(256) void k_sweep_heavy_fix(
     uint32_t* __restrict__ Lnext, const uint32_t* __restrict__ blk, const uint32_t* __restrict__ gate,
     uint32_t gate_thresh, uint32_t* __restrict__ cnt_out, const int32_t* __restrict__ hrow,
     const int64_t* __restrict__ hpb, const int64_t* __restrict__ hpn, const uint32_t* __restrict__ part,
-    const uint32_t* __restrict__ part_any, int64_t nheavy, int P, int PW, int first) {
+    const uint32_t* __restrict__ part_any, int64_t nheavy, int64_t n, int P, int PW, int first, Frontier fr,
+    int parity, const unsigned long long* __restrict__ sgate, unsigned long long* __restrict__ sum_out,
+    const int64_t* __restrict__ rxadj, int64_t m) {
     __shared__ uint32_t sh32[4];
-    if (!first && gate_sum(gate) <= gate_thresh) return;
+    __shared__ unsigned long long sh64[4];
+    const uint32_t live = sweep_live(gate, gate_thresh, first, n);
+    if (!live) return;
+    const bool sparse = sweep_sparse(sgate, first, m, fr.sparse_div);
+    unsigned long long my_sum = 0;
+    const int64_t count = sparse ? (int64_t)fr.counts[4 * parity + 2] : nheavy;
     constexpr int RPW = 64 / G;
     const int lane = threadIdx.x & 63, grp = lane / G, p = lane % G;
     uint32_t my_cnt = 0;
-    for (int64_t base = wave_index() * RPW; base < nheavy; base += wave_count() * RPW) {
-        const int64_t r = base + grp;
-        bool changed = false;
-        if (r < nheavy) {
-            const int64_t u = hrow[r];
-            const bool inL = first ? false : bit_of(Lcur, u) != 0;
-            uint32_t ub[DW];
-            bool none = true;
+    for (int64_t base = wave_index() * RPW; base < count; base += wave_count() * RPW) {
+        const int64_t i = base + grp;
+        if (i >= count) continue;
+        const int64_t r = sparse ? (int64_t)fr.HW[i] : i;
+        const int64_t u = hrow[r];
+        const bool inL = first ? false : bit_of(Lcur, u) != 0;
+        uint32_t ub[DW];
+        bool none = true;
 #pragma unroll
-            for (int i = 0; i < DW; ++i) {
-                const int q = i * G + p;
-                ub[i] = 0xFFFFFFFFu;
-                if (blk && q < P) {
-                    ub[i] = unblocked_mask(blk, u, q, PW);
-                    none = none && ub[i] == 0u;
+        for (int k = 0; k < DW; ++k) {
+            const int q = k * G + p;
+            ub[k] = 0xFFFFFFFFu;
+            if (blk && q < P) {
+                ub[k] = unblocked_mask(blk, u, q, PW);
+                none = none && ub[k] == 0u;
+            }
+        }
+        if (blk && group_all<G>(none)) continue;
+        const int64_t pb = hpb[r], pe = pb + hpn[r];
+        uint32_t acc[DW];
+        uint32_t any = 0;
+#pragma unroll
+        for (int k = 0; k < DW; ++k) acc[k] = 0u;
+        // 8 pieces per step: the tail repeats the last piece (max is idempotent)
+        for (int64_t p0 = pb; p0 < pe; p0 += 8) {
+            uint32_t pv[8][DW], pa[8];
+#pragma unroll
+            for (int j = 0; j < 8; ++j) {
+                const int64_t pc = p0 + j < pe ? p0 + j : pe - 1;
+                pa[j] = part_any[pc];
+#pragma unroll
+                for (int k = 0; k < DW; ++k) {
+                    const int q = k * G + p;
+                    pv[j][k] = part[pc * P + (q < P ? q : P - 1)];
                 }
             }
-            const bool skip = blk ? group_all<G>(none) : false;
-            if (!skip) {
-                const int64_t pb = hpb[r], pe = pb + hpn[r];
-                uint32_t acc[DW];
-                bool any = false;
+            __builtin_amdgcn_sched_barrier(0);
 #pragma unroll
-                for (int i = 0; i < DW; ++i) acc[i] = 0u;
-                for (int64_t pc = pb; pc < pe; ++pc) {
-                    any = any || part_any[pc] != 0u;
+            for (int j = 0; j < 8; ++j) {
+                any |= pa[j];
 #pragma unroll
-                    for (int i = 0; i < DW; ++i) {
-                        const int q = i * G + p;
-                        if (q < P) acc[i] = byte_max(acc[i], part[pc * P + q]);
-                    }
-                }
-                if (any || inL) {
-                    bool ch = false;
-                    uint32_t nw[DW];
-#pragma unroll
-                    for (int i = 0; i < DW; ++i) {
-                        const int q = i * G + p;
-                        nw[i] = 0;
-                        if (q < P) {
-                            const uint32_t a = A[u * P + q];
-                            nw[i] = byte_max(a, acc[i]) & ub[i];
-                            ch = ch || nw[i] != a;
-                        }
-                    }
-                    changed = group_any<G>(ch);
-                    if (changed || inL) {
-#pragma unroll
-                        for (int i = 0; i < DW; ++i) {
-                            const int q = i * G + p;
-                            if (q < P) B[u * P + q] = nw[i];
-                        }
-                    }
-                    if (changed && p == 0) {
-                        atomicOr(&Lnext[u >> 5], 1u << (u & 31));
-                        my_cnt += 1;
-                    }
-                }
+                for (int k = 0; k < DW; ++k) acc[k] = byte_max(acc[k], pv[j][k]);
             }
+        }
+        if (!any && !inL) continue;
+        bool ch = false;
+        uint32_t nw[DW];
+#pragma unroll
+        for (int k = 0; k < DW; ++k) {
+            const int q = k * G + p;
+            nw[k] = 0;
+            if (q < P) {
+                const uint32_t a = A[u * P + q];
+                nw[k] = byte_max(a, acc[k]) & ub[k];
+                ch = ch || nw[k] != a;
+            }
+        }
+        const bool changed = group_any<G>(ch);
+        if (changed || inL) {
+#pragma unroll
+            for (int k = 0; k < DW; ++k) {
+                const int q = k * G + p;
+                if (q < P) B[u * P + q] = nw[k];
+            }
+        }
+        if (changed && p == 0) {
+            atomicOr(&Lnext[u >> 5], 1u << (u & 31));
+            my_cnt += 1;
+            my_sum += (unsigned long long)(rxadj[u + 1] - rxadj[u]);
         }
     }
     const uint32_t bc = block_sum256(my_cnt, sh32);
-    if (threadIdx.x == 0 && bc) atomicAdd(&cnt_out[(blockIdx.x % NSLOT) * SLOT_U32], bc);
+    const unsigned long long bs = block_sum256(my_sum, sh64);
+    if (threadIdx.x == 0) {
+        if (bc) atomicAdd(&cnt_out[(blockIdx.x % NSLOT) * SLOT_U32], bc);
+        if (bs) atomicAdd(&sum_out[(blockIdx.x % NSLOT) * SLOT_U64], bs);
+    }
 }
 
 #define HFR_KIND_DISPATCH(kind, CALL)        \
@@ -802,16 +1271,41 @@ __global__ __launch_bounds__(256) void k_sweep_heavy_fix(
 hipError_t launch_sweep(const Layout& L, const DevGraph& g, const uint32_t* X, const SweepParams& sp, int grid,
                         hipStream_t s, hipEvent_t ev0, hipEvent_t ev1) {
     const int64_t words = (g.n + 31) / 32;
-    int lg = grid > 0 ? grid : grid_for_rows(words);
-    if (ev0) (void)hipEventRecord(ev0, s);
-    HFR_LAYOUT_DISPATCH(L, HFR_KIND_DISPATCH(g.kind, hipLaunchKernelGGL((k_sweep_light<G_, DW_, K_>), dim3(lg),
-                                                                        dim3(256), 0, s, g.xadj, g.adj, g.eh, g.thr,
-                                                                        g.thr_const, X, sp.A, sp.B, sp.Lcur, sp.Lnext,
-                                                                        sp.blk, sp.gate, sp.gate_thresh, sp.cnt_out,
-                                                                        sp.vis_out, g.n, L.P, L.PW, g.heavy_deg,
-                                                                        sp.first)));
-    if (ev1) (void)hipEventRecord(ev1, s);
+    const int lg = grid > 0 ? grid : grid_for_rows(words);
+    const int sg = 2048;  // grid of the list kernels
+    hipLaunchKernelGGL(k_sweep_frontier, dim3(sg), dim3(256), 0, s, sp.gate, sp.gate_thresh, sp.sgate, g.m, sp.first,
+                       g.n, sp.Lcur, sp.Lclear, sp.fr, sp.parity, g.rxadj, g.hslot, g.hpb, g.hpn);
+    hipLaunchKernelGGL(k_sweep_expand, dim3(sg), dim3(256), 0, s, sp.gate, sp.gate_thresh, sp.sgate, g.m, sp.first, g.n,
+                       sp.fr, sp.parity, g.rxadj, g.radj, g.hslot, g.hpb, g.hpn);
     hipError_t err = hipGetLastError();
+    if (err != hipSuccess) return err;
+    if (ev0) (void)hipEventRecord(ev0, s);
+    if (L.G == 64) {
+        const int rg = grid_for_rows((g.n + 31) / 32);
+#define HFR_ROWS64(BLK_)                                                                                              \
+    HFR_LAYOUT_DISPATCH(L, HFR_KIND_DISPATCH(g.kind, hipLaunchKernelGGL((k_sweep_rows64<DW_, K_, BLK_>), dim3(rg),     \
+                                                                        dim3(256), 0, s, g.xadj, g.adj, g.eh, g.thr,  \
+                                                                        g.thr_const, X, sp.A, sp.B, sp.Lcur, sp.Lnext, \
+                                                                        sp.blk, sp.gate, sp.gate_thresh, sp.cnt_out,  \
+                                                                        sp.vis_out, sp.sgate, sp.sum_out, g.rxadj,    \
+                                                                        g.n, g.m, L.P, L.PW, g.heavy_deg, sp.first,   \
+                                                                        sp.fr, sp.parity)))
+        if (sp.blk)
+            HFR_ROWS64(true);
+        else
+            HFR_ROWS64(false);
+#undef HFR_ROWS64
+    } else {
+        HFR_LAYOUT_DISPATCH(L, HFR_KIND_DISPATCH(g.kind, hipLaunchKernelGGL((k_sweep_light<G_, DW_, K_>), dim3(lg),
+                                                                            dim3(256), 0, s, g.xadj, g.adj, g.eh,
+                                                                            g.thr, g.thr_const, X, sp.A, sp.B, sp.Lcur,
+                                                                            sp.Lnext, sp.blk, sp.gate, sp.gate_thresh,
+                                                                            sp.cnt_out, sp.vis_out, sp.sgate,
+                                                                            sp.sum_out, g.rxadj, g.n, g.m, L.P, L.PW,
+                                                                            g.heavy_deg, sp.first, sp.fr, sp.parity)));
+    }
+    if (ev1) (void)hipEventRecord(ev1, s);
+    err = hipGetLastError();
     if (err != hipSuccess) return err;
     if (g.npieces > 0) {
         const int rpw = 64 / L.G;
@@ -819,21 +1313,124 @@ hipError_t launch_sweep(const Layout& L, const DevGraph& g, const uint32_t* X, c
         HFR_LAYOUT_DISPATCH(L, HFR_KIND_DISPATCH(g.kind, hipLaunchKernelGGL((k_sweep_heavy<G_, DW_, K_>), dim3(hg),
                                                                             dim3(256), 0, s, g.adj, g.eh, g.thr,
                                                                             g.thr_const, X, sp.A, sp.Lcur, sp.blk,
-                                                                            sp.gate, sp.gate_thresh, sp.vis_out,
-                                                                            g.hrow, g.prow, g.pe0, g.pe1, sp.part,
-                                                                            sp.part_any, g.npieces, L.P, L.PW,
-                                                                            sp.first)));
+                                                                            sp.gate, sp.gate_thresh,
+                                                                            sp.vis_heavy_out, g.hrow, g.prow, g.pe0,
+                                                                            g.pe1, sp.part, sp.part_any, g.npieces,
+                                                                            g.n, L.P, L.PW, sp.first, sp.fr,
+                                                                            sp.parity, sp.sgate, g.m)));
         err = hipGetLastError();
         if (err != hipSuccess) return err;
         const int fg = grid_for_rows((g.nheavy + rpw - 1) / rpw);
         HFR_LAYOUT_DISPATCH(L, hipLaunchKernelGGL((k_sweep_heavy_fix<G_, DW_>), dim3(fg), dim3(256), 0, s, sp.A, sp.B,
                                                   sp.Lcur, sp.Lnext, sp.blk, sp.gate, sp.gate_thresh, sp.cnt_out,
-                                                  g.hrow, g.hpb, g.hpn, sp.part, sp.part_any, g.nheavy, L.P,
-                                                  L.PW, sp.first));
+                                                  g.hrow, g.hpb, g.hpn, sp.part, sp.part_any, g.nheavy, g.n, L.P,
+                                                  L.PW, sp.first, sp.fr, sp.parity, sp.sgate, sp.sum_out, g.rxadj,
+                                                  g.m));
         err = hipGetLastError();
+        if (err != hipSuccess) return err;
     }
-    return err;
+    hipLaunchKernelGGL(k_sweep_cleanup, dim3(sg), dim3(256), 0, s, sp.gate, sp.gate_thresh, sp.sgate, g.m, sp.first,
+                       g.n, sp.fr, sp.parity, g.hrow);
+    return hipGetLastError();
 }
+
+// ----------------------------------------------------------------------------
+// Reverse CSR (in-edges) for sparse sweeps, and the heavy slot of every row.
+// ----------------------------------------------------------------------------
+
+// Exclusive prefix sum of n u32 values into n+1 int64 offsets: block sums,
+// a single-block scan of the sums, then a per-block scan with the offset.
+constexpr int SCAN_BLOCK = 1024;
+
+__global__ void k_scan_block_sums(const uint32_t* __restrict__ in, int64_t n, int64_t* sums) {
+    __shared__ int64_t sh[4];
+    const int64_t i0 = (int64_t)blockIdx.x * SCAN_BLOCK;
+    int64_t s = 0;
+    for (int k = threadIdx.x; k < SCAN_BLOCK; k += 256)
+        if (i0 + k < n) s += in[i0 + k];
+    s = block_sum256(s, sh);
+    if (threadIdx.x == 0) sums[blockIdx.x] = s;
+}
+
+__global__ void k_scan_sums(int64_t* sums, int64_t nb) {
+    // one thread: nb is at most n / 1024
+    if (threadIdx.x == 0 && blockIdx.x == 0) {
+        int64_t run = 0;
+        for (int64_t b = 0; b < nb; ++b) {
+            const int64_t v = sums[b];
+            sums[b] = run;
+            run += v;
+        }
+        sums[nb] = run;
+    }
+}
+
+__global__ void k_scan_apply(const uint32_t* __restrict__ in, int64_t n, const int64_t* __restrict__ sums,
+                             int64_t* out) {
+    __shared__ int64_t sh[SCAN_BLOCK];
+    const int64_t i0 = (int64_t)blockIdx.x * SCAN_BLOCK;
+    for (int k = threadIdx.x; k < SCAN_BLOCK; k += 256) sh[k] = i0 + k < n ? (int64_t)in[i0 + k] : 0;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        int64_t run = sums[blockIdx.x];
+        for (int k = 0; k < SCAN_BLOCK; ++k) {
+            const int64_t v = sh[k];
+            sh[k] = run;
+            run += v;
+        }
+    }
+    __syncthreads();
+    for (int k = threadIdx.x; k < SCAN_BLOCK; k += 256)
+        if (i0 + k < n) out[i0 + k] = sh[k];
+    const int64_t nb = (n + SCAN_BLOCK - 1) / SCAN_BLOCK;
+    if (blockIdx.x == nb - 1 && threadIdx.x == 0) out[n] = sums[nb];
+}
+
+// radj[cursor[v]++] = u for every edge (u, v); the order inside an in-row
+// depends on scheduling, the set does not.
+__global__ void k_rev_scatter(const int64_t* __restrict__ xadj, const int32_t* __restrict__ adj, int64_t n,
+                              int64_t* cursor, int32_t* radj) {
+    const int lane = threadIdx.x & 63;
+    for (int64_t u = wave_index(); u < n; u += wave_count()) {
+        const int64_t eb = xadj[u], ee = xadj[u + 1];
+        for (int64_t e = eb + lane; e < ee; e += 64) {
+            const int32_t v = adj[e];
+            const unsigned long long pos = atomicAdd((unsigned long long*)&cursor[v], 1ull);
+            radj[pos] = (int32_t)u;
+        }
+    }
+}
+
+__global__ void k_copy_i64(const int64_t* __restrict__ a, int64_t* b, int64_t count) {
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < count; i += (int64_t)gridDim.x * blockDim.x)
+        b[i] = a[i];
+}
+
+hipError_t launch_reverse_csr(const DevGraph& g, const uint32_t* indeg, int64_t* cursor, uint32_t* scan_tmp,
+                              hipStream_t s) {
+    const int64_t n = g.n;
+    const int64_t nb = (n + SCAN_BLOCK - 1) / SCAN_BLOCK;
+    int64_t* sums = reinterpret_cast<int64_t*>(scan_tmp);  // nb + 1 entries
+    hipLaunchKernelGGL(k_scan_block_sums, dim3((unsigned)nb), dim3(256), 0, s, indeg, n, sums);
+    hipLaunchKernelGGL(k_scan_sums, dim3(1), dim3(64), 0, s, sums, nb);
+    hipLaunchKernelGGL(k_scan_apply, dim3((unsigned)nb), dim3(256), 0, s, indeg, n, sums, g.rxadj);
+    hipLaunchKernelGGL(k_copy_i64, dim3(4096), dim3(256), 0, s, g.rxadj, cursor, n);
+    if (g.m > 0) hipLaunchKernelGGL(k_rev_scatter, dim3(8192), dim3(256), 0, s, g.xadj, g.adj, n, cursor, g.radj);
+    return hipGetLastError();
+}
+
+__global__ void k_heavy_slots(const int32_t* __restrict__ hrow, int64_t nheavy, int32_t* hslot) {
+    for (int64_t r = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; r < nheavy; r += (int64_t)gridDim.x * blockDim.x)
+        hslot[hrow[r]] = (int32_t)r;
+}
+
+hipError_t launch_heavy_slots(const DevGraph& g, hipStream_t s) {
+    hipError_t err = launch_fill_u32(reinterpret_cast<uint32_t*>(g.hslot), 0xFFFFFFFFu, g.n, s);
+    if (err != hipSuccess || g.nheavy == 0) return err;
+    hipLaunchKernelGGL(k_heavy_slots, dim3(1024), dim3(256), 0, s, g.hrow, g.nheavy, g.hslot);
+    return hipGetLastError();
+}
+
 // ----------------------------------------------------------------------------
 // Greedy step (Alg. 1).
 // ----------------------------------------------------------------------------
@@ -894,11 +1491,6 @@ hipError_t launch_argmax(const Layout& L, int64_t n, const uint32_t* M, const Gr
     return hipGetLastError();
 }
 
-DEVI uint32_t plane_valid_mask(int w, int P, int PW) {
-    const int ww = w % PW;  // word within the plane
-    const int left = P - 32 * ww;
-    return left >= 32 ? 0xFFFFFFFFu : (left <= 0 ? 0u : ((1u << left) - 1u));
-}
 
 DEVI double estimate_from_sum(uint32_t s, int J, const double* __restrict__ T) {
     const uint32_t q = s / (uint32_t)J, r = s % (uint32_t)J;

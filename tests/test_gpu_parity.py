@@ -66,13 +66,14 @@ def _build(hf, ctx, g, model, p, J, per_edge=None, **kw):
     return hf.im_build_sketches(ctx, g.xadj, g.adj, g.n, J, model=model, p=p, per_edge=per_edge, **kw)
 
 
+@pytest.mark.parametrize("sparse_div", [0, 1])
 @pytest.mark.parametrize("J", [4, 12, 32, 64, 100, 128, 132, 256, 512, 1024])
 @pytest.mark.parametrize("gname", ["er40", "rmat10", "path", "isolated"])
-def test_build_registers_and_trace(hf, ctx, gname, J):
+def test_build_registers_and_trace(hf, ctx, gname, J, sparse_div):
     g = GRAPHS[gname]
     thr = _thr(g, "const", 0.3)
     M, sweeps, tl, te = oracle.simulate(g, thr, J)
-    sk = _build(hf, ctx, g, "const", 0.3, J)
+    sk = _build(hf, ctx, g, "const", 0.3, J, sparse_div=sparse_div)
     try:
         info = sk.info()
         live, vis = sk.trace()
@@ -84,15 +85,18 @@ def test_build_registers_and_trace(hf, ctx, gname, J):
         sk.free()
 
 
+@pytest.mark.parametrize("sparse_div", [0, 1, -1])
 @pytest.mark.parametrize("model", ["const", "wc", "edge"])
 @pytest.mark.parametrize("gname", ["er300", "rmat10", "star"])
 @pytest.mark.parametrize("J,heavy,piece", [(64, 0, 0), (256, 0, 0), (256, 8, 4), (64, 16, 16), (128, 5, 3)])
-def test_build_models_and_split_rows(hf, ctx, gname, model, J, heavy, piece):
+def test_build_models_and_split_rows(hf, ctx, gname, model, J, heavy, piece, sparse_div):
+    """sparse_div 1: every sweep after the first visits only the rows next to L_t; -1: all rows."""
     g = GRAPHS[gname]
     pe = _per_edge(g) if model == "edge" else None
     thr = _thr(g, model, 0.1, pe)
     M, sweeps, tl, te = oracle.simulate(g, thr, J)
-    sk = _build(hf, ctx, g, model, 0.1, J, per_edge=pe, heavy_degree=heavy, piece_edges=piece)
+    sk = _build(hf, ctx, g, model, 0.1, J, per_edge=pe, heavy_degree=heavy, piece_edges=piece,
+                sparse_div=sparse_div)
     try:
         info = sk.info()
         if heavy:
@@ -165,20 +169,24 @@ def _compare_greedy(res, seeds, steps, K):
             assert getattr(s, f) == o[f], (k, f, getattr(s, f), o[f])
 
 
-@pytest.mark.parametrize("gname,model,p,J,K,eps", [
-    ("er300", "const", 0.1, 64, 10, (0.01, 0.3)),
-    ("rmat10", "const", 0.1, 256, 12, (0.01, 0.3)),
-    ("rmat10", "wc", 0.0, 64, 8, (0.0, 0.0)),
-    ("rmat10", "const", 0.05, 128, 8, (float("inf"), float("inf"))),
-    ("star", "edge", 0.0, 32, 6, (0.01, 0.3)),
-    ("isolated", "const", 0.5, 16, 70, (0.01, 0.3)),
+@pytest.mark.parametrize("gname,model,p,J,K,eps,sparse_div,heavy", [
+    ("er300", "const", 0.1, 64, 10, (0.01, 0.3), 0, 0),
+    ("rmat10", "const", 0.1, 256, 12, (0.01, 0.3), 0, 0),
+    ("rmat10", "const", 0.1, 256, 12, (0.01, 0.3), 1, 16),
+    ("rmat10", "wc", 0.0, 64, 8, (0.0, 0.0), 0, 0),
+    ("rmat10", "wc", 0.0, 256, 8, (0.0, 0.0), 1, 8),
+    ("rmat10", "wc", 0.0, 128, 8, (0.0, 0.0), -1, 8),
+    ("rmat10", "const", 0.05, 128, 8, (float("inf"), float("inf")), 0, 0),
+    ("star", "edge", 0.0, 32, 6, (0.01, 0.3), 0, 0),
+    ("star", "edge", 0.0, 256, 6, (0.01, 0.3), 1, 0),
+    ("isolated", "const", 0.5, 16, 70, (0.01, 0.3), 0, 0),
 ])
-def test_select_seeds(hf, ctx, gname, model, p, J, K, eps):
+def test_select_seeds(hf, ctx, gname, model, p, J, K, eps, sparse_div, heavy):
     g = GRAPHS[gname]
     pe = _per_edge(g) if model == "edge" else None
     thr = _thr(g, model, p, pe)
     res = oracle.greedy(g, thr, J, K, eps_g=eps[0], eps_l=eps[1], want_blk=True)
-    sk = _build(hf, ctx, g, model, p, J, per_edge=pe)
+    sk = _build(hf, ctx, g, model, p, J, per_edge=pe, sparse_div=sparse_div, heavy_degree=heavy)
     try:
         seeds, steps, stats = hf.im_select_seeds(sk, K, eps_g=eps[0], eps_l=eps[1])
         _compare_greedy(res, seeds, steps, K)
