@@ -34,18 +34,22 @@ WORKLOADS = {
 }
 
 
-def sweep_bytes(rec, n, m_light, J, wc):
-    """Algorithmic HBM bytes of one row-kernel sweep launch.
+def heavy_launch_bytes(rec, J, wc, m_heavy, npieces):
+    """Algorithmic HBM bytes of one launch of the split-row piece kernel (k_sweep_heavy).
 
-    Reads xadj (8(n+1)), the out-edge ids of the rows it owns (4 m_light), the live
-    bitmap L_t (n/8), per visited edge the neighbour row (J) plus its hash (4) and, for the
-    weighted cascade, the target threshold (4); writes L_{t+1} (n/8); reads and writes
-    every changed row (2J).  A launch past the stopping rule moves nothing.
+    Per edge visited with a live head: the neighbour's row (J bytes), the edge hash (4)
+    and, for the weighted cascade, the target's threshold (4).  A dense launch also reads
+    every split-row out-edge id (4 m_heavy) and its piece table (20 B per piece) and
+    writes one partial row plus a flag per piece (J + 4).  A launch past the stopping
+    rule moves nothing.
     """
     if not rec["ran"]:
         return 0
-    per_edge = J + 4 + (4 if wc else 0)
-    return 8 * (n + 1) + 4 * m_light + n // 4 + rec["light_visits"] * per_edge + 2 * J * rec["live_next"]
+    hv = rec["visits"] - rec["light_visits"]
+    b = hv * (J + 4 + (4 if wc else 0))
+    if not rec["sparse"]:
+        b += 4 * m_heavy + 20 * npieces + npieces * (J + 4)
+    return b
 
 
 def cpu_baseline(seconds_hint: float = 15.0):
@@ -68,7 +72,7 @@ def cpu_baseline(seconds_hint: float = 15.0):
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=3)
+    ap.add_argument("--steps", type=int, default=2)
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--workload", default="rmat24_wc_J256_K50", choices=sorted(WORKLOADS))
     ap.add_argument("--no-cpu-baseline", action="store_true")
@@ -95,7 +99,7 @@ def main():
     log(f"workload {w.name}: n={g.n} m={g.m} generated in {time.perf_counter() - t:.1f} s")
     deg = np.diff(g.xadj)
     heavy_deg = args.heavy_degree or 32
-    m_light = int(deg[deg <= heavy_deg].sum())
+    m_heavy = int(deg[deg > heavy_deg].sum())
     xd = torch.from_numpy(g.xadj).cuda()
     ad = torch.from_numpy(g.adj).cuda()
     torch.cuda.synchronize()
@@ -135,13 +139,17 @@ def main():
     build_s = sum(r["build_s"] for r in results)
     select_s = sum(r["select_s"] for r in results)
     sim_ms = sum(r["info"]["build_ms"] for r in results)
-    # roofline of the row sweep kernel over every timed launch (build and rebuilds)
+    # roofline of the dominant kernel (the split-row piece kernel) over every timed launch
+    # of the timed steps (build and rebuild sweeps, including launches past the stopping rule)
     recs = [rec for r in results for rec in r["sweep_log"]]
     wc = w.model == "wc"
-    tot_bytes = sum(sweep_bytes(rec, g.n, m_light, J, wc) for rec in recs)
-    tot_ms = sum(rec["kernel_ms"] for rec in recs)
+    npieces = results[-1]["info"]["heavy_pieces"]
+    tot_bytes = sum(heavy_launch_bytes(rec, J, wc, m_heavy, npieces) for rec in recs)
+    tot_ms = sum(rec["heavy_ms"] for rec in recs)
     nlaunch = len(recs)
     achieved = tot_bytes / (tot_ms * 1e-3) / 1e9 if tot_ms > 0 else 0.0
+    row_ms = sum(rec["kernel_ms"] for rec in recs)
+    row_bytes = sum(rec["light_visits"] * (J + 4 + (4 if wc else 0)) for rec in recs if rec["ran"])
     out = {
         "metric": "edge*simulation visits/s in sketch build (+ K-seed IM time)",
         "value": visits / build_s,
@@ -168,9 +176,11 @@ def main():
         "sigma": results[-1]["sigma"],
         "seeds_head": results[-1]["seeds"][:8],
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": achieved / HBM_PEAK_GBS, "traffic": None, "kernel": "k_sweep_light",
+                     "frac": achieved / HBM_PEAK_GBS, "traffic": None, "kernel": "k_sweep_heavy",
                      "launches": nlaunch, "avg_launch_ms": tot_ms / max(nlaunch, 1),
                      "algorithmic_bytes_per_launch": tot_bytes / max(nlaunch, 1)},
+        "row_kernel": {"kernel": "k_sweep_rows64", "ms": row_ms,
+                       "visit_bytes_GBs": row_bytes / (row_ms * 1e-3) / 1e9 if row_ms > 0 else 0.0},
     }
     if args.dump_sweeps:
         with open(args.dump_sweeps, "w") as fh:

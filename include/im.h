@@ -190,11 +190,11 @@ im_status im_sketch_get_info(const im_sketch* sk, im_sketch_info* info);
 im_status im_sketch_get_trace(const im_sketch* sk, int64_t* live_counts, int64_t* edge_visits, int32_t cap,
                               int32_t* written);
 
-/* One launch of the row (non-split-row) sweep kernel, recorded when the build
- * was asked to time sweeps (im_build_opts.reserved != 0): kernel_ms is its
- * device time from HIP events on the context stream (sweep_ms: all kernels
- * of the sweep); light_visits the edges
- * with a live head it visited, visits those of the whole sweep, live_next
+/* One sweep, recorded when the build was asked to time sweeps
+ * (im_build_opts.reserved != 0): kernel_ms is the device time of the row
+ * kernel, heavy_ms that of the split-row piece kernel, sweep_ms that of all
+ * kernels of the sweep, from HIP events on the context stream; light_visits the edges
+ * with a live head the row kernel visited, visits those of the whole sweep, live_next
  * |L_{t+1}|.  ran = 0 marks a launch past the stopping rule (it returned at
  * once).  simulate numbers the Simulate calls of the sketch (0 = build,
  * later ones are rebuilds inside im_select_seeds). */
@@ -204,11 +204,13 @@ typedef struct im_sweep_rec {
     int32_t ran;
     float kernel_ms;  /* row kernel */
     float sweep_ms;   /* every kernel of the sweep */
-    int32_t reserved;
+    float heavy_ms;   /* split-row piece kernel */
     int64_t light_visits;
     int64_t visits;
     int64_t live;      /* |L_t| */
     int64_t live_next; /* |L_{t+1}| */
+    int32_t sparse;    /* 1 if the sweep visited only the rows next to L_t */
+    int32_t reserved;
 } im_sweep_rec;
 
 /* Copies up to cap records of the sweep log; returns the number copied. */

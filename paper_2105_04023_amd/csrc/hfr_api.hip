@@ -45,7 +45,7 @@ constexpr int MAX_BATCH = 64;     // sweeps per batch
 constexpr int DEFAULT_HEAVY = 32;
 constexpr int DEFAULT_PIECE = 256;
 constexpr int BFS_CHUNK = 256;
-constexpr int SWEEP_TIMERS = 4 * RING;
+constexpr int SWEEP_TIMERS = 6 * RING;
 
 }  // namespace
 
@@ -198,7 +198,7 @@ size_t bytes_needed(int64_t n, int64_t m, int32_t R, im_prob_kind kind) {
     t += 3 * al((size_t)n * L.P * 4);             // register buffers
     const int64_t words = (n + 31) / 32 + 1;
     t += 3 * al(4 * words);
-    t += al((size_t)RING * NSLOT * SLOT_U32 * 4) + al((size_t)3 * RING * NSLOT * SLOT_U64 * 8) + al(48 * MAX_BATCH);
+    t += al((size_t)RING * NSLOT * SLOT_U32 * 4) + al((size_t)3 * RING * NSLOT * SLOT_U64 * 8) + al(64 * MAX_BATCH);
     // split rows: bounded by m / heavy_degree rows and m / piece + rows pieces
     const int64_t nh = m / DEFAULT_HEAVY + 1, np = m / DEFAULT_PIECE + nh + 1;
     t += al(4 * nh) + al(8 * (nh + 1)) + al(8 * nh) + al(4 * np) + 2 * al(8 * np) + al((size_t)np * L.P * 4) +
@@ -212,8 +212,9 @@ size_t bytes_needed(int64_t n, int64_t m, int32_t R, im_prob_kind kind) {
     return t;
 }
 
-// Sums of the live-count slots of sweeps [t0+1, t0+nb] and of the row-kernel
-// and split-row-kernel visit slots of sweeps [t0, t0+nb-1] into out[3i..3i+2].
+// Sums of the live-count slots of sweeps [t0+1, t0+nb], of the row-kernel
+// and split-row-kernel visit slots and of S_t for sweeps [t0, t0+nb-1] into
+// out[4i..4i+3].
 // The visit ring holds RING row-kernel entries followed by RING split-row ones.
 __global__ void k_gather_counts(const uint32_t* __restrict__ cnt, const unsigned long long* __restrict__ vis,
                                 int64_t t0, int nb, unsigned long long* out) {
@@ -222,15 +223,18 @@ __global__ void k_gather_counts(const uint32_t* __restrict__ cnt, const unsigned
     const uint32_t* c = cnt + ((t0 + i + 1) % RING) * NSLOT * SLOT_U32;
     const unsigned long long* v = vis + ((t0 + i) % RING) * NSLOT * SLOT_U64;
     const unsigned long long* vh = v + (size_t)RING * NSLOT * SLOT_U64;
-    unsigned long long sc = 0, sv = 0, sh = 0;  // the third ring region (S_t) is not gathered
+    const unsigned long long* sm = vis + (2 * (size_t)RING + (t0 + i) % RING) * NSLOT * SLOT_U64;
+    unsigned long long sc = 0, sv = 0, sh = 0, ss = 0;
     for (int k = 0; k < NSLOT; ++k) {
         sc += c[k * SLOT_U32];
         sv += v[k * SLOT_U64];
         sh += vh[k * SLOT_U64];
+        ss += sm[k * SLOT_U64];
     }
-    out[3 * i] = sc;
-    out[3 * i + 1] = sv;
-    out[3 * i + 2] = sh;
+    out[4 * i] = sc;
+    out[4 * i + 1] = sv;
+    out[4 * i + 2] = sh;
+    out[4 * i + 3] = ss;  // S_t, the in-degree sum of L_t (0 for t = 0)
 }
 
 // Zeroes the live-count slots of sweeps [t0+1, t0+nb] and the visit slots of
@@ -266,6 +270,7 @@ struct SimResult {
     int64_t visits;
     double ms;
     std::vector<int64_t> live, vis, vis_light;
+    std::vector<char> sparse;
 };
 
 // Simulate (Alg. 2) on buffers ia/ib: init (with blocked pairs if blk), then
@@ -279,6 +284,7 @@ im_status run_simulate(im_sketch* sk, int ia, int ib, const uint32_t* blk, SimRe
     res->live.assign(1, n);
     res->vis.clear();
     res->vis_light.clear();
+    res->sparse.clear();
     const int32_t sim_id = sk->simulate_count++;
     HIP_TRY(hipEventRecord(sk->ev_a, s));
     HIP_TRY(launch_init(sk->L, n, sk->HJ, sk->seed, blk, buf[0], buf[1], s));
@@ -323,23 +329,25 @@ im_status run_simulate(im_sketch* sk, int ia, int ib, const uint32_t* blk, SimRe
             sp.part = sk->part;
             sp.part_any = sk->part_any;
             sp.first = st == 0;
-            hipEvent_t e0 = nullptr, e1 = nullptr, ea = nullptr, eb = nullptr;
-            if (sk->time_sweeps && timer_idx + 3 < (int)sk->sweep_ev.size()) {
+            hipEvent_t e0 = nullptr, e1 = nullptr, ea = nullptr, eb = nullptr, e2 = nullptr, e3 = nullptr;
+            if (sk->time_sweeps && timer_idx + 5 < (int)sk->sweep_ev.size()) {
                 e0 = sk->sweep_ev[timer_idx];
                 e1 = sk->sweep_ev[timer_idx + 1];
                 ea = sk->sweep_ev[timer_idx + 2];
                 eb = sk->sweep_ev[timer_idx + 3];
-                timer_idx += 4;
+                e2 = sk->sweep_ev[timer_idx + 4];
+                e3 = sk->sweep_ev[timer_idx + 5];
+                timer_idx += 6;
             }
             if (ea) HIP_TRY(hipEventRecord(ea, s));
-            HIP_TRY(launch_sweep(sk->L, sk->g, sk->X, sp, 0, s, e0, e1));
+            HIP_TRY(launch_sweep(sk->L, sk->g, sk->X, sp, 0, s, e0, e1, e2, e3));
             if (eb) HIP_TRY(hipEventRecord(eb, s));
         }
         hipLaunchKernelGGL(k_gather_counts, dim3(1), dim3(64), 0, s, sk->cnt_ring, sk->vis_ring, t, nb,
-                           sk->gather + 3 * MAX_BATCH * batch_slot);
+                           sk->gather + 4 * MAX_BATCH * batch_slot);
         HIP_TRY(hipGetLastError());
-        HIP_TRY(hipMemcpyAsync(sk->h_gather[batch_slot], sk->gather + 3 * MAX_BATCH * batch_slot,
-                               sizeof(unsigned long long) * 3 * nb, hipMemcpyDeviceToHost, s));
+        HIP_TRY(hipMemcpyAsync(sk->h_gather[batch_slot], sk->gather + 4 * MAX_BATCH * batch_slot,
+                               sizeof(unsigned long long) * 4 * nb, hipMemcpyDeviceToHost, s));
         HIP_TRY(hipEventRecord(sk->ev_batch[batch_slot], s));
         batch_t0[batch_slot] = t;
         batch_nb[batch_slot] = nb;
@@ -353,11 +361,15 @@ im_status run_simulate(im_sketch* sk, int ia, int ib, const uint32_t* blk, SimRe
         HIP_TRY(hipEventSynchronize(sk->ev_batch[rs]));
         --inflight;
         for (int i = 0; i < batch_nb[rs]; ++i) {
-            const int64_t live = (int64_t)sk->h_gather[rs][3 * i];
-            const int64_t vis_l = (int64_t)sk->h_gather[rs][3 * i + 1];
-            const int64_t vis = vis_l + (int64_t)sk->h_gather[rs][3 * i + 2];
+            const int64_t live = (int64_t)sk->h_gather[rs][4 * i];
+            const int64_t vis_l = (int64_t)sk->h_gather[rs][4 * i + 1];
+            const int64_t vis = vis_l + (int64_t)sk->h_gather[rs][4 * i + 2];
+            const int64_t st_sum = (int64_t)sk->h_gather[rs][4 * i + 3];
+            const int64_t tt = batch_t0[rs] + i;
             res->vis.push_back(vis);
             res->vis_light.push_back(vis_l);
+            res->sparse.push_back(tt > 0 && sk->fr.sparse_div != 0 &&
+                                  (uint64_t)st_sum * sk->fr.sparse_div <= (uint64_t)sk->g.m);
             res->live.push_back(live);
             if ((uint64_t)live <= thresh) {
                 final_sweeps = (int)(batch_t0[rs] + i + 1);
@@ -374,28 +386,32 @@ im_status run_simulate(im_sketch* sk, int ia, int ib, const uint32_t* blk, SimRe
     res->live.resize(final_sweeps + 1);
     res->vis.resize(final_sweeps);
     res->vis_light.resize(final_sweeps);
+    res->sparse.resize(final_sweeps);
     res->visits = 0;
     for (int64_t v : res->vis) res->visits += v;
     res->buf = (final_sweeps & 1) ? ib : ia;
     if (sk->time_sweeps) {
         // every timed launch of the row kernel, including the ones past the
         // stopping rule that returned at once
-        for (int i = 0; i + 3 < timer_idx; i += 4) {
-            float km = 0.f, wm = 0.f;
+        for (int i = 0; i + 5 < timer_idx; i += 6) {
+            float km = 0.f, wm = 0.f, hm = 0.f;
             HIP_TRY(hipEventElapsedTime(&km, sk->sweep_ev[i], sk->sweep_ev[i + 1]));
             HIP_TRY(hipEventElapsedTime(&wm, sk->sweep_ev[i + 2], sk->sweep_ev[i + 3]));
-            const int t = i / 4;
+            HIP_TRY(hipEventElapsedTime(&hm, sk->sweep_ev[i + 4], sk->sweep_ev[i + 5]));
+            const int t = i / 6;
             im_sweep_rec rec{};
             rec.simulate = sim_id;
             rec.sweep = t;
             rec.ran = t < final_sweeps;
             rec.kernel_ms = km;
             rec.sweep_ms = wm;
+            rec.heavy_ms = hm;
             if (rec.ran) {
                 rec.light_visits = res->vis_light[t];
                 rec.visits = res->vis[t];
                 rec.live = res->live[t];
                 rec.live_next = res->live[t + 1];
+                rec.sparse = res->sparse[t];
             }
             sk->sweep_log.push_back(rec);
         }
@@ -505,7 +521,7 @@ im_status im_build_sketches(im_ctx* ctx, const im_csr* graph, const im_probs* pr
     ok = ok && sk_alloc(sk, &sk->fr.mark, words) && sk_alloc(sk, &sk->fr.items, n + m / 256 + 64) &&
          sk_alloc(sk, &sk->fr.W, n) && sk_alloc(sk, &sk->fr.counts, 8);
     ok = ok && sk_alloc(sk, &sk->cnt_ring, (size_t)RING * NSLOT * SLOT_U32) &&
-         sk_alloc(sk, &sk->vis_ring, (size_t)3 * RING * NSLOT * SLOT_U64) && sk_alloc(sk, &sk->gather, 6 * MAX_BATCH);
+         sk_alloc(sk, &sk->vis_ring, (size_t)3 * RING * NSLOT * SLOT_U64) && sk_alloc(sk, &sk->gather, 8 * MAX_BATCH);
     ok = ok && sk_alloc(sk, &sk->d_err, 4) && sk_alloc(sk, &sk->d_heavy_counts, 4) && sk_alloc(sk, &sk->d_flag, 4);
     sk->fr.chunk = 256;
     sk->fr.sparse_div = o.sparse_div < 0 ? 0u : (o.sparse_div == 0 ? 16u : (uint32_t)o.sparse_div);
@@ -515,8 +531,8 @@ im_status im_build_sketches(im_ctx* ctx, const im_csr* graph, const im_probs* pr
         sk_release(sk);
         return fail(IM_ERR_OUT_OF_BUDGET, "device allocation failed");
     }
-    if (hipHostMalloc((void**)&sk->h_gather[0], 24 * MAX_BATCH) != hipSuccess ||
-        hipHostMalloc((void**)&sk->h_gather[1], 24 * MAX_BATCH) != hipSuccess ||
+    if (hipHostMalloc((void**)&sk->h_gather[0], 32 * MAX_BATCH) != hipSuccess ||
+        hipHostMalloc((void**)&sk->h_gather[1], 32 * MAX_BATCH) != hipSuccess ||
         hipHostMalloc((void**)&sk->h_small, 64) != hipSuccess) {
         sk_release(sk);
         return fail(IM_ERR_DEVICE, "pinned host allocation failed");

@@ -126,7 +126,8 @@ hipError_t launch_heavy_pieces(const DevGraph& g, int64_t piece_edges, hipStream
 hipError_t launch_init(const Layout& L, int64_t n, const uint32_t* HJ, uint32_t seed, const uint32_t* blk,
                        uint32_t* A, uint32_t* B, hipStream_t s);
 hipError_t launch_sweep(const Layout& L, const DevGraph& g, const uint32_t* X, const SweepParams& sp, int grid,
-                        hipStream_t s, hipEvent_t ev_light_begin, hipEvent_t ev_light_end);
+                        hipStream_t s, hipEvent_t ev_light_begin, hipEvent_t ev_light_end,
+                        hipEvent_t ev_heavy_begin, hipEvent_t ev_heavy_end);
 hipError_t launch_reverse_csr(const DevGraph& g, const uint32_t* indeg, int64_t* cursor, uint32_t* scan_tmp,
                               hipStream_t s);
 hipError_t launch_heavy_slots(const DevGraph& g, hipStream_t s);

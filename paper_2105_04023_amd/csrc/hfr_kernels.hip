@@ -1269,7 +1269,7 @@ __global__ __launch_bounds__(256) void k_sweep_heavy_fix(
     } while (0)
 
 hipError_t launch_sweep(const Layout& L, const DevGraph& g, const uint32_t* X, const SweepParams& sp, int grid,
-                        hipStream_t s, hipEvent_t ev0, hipEvent_t ev1) {
+                        hipStream_t s, hipEvent_t ev0, hipEvent_t ev1, hipEvent_t ev2, hipEvent_t ev3) {
     const int64_t words = (g.n + 31) / 32;
     const int lg = grid > 0 ? grid : grid_for_rows(words);
     const int sg = 2048;  // grid of the list kernels
@@ -1307,6 +1307,7 @@ hipError_t launch_sweep(const Layout& L, const DevGraph& g, const uint32_t* X, c
     if (ev1) (void)hipEventRecord(ev1, s);
     err = hipGetLastError();
     if (err != hipSuccess) return err;
+    if (ev2) (void)hipEventRecord(ev2, s);
     if (g.npieces > 0) {
         const int rpw = 64 / L.G;
         const int hg = grid_for_rows((g.npieces + rpw - 1) / rpw);
@@ -1320,6 +1321,7 @@ hipError_t launch_sweep(const Layout& L, const DevGraph& g, const uint32_t* X, c
                                                                             sp.parity, sp.sgate, g.m)));
         err = hipGetLastError();
         if (err != hipSuccess) return err;
+        if (ev3) (void)hipEventRecord(ev3, s);
         const int fg = grid_for_rows((g.nheavy + rpw - 1) / rpw);
         HFR_LAYOUT_DISPATCH(L, hipLaunchKernelGGL((k_sweep_heavy_fix<G_, DW_>), dim3(fg), dim3(256), 0, s, sp.A, sp.B,
                                                   sp.Lcur, sp.Lnext, sp.blk, sp.gate, sp.gate_thresh, sp.cnt_out,
@@ -1328,6 +1330,8 @@ hipError_t launch_sweep(const Layout& L, const DevGraph& g, const uint32_t* X, c
                                                   g.m));
         err = hipGetLastError();
         if (err != hipSuccess) return err;
+    } else if (ev3) {
+        (void)hipEventRecord(ev3, s);
     }
     hipLaunchKernelGGL(k_sweep_cleanup, dim3(sg), dim3(256), 0, s, sp.gate, sp.gate_thresh, sp.sgate, g.m, sp.first,
                        g.n, sp.fr, sp.parity, g.hrow);
