@@ -154,9 +154,6 @@ DEVI uint32_t gate_sum(const uint32_t* __restrict__ gate) {
     return s;
 }
 
-DEVI uint32_t edge_thr(int kind, uint32_t tconst, const uint32_t* __restrict__ thr, int64_t e, int32_t v) {
-    return kind == THR_CONST ? tconst : (kind == THR_TARGET ? thr[v] : thr[e]);
-}
 
 // ----------------------------------------------------------------------------
 // Utilities and graph preparation.
@@ -1561,11 +1558,17 @@ hipError_t launch_select(const Layout& L, const DevGraph& g, const uint32_t* M, 
 // each edge (v, w): the samples where the edge is live and v is in the
 // frontier are OR-ed into w's blocked bits; bits that were not set before
 // form w's frontier of the next level, and w is queued once per level.
-template <int G, int DW>
+//
+// A G-lane group serves one entry: it reads G edges per window, tests every
+// edge against its 4*DW registers per lane, and collects the edges with a
+// candidate bit in a batch.  Lane p of the group owns word p % (4 PW) of edge
+// slot p / (4 PW) of the batch, so one atomic instruction updates the blocked
+// words of G / (4 PW) edges at once (8 edges at R = 256).
+template <int G, int DW, int KIND>
 __global__ __launch_bounds__(256) void k_bfs_expand(const int64_t* __restrict__ xadj, const int32_t* __restrict__ adj,
                                                     const uint32_t* __restrict__ eh, const uint32_t* __restrict__ thr,
-                                                    uint32_t thr_const, int kind, const uint32_t* __restrict__ X,
-                                                    GreedyBufs b, int cur, int32_t level_id_next, int P, int PW) {
+                                                    uint32_t thr_const, const uint32_t* __restrict__ X, GreedyBufs b,
+                                                    int cur, int32_t level_id_next, int P, int PW) {
     __shared__ unsigned long long sh64[4];
     const uint32_t size = b.qsize[cur % 3];
     if (size == 0) return;
@@ -1577,22 +1580,26 @@ __global__ __launch_bounds__(256) void k_bfs_expand(const int64_t* __restrict__ 
     int2* Qn = b.Q[(cur + 1) & 1];
     uint32_t* qn = &b.qsize[(cur + 1) % 3];
     uint32_t x[DW][4];
-#pragma unroll
-    for (int i = 0; i < DW; ++i) {
-        const int q = i * G + p;
-#pragma unroll
-        for (int k = 0; k < 4; ++k) x[i][k] = q < P ? X[4 * q + k] : 0u;
-    }
+    load_sim_words<G, DW>(X, P, p, x);
+    const uint32_t ntv = to_vgpr(0u - thr_const);
+    const int W = 4 * PW;      // words of a vertex bitset = words of an edge's candidate set
+    const int EPB = G / W;     // edges per batch (>= 1)
+    const int sb = p / W, sw = p % W;
+    const bool slot_ok = sb < EPB;
+    const int sk = sw / PW, sww = sw % PW;  // plane and word-in-plane of this lane's word
+    const uint64_t gmask = G == 64 ? ~0ull : ((1ull << G) - 1ull);
+    const uint64_t wmask = W >= 64 ? ~0ull : ((1ull << W) - 1ull);
     unsigned long long my_new = 0;
-    const int W = 4 * PW;
     for (int64_t base = wave_index() * RPW; base < (int64_t)size; base += wave_count() * RPW) {
         const int64_t ent = base + grp;
         const bool ok = ent < (int64_t)size;
-        int64_t e0 = 0, e1 = 0, v = 0;
-        uint32_t fb[DW];  // frontier bits of this lane's 4*DW registers, bit (4i + k)
+        int64_t e0 = 0, e1 = 0;
+        uint32_t fb[DW];  // frontier bits of this lane's registers, bit (k) of fb[i] for register 4q+k
+#pragma unroll
+        for (int i = 0; i < DW; ++i) fb[i] = 0u;
         if (ok) {
             const int2 qe = Qc[ent];
-            v = qe.x;
+            const int64_t v = qe.x;
             const int64_t vb = xadj[v], ve = xadj[v + 1];
             e0 = vb + (int64_t)qe.y * b.bfs_chunk;
             e1 = e0 + b.bfs_chunk < ve ? e0 + b.bfs_chunk : ve;
@@ -1607,64 +1614,88 @@ __global__ __launch_bounds__(256) void k_bfs_expand(const int64_t* __restrict__ 
                 fb[i] = f;
             }
         }
-        for (int64_t e = e0; e < e1; ++e) {
-            const int64_t w = adj[e];
-            const uint32_t hh = eh[e];
-            const uint32_t nt = 0u - edge_thr(kind, thr_const, thr, e, (int32_t)w);
-            const int64_t wdeg = xadj[w + 1] - xadj[w];
-            bool anynew = false;
-#pragma unroll
-            for (int i = 0; i < DW; ++i) {
-#pragma unroll
-                for (int k = 0; k < 4; ++k) {
-                    const bool c = (((x[i][k] ^ hh) + nt) >> 31) & (fb[i] >> k) & 1u;
-                    const uint64_t bal = __ballot(c);
-                    // plane word(s) this group contributes for (i, k)
-                    if constexpr (G == 64) {
-                        const uint32_t lo = (uint32_t)bal, hi = (uint32_t)(bal >> 32);
-                        const int wlo = k * PW + 2 * i;
-                        // lanes 0/1 of the wave issue the two atomics
-                        uint32_t val = lane == 0 ? lo : (lane == 1 ? hi : 0u);
-                        if (val) {
-                            const int wi = wlo + lane;
-                            const uint32_t old = atomicOr(&b.blk[w * W + wi], val);
-                            const uint32_t nb = val & ~old;
-                            if (nb) {
-                                if (wdeg > 0) atomicOr(&Fn[w * W + wi], nb);
-                                my_new += __builtin_popcount(nb);
-                                anynew = true;
-                            }
-                        }
-                    } else {
-                        const uint32_t val = p == 0 ? (uint32_t)((bal >> (grp * G)) & ((1ull << G) - 1)) : 0u;
-                        if (val) {
-                            const int wi = k * PW;
-                            const uint32_t old = atomicOr(&b.blk[w * W + wi], val);
-                            const uint32_t nb = val & ~old;
-                            if (nb) {
-                                if (wdeg > 0) atomicOr(&Fn[w * W + wi], nb);
-                                my_new += __builtin_popcount(nb);
-                                anynew = true;
-                            }
-                        }
-                    }
+        uint32_t myval = 0;
+        int64_t myw = 0, mywdeg = 0;
+        int nb = 0;
+        auto flush = [&]() {
+            uint32_t nbits = 0;
+            if (myval) {
+                const uint32_t old = atomicOr(&b.blk[myw * W + sw], myval);
+                nbits = myval & ~old;
+                if (nbits) {
+                    if (mywdeg > 0) atomicOr(&Fn[myw * W + sw], nbits);
+                    my_new += (unsigned long long)__builtin_popcount(nbits);
                 }
             }
-            const bool gnew = group_any<G>(anynew);
-            if (gnew && wdeg > 0) {
-                int64_t pos = 0, nch = 0;
-                if (p == 0) {
-                    const int32_t old = atomicMax(&b.stamp[w], level_id_next);
-                    if (old < level_id_next) {
-                        nch = (wdeg + b.bfs_chunk - 1) / b.bfs_chunk;
-                        pos = atomicAdd(qn, (uint32_t)nch);
+            const uint64_t bal = __ballot(nbits != 0u);
+            if (sw == 0 && slot_ok && mywdeg > 0 && ((bal >> (grp * G + sb * W)) & wmask) != 0ull) {
+                const int32_t old = atomicMax(&b.stamp[myw], level_id_next);
+                if (old < level_id_next) {
+                    const int64_t nch = (mywdeg + b.bfs_chunk - 1) / b.bfs_chunk;
+                    const uint32_t pos = atomicAdd(qn, (uint32_t)nch);
+                    for (int64_t c = 0; c < nch; ++c) Qn[pos + c] = make_int2((int)myw, (int)c);
+                }
+            }
+            myval = 0;
+        };
+        for (int64_t w0 = e0; w0 < e1; w0 += G) {
+            const int64_t e = w0 + p;
+            const bool in = e < e1;
+            const int32_t wv = in ? adj[e] : 0;
+            const uint32_t hh = in ? eh[e] : 0u;
+            uint32_t tt = 0u;
+            if constexpr (KIND == THR_TARGET) tt = in ? thr[wv] : 0u;
+            if constexpr (KIND == THR_EDGE) tt = in ? thr[e] : 0u;
+            const int64_t wd = in ? xadj[wv + 1] - xadj[wv] : 0;
+            const int nwin = (int)(e1 - w0 < G ? e1 - w0 : G);
+            for (int j = 0; j < nwin; ++j) {
+                uint32_t hb, nt = ntv;
+                int32_t wj;
+                int64_t wdj;
+                if constexpr (G == 64) {
+                    hb = (uint32_t)__builtin_amdgcn_readlane((int)hh, j);
+                    if constexpr (KIND != THR_CONST) nt = 0u - (uint32_t)__builtin_amdgcn_readlane((int)tt, j);
+                    wj = __builtin_amdgcn_readlane(wv, j);
+                    wdj = __builtin_amdgcn_readlane((int)wd, j);
+                } else {
+                    hb = __shfl(hh, grp * G + j, 64);
+                    if constexpr (KIND != THR_CONST) nt = 0u - __shfl(tt, grp * G + j, 64);
+                    wj = __shfl(wv, grp * G + j, 64);
+                    wdj = __shfl((int)wd, grp * G + j, 64);
+                }
+                uint32_t cw = 0;
+                bool anyc = false;
+#pragma unroll
+                for (int i = 0; i < DW; ++i) {
+#pragma unroll
+                    for (int k = 0; k < 4; ++k) {
+                        const bool c = (int32_t)((x[i][k] ^ hb) + nt) < 0 && ((fb[i] >> k) & 1u);
+                        const uint64_t bal = __ballot(c);
+                        if constexpr (G == 64) {
+                            const uint32_t lo = (uint32_t)bal, hi = (uint32_t)(bal >> 32);
+                            if (sk == k && sww == 2 * i) cw = lo;
+                            if (sk == k && sww == 2 * i + 1) cw = hi;
+                            anyc = anyc || bal != 0ull;
+                        } else {
+                            const uint32_t gb = (uint32_t)((bal >> (grp * G)) & gmask);
+                            if (sk == k) cw = gb;
+                            anyc = anyc || gb != 0u;
+                        }
                     }
                 }
-                nch = __shfl(nch, grp * G, 64);
-                pos = __shfl(pos, grp * G, 64);
-                for (int64_t c = p; c < nch; c += G) Qn[pos + c] = make_int2((int)w, (int)c);
+                if (!anyc) continue;
+                if (sb == nb) {
+                    myval = cw;
+                    myw = wj;
+                    mywdeg = wdj;
+                }
+                if (++nb == EPB) {
+                    flush();
+                    nb = 0;
+                }
             }
         }
+        if (nb > 0) flush();
     }
     const unsigned long long bn = block_sum256(my_new, sh64);
     if (threadIdx.x == 0 && bn) atomicAdd(&b.R[(blockIdx.x % NSLOT) * SLOT_U64], bn);
@@ -1690,8 +1721,10 @@ __global__ void k_bfs_cleanup(GreedyBufs b, int cur, int PW) {
 
 hipError_t launch_bfs_level(const Layout& L, const DevGraph& g, const uint32_t* X, const GreedyBufs& b, int level,
                             int32_t level_id_next, int grid, hipStream_t s) {
-    HFR_LAYOUT_DISPATCH(L, hipLaunchKernelGGL((k_bfs_expand<G_, DW_>), dim3(grid), dim3(256), 0, s, g.xadj, g.adj, g.eh,
-                                              g.thr, g.thr_const, g.kind, X, b, level, level_id_next, L.P, L.PW));
+    HFR_LAYOUT_DISPATCH(L, HFR_KIND_DISPATCH(g.kind, hipLaunchKernelGGL((k_bfs_expand<G_, DW_, K_>), dim3(grid),
+                                                                        dim3(256), 0, s, g.xadj, g.adj, g.eh, g.thr,
+                                                                        g.thr_const, X, b, level, level_id_next, L.P,
+                                                                        L.PW)));
     hipError_t err = hipGetLastError();
     if (err != hipSuccess) return err;
     hipLaunchKernelGGL(k_bfs_cleanup, dim3(256), dim3(256), 0, s, b, level, L.PW);
