@@ -93,6 +93,7 @@ struct im_sketch {
     int32_t* d_flag = nullptr;
     uint32_t* d_err = nullptr;
     unsigned long long* d_heavy_counts = nullptr;
+    uint32_t stamp_ctr = 0;  // last per-sweep stamp handed out
 
     // pinned host staging
     unsigned long long* h_gather[2] = {nullptr, nullptr};
@@ -190,7 +191,7 @@ size_t bytes_needed(int64_t n, int64_t m, int32_t R, im_prob_kind kind) {
     auto al = [](size_t b) { return (std::max<size_t>(b, 1) + 255) & ~size_t(255); };
     size_t t = 0;
     t += al(8 * (n + 1)) + al(4 * m) + al(4 * m);  // xadj, adj, edge hashes
-    t += al(8 * (n + 1)) + al(4 * m) + al(4 * n);  // reverse CSR, heavy slots
+    t += al(8 * (n + 1)) + 2 * al(4 * m) + al(4 * n);  // reverse CSR with pieces, heavy slots
     t += al(4 * ((n + 31) / 32 + 1)) + al(8 * (n + m / 256 + 64)) + al(4 * n) + al(32);  // sparse lists
     if (kind == IM_PROB_WEIGHTED_CASCADE) t += al(4 * n);
     if (kind == IM_PROB_PER_EDGE) t += al(4 * m);
@@ -202,10 +203,10 @@ size_t bytes_needed(int64_t n, int64_t m, int32_t R, im_prob_kind kind) {
     // split rows: bounded by m / heavy_degree rows and m / piece + rows pieces
     const int64_t nh = m / DEFAULT_HEAVY + 1, np = m / DEFAULT_PIECE + nh + 1;
     t += al(4 * nh) + al(8 * (nh + 1)) + al(8 * nh) + al(4 * np) + 2 * al(8 * np) + al((size_t)np * L.P * 4) +
-         al(4 * np) + al(4 * nh) + al(4 * np);
+         al(4 * np) + al(4 * nh) + al(4 * np) + al(4 * (np / 32 + 1));
     // greedy
     const size_t W = 4 * (size_t)L.PW;
-    t += 3 * al((size_t)n * W * 4);
+    t += 3 * al((size_t)n * W * 4) + al(4 * words);
     t += 2 * al(8 * qcap_for(n, m)) + al(64) + al(4 * n) + al(n) + 2 * al(4 * L.P) + al(8) +
          al(NSLOT * SLOT_U64 * 8) + al(8);
     t += al(sizeof(StepRec) * 64) + al(4 * 64) + al(16) + al(16) + al(64);
@@ -288,6 +289,7 @@ im_status run_simulate(im_sketch* sk, int ia, int ib, const uint32_t* blk, SimRe
     const int32_t sim_id = sk->simulate_count++;
     HIP_TRY(hipEventRecord(sk->ev_a, s));
     HIP_TRY(launch_init(sk->L, n, sk->HJ, sk->seed, blk, buf[0], buf[1], s));
+    if (blk) HIP_TRY(launch_full_blocked(sk->L, n, blk, sk->gb.fullblk, s));
     HIP_TRY(launch_fill_u32(sk->fr.mark, 0u, (n + 31) / 32 + 1, s));
     HIP_TRY(launch_fill_u32(sk->fr.counts, 0u, 8, s));
     int final_sweeps = -1;
@@ -317,6 +319,13 @@ im_status run_simulate(im_sketch* sk, int ia, int ib, const uint32_t* blk, SimRe
             sp.Lnext = sk->Lbm[(st + 1) % 3];
             sp.Lclear = sk->Lbm[(st + 2) % 3];
             sp.fr = sk->fr;
+            // piece flags of earlier sweeps never equal this sweep's stamp
+            if (++sk->stamp_ctr == 0u) {
+                if (sk->g.npieces > 0) HIP_TRY(launch_fill_u32(sk->part_any, 0u, sk->g.npieces, s));
+                sk->stamp_ctr = 1u;
+            }
+            sp.fr.stamp = sk->stamp_ctr;
+            sp.fullblk = blk ? sk->gb.fullblk : nullptr;
             sp.parity = (int)(st & 1);
             sp.blk = blk;
             sp.gate = st == 0 ? nullptr : cnt_slots(sk, st);
@@ -517,7 +526,8 @@ im_status im_build_sketches(im_ctx* ctx, const im_csr* graph, const im_probs* pr
     const int64_t words = (n + 31) / 32 + 1;
     ok = ok && sk_alloc(sk, &sk->Lbm[0], words) && sk_alloc(sk, &sk->Lbm[1], words) &&
          sk_alloc(sk, &sk->Lbm[2], words);
-    ok = ok && sk_alloc(sk, &g.rxadj, n + 1) && sk_alloc(sk, &g.radj, m) && sk_alloc(sk, &g.hslot, n);
+    ok = ok && sk_alloc(sk, &g.rxadj, n + 1) && sk_alloc(sk, &g.radj, m) && sk_alloc(sk, &g.rpiece, m) &&
+         sk_alloc(sk, &g.hslot, n);
     ok = ok && sk_alloc(sk, &sk->fr.mark, words) && sk_alloc(sk, &sk->fr.items, n + m / 256 + 64) &&
          sk_alloc(sk, &sk->fr.W, n) && sk_alloc(sk, &sk->fr.counts, 8);
     ok = ok && sk_alloc(sk, &sk->cnt_ring, (size_t)RING * NSLOT * SLOT_U32) &&
@@ -594,25 +604,11 @@ im_status im_build_sketches(im_ctx* ctx, const im_csr* graph, const im_probs* pr
                 if (sk->h_small[0] & 4u) return fail(IM_ERR_INVALID_ARG, "a per-edge probability is outside [0, 1]");
             }
         }
-        // in-degrees: weighted-cascade thresholds and the reverse CSR
-        {
-            const int64_t nb = (n + 1023) / 1024;
-            void* p = ctx_alloc(ctx, 4 * n + 8 * (n + 1) + 8 * (nb + 2) + 512);
-            if (!p) return fail(IM_ERR_OUT_OF_BUDGET, "temporary allocation failed");
-            uint32_t* indeg = (uint32_t*)p;
-            int64_t* cursor = (int64_t*)((char*)p + ((4 * n + 255) & ~int64_t(255)));
-            uint32_t* scan_tmp = (uint32_t*)((char*)cursor + ((8 * (n + 1) + 255) & ~int64_t(255)));
-            HIP_TRY(launch_fill_u32(indeg, 0u, n, s));
-            HIP_TRY(launch_indegree(g, indeg, s));
-            if (g.kind == THR_TARGET) HIP_TRY(launch_wc_thresholds(indeg, g.thr, n, s));
-            HIP_TRY(launch_reverse_csr(g, indeg, cursor, scan_tmp, s));
-            HIP_TRY(hipStreamSynchronize(s));
-            ctx_free(ctx, p);
-        }
         // split rows
         const int64_t heavy = o.heavy_degree > 0 ? o.heavy_degree : DEFAULT_HEAVY;
         const int64_t piece = o.piece_edges > 0 ? o.piece_edges : DEFAULT_PIECE;
         g.heavy_deg = heavy;
+        g.piece_edges = piece;
         HIP_TRY(hipMemsetAsync(sk->d_heavy_counts, 0, 32, s));
         HIP_TRY(launch_heavy_count(g, piece, sk->d_heavy_counts, s));
         unsigned long long hc[2] = {0, 0};
@@ -628,16 +624,36 @@ im_status im_build_sketches(im_ctx* ctx, const im_csr* graph, const im_probs* pr
             if (!ok2) return fail(IM_ERR_OUT_OF_BUDGET, "device allocation failed (split rows)");
             HIP_TRY(launch_heavy_assign(g, piece, sk->d_heavy_counts, s));
             HIP_TRY(launch_heavy_pieces(g, piece, s));
-            if (!sk_alloc(sk, &sk->fr.HW, g.nheavy) || !sk_alloc(sk, &sk->fr.HP, g.npieces))
+            if (!sk_alloc(sk, &sk->fr.HW, g.nheavy) || !sk_alloc(sk, &sk->fr.HP, g.npieces) ||
+                !sk_alloc(sk, &sk->fr.pmark, g.npieces / 32 + 1))
                 return fail(IM_ERR_OUT_OF_BUDGET, "device allocation failed (sparse lists)");
+            HIP_TRY(launch_fill_u32(sk->part_any, 0u, g.npieces, s));
+            HIP_TRY(launch_fill_u32(sk->fr.pmark, 0u, g.npieces / 32 + 1, s));
         }
         HIP_TRY(launch_heavy_slots(g, s));
+        // in-degrees: weighted-cascade thresholds and the reverse CSR (whose in-edges
+        // carry the piece of their split source row)
+        {
+            const int64_t nb = (n + 1023) / 1024;
+            void* p = ctx_alloc(ctx, 4 * n + 8 * (n + 1) + 8 * (nb + 2) + 512);
+            if (!p) return fail(IM_ERR_OUT_OF_BUDGET, "temporary allocation failed");
+            uint32_t* indeg = (uint32_t*)p;
+            int64_t* cursor = (int64_t*)((char*)p + ((4 * n + 255) & ~int64_t(255)));
+            uint32_t* scan_tmp = (uint32_t*)((char*)cursor + ((8 * (n + 1) + 255) & ~int64_t(255)));
+            HIP_TRY(launch_fill_u32(indeg, 0u, n, s));
+            HIP_TRY(launch_indegree(g, indeg, s));
+            if (g.kind == THR_TARGET) HIP_TRY(launch_wc_thresholds(indeg, g.thr, n, s));
+            HIP_TRY(launch_reverse_csr(g, indeg, cursor, scan_tmp, s));
+            HIP_TRY(hipStreamSynchronize(s));
+            ctx_free(ctx, p);
+        }
         // greedy buffers
         const size_t W = 4 * (size_t)L.PW;
         GreedyBufs& b = sk->gb;
         b.qcap = qcap_for(n, m);
         b.bfs_chunk = BFS_CHUNK;
-        bool ok3 = sk_alloc(sk, &b.blk, n * W) && sk_alloc(sk, &b.F[0], n * W) && sk_alloc(sk, &b.F[1], n * W) &&
+        bool ok3 = sk_alloc(sk, &b.blk, n * W) && sk_alloc(sk, &b.fullblk, words) && sk_alloc(sk, &b.F[0], n * W) &&
+                   sk_alloc(sk, &b.F[1], n * W) &&
                    sk_alloc(sk, &b.Q[0], b.qcap) && sk_alloc(sk, &b.Q[1], b.qcap) && sk_alloc(sk, &b.qsize, 16) &&
                    sk_alloc(sk, &b.stamp, n) && sk_alloc(sk, &b.inS, n) && sk_alloc(sk, &b.MS, L.P) &&
                    sk_alloc(sk, &b.merged, L.P) && sk_alloc(sk, &b.key, 1) &&

@@ -50,6 +50,8 @@ struct DevGraph {
     int64_t* rxadj = nullptr;   // [n + 1]
     int32_t* radj = nullptr;    // [m]
     int32_t* hslot = nullptr;   // heavy slot of each row, -1 for rows processed whole [n]
+    int32_t* rpiece = nullptr;  // per in-edge: piece of its split source row, -1 otherwise [m]
+    int64_t piece_edges = 256;
 };
 
 // Work lists of a sparse sweep.  Counters come in two sets selected by the
@@ -61,6 +63,8 @@ struct Frontier {
     int32_t* HW = nullptr;      // heavy row slots
     int32_t* HP = nullptr;      // pieces of listed heavy rows
     uint32_t* counts = nullptr; // [2][4]: items, W, HW, HP
+    uint32_t* pmark = nullptr;  // npieces bits: piece already listed in this sweep
+    uint32_t stamp = 0;         // unique per sweep (never 0): piece flags of this sweep
     int32_t chunk = 256;        // in-edges per item
     uint32_t sparse_div = 8;    // sweep t > 0 is sparse iff S_t * sparse_div <= m (0: never)
 };
@@ -82,6 +86,7 @@ struct SweepParams {
     uint32_t* Lclear;          // bitmap of L_{t-1}, zeroed during this sweep for L_{t+2}
     const unsigned long long* sgate;  // slots of S_t = sum of in-degrees over L_t (nullptr on the first sweep)
     unsigned long long* sum_out;      // slots of S_{t+1}
+    const uint32_t* fullblk;   // n bits: vertex blocked in every sample (nullptr with blk)
     Frontier fr;
     int parity;                // t & 1
     int first;
@@ -89,6 +94,7 @@ struct SweepParams {
 
 struct GreedyBufs {
     uint32_t* blk;     // n * 4 * PW
+    uint32_t* fullblk; // n bits: blocked in every sample
     uint32_t* F[2];    // frontier bits, same shape as blk
     int2* Q[2];        // queue entries (vertex, chunk)
     uint32_t* qsize;   // 3 ring counters (+ level counter at [3])
@@ -131,6 +137,7 @@ hipError_t launch_sweep(const Layout& L, const DevGraph& g, const uint32_t* X, c
 hipError_t launch_reverse_csr(const DevGraph& g, const uint32_t* indeg, int64_t* cursor, uint32_t* scan_tmp,
                               hipStream_t s);
 hipError_t launch_heavy_slots(const DevGraph& g, hipStream_t s);
+hipError_t launch_full_blocked(const Layout& L, int64_t n, const uint32_t* blk, uint32_t* fullblk, hipStream_t s);
 hipError_t launch_argmax(const Layout& L, int64_t n, const uint32_t* M, const GreedyBufs& b, hipStream_t s);
 hipError_t launch_select(const Layout& L, const DevGraph& g, const uint32_t* M, const GreedyBufs& b,
                          StepRec* rec, int32_t* seeds_dev, int k, int32_t level_id, hipStream_t s);

@@ -608,27 +608,16 @@ DEVI uint32_t wave_excl_scan(uint32_t c, uint32_t* total) {
     return x - c;
 }
 
-// Appends heavy slot r and its pieces to the sparse lists (one thread).
-DEVI void list_heavy(Frontier& fr, uint32_t* cnt, int32_t r, const int64_t* __restrict__ hpb,
-                     const int64_t* __restrict__ hpn) {
-    const uint32_t hw = atomicAdd(&cnt[2], 1u);
-    fr.HW[hw] = r;
-    const int64_t np = hpn[r], pb = hpb[r];
-    const uint32_t hp = atomicAdd(&cnt[3], (uint32_t)np);
-    for (int64_t i = 0; i < np; ++i) fr.HP[hp + i] = (int32_t)(pb + i);
-}
 
 // First kernel of every sweep.  Zeroes the bitmap that will hold L_{t+2}; in a
-// sparse sweep also lists L_t (marked, for the copy rule) and the in-edge
-// chunks of every vertex of L_t.
+// sparse sweep also lists L_t (marked, for the copy rule; split rows go to HW
+// without pieces) and the in-edge chunks of every vertex of L_t.
 __global__ __launch_bounds__(256) void k_sweep_frontier(const uint32_t* __restrict__ gate, uint32_t gate_thresh,
                                                         const unsigned long long* __restrict__ sgate, int64_t m,
                                                         int first, int64_t n, const uint32_t* __restrict__ Lcur,
                                                         uint32_t* __restrict__ Lclear, Frontier fr, int parity,
                                                         const int64_t* __restrict__ rxadj,
-                                                        const int32_t* __restrict__ hslot,
-                                                        const int64_t* __restrict__ hpb,
-                                                        const int64_t* __restrict__ hpn) {
+                                                        const int32_t* __restrict__ hslot) {
     const uint32_t live = sweep_live(gate, gate_thresh, first, n);
     if (!live) return;
     const int64_t nwords = (n + 31) >> 5;
@@ -667,7 +656,7 @@ __global__ __launch_bounds__(256) void k_sweep_frontier(const uint32_t* __restri
                 if (r < 0)
                     fr.W[bl++] = (int32_t)v;
                 else
-                    list_heavy(fr, cnt, r, hpb, hpn);
+                    fr.HW[atomicAdd(&cnt[2], 1u)] = r;
                 const int64_t nc = (rxadj[v + 1] - rxadj[v] + fr.chunk - 1) / fr.chunk;
                 for (int64_t c = 0; c < nc; ++c) fr.items[bi++] = make_int2((int)v, (int)c);
             }
@@ -675,15 +664,16 @@ __global__ __launch_bounds__(256) void k_sweep_frontier(const uint32_t* __restri
     }
 }
 
-// Sparse sweep: marks the in-neighbours of L_t and lists the new ones.
+// Sparse sweep: marks the in-neighbours of L_t and lists the new ones.  A
+// split source row is listed once (HW) and only the pieces holding an edge
+// into L_t are listed (HP).
 __global__ __launch_bounds__(256) void k_sweep_expand(const uint32_t* __restrict__ gate, uint32_t gate_thresh,
                                                       const unsigned long long* __restrict__ sgate, int64_t m,
                                                       int first, int64_t n, Frontier fr, int parity,
                                                       const int64_t* __restrict__ rxadj,
                                                       const int32_t* __restrict__ radj,
-                                                      const int32_t* __restrict__ hslot,
-                                                      const int64_t* __restrict__ hpb,
-                                                      const int64_t* __restrict__ hpn) {
+                                                      const int32_t* __restrict__ rpiece,
+                                                      const int32_t* __restrict__ hslot) {
     const uint32_t live = sweep_live(gate, gate_thresh, first, n);
     if (!live || !sweep_sparse(sgate, first, m, fr.sparse_div)) return;
     uint32_t* cnt = fr.counts + 4 * parity;
@@ -700,11 +690,18 @@ __global__ __launch_bounds__(256) void k_sweep_expand(const uint32_t* __restrict
             int32_t u = 0, r = -1;
             if (e < e1) {
                 u = radj[e];
+                r = hslot[u];
                 const uint32_t bit = 1u << (u & 31);
                 // most in-neighbours are reached from several live vertices: test
                 // before paying for the atomic
                 if ((fr.mark[u >> 5] & bit) == 0u) fresh = (atomicOr(&fr.mark[u >> 5], bit) & bit) == 0u;
-                if (fresh) r = hslot[u];
+                if (r >= 0) {
+                    const int32_t pc = rpiece[e];
+                    const uint32_t pbit = 1u << (pc & 31);
+                    if ((fr.pmark[pc >> 5] & pbit) == 0u && (atomicOr(&fr.pmark[pc >> 5], pbit) & pbit) == 0u)
+                        fr.HP[atomicAdd(&cnt[3], 1u)] = pc;
+                    if (fresh) fr.HW[atomicAdd(&cnt[2], 1u)] = r;
+                }
             }
             const bool lt = fresh && r < 0;
             const uint64_t bal = __ballot(lt);
@@ -714,7 +711,6 @@ __global__ __launch_bounds__(256) void k_sweep_expand(const uint32_t* __restrict
                 base = __shfl(base, 0, 64);
                 if (lt) fr.W[base + (uint32_t)__builtin_popcountll(bal & ((1ull << lane) - 1ull))] = u;
             }
-            if (fresh && r >= 0) list_heavy(fr, cnt, r, hpb, hpn);
         }
     }
 }
@@ -732,9 +728,10 @@ __global__ __launch_bounds__(256) void k_sweep_cleanup(const uint32_t* __restric
     if (tid < 4) fr.counts[4 * (parity ^ 1) + tid] = 0u;
     if (!sweep_sparse(sgate, first, m, fr.sparse_div)) return;
     const uint32_t* cnt = fr.counts + 4 * parity;
-    const int64_t nw = cnt[1], nh = cnt[2];
+    const int64_t nw = cnt[1], nh = cnt[2], np = cnt[3];
     for (int64_t i = tid; i < nw; i += stride) fr.mark[fr.W[i] >> 5] = 0u;
     for (int64_t i = tid; i < nh; i += stride) fr.mark[hrow[fr.HW[i]] >> 5] = 0u;
+    for (int64_t i = tid; i < np; i += stride) fr.pmark[fr.HP[i] >> 5] = 0u;
 }
 
 // Merge of one whole row (one G-lane group): returns true if it changed.
@@ -745,11 +742,11 @@ DEVI bool sweep_row(int64_t u, const int64_t* __restrict__ xadj, const int32_t* 
                     const uint32_t* __restrict__ eh, const uint32_t* __restrict__ thr, uint32_t ntv,
                     const uint32_t (&x)[DW][4], const uint32_t* __restrict__ A, uint32_t* __restrict__ B,
                     const uint32_t* __restrict__ Lcur, uint32_t* __restrict__ Lnext, const uint32_t* __restrict__ blk,
-                    int64_t heavy_deg, int P, int PW, int first, bool dense_word, int lane, int p,
-                    unsigned long long& my_vis) {
+                    const uint32_t* __restrict__ fullblk, int64_t heavy_deg, int P, int PW, int first,
+                    bool dense_word, int lane, int p, unsigned long long& my_vis) {
     const int64_t eb = xadj[u], ee = xadj[u + 1];
     const bool inL = first ? false : bit_of(Lcur, u) != 0;
-    bool active = ee - eb <= heavy_deg && (ee > eb || inL);
+    bool active = ee - eb <= heavy_deg && (ee > eb || inL) && !(fullblk && bit_of(fullblk, u));
     uint32_t ub[DW];
 #pragma unroll
     for (int i = 0; i < DW; ++i) ub[i] = 0xFFFFFFFFu;
@@ -805,7 +802,7 @@ __global__ __launch_bounds__(256) void k_sweep_light(
     uint32_t gate_thresh, uint32_t* __restrict__ cnt_out, unsigned long long* __restrict__ vis_out,
     const unsigned long long* __restrict__ sgate, unsigned long long* __restrict__ sum_out,
     const int64_t* __restrict__ rxadj, int64_t n, int64_t m, int P, int PW, int64_t heavy_deg, int first, Frontier fr,
-    int parity) {
+    int parity, const uint32_t* __restrict__ fullblk) {
     __shared__ unsigned long long sh64[4];
     __shared__ uint32_t sh32[4];
     const uint32_t live = sweep_live(gate, gate_thresh, first, n);
@@ -827,8 +824,8 @@ __global__ __launch_bounds__(256) void k_sweep_light(
                 const int64_t u = c * 32 + rr + grp;
                 bool changed = false;
                 if (u < n)
-                    changed = sweep_row<G, DW, KIND>(u, xadj, adj, eh, thr, ntv, x, A, B, Lcur, Lnext, blk, heavy_deg,
-                                                     P, PW, first, true, lane, p, my_vis);
+                    changed = sweep_row<G, DW, KIND>(u, xadj, adj, eh, thr, ntv, x, A, B, Lcur, Lnext, blk, fullblk,
+                                                     heavy_deg, P, PW, first, true, lane, p, my_vis);
                 if (changed && p == 0) my_sum += (unsigned long long)(rxadj[u + 1] - rxadj[u]);
                 const uint64_t bal = __ballot(changed && p == 0);
 #pragma unroll
@@ -846,7 +843,7 @@ __global__ __launch_bounds__(256) void k_sweep_light(
             bool changed = false;
             if (i < nw)
                 changed = sweep_row<G, DW, KIND>(fr.W[i], xadj, adj, eh, thr, ntv, x, A, B, Lcur, Lnext, blk,
-                                                 heavy_deg, P, PW, first, false, lane, p, my_vis);
+                                                 fullblk, heavy_deg, P, PW, first, false, lane, p, my_vis);
             if (changed && p == 0) {
                 my_cnt += 1;
                 my_sum += (unsigned long long)(rxadj[fr.W[i] + 1] - rxadj[fr.W[i]]);
@@ -880,7 +877,7 @@ __global__ __launch_bounds__(256) void k_sweep_rows64(
     uint32_t gate_thresh, uint32_t* __restrict__ cnt_out, unsigned long long* __restrict__ vis_out,
     const unsigned long long* __restrict__ sgate, unsigned long long* __restrict__ sum_out,
     const int64_t* __restrict__ rxadj, int64_t n, int64_t m, int P, int PW, int64_t heavy_deg, int first, Frontier fr,
-    int parity) {
+    int parity, const uint32_t* __restrict__ fullblk) {
     __shared__ unsigned long long sh64[4];
     __shared__ uint32_t sh32[4];
     __shared__ uint32_t s_off[4][33];
@@ -912,11 +909,8 @@ __global__ __launch_bounds__(256) void k_sweep_rows64(
                 ee = eb;  // split row: handled by the piece kernels
             } else {
                 inL = !first && bit_of(Lcur, u) != 0u;
-                if (BLK && ee > eb) {
-                    bool all = true;
-                    for (int w = 0; w < 4 * PW; ++w) all = all && (blk[u * 4 * PW + w] | ~plane_valid_mask(w, P, PW)) == 0xFFFFFFFFu;
-                    if (all) ee = eb;  // blocked in every sample: cannot change, never in L
-                }
+                // blocked in every sample: cannot change, never in L
+                if (BLK && ee > eb && bit_of(fullblk, u)) ee = eb;
             }
         }
         uint32_t total;
@@ -1106,7 +1100,8 @@ __global__ __launch_bounds__(256) void k_sweep_heavy(
     uint32_t gate_thresh, unsigned long long* __restrict__ vis_out, const int32_t* __restrict__ hrow,
     const int32_t* __restrict__ prow, const int64_t* __restrict__ pe0, const int64_t* __restrict__ pe1,
     uint32_t* __restrict__ part, uint32_t* __restrict__ part_any, int64_t npieces, int64_t n, int P, int PW,
-    int first, Frontier fr, int parity, const unsigned long long* __restrict__ sgate, int64_t m) {
+    int first, Frontier fr, int parity, const unsigned long long* __restrict__ sgate, int64_t m,
+    const uint32_t* __restrict__ fullblk) {
     __shared__ unsigned long long sh64[4];
     const uint32_t live = sweep_live(gate, gate_thresh, first, n);
     if (!live) return;
@@ -1122,29 +1117,22 @@ __global__ __launch_bounds__(256) void k_sweep_heavy(
         const int64_t i = base + grp;
         if (i >= count) continue;
         const int64_t pc = sparse ? (int64_t)fr.HP[i] : i;
-        const int64_t u = hrow[prow[pc]];
-        bool skip = false;
-        if (blk) {
-            bool none = true;
-#pragma unroll
-            for (int k = 0; k < DW; ++k) {
-                const int q = k * G + p;
-                if (q < P) none = none && unblocked_mask(blk, u, q, PW) == 0u;
-            }
-            skip = group_all<G>(none);
-        }
+        const bool skip = fullblk && bit_of(fullblk, hrow[prow[pc]]) != 0u;
         Acc acc[DW];
 #pragma unroll
         for (int k = 0; k < DW; ++k) acc[k].e = acc[k].o = 0u;
         uint32_t vis = 0;
         if (!skip) vis = merge_edges<G, DW, KIND>(pe0[pc], pe1[pc], adj, eh, thr, ntv, A, Lcur, first, P, lane, p, x, acc);
+        // vis is uniform over the group; a partial without live edges is never read
+        if (vis > 0) {
 #pragma unroll
-        for (int k = 0; k < DW; ++k) {
-            const int q = k * G + p;
-            if (q < P) part[pc * P + q] = acc[k].e | acc[k].o;
+            for (int k = 0; k < DW; ++k) {
+                const int q = k * G + p;
+                if (q < P) part[pc * P + q] = acc[k].e | acc[k].o;
+            }
         }
         if (p == 0) {
-            part_any[pc] = vis > 0 ? 1u : 0u;
+            part_any[pc] = vis > 0 ? fr.stamp : 0u;
             my_vis += vis;
         }
     }
@@ -1152,7 +1140,8 @@ __global__ __launch_bounds__(256) void k_sweep_heavy(
     if (threadIdx.x == 0 && bv) atomicAdd(&vis_out[(blockIdx.x % NSLOT) * SLOT_U64], bv);
 }
 
-// One G-lane group per split row: combine its pieces with its own row.
+// One G-lane group per split row: combine the pieces merged in this sweep
+// (flag == stamp) with the row itself.
 template <int G, int DW>
 __global__ __launch_bounds__(256) void k_sweep_heavy_fix(
     const uint32_t* __restrict__ A, uint32_t* __restrict__ B, const uint32_t* __restrict__ Lcur,
@@ -1161,59 +1150,76 @@ __global__ __launch_bounds__(256) void k_sweep_heavy_fix(
     const int64_t* __restrict__ hpb, const int64_t* __restrict__ hpn, const uint32_t* __restrict__ part,
     const uint32_t* __restrict__ part_any, int64_t nheavy, int64_t n, int P, int PW, int first, Frontier fr,
     int parity, const unsigned long long* __restrict__ sgate, unsigned long long* __restrict__ sum_out,
-    const int64_t* __restrict__ rxadj, int64_t m) {
+    const int64_t* __restrict__ rxadj, int64_t m, const uint32_t* __restrict__ fullblk) {
     __shared__ uint32_t sh32[4];
     __shared__ unsigned long long sh64[4];
     const uint32_t live = sweep_live(gate, gate_thresh, first, n);
     if (!live) return;
     const bool sparse = sweep_sparse(sgate, first, m, fr.sparse_div);
-    unsigned long long my_sum = 0;
     const int64_t count = sparse ? (int64_t)fr.counts[4 * parity + 2] : nheavy;
+    const uint32_t stamp = fr.stamp;
     constexpr int RPW = 64 / G;
     const int lane = threadIdx.x & 63, grp = lane / G, p = lane % G;
     uint32_t my_cnt = 0;
+    unsigned long long my_sum = 0;
     for (int64_t base = wave_index() * RPW; base < count; base += wave_count() * RPW) {
         const int64_t i = base + grp;
         if (i >= count) continue;
         const int64_t r = sparse ? (int64_t)fr.HW[i] : i;
         const int64_t u = hrow[r];
+        if (fullblk && bit_of(fullblk, u)) continue;
         const bool inL = first ? false : bit_of(Lcur, u) != 0;
         uint32_t ub[DW];
-        bool none = true;
 #pragma unroll
         for (int k = 0; k < DW; ++k) {
             const int q = k * G + p;
-            ub[k] = 0xFFFFFFFFu;
-            if (blk && q < P) {
-                ub[k] = unblocked_mask(blk, u, q, PW);
-                none = none && ub[k] == 0u;
-            }
+            ub[k] = (blk && q < P) ? unblocked_mask(blk, u, q, PW) : 0xFFFFFFFFu;
         }
-        if (blk && group_all<G>(none)) continue;
-        const int64_t pb = hpb[r], pe = pb + hpn[r];
+        const int64_t pb = hpb[r], np = hpn[r];
         uint32_t acc[DW];
-        uint32_t any = 0;
+        bool any = false;
 #pragma unroll
         for (int k = 0; k < DW; ++k) acc[k] = 0u;
-        // 8 pieces per step: the tail repeats the last piece (max is idempotent)
-        for (int64_t p0 = pb; p0 < pe; p0 += 8) {
-            uint32_t pv[8][DW], pa[8];
+        if constexpr (G == 64) {
+            // 64 piece flags per load; the pieces of this sweep are merged 8 at a time
+            for (int64_t c0 = 0; c0 < np; c0 += 64) {
+                const bool hit = c0 + lane < np && part_any[pb + c0 + lane] == stamp;
+                uint64_t mask = __ballot(hit);
+                any = any || mask != 0ull;
+                while (mask) {
+                    int idx[8];
+                    int last = __builtin_ctzll(mask);
 #pragma unroll
-            for (int j = 0; j < 8; ++j) {
-                const int64_t pc = p0 + j < pe ? p0 + j : pe - 1;
-                pa[j] = part_any[pc];
+                    for (int b = 0; b < 8; ++b) {
+                        if (mask) last = __builtin_ctzll(mask);
+                        idx[b] = last;
+                        mask &= mask - 1;
+                    }
+                    uint32_t pv[8][DW];
+#pragma unroll
+                    for (int b = 0; b < 8; ++b) {
+#pragma unroll
+                        for (int k = 0; k < DW; ++k) {
+                            const int q = k * 64 + lane;
+                            pv[b][k] = part[(pb + c0 + idx[b]) * P + (q < P ? q : P - 1)];
+                        }
+                    }
+                    __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+                    for (int b = 0; b < 8; ++b)
+#pragma unroll
+                        for (int k = 0; k < DW; ++k) acc[k] = byte_max(acc[k], pv[b][k]);
+                }
+            }
+        } else {
+            for (int64_t c = 0; c < np; ++c) {
+                if (part_any[pb + c] != stamp) continue;
+                any = true;
 #pragma unroll
                 for (int k = 0; k < DW; ++k) {
                     const int q = k * G + p;
-                    pv[j][k] = part[pc * P + (q < P ? q : P - 1)];
+                    if (q < P) acc[k] = byte_max(acc[k], part[(pb + c) * P + q]);
                 }
-            }
-            __builtin_amdgcn_sched_barrier(0);
-#pragma unroll
-            for (int j = 0; j < 8; ++j) {
-                any |= pa[j];
-#pragma unroll
-                for (int k = 0; k < DW; ++k) acc[k] = byte_max(acc[k], pv[j][k]);
             }
         }
         if (!any && !inL) continue;
@@ -1271,9 +1277,9 @@ hipError_t launch_sweep(const Layout& L, const DevGraph& g, const uint32_t* X, c
     const int lg = grid > 0 ? grid : grid_for_rows(words);
     const int sg = 2048;  // grid of the list kernels
     hipLaunchKernelGGL(k_sweep_frontier, dim3(sg), dim3(256), 0, s, sp.gate, sp.gate_thresh, sp.sgate, g.m, sp.first,
-                       g.n, sp.Lcur, sp.Lclear, sp.fr, sp.parity, g.rxadj, g.hslot, g.hpb, g.hpn);
+                       g.n, sp.Lcur, sp.Lclear, sp.fr, sp.parity, g.rxadj, g.hslot);
     hipLaunchKernelGGL(k_sweep_expand, dim3(sg), dim3(256), 0, s, sp.gate, sp.gate_thresh, sp.sgate, g.m, sp.first, g.n,
-                       sp.fr, sp.parity, g.rxadj, g.radj, g.hslot, g.hpb, g.hpn);
+                       sp.fr, sp.parity, g.rxadj, g.radj, g.rpiece, g.hslot);
     hipError_t err = hipGetLastError();
     if (err != hipSuccess) return err;
     if (ev0) (void)hipEventRecord(ev0, s);
@@ -1286,7 +1292,7 @@ hipError_t launch_sweep(const Layout& L, const DevGraph& g, const uint32_t* X, c
                                                                         sp.blk, sp.gate, sp.gate_thresh, sp.cnt_out,  \
                                                                         sp.vis_out, sp.sgate, sp.sum_out, g.rxadj,    \
                                                                         g.n, g.m, L.P, L.PW, g.heavy_deg, sp.first,   \
-                                                                        sp.fr, sp.parity)))
+                                                                        sp.fr, sp.parity, sp.fullblk)))
         if (sp.blk)
             HFR_ROWS64(true);
         else
@@ -1299,7 +1305,8 @@ hipError_t launch_sweep(const Layout& L, const DevGraph& g, const uint32_t* X, c
                                                                             sp.Lnext, sp.blk, sp.gate, sp.gate_thresh,
                                                                             sp.cnt_out, sp.vis_out, sp.sgate,
                                                                             sp.sum_out, g.rxadj, g.n, g.m, L.P, L.PW,
-                                                                            g.heavy_deg, sp.first, sp.fr, sp.parity)));
+                                                                            g.heavy_deg, sp.first, sp.fr, sp.parity,
+                                                                            sp.fullblk)));
     }
     if (ev1) (void)hipEventRecord(ev1, s);
     err = hipGetLastError();
@@ -1315,7 +1322,7 @@ hipError_t launch_sweep(const Layout& L, const DevGraph& g, const uint32_t* X, c
                                                                             sp.vis_heavy_out, g.hrow, g.prow, g.pe0,
                                                                             g.pe1, sp.part, sp.part_any, g.npieces,
                                                                             g.n, L.P, L.PW, sp.first, sp.fr,
-                                                                            sp.parity, sp.sgate, g.m)));
+                                                                            sp.parity, sp.sgate, g.m, sp.fullblk)));
         err = hipGetLastError();
         if (err != hipSuccess) return err;
         if (ev3) (void)hipEventRecord(ev3, s);
@@ -1324,7 +1331,7 @@ hipError_t launch_sweep(const Layout& L, const DevGraph& g, const uint32_t* X, c
                                                   sp.Lcur, sp.Lnext, sp.blk, sp.gate, sp.gate_thresh, sp.cnt_out,
                                                   g.hrow, g.hpb, g.hpn, sp.part, sp.part_any, g.nheavy, g.n, L.P,
                                                   L.PW, sp.first, sp.fr, sp.parity, sp.sgate, sp.sum_out, g.rxadj,
-                                                  g.m));
+                                                  g.m, sp.fullblk));
         err = hipGetLastError();
         if (err != hipSuccess) return err;
     } else if (ev3) {
@@ -1390,14 +1397,18 @@ __global__ void k_scan_apply(const uint32_t* __restrict__ in, int64_t n, const i
 // radj[cursor[v]++] = u for every edge (u, v); the order inside an in-row
 // depends on scheduling, the set does not.
 __global__ void k_rev_scatter(const int64_t* __restrict__ xadj, const int32_t* __restrict__ adj, int64_t n,
-                              int64_t* cursor, int32_t* radj) {
+                              int64_t* cursor, int32_t* radj, int32_t* rpiece, const int32_t* __restrict__ hslot,
+                              const int64_t* __restrict__ hpb, int64_t piece) {
     const int lane = threadIdx.x & 63;
     for (int64_t u = wave_index(); u < n; u += wave_count()) {
         const int64_t eb = xadj[u], ee = xadj[u + 1];
+        const int32_t r = hslot[u];
+        const int64_t base = r >= 0 ? hpb[r] : 0;
         for (int64_t e = eb + lane; e < ee; e += 64) {
             const int32_t v = adj[e];
             const unsigned long long pos = atomicAdd((unsigned long long*)&cursor[v], 1ull);
             radj[pos] = (int32_t)u;
+            rpiece[pos] = r >= 0 ? (int32_t)(base + (e - eb) / piece) : -1;
         }
     }
 }
@@ -1416,7 +1427,31 @@ hipError_t launch_reverse_csr(const DevGraph& g, const uint32_t* indeg, int64_t*
     hipLaunchKernelGGL(k_scan_sums, dim3(1), dim3(64), 0, s, sums, nb);
     hipLaunchKernelGGL(k_scan_apply, dim3((unsigned)nb), dim3(256), 0, s, indeg, n, sums, g.rxadj);
     hipLaunchKernelGGL(k_copy_i64, dim3(4096), dim3(256), 0, s, g.rxadj, cursor, n);
-    if (g.m > 0) hipLaunchKernelGGL(k_rev_scatter, dim3(8192), dim3(256), 0, s, g.xadj, g.adj, n, cursor, g.radj);
+    if (g.m > 0)
+        hipLaunchKernelGGL(k_rev_scatter, dim3(8192), dim3(256), 0, s, g.xadj, g.adj, n, cursor, g.radj, g.rpiece,
+                           g.hslot, g.hpb, g.piece_edges);
+    return hipGetLastError();
+}
+
+// fullblk bit u = 1 iff vertex u is blocked in every sample.
+__global__ void k_full_blocked(const uint32_t* __restrict__ blk, uint32_t* fullblk, int64_t n, int P, int PW) {
+    const int64_t nwords = (n + 31) / 32;
+    const int W = 4 * PW;
+    for (int64_t w = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; w < nwords; w += (int64_t)gridDim.x * blockDim.x) {
+        uint32_t bits = 0;
+        for (int j = 0; j < 32; ++j) {
+            const int64_t u = w * 32 + j;
+            if (u >= n) break;
+            bool all = true;
+            for (int k = 0; k < W && all; ++k) all = (blk[u * W + k] | ~plane_valid_mask(k, P, PW)) == 0xFFFFFFFFu;
+            if (all) bits |= 1u << j;
+        }
+        fullblk[w] = bits;
+    }
+}
+
+hipError_t launch_full_blocked(const Layout& L, int64_t n, const uint32_t* blk, uint32_t* fullblk, hipStream_t s) {
+    hipLaunchKernelGGL(k_full_blocked, dim3(2048), dim3(256), 0, s, blk, fullblk, n, L.P, L.PW);
     return hipGetLastError();
 }
 
