@@ -23,6 +23,13 @@
 #include <stddef.h>
 #include <stdint.h>
 
+/* Entry points are the only symbols the shared library exports. */
+#if defined(__GNUC__)
+#define IM_API __attribute__((visibility("default")))
+#else
+#define IM_API
+#endif
+
 #ifdef __cplusplus
 extern "C" {
 #endif
@@ -139,14 +146,14 @@ typedef void (*im_free_fn)(void* ptr, void* user);
 /* Creates a context on HIP device `device`.  `stream` is a hipStream_t (NULL =
  * the null stream) that must outlive the context.  hbm_budget bounds the
  * device bytes all sketches of this context may hold (0 = no bound). */
-im_status im_ctx_create(int32_t device, void* stream, size_t hbm_budget, im_alloc_fn alloc, im_free_fn dealloc,
+IM_API im_status im_ctx_create(int32_t device, void* stream, size_t hbm_budget, im_alloc_fn alloc, im_free_fn dealloc,
                         void* user, im_ctx** out);
-void im_ctx_free(im_ctx* ctx);
+IM_API void im_ctx_free(im_ctx* ctx);
 /* Device bytes currently held by sketches of the context. */
-size_t im_ctx_bytes_in_use(const im_ctx* ctx);
+IM_API size_t im_ctx_bytes_in_use(const im_ctx* ctx);
 
 /* Device bytes a sketch of this shape would hold (for admission by budget). */
-size_t im_sketch_bytes_needed(int64_t n, int64_t m, int32_t R, im_prob_kind kind);
+IM_API size_t im_sketch_bytes_needed(int64_t n, int64_t m, int32_t R, im_prob_kind kind);
 
 /*
  * Builds the per-vertex sketches (Alg. 1 initialisation and Alg. 2 Simulate).
@@ -158,7 +165,7 @@ size_t im_sketch_bytes_needed(int64_t n, int64_t m, int32_t R, im_prob_kind kind
  * hash_seed: seed of every hash.  opts may be NULL.
  * On success *out owns the graph copy and the registers.
  */
-im_status im_build_sketches(im_ctx* ctx, const im_csr* graph, const im_probs* probs, int32_t R, uint32_t hash_seed,
+IM_API im_status im_build_sketches(im_ctx* ctx, const im_csr* graph, const im_probs* probs, int32_t R, uint32_t hash_seed,
                             const im_build_opts* opts, im_sketch** out);
 
 /*
@@ -167,11 +174,11 @@ im_status im_build_sketches(im_ctx* ctx, const im_csr* graph, const im_probs* pr
  * e = 2^(mean_j max_v M_v[j]) / 0.77351, returned as binary32.  verts is a host
  * array of ids in [0, n); count >= 1.
  */
-im_status im_estimate(im_sketch* sk, const int32_t* verts, int64_t count, float* out_estimate);
+IM_API im_status im_estimate(im_sketch* sk, const int32_t* verts, int64_t count, float* out_estimate);
 
 /* Per-vertex estimates of the build's registers: out[v] = Estimate(M_v) as
  * binary32.  out holds n floats; out_on_device selects a device pointer. */
-im_status im_estimate_all(im_sketch* sk, float* out, int32_t out_on_device);
+IM_API im_status im_estimate_all(im_sketch* sk, float* out, int32_t out_on_device);
 
 /*
  * Greedy seed selection with error-adaptive rebuild (Alg. 1).  Starts from the
@@ -180,14 +187,14 @@ im_status im_estimate_all(im_sketch* sk, float* out, int32_t out_on_device);
  * out_seeds: K ids.  out_steps: K records or NULL.  stats may be NULL.
  * opts NULL selects eps_g = 0.01, eps_l = 0.3.
  */
-im_status im_select_seeds(im_sketch* sk, int32_t K, const im_select_opts* opts, int32_t* out_seeds,
+IM_API im_status im_select_seeds(im_sketch* sk, int32_t K, const im_select_opts* opts, int32_t* out_seeds,
                           im_step* out_steps, im_select_stats* stats);
 
 /* Build information; trace of the build: live_counts[t] = |L_t| (t = 0..sweeps)
  * and edge_visits[t] = edges with a live head in sweep t (t < sweeps); cap
  * bounds both arrays; *written receives sweeps+1. */
-im_status im_sketch_get_info(const im_sketch* sk, im_sketch_info* info);
-im_status im_sketch_get_trace(const im_sketch* sk, int64_t* live_counts, int64_t* edge_visits, int32_t cap,
+IM_API im_status im_sketch_get_info(const im_sketch* sk, im_sketch_info* info);
+IM_API im_status im_sketch_get_trace(const im_sketch* sk, int64_t* live_counts, int64_t* edge_visits, int32_t cap,
                               int32_t* written);
 
 /* One sweep, recorded when the build was asked to time sweeps
@@ -214,25 +221,25 @@ typedef struct im_sweep_rec {
 } im_sweep_rec;
 
 /* Copies up to cap records of the sweep log; returns the number copied. */
-int32_t im_sketch_get_sweep_log(const im_sketch* sk, im_sweep_rec* out, int32_t cap);
-void im_sketch_clear_sweep_log(im_sketch* sk);
+IM_API int32_t im_sketch_get_sweep_log(const im_sketch* sk, im_sweep_rec* out, int32_t cap);
+IM_API void im_sketch_clear_sweep_log(im_sketch* sk);
 
 /* Copies registers to the host, n*R bytes, vertex-major (R registers of a
  * vertex adjacent).  which = 0: registers of the build; which = 1: registers
  * in force at the end of the last im_select_seeds. */
-im_status im_sketch_get_registers(const im_sketch* sk, int32_t which, uint8_t* out);
+IM_API im_status im_sketch_get_registers(const im_sketch* sk, int32_t which, uint8_t* out);
 
 /* Copies the blocked pairs of the last im_select_seeds (the reach of S in
  * every sample) to the host as n*R bytes (1 = blocked). */
-im_status im_sketch_get_blocked(const im_sketch* sk, uint8_t* out);
+IM_API im_status im_sketch_get_blocked(const im_sketch* sk, uint8_t* out);
 
-void im_sketch_free(im_sketch* sk);
+IM_API void im_sketch_free(im_sketch* sk);
 
 /* Thread-local message of the last failed call on this thread ("" if none). */
-const char* im_last_error(void);
+IM_API const char* im_last_error(void);
 
 /* Library version string. */
-const char* im_version(void);
+IM_API const char* im_version(void);
 
 #ifdef __cplusplus
 }

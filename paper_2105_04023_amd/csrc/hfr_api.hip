@@ -21,12 +21,11 @@
 #include <string>
 #include <vector>
 
-#include "../../include/im.h"
-#include "hfr_internal.h"
+#include "hfr_host.h"
 
 using namespace hfr;
 
-namespace {
+namespace hfr {
 
 thread_local std::string g_last_error;
 
@@ -40,6 +39,31 @@ im_status fail(im_status st, const char* fmt, ...) {
     return st;
 }
 
+void* ctx_alloc(im_ctx* c, size_t bytes) {
+    bytes = (bytes + 255) & ~size_t(255);
+    if (bytes == 0) bytes = 256;
+    void* p = nullptr;
+    if (c->af) {
+        p = c->af(bytes, c->user);
+    } else if (hipMalloc(&p, bytes) != hipSuccess) {
+        (void)hipGetLastError();
+        p = nullptr;
+    }
+    return p;
+}
+
+void ctx_free(im_ctx* c, void* p) {
+    if (!p) return;
+    if (c->ff)
+        c->ff(p, c->user);
+    else
+        (void)hipFree(p);
+}
+
+}  // namespace hfr
+
+namespace {
+
 constexpr int RING = 256;         // sweeps held by the counter ring
 constexpr int MAX_BATCH = 64;     // sweeps per batch
 constexpr int DEFAULT_HEAVY = 32;
@@ -48,16 +72,6 @@ constexpr int BFS_CHUNK = 256;
 constexpr int SWEEP_TIMERS = 6 * RING;
 
 }  // namespace
-
-struct im_ctx {
-    int device = 0;
-    hipStream_t stream = nullptr;
-    size_t budget = 0;
-    size_t in_use = 0;
-    im_alloc_fn af = nullptr;
-    im_free_fn ff = nullptr;
-    void* user = nullptr;
-};
 
 struct DevBuf {
     void* p;
@@ -116,27 +130,6 @@ struct im_sketch {
 };
 
 namespace {
-
-void* ctx_alloc(im_ctx* c, size_t bytes) {
-    bytes = (bytes + 255) & ~size_t(255);
-    if (bytes == 0) bytes = 256;
-    void* p = nullptr;
-    if (c->af) {
-        p = c->af(bytes, c->user);
-    } else if (hipMalloc(&p, bytes) != hipSuccess) {
-        (void)hipGetLastError();
-        p = nullptr;
-    }
-    return p;
-}
-
-void ctx_free(im_ctx* c, void* p) {
-    if (!p) return;
-    if (c->ff)
-        c->ff(p, c->user);
-    else
-        (void)hipFree(p);
-}
 
 template <typename T>
 bool sk_alloc(im_sketch* sk, T** out, size_t count) {
@@ -438,7 +431,7 @@ im_status check_sketch(const im_sketch* sk) {
 
 extern "C" {
 
-const char* im_last_error(void) { return g_last_error.c_str(); }
+const char* im_last_error(void) { return hfr::g_last_error.c_str(); }
 
 const char* im_version(void) { return "hipfuser 0.1 (gfx950)"; }
 

@@ -14,146 +14,10 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include "hfr_device.h"
 #include "hfr_internal.h"
 
 namespace hfr {
-
-#define DEVI __device__ __forceinline__
-
-// ----------------------------------------------------------------------------
-// MurmurHash3 x86_32 for 4- and 8-byte keys (public-domain algorithm).
-// ----------------------------------------------------------------------------
-DEVI uint32_t rotl32(uint32_t x, int r) { return (x << r) | (x >> (32 - r)); }
-DEVI uint32_t mm3_round(uint32_t h, uint32_t k) {
-    k *= 0xcc9e2d51u;
-    k = rotl32(k, 15);
-    k *= 0x1b873593u;
-    h ^= k;
-    h = rotl32(h, 13);
-    return h * 5u + 0xe6546b64u;
-}
-DEVI uint32_t mm3_tail(uint32_t h, uint32_t len) {
-    h ^= len;
-    h ^= h >> 16;
-    h *= 0x85ebca6bu;
-    h ^= h >> 13;
-    h *= 0xc2b2ae35u;
-    h ^= h >> 16;
-    return h;
-}
-DEVI uint32_t mm3_key4(uint32_t a, uint32_t seed) { return mm3_tail(mm3_round(seed, a), 4u); }
-DEVI uint32_t mm3_key8(uint32_t a, uint32_t b, uint32_t seed) { return mm3_tail(mm3_round(mm3_round(seed, a), b), 8u); }
-
-DEVI uint32_t lead_zeros(uint32_t x) { return x == 0u ? 32u : (uint32_t)__builtin_clz(x); }
-
-// ----------------------------------------------------------------------------
-// Packed byte helpers (register values are <= 32).
-// ----------------------------------------------------------------------------
-typedef unsigned short u16x2 __attribute__((ext_vector_type(2)));
-
-DEVI uint32_t pk_max16(uint32_t a, uint32_t b) {
-    u16x2 x = __builtin_bit_cast(u16x2, a);
-    u16x2 y = __builtin_bit_cast(u16x2, b);
-    return __builtin_bit_cast(uint32_t, __builtin_elementwise_max(x, y));
-}
-
-// Byte-wise max of two packed dwords.
-DEVI uint32_t byte_max(uint32_t a, uint32_t b) {
-    return pk_max16(a & 0x00FF00FFu, b & 0x00FF00FFu) | pk_max16(a & 0xFF00FF00u, b & 0xFF00FF00u);
-}
-
-// Accumulator of merged registers split into even bytes (0, 2) and odd bytes
-// (1, 3) so that one v_pk_max_u16 merges two registers.
-struct Acc {
-    uint32_t e, o;
-};
-
-// Merge neighbour dword d into acc for the simulations whose edge is live.
-// Simulation k of this dword is live iff (x_k xor hh) < thr; both sides are
-// below 2^31, so the sign bit of (x_k xor hh) - thr is the live bit.  v_perm
-// selectors 9 and 11 replicate bit 31 of the low / high source into a byte.
-DEVI void merge_live(Acc& acc, uint32_t d, uint32_t x0, uint32_t x1, uint32_t x2, uint32_t x3, uint32_t hh,
-                     uint32_t negthr) {
-    uint32_t s0 = (x0 ^ hh) + negthr;
-    uint32_t s1 = (x1 ^ hh) + negthr;
-    uint32_t s2 = (x2 ^ hh) + negthr;
-    uint32_t s3 = (x3 ^ hh) + negthr;
-    uint32_t me = __builtin_amdgcn_perm(s2, s0, 0x0C0B0C09u);  // bytes 0, 2
-    uint32_t mo = __builtin_amdgcn_perm(s3, s1, 0x0B0C090Cu);  // bytes 1, 3
-    acc.e = pk_max16(acc.e, d & me);
-    acc.o = pk_max16(acc.o, d & mo);
-}
-
-// Max of row dword a with an accumulator.
-DEVI uint32_t acc_max(uint32_t a, const Acc& acc) {
-    return pk_max16(a & 0x00FF00FFu, acc.e) | pk_max16(a & 0xFF00FF00u, acc.o);
-}
-
-DEVI uint32_t bit_of(const uint32_t* __restrict__ bm, int64_t v) { return (bm[v >> 5] >> (v & 31)) & 1u; }
-
-// Byte mask of the unblocked registers of dword q of vertex u.
-DEVI uint32_t unblocked_mask(const uint32_t* __restrict__ blk, int64_t u, int q, int PW) {
-    const uint32_t* b = blk + u * 4 * PW + (q >> 5);
-    const int s = q & 31;
-    uint32_t m = 0;
-#pragma unroll
-    for (int k = 0; k < 4; ++k) m |= (((b[k * PW] >> s) & 1u) ? 0u : 0xFFu) << (8 * k);
-    return m;
-}
-
-DEVI uint32_t plane_valid_mask(int w, int P, int PW) {
-    const int ww = w % PW;  // word within the plane
-    const int left = P - 32 * ww;
-    return left >= 32 ? 0xFFFFFFFFu : (left <= 0 ? 0u : ((1u << left) - 1u));
-}
-
-template <typename T>
-DEVI T wave_sum(T v) {
-#pragma unroll
-    for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
-    return v;
-}
-
-// Sum over the 256 threads of a block; result valid in thread 0.
-template <typename T>
-DEVI T block_sum256(T v, T* sh) {
-    v = wave_sum(v);
-    const int w = threadIdx.x >> 6;
-    if ((threadIdx.x & 63) == 0) sh[w] = v;
-    __syncthreads();
-    T r = 0;
-    if (threadIdx.x == 0) r = sh[0] + sh[1] + sh[2] + sh[3];
-    __syncthreads();
-    return r;
-}
-
-// True if any lane of this lane's G-lane group has `c` set.
-template <int G>
-DEVI bool group_any(bool c) {
-    const uint64_t b = __ballot(c);
-    if constexpr (G == 64) {
-        return b != 0;
-    } else {
-        const int grp = (threadIdx.x & 63) / G;
-        return ((b >> (grp * G)) & ((1ull << G) - 1)) != 0;
-    }
-}
-
-template <int G>
-DEVI bool group_all(bool c) {
-    return !group_any<G>(!c);
-}
-
-DEVI int64_t wave_index() { return __builtin_amdgcn_readfirstlane((int)((blockIdx.x * blockDim.x + threadIdx.x) >> 6)); }
-DEVI int64_t wave_count() { return (int64_t)(gridDim.x * blockDim.x) >> 6; }
-
-DEVI uint32_t gate_sum(const uint32_t* __restrict__ gate) {
-    uint32_t s = 0;
-#pragma unroll
-    for (int i = 0; i < NSLOT; ++i) s += gate[i * SLOT_U32];
-    return s;
-}
-
 
 // ----------------------------------------------------------------------------
 // Utilities and graph preparation.
@@ -218,22 +82,9 @@ hipError_t launch_indegree(const DevGraph& g, uint32_t* indeg, hipStream_t s) {
     return hipGetLastError();
 }
 
-// Weighted cascade (Sec. 2.1): w_uv = 1/d_v as the binary32 quotient
-// 1.0f / (float)d_v.  For an integer-valued binary32 divisor below 2^24 in
-// mantissa, the double quotient rounded to binary32 equals the correctly
-// rounded binary32 quotient (its binary expansion has no run of 28 equal
-// bits), so the double route is exact.
 __global__ void k_wc_thresholds(const uint32_t* __restrict__ indeg, uint32_t* thr, int64_t n) {
-    for (int64_t v = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; v < n; v += (int64_t)gridDim.x * blockDim.x) {
-        const uint32_t d = indeg[v];
-        if (d == 0) {
-            thr[v] = 0;
-            continue;
-        }
-        const float df = (float)d;
-        const float w = (float)(1.0 / (double)df);
-        thr[v] = live_threshold(w);
-    }
+    for (int64_t v = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; v < n; v += (int64_t)gridDim.x * blockDim.x)
+        thr[v] = wc_threshold(indeg[v]);
 }
 
 hipError_t launch_wc_thresholds(const uint32_t* indeg, uint32_t* thr, int64_t n, hipStream_t s) {
@@ -456,126 +307,6 @@ hipError_t launch_init(const Layout& L, int64_t n, const uint32_t* HJ, uint32_t 
 // (k_sweep_heavy) and combined by k_sweep_heavy_fix.
 // ----------------------------------------------------------------------------
 
-// Copies a wave-uniform value into a VGPR, so that v_xad_u32 can take the
-// edge hash as its single scalar operand.
-DEVI uint32_t to_vgpr(uint32_t s) {
-    uint32_t v;
-    asm volatile("v_mov_b32 %0, %1" : "=v"(v) : "s"(s));
-    return v;
-}
-
-constexpr int UB = 8;  // neighbour rows in flight per wave
-
-// G = 64 (one row per wave): the row's out-edges are read 64 at a time with
-// one coalesced load per array, the heads in L_t are found with one ballot,
-// and the rows of up to UB live heads are loaded back-to-back before they are
-// merged.  Returns the number of edges with a live head.
-template <int DW, int KIND>
-DEVI uint32_t merge_edges64(int64_t eb, int64_t ee, const int32_t* __restrict__ adj, const uint32_t* __restrict__ eh,
-                            const uint32_t* __restrict__ thr, uint32_t ntv, const uint32_t* __restrict__ A,
-                            const uint32_t* __restrict__ Lcur, int first, int P, int lane,
-                            const uint32_t (&x)[DW][4], Acc (&acc)[DW]) {
-    uint32_t vis = 0;
-    // the next window's edge ids are loaded while the current one is merged
-    bool in_n = eb + lane < ee;
-    int32_t v_n = in_n ? adj[eb + lane] : 0;
-    for (int64_t w0 = eb; w0 < ee; w0 += 64) {
-        const int64_t e = w0 + lane;
-        const bool in = in_n;
-        const int32_t v = v_n;
-        in_n = w0 + 64 + lane < ee;
-        v_n = in_n ? adj[w0 + 64 + lane] : 0;
-        const bool lv = in && (first || bit_of(Lcur, v) != 0u);
-        const uint32_t hh = in ? eh[e] : 0u;
-        uint32_t tt = 0u;
-        if constexpr (KIND == THR_TARGET) tt = in ? thr[v] : 0u;
-        if constexpr (KIND == THR_EDGE) tt = in ? thr[e] : 0u;
-        uint64_t mask = __ballot(lv);
-        vis += (uint32_t)__builtin_popcountll(mask);
-        while (mask) {
-            // up to UB live edges; unused slots repeat the last one (max-merge is
-            // idempotent), so every load is issued without a branch
-            int idx[UB];
-            int last = __builtin_ctzll(mask);
-#pragma unroll
-            for (int b = 0; b < UB; ++b) {
-                if (mask) last = __builtin_ctzll(mask);
-                idx[b] = last;
-                mask &= mask - 1;
-            }
-            // lanes past the row (q >= P) load a valid dword of it instead; their
-            // results are never stored
-            uint32_t d[UB][DW];
-#pragma unroll
-            for (int b = 0; b < UB; ++b) {
-                const int64_t vb = __builtin_amdgcn_readlane(v, idx[b]);
-                const uint32_t* __restrict__ row = A + vb * P;
-#pragma unroll
-                for (int i = 0; i < DW; ++i) {
-                    const int q = i * 64 + lane;
-                    d[b][i] = row[q < P ? q : P - 1];
-                }
-            }
-            __builtin_amdgcn_sched_barrier(0);
-#pragma unroll
-            for (int b = 0; b < UB; ++b) {
-                const uint32_t hb = (uint32_t)__builtin_amdgcn_readlane((int)hh, idx[b]);
-                uint32_t nt = ntv;
-                if constexpr (KIND != THR_CONST) nt = 0u - (uint32_t)__builtin_amdgcn_readlane((int)tt, idx[b]);
-#pragma unroll
-                for (int i = 0; i < DW; ++i) merge_live(acc[i], d[b][i], x[i][0], x[i][1], x[i][2], x[i][3], hb, nt);
-            }
-        }
-    }
-    return vis;
-}
-
-// G < 64 (several rows per wave): each G-lane group walks its own row's edges.
-template <int G, int DW, int KIND>
-DEVI uint32_t merge_edges_grp(int64_t eb, int64_t ee, const int32_t* __restrict__ adj,
-                              const uint32_t* __restrict__ eh, const uint32_t* __restrict__ thr, uint32_t ntv,
-                              const uint32_t* __restrict__ A, const uint32_t* __restrict__ Lcur, int first, int P,
-                              int p, const uint32_t (&x)[DW][4], Acc (&acc)[DW]) {
-    uint32_t vis = 0;
-    for (int64_t e = eb; e < ee; ++e) {
-        const int32_t v = adj[e];
-        if (!first && !bit_of(Lcur, v)) continue;
-        ++vis;
-        const uint32_t hh = eh[e];
-        uint32_t nt = ntv;
-        if constexpr (KIND == THR_TARGET) nt = 0u - thr[v];
-        if constexpr (KIND == THR_EDGE) nt = 0u - thr[e];
-        const uint32_t* __restrict__ row = A + (int64_t)v * P;
-#pragma unroll
-        for (int i = 0; i < DW; ++i) {
-            const int q = i * G + p;
-            if (q < P) merge_live(acc[i], row[q], x[i][0], x[i][1], x[i][2], x[i][3], hh, nt);
-        }
-    }
-    return vis;
-}
-
-template <int G, int DW, int KIND>
-DEVI uint32_t merge_edges(int64_t eb, int64_t ee, const int32_t* __restrict__ adj, const uint32_t* __restrict__ eh,
-                          const uint32_t* __restrict__ thr, uint32_t ntv, const uint32_t* __restrict__ A,
-                          const uint32_t* __restrict__ Lcur, int first, int P, int lane, int p,
-                          const uint32_t (&x)[DW][4], Acc (&acc)[DW]) {
-    if constexpr (G == 64)
-        return merge_edges64<DW, KIND>(eb, ee, adj, eh, thr, ntv, A, Lcur, first, P, lane, x, acc);
-    else
-        return merge_edges_grp<G, DW, KIND>(eb, ee, adj, eh, thr, ntv, A, Lcur, first, P, p, x, acc);
-}
-
-template <int G, int DW>
-DEVI void load_sim_words(const uint32_t* __restrict__ X, int P, int p, uint32_t (&x)[DW][4]) {
-#pragma unroll
-    for (int i = 0; i < DW; ++i) {
-        const int q = i * G + p;
-#pragma unroll
-        for (int k = 0; k < 4; ++k) x[i][k] = q < P ? X[4 * q + k] : 0u;
-    }
-}
-
 // Live count |L_t| of a running sweep, or 0 when the sweep is past the
 // stopping rule (the kernel then returns).
 DEVI uint32_t sweep_live(const uint32_t* __restrict__ gate, uint32_t gate_thresh, int first, int64_t n) {
@@ -732,65 +463,6 @@ __global__ __launch_bounds__(256) void k_sweep_cleanup(const uint32_t* __restric
     for (int64_t i = tid; i < nw; i += stride) fr.mark[fr.W[i] >> 5] = 0u;
     for (int64_t i = tid; i < nh; i += stride) fr.mark[hrow[fr.HW[i]] >> 5] = 0u;
     for (int64_t i = tid; i < np; i += stride) fr.pmark[fr.HP[i] >> 5] = 0u;
-}
-
-// Merge of one whole row (one G-lane group): returns true if it changed.
-// dense_word: the caller stores L_{t+1} words itself; otherwise the bit is set
-// atomically.
-template <int G, int DW, int KIND>
-DEVI bool sweep_row(int64_t u, const int64_t* __restrict__ xadj, const int32_t* __restrict__ adj,
-                    const uint32_t* __restrict__ eh, const uint32_t* __restrict__ thr, uint32_t ntv,
-                    const uint32_t (&x)[DW][4], const uint32_t* __restrict__ A, uint32_t* __restrict__ B,
-                    const uint32_t* __restrict__ Lcur, uint32_t* __restrict__ Lnext, const uint32_t* __restrict__ blk,
-                    const uint32_t* __restrict__ fullblk, int64_t heavy_deg, int P, int PW, int first,
-                    bool dense_word, int lane, int p, unsigned long long& my_vis) {
-    const int64_t eb = xadj[u], ee = xadj[u + 1];
-    const bool inL = first ? false : bit_of(Lcur, u) != 0;
-    bool active = ee - eb <= heavy_deg && (ee > eb || inL) && !(fullblk && bit_of(fullblk, u));
-    uint32_t ub[DW];
-#pragma unroll
-    for (int i = 0; i < DW; ++i) ub[i] = 0xFFFFFFFFu;
-    if (active && blk) {
-        bool none = true;
-#pragma unroll
-        for (int i = 0; i < DW; ++i) {
-            const int q = i * G + p;
-            if (q < P) {
-                ub[i] = unblocked_mask(blk, u, q, PW);
-                none = none && ub[i] == 0u;
-            }
-        }
-        active = !group_all<G>(none);
-    }
-    if (!active) return false;
-    Acc acc[DW];
-#pragma unroll
-    for (int i = 0; i < DW; ++i) acc[i].e = acc[i].o = 0u;
-    const uint32_t vis = merge_edges<G, DW, KIND>(eb, ee, adj, eh, thr, ntv, A, Lcur, first, P, lane, p, x, acc);
-    if (p == 0) my_vis += vis;
-    if (vis == 0 && !inL) return false;
-    bool ch = false;
-    uint32_t nw[DW];
-#pragma unroll
-    for (int i = 0; i < DW; ++i) {
-        const int q = i * G + p;
-        nw[i] = 0;
-        if (q < P) {
-            const uint32_t a = A[u * P + q];
-            nw[i] = acc_max(a, acc[i]) & ub[i];
-            ch = ch || nw[i] != a;
-        }
-    }
-    const bool changed = group_any<G>(ch);
-    if (changed || inL) {
-#pragma unroll
-        for (int i = 0; i < DW; ++i) {
-            const int q = i * G + p;
-            if (q < P) B[u * P + q] = nw[i];
-        }
-    }
-    if (changed && !dense_word && p == 0) atomicOr(&Lnext[u >> 5], 1u << (u & 31));
-    return changed;
 }
 
 template <int G, int DW, int KIND>
@@ -1168,81 +840,8 @@ __global__ __launch_bounds__(256) void k_sweep_heavy_fix(
         const int64_t r = sparse ? (int64_t)fr.HW[i] : i;
         const int64_t u = hrow[r];
         if (fullblk && bit_of(fullblk, u)) continue;
-        const bool inL = first ? false : bit_of(Lcur, u) != 0;
-        uint32_t ub[DW];
-#pragma unroll
-        for (int k = 0; k < DW; ++k) {
-            const int q = k * G + p;
-            ub[k] = (blk && q < P) ? unblocked_mask(blk, u, q, PW) : 0xFFFFFFFFu;
-        }
-        const int64_t pb = hpb[r], np = hpn[r];
-        uint32_t acc[DW];
-        bool any = false;
-#pragma unroll
-        for (int k = 0; k < DW; ++k) acc[k] = 0u;
-        if constexpr (G == 64) {
-            // 64 piece flags per load; the pieces of this sweep are merged 8 at a time
-            for (int64_t c0 = 0; c0 < np; c0 += 64) {
-                const bool hit = c0 + lane < np && part_any[pb + c0 + lane] == stamp;
-                uint64_t mask = __ballot(hit);
-                any = any || mask != 0ull;
-                while (mask) {
-                    int idx[8];
-                    int last = __builtin_ctzll(mask);
-#pragma unroll
-                    for (int b = 0; b < 8; ++b) {
-                        if (mask) last = __builtin_ctzll(mask);
-                        idx[b] = last;
-                        mask &= mask - 1;
-                    }
-                    uint32_t pv[8][DW];
-#pragma unroll
-                    for (int b = 0; b < 8; ++b) {
-#pragma unroll
-                        for (int k = 0; k < DW; ++k) {
-                            const int q = k * 64 + lane;
-                            pv[b][k] = part[(pb + c0 + idx[b]) * P + (q < P ? q : P - 1)];
-                        }
-                    }
-                    __builtin_amdgcn_sched_barrier(0);
-#pragma unroll
-                    for (int b = 0; b < 8; ++b)
-#pragma unroll
-                        for (int k = 0; k < DW; ++k) acc[k] = byte_max(acc[k], pv[b][k]);
-                }
-            }
-        } else {
-            for (int64_t c = 0; c < np; ++c) {
-                if (part_any[pb + c] != stamp) continue;
-                any = true;
-#pragma unroll
-                for (int k = 0; k < DW; ++k) {
-                    const int q = k * G + p;
-                    if (q < P) acc[k] = byte_max(acc[k], part[(pb + c) * P + q]);
-                }
-            }
-        }
-        if (!any && !inL) continue;
-        bool ch = false;
-        uint32_t nw[DW];
-#pragma unroll
-        for (int k = 0; k < DW; ++k) {
-            const int q = k * G + p;
-            nw[k] = 0;
-            if (q < P) {
-                const uint32_t a = A[u * P + q];
-                nw[k] = byte_max(a, acc[k]) & ub[k];
-                ch = ch || nw[k] != a;
-            }
-        }
-        const bool changed = group_any<G>(ch);
-        if (changed || inL) {
-#pragma unroll
-            for (int k = 0; k < DW; ++k) {
-                const int q = k * G + p;
-                if (q < P) B[u * P + q] = nw[k];
-            }
-        }
+        const bool changed =
+            fix_row<G, DW>(r, u, A, B, Lcur, blk, hpb, hpn, part, part_any, stamp, P, PW, first, lane, p);
         if (changed && p == 0) {
             atomicOr(&Lnext[u >> 5], 1u << (u & 31));
             my_cnt += 1;
@@ -1479,37 +1078,8 @@ __global__ __launch_bounds__(256) void k_argmax(const uint32_t* __restrict__ M, 
                                                 int64_t n, int P) {
     __shared__ unsigned long long sh[4];
     constexpr int RPW = 64 / G;
-    const int lane = threadIdx.x & 63, grp = lane / G, p = lane % G;
-    uint32_t ms[DW];
-#pragma unroll
-    for (int i = 0; i < DW; ++i) {
-        const int q = i * G + p;
-        ms[i] = q < P ? MS[q] : 0u;
-    }
-    unsigned long long best = 0;
-    for (int64_t base = wave_index() * RPW; base < n; base += wave_count() * RPW) {
-        const int64_t u = base + grp;
-        const bool ok = u < n && inS[u] == 0;
-        uint32_t s = 0;
-        if (ok) {
-#pragma unroll
-            for (int i = 0; i < DW; ++i) {
-                const int q = i * G + p;
-                if (q < P) s = __builtin_amdgcn_sad_u8(byte_max(ms[i], M[u * P + q]), 0u, s);
-            }
-        }
-#pragma unroll
-        for (int off = G / 2; off > 0; off >>= 1) s += __shfl_xor(s, off, 64);
-        if (ok && p == 0) {
-            const unsigned long long key = ((unsigned long long)s << 32) | (unsigned long long)(0xFFFFFFFFu - (uint32_t)u);
-            best = key > best ? key : best;
-        }
-    }
-#pragma unroll
-    for (int off = 32; off > 0; off >>= 1) {
-        const unsigned long long o = __shfl_xor(best, off, 64);
-        best = o > best ? o : best;
-    }
+    const int lane = threadIdx.x & 63;
+    unsigned long long best = best_score_rows<G, DW>(wave_index() * RPW, n, wave_count() * RPW, M, MS, inS, P);
     const int w = threadIdx.x >> 6;
     if (lane == 0) sh[w] = best;
     __syncthreads();
@@ -1528,55 +1098,19 @@ hipError_t launch_argmax(const Layout& L, int64_t n, const uint32_t* M, const Gr
 }
 
 
-DEVI double estimate_from_sum(uint32_t s, int J, const double* __restrict__ T) {
-    const uint32_t q = s / (uint32_t)J, r = s % (uint32_t)J;
-    return ldexp(T[r], (int)q) / 0.77351;
-}
 
-// One wave: takes the argmax, records the step, computes e = Estimate(Merge(M_S',
-// M_s)) and starts the Monte-Carlo reach of s: every pair (s, j) not blocked
-// yet becomes blocked and forms the level-0 frontier.
+// One wave: takes the argmax, records the step, computes e and starts the
+// Monte-Carlo reach of s (see select_seed).
 __global__ void k_select(const int64_t* __restrict__ xadj, const uint32_t* __restrict__ M, GreedyBufs b, StepRec* rec,
                          int32_t* seeds, int k, int J, int P, int PW, int32_t level_id, int64_t n) {
-    const int lane = threadIdx.x;
     const unsigned long long key = *b.key;
-    const int64_t s = (int64_t)(0xFFFFFFFFu - (uint32_t)(key & 0xFFFFFFFFull));
-    if (key == 0ull || s >= n) {  // no candidate: report and touch nothing else
-        if (lane == 0) {
-            rec->seed = -1;
-            seeds[k] = -1;
-            b.qsize[0] = 0u;
-        }
-        return;
-    }
-    uint32_t sum = 0;
-    for (int q = lane; q < P; q += 64) {
-        const uint32_t mg = byte_max(b.MS[q], M[s * P + q]);
-        b.merged[q] = mg;
-        sum = __builtin_amdgcn_sad_u8(mg, 0u, sum);
-    }
-    sum = wave_sum(sum);
-    const int64_t deg = xadj[s + 1] - xadj[s];
-    uint32_t newcnt = 0;
-    for (int w = lane; w < 4 * PW; w += 64) {
-        const uint32_t old = b.blk[s * 4 * PW + w];
-        const uint32_t nb = ~old & plane_valid_mask(w, P, PW);
-        b.blk[s * 4 * PW + w] = old | nb;
-        newcnt += __builtin_popcount(nb);
-        if (deg > 0) b.F[0][s * 4 * PW + w] = nb;
-    }
-    newcnt = wave_sum(newcnt);
-    const int64_t nch = (deg > 0 && newcnt > 0) ? (deg + b.bfs_chunk - 1) / b.bfs_chunk : 0;
-    for (int64_t c = lane; c < nch; c += 64) b.Q[0][c] = make_int2((int)s, (int)c);
-    if (lane == 0) {
-        b.inS[s] = 1;
-        seeds[k] = (int32_t)s;
-        rec->seed = (int32_t)s;
-        rec->score = (int64_t)(key >> 32);
-        rec->e = estimate_from_sum(sum, J, b.T);
-        b.qsize[0] = (uint32_t)nch;
-        if (nch) b.stamp[s] = level_id;
-        if (newcnt) atomicAdd(&b.R[0], (unsigned long long)newcnt);
+    uint32_t nch = 0, newcnt = 0;
+    double e = 0.0;
+    const bool ok = select_seed(key, n, J, P, PW, xadj, M, b.MS, b.merged, b.blk, b.F[0], b.Q[0], b.inS, b.stamp,
+                                level_id, b.bfs_chunk, b.T, rec, seeds, k, &nch, &newcnt, &e);
+    if (threadIdx.x == 0) {
+        b.qsize[0] = nch;
+        if (ok && newcnt) atomicAdd(&b.R[0], (unsigned long long)newcnt);
         *b.key = 0ull;
     }
 }
@@ -1588,17 +1122,7 @@ hipError_t launch_select(const Layout& L, const DevGraph& g, const uint32_t* M, 
     return hipGetLastError();
 }
 
-// One BFS level of the Monte-Carlo reach over all samples at once.  A queue
-// entry is (vertex v, chunk c) covering at most bfs_chunk out-edges of v.  For
-// each edge (v, w): the samples where the edge is live and v is in the
-// frontier are OR-ed into w's blocked bits; bits that were not set before
-// form w's frontier of the next level, and w is queued once per level.
-//
-// A G-lane group serves one entry: it reads G edges per window, tests every
-// edge against its 4*DW registers per lane, and collects the edges with a
-// candidate bit in a batch.  Lane p of the group owns word p % (4 PW) of edge
-// slot p / (4 PW) of the batch, so one atomic instruction updates the blocked
-// words of G / (4 PW) edges at once (8 edges at R = 256).
+// One BFS level over the queue of level `cur` (see bfs_expand_entries).
 template <int G, int DW, int KIND>
 __global__ __launch_bounds__(256) void k_bfs_expand(const int64_t* __restrict__ xadj, const int32_t* __restrict__ adj,
                                                     const uint32_t* __restrict__ eh, const uint32_t* __restrict__ thr,
@@ -1608,130 +1132,14 @@ __global__ __launch_bounds__(256) void k_bfs_expand(const int64_t* __restrict__ 
     const uint32_t size = b.qsize[cur % 3];
     if (size == 0) return;
     constexpr int RPW = 64 / G;
-    const int lane = threadIdx.x & 63, grp = lane / G, p = lane % G;
-    const uint32_t* __restrict__ Fc = b.F[cur & 1];
-    uint32_t* Fn = b.F[(cur + 1) & 1];
-    const int2* __restrict__ Qc = b.Q[cur & 1];
-    int2* Qn = b.Q[(cur + 1) & 1];
-    uint32_t* qn = &b.qsize[(cur + 1) % 3];
+    const int p = (threadIdx.x & 63) % G;
     uint32_t x[DW][4];
     load_sim_words<G, DW>(X, P, p, x);
     const uint32_t ntv = to_vgpr(0u - thr_const);
-    const int W = 4 * PW;      // words of a vertex bitset = words of an edge's candidate set
-    const int EPB = G / W;     // edges per batch (>= 1)
-    const int sb = p / W, sw = p % W;
-    const bool slot_ok = sb < EPB;
-    const int sk = sw / PW, sww = sw % PW;  // plane and word-in-plane of this lane's word
-    const uint64_t gmask = G == 64 ? ~0ull : ((1ull << G) - 1ull);
-    const uint64_t wmask = W >= 64 ? ~0ull : ((1ull << W) - 1ull);
-    unsigned long long my_new = 0;
-    for (int64_t base = wave_index() * RPW; base < (int64_t)size; base += wave_count() * RPW) {
-        const int64_t ent = base + grp;
-        const bool ok = ent < (int64_t)size;
-        int64_t e0 = 0, e1 = 0;
-        uint32_t fb[DW];  // frontier bits of this lane's registers, bit (k) of fb[i] for register 4q+k
-#pragma unroll
-        for (int i = 0; i < DW; ++i) fb[i] = 0u;
-        if (ok) {
-            const int2 qe = Qc[ent];
-            const int64_t v = qe.x;
-            const int64_t vb = xadj[v], ve = xadj[v + 1];
-            e0 = vb + (int64_t)qe.y * b.bfs_chunk;
-            e1 = e0 + b.bfs_chunk < ve ? e0 + b.bfs_chunk : ve;
-#pragma unroll
-            for (int i = 0; i < DW; ++i) {
-                const int q = i * G + p;
-                uint32_t f = 0;
-                if (q < P) {
-#pragma unroll
-                    for (int k = 0; k < 4; ++k) f |= ((Fc[v * W + k * PW + (q >> 5)] >> (q & 31)) & 1u) << k;
-                }
-                fb[i] = f;
-            }
-        }
-        uint32_t myval = 0;
-        int64_t myw = 0, mywdeg = 0;
-        int nb = 0;
-        auto flush = [&]() {
-            uint32_t nbits = 0;
-            if (myval) {
-                const uint32_t old = atomicOr(&b.blk[myw * W + sw], myval);
-                nbits = myval & ~old;
-                if (nbits) {
-                    if (mywdeg > 0) atomicOr(&Fn[myw * W + sw], nbits);
-                    my_new += (unsigned long long)__builtin_popcount(nbits);
-                }
-            }
-            const uint64_t bal = __ballot(nbits != 0u);
-            if (sw == 0 && slot_ok && mywdeg > 0 && ((bal >> (grp * G + sb * W)) & wmask) != 0ull) {
-                const int32_t old = atomicMax(&b.stamp[myw], level_id_next);
-                if (old < level_id_next) {
-                    const int64_t nch = (mywdeg + b.bfs_chunk - 1) / b.bfs_chunk;
-                    const uint32_t pos = atomicAdd(qn, (uint32_t)nch);
-                    for (int64_t c = 0; c < nch; ++c) Qn[pos + c] = make_int2((int)myw, (int)c);
-                }
-            }
-            myval = 0;
-        };
-        for (int64_t w0 = e0; w0 < e1; w0 += G) {
-            const int64_t e = w0 + p;
-            const bool in = e < e1;
-            const int32_t wv = in ? adj[e] : 0;
-            const uint32_t hh = in ? eh[e] : 0u;
-            uint32_t tt = 0u;
-            if constexpr (KIND == THR_TARGET) tt = in ? thr[wv] : 0u;
-            if constexpr (KIND == THR_EDGE) tt = in ? thr[e] : 0u;
-            const int64_t wd = in ? xadj[wv + 1] - xadj[wv] : 0;
-            const int nwin = (int)(e1 - w0 < G ? e1 - w0 : G);
-            for (int j = 0; j < nwin; ++j) {
-                uint32_t hb, nt = ntv;
-                int32_t wj;
-                int64_t wdj;
-                if constexpr (G == 64) {
-                    hb = (uint32_t)__builtin_amdgcn_readlane((int)hh, j);
-                    if constexpr (KIND != THR_CONST) nt = 0u - (uint32_t)__builtin_amdgcn_readlane((int)tt, j);
-                    wj = __builtin_amdgcn_readlane(wv, j);
-                    wdj = __builtin_amdgcn_readlane((int)wd, j);
-                } else {
-                    hb = __shfl(hh, grp * G + j, 64);
-                    if constexpr (KIND != THR_CONST) nt = 0u - __shfl(tt, grp * G + j, 64);
-                    wj = __shfl(wv, grp * G + j, 64);
-                    wdj = __shfl((int)wd, grp * G + j, 64);
-                }
-                uint32_t cw = 0;
-                bool anyc = false;
-#pragma unroll
-                for (int i = 0; i < DW; ++i) {
-#pragma unroll
-                    for (int k = 0; k < 4; ++k) {
-                        const bool c = (int32_t)((x[i][k] ^ hb) + nt) < 0 && ((fb[i] >> k) & 1u);
-                        const uint64_t bal = __ballot(c);
-                        if constexpr (G == 64) {
-                            const uint32_t lo = (uint32_t)bal, hi = (uint32_t)(bal >> 32);
-                            if (sk == k && sww == 2 * i) cw = lo;
-                            if (sk == k && sww == 2 * i + 1) cw = hi;
-                            anyc = anyc || bal != 0ull;
-                        } else {
-                            const uint32_t gb = (uint32_t)((bal >> (grp * G)) & gmask);
-                            if (sk == k) cw = gb;
-                            anyc = anyc || gb != 0u;
-                        }
-                    }
-                }
-                if (!anyc) continue;
-                if (sb == nb) {
-                    myval = cw;
-                    myw = wj;
-                    mywdeg = wdj;
-                }
-                if (++nb == EPB) {
-                    flush();
-                    nb = 0;
-                }
-            }
-        }
-        if (nb > 0) flush();
-    }
+    const unsigned long long my_new = bfs_expand_entries<G, DW, KIND>(
+        wave_index() * RPW, (int64_t)size, wave_count() * RPW, xadj, adj, eh, thr, ntv, x, b.F[cur & 1],
+        b.F[(cur + 1) & 1], b.Q[cur & 1], b.Q[(cur + 1) & 1], &b.qsize[(cur + 1) % 3], b.blk, b.stamp, level_id_next,
+        b.bfs_chunk, P, PW);
     const unsigned long long bn = block_sum256(my_new, sh64);
     if (threadIdx.x == 0 && bn) atomicAdd(&b.R[(blockIdx.x % NSLOT) * SLOT_U64], bn);
 }
@@ -1766,7 +1174,7 @@ hipError_t launch_bfs_level(const Layout& L, const DevGraph& g, const uint32_t* 
     return hipGetLastError();
 }
 
-// Error-adaptive decision of Alg. 1 in FP64 (one wave; lane 0 computes).
+// Error-adaptive decision of Alg. 1 (one wave; see decide_step).
 __global__ void k_decide(GreedyBufs b, StepRec* rec, int k, int K, double eps_g, double eps_l, int J, int P,
                          int32_t* rebuild_flag) {
     __shared__ int flags[2];
@@ -1775,22 +1183,8 @@ __global__ void k_decide(GreedyBufs b, StepRec* rec, int k, int K, double eps_g,
         unsigned long long R = 0;
         for (int i = 0; i < NSLOT; ++i) R += b.R[i * SLOT_U64];
         const unsigned long long R0 = *b.Rreb;
-        const double sigma = (double)R / (double)J;
-        const double delta = (double)(R - R0) / (double)J;
-        const double e = rec->e;
-        const double err_l = delta == 0.0 ? __builtin_inf() : fabs((e - delta) / delta);
-        const double err_g = fabs((e - delta) / sigma);
-        const int fresh = (err_l < eps_l) || (err_g < eps_g);
-        const int rebuild = (k < K) && !fresh;
-        rec->reach = (int64_t)R;
-        rec->sigma = sigma;
-        rec->delta = delta;
-        rec->err_l = err_l;
-        rec->err_g = err_g;
-        rec->fresh = fresh;
-        rec->rebuilt = rebuild;
-        rec->sweeps = 0;
-        rec->visits = 0;
+        int fresh = 0;
+        const int rebuild = decide_step(R, R0, J, k, K, eps_g, eps_l, rec->e, rec, &fresh);
         if (rebuild) *b.Rreb = R;
         *rebuild_flag = rebuild;
         flags[0] = fresh;
