@@ -235,6 +235,85 @@ IM_API im_status im_sketch_get_blocked(const im_sketch* sk, uint8_t* out);
 
 IM_API void im_sketch_free(im_sketch* sk);
 
+/*
+ * ---------------------------------------------------------------------------
+ * Batched solve: many independent problems (graphs of uneven sizes, edge
+ * models and R) solved together by ONE persistent kernel launch, captured
+ * once in a HIP graph at im_batch_create and replayed by im_batch_run.  Each
+ * job computes exactly what im_build_sketches followed by im_select_seeds
+ * computes for it alone (Alg. 1 with Alg. 2): the same registers, sweep
+ * counts, edge visits, seeds and step records.  The work decomposition
+ * (lanes per row, tile sizes, grid) never changes a result.
+ * ---------------------------------------------------------------------------
+ */
+typedef struct im_batch_job {
+    im_csr graph;        /* host or device CSR (graph.on_device); copied at create, not retained */
+    im_probs probs;      /* per_edge resides where the CSR resides */
+    int32_t R;           /* registers (= simulations) per vertex: a multiple of 4 in [4, 256] */
+    int32_t K;           /* seeds to select, in [1, n] */
+    uint32_t hash_seed;  /* seed of every hash, as in im_build_sketches */
+    int32_t reserved;
+    double eps_c;        /* early exit of every Simulate, as im_build_opts.eps_c */
+    double eps_g, eps_l; /* rebuild thresholds, as im_select_opts (no defaults are substituted) */
+} im_batch_job;
+
+/* Work decomposition of the persistent solver.  Zero selects the default.
+ * autotune = 1: im_batch_create solves the batch once per candidate
+ * decomposition (lanes per row, tile size, grid), keeps the fastest, and
+ * fails with IM_ERR_DEVICE if any two candidates disagree on a seed. */
+typedef struct im_batch_opts {
+    int32_t autotune;
+    int32_t lanes_per_row; /* power of two in [max(4, R_max/4), 64]; default the smallest */
+    int32_t tile_edges;    /* edges per sweep tile; default 8192 */
+    int32_t heavy_degree;  /* rows with more out-edges are split into pieces; default 512 */
+    int32_t piece_edges;   /* edges per piece; default 512 */
+    int32_t workgroups;    /* persistent grid, 256-thread workgroups; default 4 per compute unit */
+    int32_t reserved[2];
+} im_batch_opts;
+
+typedef struct im_batch_job_result {
+    int32_t status;       /* IM_OK, or the device-side error that stopped this job */
+    int32_t build_sweeps; /* sweeps of the build */
+    int32_t rebuilds;
+    int32_t reserved;
+    int64_t build_visits; /* edges with a live head, summed over the build's sweeps */
+    int64_t rebuild_sweeps;
+    int64_t rebuild_visits;
+    int64_t bfs_levels;   /* reach levels with work, over all steps */
+} im_batch_job_result;
+
+typedef struct im_batch_stats {
+    double device_ms;   /* the replayed launch, from HIP events */
+    double wall_ms;     /* host wall time of im_batch_run */
+    int64_t tiles;      /* tiles processed */
+    int64_t phases;     /* phase transitions over all jobs */
+    int32_t lanes_per_row, tile_edges, heavy_degree, piece_edges, workgroups;
+    int32_t candidates; /* decompositions the autotuner timed (0 without autotuning) */
+} im_batch_stats;
+
+typedef struct im_batch im_batch;
+
+/* Validates and uploads every job (count >= 1), allocates all device state
+ * through the context (IM_ERR_OUT_OF_BUDGET beyond its budget) and captures
+ * the launch.  opts may be NULL.  On success *out owns everything. */
+IM_API im_status im_batch_create(im_ctx* ctx, int32_t count, const im_batch_job* jobs, const im_batch_opts* opts,
+                                 im_batch** out);
+/* Solves every job (one graph launch on a stream of the batch, ordered after
+ * work already enqueued on the context's stream) and waits for it.  May be
+ * called repeatedly; each run starts from the uploaded graphs.  stats may be
+ * NULL.  A device-side stop (watchdog) returns IM_ERR_DEVICE and poisons b. */
+IM_API im_status im_batch_run(im_batch* b, im_batch_stats* stats);
+/* Results of job `job` (the caller's index) from the last run: K seeds,
+ * K step records (or NULL), counters (or NULL).  Returns the job's status. */
+IM_API im_status im_batch_get_result(const im_batch* b, int32_t job, int32_t* out_seeds, im_step* out_steps,
+                                     im_batch_job_result* res);
+/* Registers of job `job` after the last run, n*R bytes vertex-major:
+ * which = 0 those of the build, 1 those in force at the end of the greedy loop. */
+IM_API im_status im_batch_get_registers(const im_batch* b, int32_t job, int32_t which, uint8_t* out);
+/* Device bytes held by the batch. */
+IM_API size_t im_batch_device_bytes(const im_batch* b);
+IM_API void im_batch_free(im_batch* b);
+
 /* Thread-local message of the last failed call on this thread ("" if none). */
 IM_API const char* im_last_error(void);
 

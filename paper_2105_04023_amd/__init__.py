@@ -14,8 +14,8 @@ import numpy as np
 
 from . import _binding as B
 
-__all__ = ["Context", "Sketch", "im_build_sketches", "im_estimate", "im_estimate_all", "im_select_seeds",
-           "ImError"]
+__all__ = ["Context", "Sketch", "Batch", "BatchJob", "im_build_sketches", "im_estimate", "im_estimate_all",
+           "im_select_seeds", "im_batch_create", "ImError"]
 
 ImError = B.ImError
 _KIND = {"const": B.IM_PROB_CONSTANT, "wc": B.IM_PROB_WEIGHTED_CASCADE, "edge": B.IM_PROB_PER_EDGE}
@@ -216,3 +216,98 @@ def im_select_seeds(sk: Sketch, K: int, eps_g: float = 0.01, eps_l: float = 0.3)
                                    ctypes.cast(steps, ctypes.c_void_p), ctypes.byref(stats)))
     st = [Step(**{f: getattr(s, f) for f, _ in B.im_step._fields_}) for s in steps]
     return seeds, st, {f: getattr(stats, f) for f, _ in B.im_select_stats._fields_}
+
+
+@dataclass
+class BatchJob:
+    """One problem of a batched solve (see im_batch_create).  xadj/adj/per_edge are numpy
+    arrays or device tensors (all of one kind)."""
+    xadj: object
+    adj: object
+    n: int
+    R: int
+    K: int
+    model: str = "const"
+    p: float = 0.0
+    per_edge: object = None
+    hash_seed: int = 0
+    eps_c: float = 0.0
+    eps_g: float = 0.01
+    eps_l: float = 0.3
+
+
+class Batch:
+    """Handle of a batched solve: every job's graph resident on the device, one captured launch."""
+
+    def __init__(self, ctx: Context, handle, jobs):
+        self.ctx, self.handle, self.lib = ctx, handle, ctx.lib
+        self.ns = [j.n for j in jobs]
+        self.Rs = [j.R for j in jobs]
+        self.Ks = [j.K for j in jobs]
+
+    def run(self) -> dict:
+        st = B.im_batch_stats()
+        B.check(self.lib.im_batch_run(self.handle, ctypes.byref(st)))
+        return {f: getattr(st, f) for f, _ in B.im_batch_stats._fields_}
+
+    def result(self, job: int):
+        """(seeds, steps, counters) of job `job` from the last run."""
+        K = self.Ks[job]
+        seeds = np.zeros(K, dtype=np.int32)
+        steps = (B.im_step * K)()
+        res = B.im_batch_job_result()
+        B.check(self.lib.im_batch_get_result(self.handle, job, seeds.ctypes.data, ctypes.cast(steps, ctypes.c_void_p),
+                                             ctypes.byref(res)))
+        st = [Step(**{f: getattr(s, f) for f, _ in B.im_step._fields_}) for s in steps]
+        return seeds, st, {f: getattr(res, f) for f, _ in B.im_batch_job_result._fields_}
+
+    def registers(self, job: int, which: int = 0) -> np.ndarray:
+        out = np.empty((self.ns[job], self.Rs[job]), dtype=np.uint8)
+        B.check(self.lib.im_batch_get_registers(self.handle, job, which, out.ctypes.data))
+        return out
+
+    def device_bytes(self) -> int:
+        return int(self.lib.im_batch_device_bytes(self.handle))
+
+    def free(self):
+        if self.handle:
+            self.lib.im_batch_free(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.free()
+        except Exception:
+            pass
+
+
+def im_batch_create(ctx: Context, jobs, autotune: bool = False, lanes_per_row: int = 0, tile_edges: int = 0,
+                    heavy_degree: int = 0, piece_edges: int = 0, workgroups: int = 0) -> Batch:
+    """Uploads every job and captures the persistent launch (Alg. 1 + Alg. 2 per job)."""
+    torch = _torch()
+    arr = (B.im_batch_job * len(jobs))()
+    keep = []
+    for i, j in enumerate(jobs):
+        xp, xdev, xk = _ptr_and_residency(j.xadj, (np.int64, torch.int64))
+        ap, adev, ak = _ptr_and_residency(j.adj, (np.int32, torch.int32))
+        if xdev != adev:
+            raise ValueError("xadj and adj must both be host arrays or both device tensors")
+        m = int(len(j.adj)) if not isinstance(j.adj, torch.Tensor) else int(j.adj.numel())
+        keep += [xk, ak]
+        pe_ptr = None
+        if j.model == "edge":
+            pp, pdev, pk = _ptr_and_residency(j.per_edge, (np.float32, torch.float32))
+            if pdev != xdev:
+                raise ValueError("per-edge probabilities must reside where the CSR resides")
+            pe_ptr = pp
+            keep.append(pk)
+        arr[i].graph = B.im_csr(j.n, m, xp, ap, xdev)
+        arr[i].probs = B.im_probs(_KIND[j.model], float(j.p), pe_ptr)
+        arr[i].R, arr[i].K, arr[i].hash_seed = j.R, j.K, j.hash_seed & 0xFFFFFFFF
+        arr[i].eps_c, arr[i].eps_g, arr[i].eps_l = j.eps_c, j.eps_g, j.eps_l
+    opts = B.im_batch_opts(1 if autotune else 0, lanes_per_row, tile_edges, heavy_degree, piece_edges, workgroups)
+    h = ctypes.c_void_p()
+    B.check(ctx.lib.im_batch_create(ctx.handle, len(jobs), ctypes.cast(arr, ctypes.c_void_p), ctypes.byref(opts),
+                                    ctypes.byref(h)))
+    del keep
+    return Batch(ctx, h, jobs)

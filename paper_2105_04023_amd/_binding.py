@@ -21,7 +21,8 @@ EXPORTED = [
     "im_ctx_create", "im_ctx_free", "im_ctx_bytes_in_use", "im_sketch_bytes_needed", "im_build_sketches",
     "im_estimate", "im_estimate_all", "im_select_seeds", "im_sketch_get_info", "im_sketch_get_trace",
     "im_sketch_get_registers", "im_sketch_get_blocked", "im_sketch_free", "im_last_error", "im_version",
-    "im_sketch_get_sweep_log", "im_sketch_clear_sweep_log",
+    "im_sketch_get_sweep_log", "im_sketch_clear_sweep_log", "im_batch_create", "im_batch_run", "im_batch_get_result",
+    "im_batch_get_registers", "im_batch_device_bytes", "im_batch_free",
 ]
 
 
@@ -76,6 +77,31 @@ class im_select_stats(ctypes.Structure):
                 ("wall_ms", ctypes.c_double)]
 
 
+class im_batch_job(ctypes.Structure):
+    _fields_ = [("graph", im_csr), ("probs", im_probs), ("R", ctypes.c_int32), ("K", ctypes.c_int32),
+                ("hash_seed", ctypes.c_uint32), ("reserved", ctypes.c_int32), ("eps_c", ctypes.c_double),
+                ("eps_g", ctypes.c_double), ("eps_l", ctypes.c_double)]
+
+
+class im_batch_opts(ctypes.Structure):
+    _fields_ = [("autotune", ctypes.c_int32), ("lanes_per_row", ctypes.c_int32), ("tile_edges", ctypes.c_int32),
+                ("heavy_degree", ctypes.c_int32), ("piece_edges", ctypes.c_int32), ("workgroups", ctypes.c_int32),
+                ("reserved", ctypes.c_int32 * 2)]
+
+
+class im_batch_job_result(ctypes.Structure):
+    _fields_ = [("status", ctypes.c_int32), ("build_sweeps", ctypes.c_int32), ("rebuilds", ctypes.c_int32),
+                ("reserved", ctypes.c_int32), ("build_visits", ctypes.c_int64), ("rebuild_sweeps", ctypes.c_int64),
+                ("rebuild_visits", ctypes.c_int64), ("bfs_levels", ctypes.c_int64)]
+
+
+class im_batch_stats(ctypes.Structure):
+    _fields_ = [("device_ms", ctypes.c_double), ("wall_ms", ctypes.c_double), ("tiles", ctypes.c_int64),
+                ("phases", ctypes.c_int64), ("lanes_per_row", ctypes.c_int32), ("tile_edges", ctypes.c_int32),
+                ("heavy_degree", ctypes.c_int32), ("piece_edges", ctypes.c_int32), ("workgroups", ctypes.c_int32),
+                ("candidates", ctypes.c_int32)]
+
+
 ALLOC_FN = ctypes.CFUNCTYPE(ctypes.c_void_p, ctypes.c_size_t, ctypes.c_void_p)
 FREE_FN = ctypes.CFUNCTYPE(None, ctypes.c_void_p, ctypes.c_void_p)
 
@@ -111,6 +137,12 @@ def load(path: str = LIB_PATH):
         "im_version": ([], ctypes.c_char_p),
         "im_sketch_get_sweep_log": ([p, p, i32], i32),
         "im_sketch_clear_sweep_log": ([p], None),
+        "im_batch_create": ([p, i32, p, ctypes.POINTER(im_batch_opts), ctypes.POINTER(p)], ctypes.c_int),
+        "im_batch_run": ([p, ctypes.POINTER(im_batch_stats)], ctypes.c_int),
+        "im_batch_get_result": ([p, i32, p, p, ctypes.POINTER(im_batch_job_result)], ctypes.c_int),
+        "im_batch_get_registers": ([p, i32, i32, p], ctypes.c_int),
+        "im_batch_device_bytes": ([p], sz),
+        "im_batch_free": ([p], None),
     }
     for name, (args, res) in sig.items():
         fn = getattr(lib, name)

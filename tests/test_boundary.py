@@ -72,3 +72,29 @@ def test_bytes_needed_is_host_only(lib_path):
     assert b > 3 * n * R  # three register buffers dominate
     assert lib.im_sketch_bytes_needed(n, m, 6, 0) == 0  # R not a multiple of 4
     assert lib.im_sketch_bytes_needed(0, m, R, 0) == 0
+
+
+def test_ctypes_structs_match_the_c_layout(tmp_path):
+    """Every struct the binding mirrors has the size and field offsets of include/im.h (gcc)."""
+    import ctypes
+
+    from paper_2105_04023_amd import _binding as B
+
+    structs = [B.im_csr, B.im_probs, B.im_build_opts, B.im_select_opts, B.im_step, B.im_sketch_info,
+               B.im_sweep_rec, B.im_select_stats, B.im_batch_job, B.im_batch_opts, B.im_batch_job_result,
+               B.im_batch_stats]
+    lines = ['#include <stdio.h>', '#include <stddef.h>', '#include "im.h"', "int main(void) {"]
+    for s in structs:
+        lines.append(f'printf("{s.__name__} %zu\\n", sizeof({s.__name__}));')
+        for f, _ in s._fields_:
+            lines.append(f'printf("{s.__name__}.{f} %zu\\n", offsetof({s.__name__}, {f}));')
+    lines.append("return 0; }")
+    src = tmp_path / "layout.c"
+    src.write_text("\n".join(lines))
+    exe = tmp_path / "layout"
+    subprocess.check_call(["gcc", "-std=c99", "-I", os.path.join(ROOT, "include"), str(src), "-o", str(exe)])
+    out = dict(line.rsplit(" ", 1) for line in subprocess.check_output([str(exe)], text=True).splitlines())
+    for s in structs:
+        assert int(out[s.__name__]) == ctypes.sizeof(s), s.__name__
+        for f, _ in s._fields_:
+            assert int(out[f"{s.__name__}.{f}"]) == getattr(s, f).offset, (s.__name__, f)
