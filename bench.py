@@ -69,6 +69,76 @@ def cpu_baseline(seconds_hint: float = 15.0):
             "host_cpu": platform.processor() or platform.machine(), "host_nproc": os.cpu_count()}
 
 
+def batch_leg(hf, ctx, steps: int, warmup: int):
+    """64 independent R-MAT jobs (log2 n uniform in 12..18, average degree uniform in [8, 32], p in
+    {0.005, 0.01, 0.05}, R=128, K=20): one persistent graph-captured launch (autotuned decomposition)
+    against the same jobs solved one graph per call back-to-back (im_build_sketches + im_select_seeds),
+    both from device-resident CSRs.  Every job's seeds must agree between the two."""
+    import torch
+
+    import synth
+
+    J, K = 128, 20
+    t = time.perf_counter()
+    recipe = synth.batch_recipe()
+    graphs = [(synth.rmat(scale, draws, seed=seed), p) for scale, draws, p, seed in recipe]
+    dev = [(torch.from_numpy(g.xadj).cuda(), torch.from_numpy(g.adj).cuda(), g, p) for g, p in graphs]
+    torch.cuda.synchronize()
+    n_tot = sum(g.n for g, _ in graphs)
+    m_tot = sum(g.m for g, _ in graphs)
+    log(f"batch workload: {len(graphs)} graphs, n={n_tot} m={m_tot}, generated in {time.perf_counter() - t:.1f} s")
+    jobs = [hf.BatchJob(x, a, g.n, J, K, model="const", p=p) for x, a, g, p in dev]
+    t = time.perf_counter()
+    b = hf.im_batch_create(ctx, jobs, autotune=True)
+    create_s = time.perf_counter() - t
+    try:
+        for _ in range(warmup):
+            b.run()
+        runs = [b.run() for _ in range(steps)]
+        res = [b.result(i) for i in range(len(jobs))]
+        batch_seeds = [list(map(int, r[0])) for r in res]
+        build_visits = sum(r[2]["build_visits"] for r in res)
+        rebuild_visits = sum(r[2]["rebuild_visits"] for r in res)
+        tune = {k: runs[-1][k] for k in ("lanes_per_row", "tile_edges", "heavy_degree", "piece_edges", "workgroups",
+                                          "candidates")}
+        phases, tiles = runs[-1]["phases"], runs[-1]["tiles"]
+    finally:
+        b.free()
+
+    def plain_pass():
+        out = []
+        for x, a, g, p in dev:
+            sk = hf.im_build_sketches(ctx, x, a, g.n, J, model="const", p=p)
+            try:
+                seeds, _, _ = hf.im_select_seeds(sk, K)
+            finally:
+                sk.free()
+            out.append(list(map(int, seeds)))
+        return out
+
+    for _ in range(warmup):
+        plain_pass()
+    torch.cuda.synchronize()
+    t = time.perf_counter()
+    for _ in range(steps):
+        plain_seeds = plain_pass()
+    torch.cuda.synchronize()
+    plain_ms = (time.perf_counter() - t) * 1e3 / steps
+    batch_ms = sum(r["wall_ms"] for r in runs) / len(runs)
+    batch_dev_ms = sum(r["device_ms"] for r in runs) / len(runs)
+    log(f"batched {batch_ms:.1f} ms (device {batch_dev_ms:.1f} ms, {tune}), plain {plain_ms:.1f} ms")
+    return {
+        "workload": "batch64_rmat_log2n12-18_deg8-32_p{0.005,0.01,0.05}_J128_K20",
+        "jobs": len(jobs), "n_total": n_tot, "m_total": m_tot, "R": J, "K": K,
+        "batched_ms": batch_ms, "batched_device_ms": batch_dev_ms, "plain_ms": plain_ms,
+        "speedup_vs_plain": plain_ms / batch_ms,
+        "batched_build_visits_per_s": build_visits * J / (batch_ms * 1e-3),
+        "build_visits": build_visits * J, "rebuild_visits": rebuild_visits * J,
+        "seeds_equal_to_plain": batch_seeds == plain_seeds,
+        "create_s": create_s, "decomposition": tune, "phases": phases, "tiles": tiles,
+    }
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -76,6 +146,7 @@ def main():
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--workload", default="rmat24_wc_J256_K50", choices=sorted(WORKLOADS))
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-batch", action="store_true", help="skip the batched-vs-plain comparison")
     ap.add_argument("--K", type=int, default=0, help="override K")
     ap.add_argument("--sparse-div", type=int, default=0)
     ap.add_argument("--heavy-degree", type=int, default=0)
@@ -151,7 +222,7 @@ def main():
     row_ms = sum(rec["kernel_ms"] for rec in recs)
     row_bytes = sum(rec["light_visits"] * (J + 4 + (4 if wc else 0)) for rec in recs if rec["ran"])
     out = {
-        "metric": "edge*simulation visits/s in sketch build (+ K-seed IM time)",
+        "metric": "edge*simulation visits/s in sketch build (+ K-seed IM time; batched vs plain in 'batched')",
         "value": visits / build_s,
         "unit": "edge*sim visits/s",
         "n_gpus": 1,
@@ -182,6 +253,8 @@ def main():
         "row_kernel": {"kernel": "k_sweep_rows64", "ms": row_ms,
                        "visit_bytes_GBs": row_bytes / (row_ms * 1e-3) / 1e9 if row_ms > 0 else 0.0},
     }
+    if not args.no_batch:
+        out["batched"] = batch_leg(hf, ctx, args.steps, args.warmup)
     if args.dump_sweeps:
         with open(args.dump_sweeps, "w") as fh:
             json.dump(results[-1]["sweep_log"], fh)

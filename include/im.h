@@ -268,7 +268,10 @@ typedef struct im_batch_opts {
     int32_t heavy_degree;  /* rows with more out-edges are split into pieces; default 512 */
     int32_t piece_edges;   /* edges per piece; default 512 */
     int32_t workgroups;    /* persistent grid, 256-thread workgroups; default 4 per compute unit */
-    int32_t reserved[2];
+    int32_t pin_edges;     /* jobs with at most this many edges run on one XCD each; default half
+                              of one XCD's share of the batch's edges; negative: every job runs
+                              on every XCD */
+    int32_t reserved;
 } im_batch_opts;
 
 typedef struct im_batch_job_result {

@@ -282,7 +282,7 @@ class Batch:
 
 
 def im_batch_create(ctx: Context, jobs, autotune: bool = False, lanes_per_row: int = 0, tile_edges: int = 0,
-                    heavy_degree: int = 0, piece_edges: int = 0, workgroups: int = 0) -> Batch:
+                    heavy_degree: int = 0, piece_edges: int = 0, workgroups: int = 0, pin_edges: int = 0) -> Batch:
     """Uploads every job and captures the persistent launch (Alg. 1 + Alg. 2 per job)."""
     torch = _torch()
     arr = (B.im_batch_job * len(jobs))()
@@ -305,7 +305,8 @@ def im_batch_create(ctx: Context, jobs, autotune: bool = False, lanes_per_row: i
         arr[i].probs = B.im_probs(_KIND[j.model], float(j.p), pe_ptr)
         arr[i].R, arr[i].K, arr[i].hash_seed = j.R, j.K, j.hash_seed & 0xFFFFFFFF
         arr[i].eps_c, arr[i].eps_g, arr[i].eps_l = j.eps_c, j.eps_g, j.eps_l
-    opts = B.im_batch_opts(1 if autotune else 0, lanes_per_row, tile_edges, heavy_degree, piece_edges, workgroups)
+    opts = B.im_batch_opts(1 if autotune else 0, lanes_per_row, tile_edges, heavy_degree, piece_edges, workgroups,
+                           pin_edges)
     h = ctypes.c_void_p()
     B.check(ctx.lib.im_batch_create(ctx.handle, len(jobs), ctypes.cast(arr, ctypes.c_void_p), ctypes.byref(opts),
                                     ctypes.byref(h)))

@@ -86,7 +86,7 @@ class im_batch_job(ctypes.Structure):
 class im_batch_opts(ctypes.Structure):
     _fields_ = [("autotune", ctypes.c_int32), ("lanes_per_row", ctypes.c_int32), ("tile_edges", ctypes.c_int32),
                 ("heavy_degree", ctypes.c_int32), ("piece_edges", ctypes.c_int32), ("workgroups", ctypes.c_int32),
-                ("reserved", ctypes.c_int32 * 2)]
+                ("pin_edges", ctypes.c_int32), ("reserved", ctypes.c_int32)]
 
 
 class im_batch_job_result(ctypes.Structure):

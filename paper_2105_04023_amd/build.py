@@ -27,13 +27,19 @@ FLAGS = [
 ]
 
 
+# The batched solver pins each job to one XCD and synchronises the CUs of that XCD
+# through their shared L2: threadgroup-split mode gives workgroup scope exactly
+# that meaning (release = wait for stores to reach L2, acquire = invalidate L1).
+EXTRA = {"hfr_batch.hip": ["-mtgsplit"]}
+
+
 def build(verbose: bool = False) -> str:
     """Compiles every source (always) and links the shared library."""
     os.makedirs(OBJDIR, exist_ok=True)
 
     def compile_one(src):
         obj = os.path.join(OBJDIR, src + ".o")
-        cmd = [HIPCC, *FLAGS, "-c", os.path.join(CSRC, src), "-o", obj]
+        cmd = [HIPCC, *FLAGS, *EXTRA.get(src, []), "-c", os.path.join(CSRC, src), "-o", obj]
         if verbose:
             print(" ".join(cmd), flush=True)
         subprocess.check_call(cmd)

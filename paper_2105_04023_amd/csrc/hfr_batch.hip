@@ -16,10 +16,18 @@
 // abort flag and leaves, which makes every other wave leave as well; only a
 // broken invariant can cause that, and the run then reports an error.
 //
-// Memory ordering: a wave releases (agent scope) before it counts a finished
-// tile and acquires after it claims one, so every tile of a phase sees all
-// writes of the phases before it, on every XCD.  Phase descriptors and
-// counters are read and written with atomic operations only.
+// Memory ordering: a wave releases before it counts a finished tile and
+// acquires after it claims one, so every tile of a phase sees all writes of
+// the phases before it.  Large jobs are served by every wave of the grid and
+// use agent scope (L2 write-back and invalidation across the XCDs).  Small
+// jobs, whose long chains of short phases make the per-phase cost dominant,
+// are pinned to one XCD at create (balanced by size over the XCDs found on
+// the device) and served only by waves on that XCD (hardware register
+// XCC_ID): all their data moves through one L2, and since this file is
+// compiled in threadgroup-split mode, where workgroup scope spans the CUs
+// that share an L2, their release is a wait for stores to reach L2 and their
+// acquire an L1 invalidation.  Phase descriptors and control words are
+// accessed with agent-scope atomic operations only.
 #include <hip/hip_runtime.h>
 #include <math.h>
 #include <string.h>
@@ -100,6 +108,7 @@ struct BJob {
     uint32_t thr_const;
     int32_t kind;
     int32_t J, P, PW, K;
+    int32_t pinned;  // served by the waves of one XCD only
     uint32_t seed;
     uint32_t thresh;  // the Simulate stops once |L| <= thresh
     double eps_g, eps_l;
@@ -134,22 +143,41 @@ struct BJob {
     BCtl* ctl;
 };
 
+constexpr int MAX_XCC = 16;
+
 struct BGlobal {
+    int32_t xbeg[MAX_XCC], xend[MAX_XCC];  // pinned jobs [xbeg[x], xend[x]) run on XCD x (host-written)
+    int32_t gbeg, gend;                    // jobs [gbeg, gend) run on every XCD
     alignas(128) uint32_t jobs_done;
     alignas(128) uint32_t abort;  // nonzero: the watchdog fired
     alignas(128) unsigned long long tiles;
     unsigned long long phases;
 };
 
-// ---- atomics (agent scope) ----
-DEVI unsigned long long ld64(const unsigned long long* p) {
+// ---- atomics ----
+#define JOB_SCOPE __HIP_MEMORY_SCOPE_AGENT
+DEVI unsigned long long ld64(const unsigned long long* p) { return __hip_atomic_load(p, __ATOMIC_RELAXED, JOB_SCOPE); }
+DEVI uint32_t ld32(const uint32_t* p) { return __hip_atomic_load(p, __ATOMIC_RELAXED, JOB_SCOPE); }
+DEVI void st64(unsigned long long* p, unsigned long long v) { __hip_atomic_store(p, v, __ATOMIC_RELAXED, JOB_SCOPE); }
+DEVI void st32(uint32_t* p, uint32_t v) { __hip_atomic_store(p, v, __ATOMIC_RELAXED, JOB_SCOPE); }
+DEVI uint32_t ld32_all(const uint32_t* p) {
     return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
-DEVI uint32_t ld32(const uint32_t* p) { return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT); }
-DEVI void st64(unsigned long long* p, unsigned long long v) {
-    __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+DEVI void job_release(bool pinned) {
+    if (pinned)
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
+    else
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
 }
-DEVI void st32(uint32_t* p, uint32_t v) { __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT); }
+DEVI void job_acquire(bool pinned) {
+    if (pinned)
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
+    else
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+}
+
+// Index of the XCD this wave runs on.
+DEVI uint32_t xcc_id() { return __builtin_amdgcn_s_getreg((3 << 11) | 20) & (MAX_XCC - 1); }
 
 DEVI unsigned long long bcast64(unsigned long long v) {
     const uint32_t lo = __builtin_amdgcn_readfirstlane((uint32_t)v);
@@ -646,32 +674,43 @@ DEVI void advance(const BJob& jb, BGlobal* gl, uint32_t seq) {
         store_desc(&c->d, d);
         st32(&c->done, 0u);
     }
-    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+    job_release(jb.pinned != 0);
     if (lane == 0) {
         st64(&c->dsc, ((unsigned long long)(seq + 1) << 32) | ntiles);
-        __hip_atomic_store(&c->claim, (unsigned long long)(seq + 1) << 32, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+        __hip_atomic_store(&c->claim, (unsigned long long)(seq + 1) << 32, __ATOMIC_RELEASE, JOB_SCOPE);
         atomicAdd(&gl->phases, 1ull);
         if (phase == PH_DONE) atomicAdd(&gl->jobs_done, 1u);
     }
 }
 
-// The persistent solver.  Every wave loops: claim a tile of some job, run it,
-// count it, and advance the job when it completed the phase's last tile.
+// The persistent solver.  Every wave loops: claim a tile of a pinned job of
+// its XCD or of a job served by all XCDs, run it, count it, and advance the
+// job when it completed the phase's last tile.  A wave that finds nothing
+// backs off (up to ~28 us) before it scans again; it raises the abort flag
+// when the claim words it scans have not changed for `timeout` ticks.
 template <int G, int DW>
 __global__ __launch_bounds__(256) void k_batch(const BJob* __restrict__ jobs, int njobs, BGlobal* gl,
                                                unsigned long long timeout_ticks) {
     const int lane = threadIdx.x & 63;
-    int start = (int)(wave_index() % njobs);
+    const uint32_t x = xcc_id();
+    const int pb = gl->xbeg[x], n1 = gl->xend[x] - pb;
+    const int gb = gl->gbeg, n2 = gl->gend - gb;
+    const int nmine = n1 + n2;
+    if (nmine <= 0) return;
+    int start = (int)(wave_index() % nmine);
     bool idle = false;
-    unsigned long long idle_t0 = 0, my_tiles = 0;
+    int backoff = 0;
+    unsigned long long idle_t0 = 0, last_sig = 0, my_tiles = 0;
     while (true) {
-        const uint32_t stop = lane == 0 ? (ld32(&gl->abort) | (ld32(&gl->jobs_done) >= (uint32_t)njobs ? 1u : 0u)) : 0u;
+        const uint32_t stop =
+            lane == 0 ? (ld32_all(&gl->abort) | (ld32_all(&gl->jobs_done) >= (uint32_t)njobs ? 1u : 0u)) : 0u;
         if (__builtin_amdgcn_readfirstlane(stop)) break;
         int jsel = -1;
-        unsigned long long claim = 0, dsc = 0;
-        for (int i = 0; i < njobs && jsel < 0; ++i) {
-            int j = start + i;
-            if (j >= njobs) j -= njobs;
+        unsigned long long claim = 0, dsc = 0, sig = 0;
+        for (int i = 0; i < nmine && jsel < 0; ++i) {
+            int idx = start + i;
+            if (idx >= nmine) idx -= nmine;
+            const int j = idx < n1 ? pb + idx : gb + (idx - n1);
             BCtl* c = jobs[j].ctl;
             unsigned long long w = 0, ds = 0;
             if (lane == 0) {
@@ -680,11 +719,12 @@ __global__ __launch_bounds__(256) void k_batch(const BJob* __restrict__ jobs, in
             }
             w = bcast64(w);
             ds = bcast64(ds);
+            sig = sig * 0x9E3779B97F4A7C15ull + w;
             if ((w >> 32) != (ds >> 32) || (uint32_t)w >= (uint32_t)ds) continue;
             unsigned long long old = 0, ds2 = 0;
             if (lane == 0) {
-                old = __hip_atomic_fetch_add(&c->claim, 1ull, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT);
-                ds2 = __hip_atomic_load(&c->dsc, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT);
+                old = __hip_atomic_fetch_add(&c->claim, 1ull, __ATOMIC_ACQUIRE, JOB_SCOPE);
+                ds2 = __hip_atomic_load(&c->dsc, __ATOMIC_ACQUIRE, JOB_SCOPE);
             }
             old = bcast64(old);
             ds2 = bcast64(ds2);
@@ -693,44 +733,53 @@ __global__ __launch_bounds__(256) void k_batch(const BJob* __restrict__ jobs, in
                 jsel = j;
                 claim = old;
                 dsc = ds2;
+                start = idx;
             }
         }
         if (jsel < 0) {
             const unsigned long long now = wall_clock64();
-            if (!idle) {
+            if (!idle || sig != last_sig) {  // some job moved: not stuck
                 idle = true;
                 idle_t0 = now;
+                last_sig = sig;
             } else if (now - idle_t0 > timeout_ticks) {
                 if (lane == 0) atomicOr(&gl->abort, 1u);
                 break;
             }
-            __builtin_amdgcn_s_sleep(4);
+            if (backoff < 10) ++backoff;
+            for (int i = 0; i < (1 << backoff); ++i) __builtin_amdgcn_s_sleep(1);
             continue;
         }
         idle = false;
-        start = jsel;
-        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+        backoff = 0;
         const BJob& jb = jobs[jsel];
+        const bool pinned = jb.pinned != 0;
+        job_acquire(pinned);
         BCtl* c = jb.ctl;
         const BDesc d = load_desc(&c->d);
         run_tile<G, DW>(jb, c, d, (int)(uint32_t)claim);
         ++my_tiles;
-        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+        job_release(pinned);
         uint32_t prev = 0;
-        if (lane == 0) prev = __hip_atomic_fetch_add(&c->done, 1u, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_AGENT);
+        if (lane == 0) prev = __hip_atomic_fetch_add(&c->done, 1u, __ATOMIC_ACQ_REL, JOB_SCOPE);
         prev = __builtin_amdgcn_readfirstlane(prev);
         if (prev + 1 == (uint32_t)dsc) {
-            __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+            job_acquire(pinned);
             advance(jb, gl, (uint32_t)(dsc >> 32));
         }
     }
     if (lane == 0 && my_tiles) atomicAdd(&gl->tiles, my_tiles);
 }
 
+// Records the XCD ids that run waves of a large grid (bit x of *mask).
+__global__ void k_xcc_probe(uint32_t* mask) {
+    if ((threadIdx.x & 63) == 0) atomicOr(mask, 1u << xcc_id());
+}
+
 // Arms every job at phase PH_INIT0 (sequence 1) and clears the run counters.
 __global__ void k_batch_arm(const BJob* __restrict__ jobs, int njobs, BGlobal* gl) {
     const int j = blockIdx.x * blockDim.x + threadIdx.x;
-    if (j == 0) {
+    if (j == 0) {  // the job ranges per XCD stay as the host wrote them
         gl->jobs_done = 0;
         gl->abort = 0;
         gl->tiles = 0;
@@ -763,6 +812,7 @@ struct BatchCfg {
     int heavy_degree = 512;
     int piece_edges = 512;
     int workgroups = 0;
+    int64_t pin_edges = 0;  // jobs with at most this many edges run on one XCD (< 0: none)
 };
 
 struct HostJob {
@@ -787,8 +837,9 @@ using namespace hfr;
 struct im_batch {
     im_ctx* ctx = nullptr;
     bool poisoned = false;
-    std::vector<HostJob> jobs;      // sorted by decreasing edge count
-    std::vector<int32_t> order_of;  // caller's index -> position in jobs
+    std::vector<HostJob> jobs;      // in the caller's order
+    std::vector<int32_t> perm;      // device position -> caller's index (see place_jobs)
+    std::vector<int> xccs;          // XCD ids that run waves
     std::vector<void*> bufs;
     size_t bytes = 0;
     BJob* d_jobs = nullptr;
@@ -804,6 +855,11 @@ struct im_batch {
     bool ran = false;
     std::vector<BCtl> h_ctl;
     BGlobal h_gl{};
+    int32_t xbeg[MAX_XCC] = {}, xend[MAX_XCC] = {};  // job ranges per XCD id
+    int32_t gbeg = 0, gend = 0;                        // jobs served by every XCD
+    int nxcc = 0;                                      // XCDs found by the probe
+    int32_t pin_request = 0;                           // im_batch_opts.pin_edges
+    int grid = 0;                                      // workgroups of the captured launch
 };
 
 namespace {
@@ -850,11 +906,17 @@ int min_lanes(int Pmax) {
 }
 
 // Tile tables of one job for a decomposition: row tiles of whole 32-row
-// words holding about tile_edges merged edges (one per row counted too),
-// pieces of split rows, and the tile sizes of the other phases.
+// words holding about te merged edges (one per row counted too), pieces of
+// split rows, and the tile sizes of the other phases.  te is tile_edges, or
+// less for small jobs so that a phase still spreads over about MIN_TILES
+// tiles: a tile's rows are walked by one wave, one dependent chain of loads
+// per row group, so small tiles bound the latency of a phase.
+constexpr int64_t MIN_TILES = 512;
+
 void make_tiles(const HostJob& h, const BatchCfg& cfg, std::vector<int32_t>& rtile, BJob& dj) {
     const int RPW = 64 / cfg.G;
     const int64_t n = h.n;
+    const int64_t te = std::max<int64_t>(64, std::min<int64_t>(cfg.tile_edges, (h.m + n) / MIN_TILES));
     rtile.clear();
     rtile.push_back(0);
     int64_t acc = 0;
@@ -864,18 +926,18 @@ void make_tiles(const HostJob& h, const BatchCfg& cfg, std::vector<int32_t>& rti
             const int64_t dgr = h.xadj[u + 1] - h.xadj[u];
             acc += (dgr <= cfg.heavy_degree ? dgr : 0) + 1;
         }
-        if (acc >= cfg.tile_edges || we == n) {
+        if (acc >= te || we == n) {
             rtile.push_back((int32_t)we);
             acc = 0;
         }
     }
     dj.nrt = (int32_t)(rtile.size() - 1);
-    const int64_t ppt = (int64_t)RPW * std::max<int64_t>(1, cfg.tile_edges / ((int64_t)cfg.piece_edges * RPW));
+    const int64_t ppt = (int64_t)RPW * std::max<int64_t>(1, te / ((int64_t)cfg.piece_edges * RPW));
     dj.ppt = (int32_t)ppt;
     dj.npt = (int32_t)((h.pe0.size() + ppt - 1) / ppt);
     dj.hpt = RPW * 4;
     dj.nht = (int32_t)((h.hrow.size() + dj.hpt - 1) / dj.hpt);
-    dj.ept = std::max(RPW, (int)(cfg.tile_edges / BFS_CHUNK_B / RPW) * RPW);
+    dj.ept = std::max(RPW, (int)(te / BFS_CHUNK_B / RPW) * RPW);
     dj.cpt = 1024;
 }
 
@@ -901,19 +963,63 @@ void split_rows(HostJob& h, int64_t heavy, int64_t piece) {
     }
 }
 
+// Placement for the current decomposition: jobs with at most pin_edges edges
+// are pinned to XCDs, largest first onto the least loaded; the others are
+// served by every XCD.  Device order: the global jobs (largest first), then
+// the pinned jobs of each XCD (largest first), so that within every scan
+// range the largest jobs' phases are claimed first.
+void place_jobs(im_batch* b) {
+    const int count = (int)b->jobs.size();
+    std::vector<int32_t> ord(count), home(count, -1);
+    for (int i = 0; i < count; ++i) ord[i] = i;
+    std::stable_sort(ord.begin(), ord.end(), [&](int a, int c) { return b->jobs[a].m > b->jobs[c].m; });
+    std::vector<double> load(b->xccs.size(), 0.0);
+    for (int i : ord) {
+        if (b->jobs[i].m > b->cfg.pin_edges) continue;
+        const size_t x = std::min_element(load.begin(), load.end()) - load.begin();
+        home[i] = (int32_t)x;
+        load[x] += (double)(b->jobs[i].m + b->jobs[i].n) * (double)b->jobs[i].J;
+    }
+    std::stable_sort(ord.begin(), ord.end(), [&](int a, int c) { return home[a] < home[c]; });
+    b->perm = ord;
+    for (int x = 0; x < MAX_XCC; ++x) b->xbeg[x] = b->xend[x] = 0;
+    b->gbeg = b->gend = 0;
+    for (int k = 0; k < count; ++k) {
+        const int hx = home[ord[k]];
+        b->jobs[ord[k]].dj.pinned = hx >= 0;
+        if (hx < 0) {
+            b->gend = k + 1;
+            continue;
+        }
+        const int x = b->xccs[hx];
+        if (b->xend[x] == 0 && b->xbeg[x] == 0) b->xbeg[x] = k;
+        b->xend[x] = k + 1;
+    }
+}
+
+// Places the jobs and uploads the tile tables, the job array and the job
+// ranges of the current decomposition.
 im_status upload_tiles(im_batch* b) {
     hipStream_t s = b->stream;
+    place_jobs(b);
     std::vector<BJob> dj(b->jobs.size());
-    for (size_t i = 0; i < b->jobs.size(); ++i) {
-        HostJob& h = b->jobs[i];
+    for (size_t k = 0; k < b->jobs.size(); ++k) {
+        HostJob& h = b->jobs[b->perm[k]];
         std::vector<int32_t> rt;
         make_tiles(h, b->cfg, rt, h.dj);
         if ((int64_t)rt.size() > h.rtile_cap) return fail(IM_ERR_STATE, "row tile table overflow");
         BHIP(hipMemcpyAsync(h.d_rtile, rt.data(), 4 * rt.size(), hipMemcpyHostToDevice, s));
         BHIP(hipStreamSynchronize(s));
-        dj[i] = h.dj;
+        dj[k] = h.dj;
     }
     BHIP(hipMemcpyAsync(b->d_jobs, dj.data(), sizeof(BJob) * dj.size(), hipMemcpyHostToDevice, s));
+    BGlobal g0;
+    memset(&g0, 0, sizeof(g0));
+    memcpy(g0.xbeg, b->xbeg, sizeof(g0.xbeg));
+    memcpy(g0.xend, b->xend, sizeof(g0.xend));
+    g0.gbeg = b->gbeg;
+    g0.gend = b->gend;
+    BHIP(hipMemcpyAsync(b->d_gl, &g0, sizeof(g0), hipMemcpyHostToDevice, s));
     BHIP(hipStreamSynchronize(s));
     return IM_OK;
 }
@@ -929,7 +1035,11 @@ im_status capture(im_batch* b) {
     }
     hipStream_t s = b->stream;
     const int nj = (int)b->jobs.size();
-    const int grid = b->cfg.workgroups;
+    // workgroups are dispatched round-robin over the XCDs: a multiple of their
+    // count gives every XCD the same share of waves
+    const int nx = std::max(1, b->nxcc);
+    const int grid = (std::max(b->cfg.workgroups, nx) + nx - 1) / nx * nx;
+    b->grid = grid;
     BHIP(hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal));
     hipLaunchKernelGGL(k_batch_arm, dim3((nj + 255) / 256), dim3(256), 0, s, b->d_jobs, nj, b->d_gl);
     switch (b->cfg.G) {
@@ -1051,6 +1161,7 @@ im_status im_batch_create(im_ctx* ctx, int32_t count, const im_batch_job* jobs, 
     if (o.tile_edges) b->cfg.tile_edges = o.tile_edges;
     if (o.heavy_degree) b->cfg.heavy_degree = o.heavy_degree;
     if (o.piece_edges) b->cfg.piece_edges = o.piece_edges;
+    b->pin_request = o.pin_edges;
     b->cfg.workgroups = o.workgroups ? o.workgroups : 4 * b->cus;
 
     auto bail = [&](im_status st) {
@@ -1088,18 +1199,31 @@ im_status im_batch_create(im_ctx* ctx, int32_t count, const im_batch_job* jobs, 
         for (int64_t e = 0; e < h.m; ++e)
             if (h.adj[e] < 0 || h.adj[e] >= h.n) return bail(fail(IM_ERR_INVALID_GRAPH, "job %d: adj holds an id outside [0, n)", i));
     }
-    // the largest jobs first: their phases are claimed first
-    std::vector<int32_t> ord(count);
-    for (int i = 0; i < count; ++i) ord[i] = i;
-    std::stable_sort(ord.begin(), ord.end(), [&](int a, int c) { return b->jobs[a].m > b->jobs[c].m; });
+    // XCDs that run waves: a probe launch records their ids
+    uint32_t xmask = 0;
     {
-        std::vector<HostJob> sorted;
-        sorted.reserve(count);
-        for (int i : ord) sorted.push_back(std::move(b->jobs[i]));
-        b->jobs.swap(sorted);
+        uint32_t* dmask = balloc<uint32_t>(b, 1);
+        if (!dmask) return bail(fail(IM_ERR_OUT_OF_BUDGET, "device allocation failed"));
+        if (hipMemsetAsync(dmask, 0, 4, s) != hipSuccess) return bail(fail(IM_ERR_DEVICE, "memset failed"));
+        hipLaunchKernelGGL(k_xcc_probe, dim3(4 * b->cus), dim3(256), 0, s, dmask);
+        if (hipGetLastError() != hipSuccess || hipMemcpyAsync(&xmask, dmask, 4, hipMemcpyDeviceToHost, s) != hipSuccess ||
+            hipStreamSynchronize(s) != hipSuccess)
+            return bail(fail(IM_ERR_DEVICE, "XCD probe failed"));
     }
-    b->order_of.assign(count, 0);
-    for (int i = 0; i < count; ++i) b->order_of[b->jobs[i].index] = i;
+    std::vector<int> xccs;
+    for (int x = 0; x < MAX_XCC; ++x)
+        if (xmask & (1u << x)) xccs.push_back(x);
+    if (xccs.empty()) return bail(fail(IM_ERR_DEVICE, "XCD probe found no XCD"));
+    b->nxcc = (int)xccs.size();
+    b->xccs = xccs;
+    {
+        // default: a job runs on one XCD unless it holds more than half of an
+        // XCD's fair share of the batch's edges
+        int64_t mtot = 0;
+        for (const HostJob& h : b->jobs) mtot += h.m;
+        const int64_t dflt = std::max<int64_t>(1 << 16, mtot / (2 * (int64_t)xccs.size()));
+        b->cfg.pin_edges = b->pin_request > 0 ? b->pin_request : (b->pin_request < 0 ? -1 : dflt);
+    }
 
     for (HostJob& h : b->jobs) {
         const im_batch_job& j = jobs[h.index];
@@ -1179,6 +1303,9 @@ im_status im_batch_create(im_ctx* ctx, int32_t count, const im_batch_job* jobs, 
         dj.pe1 = pe1;
         dj.thr = thr;
         dj.indeg = indeg;
+        // queue entries always name a vertex, even before they are first written
+        if (hipMemsetAsync(dj.Q[0], 0, 8 * qcap, s) != hipSuccess || hipMemsetAsync(dj.Q[1], 0, 8 * qcap, s) != hipSuccess)
+            return bail(fail(IM_ERR_DEVICE, "queue initialisation failed"));
         if (hipMemcpyAsync(xadj, h.xadj.data(), 8 * (n + 1), hipMemcpyHostToDevice, s) != hipSuccess ||
             (m > 0 && hipMemcpyAsync(adj, h.adj.data(), 4 * m, hipMemcpyHostToDevice, s) != hipSuccess))
             return bail(fail(IM_ERR_DEVICE, "CSR upload failed"));
@@ -1226,16 +1353,16 @@ im_status im_batch_create(im_ctx* ctx, int32_t count, const im_batch_job* jobs, 
         // every candidate decomposition solves the batch once; the fastest is
         // kept and all of them must agree on every seed
         std::vector<BatchCfg> cands;
-        std::vector<int> Gs = {b->cfg.G};
-        if (!o.lanes_per_row && b->cfg.G < 64) Gs.push_back(64);
-        std::vector<int> tiles = o.tile_edges ? std::vector<int>{o.tile_edges} : std::vector<int>{4096, 16384};
+        std::vector<int> tiles = o.tile_edges ? std::vector<int>{o.tile_edges} : std::vector<int>{2048, 4096, 8192};
+        std::vector<int64_t> pins = o.pin_edges ? std::vector<int64_t>{b->cfg.pin_edges}
+                                                : std::vector<int64_t>{b->cfg.pin_edges, -1};
         std::vector<int> wgs = o.workgroups ? std::vector<int>{o.workgroups} : std::vector<int>{2 * b->cus, 4 * b->cus};
-        for (int G : Gs)
-            for (int te : tiles)
+        for (int te : tiles)
+            for (int64_t pe : pins)
                 for (int wg : wgs) {
                     BatchCfg c = b->cfg;
-                    c.G = G;
                     c.tile_edges = te;
+                    c.pin_edges = pe;
                     c.workgroups = wg;
                     cands.push_back(c);
                 }
@@ -1282,7 +1409,7 @@ im_status im_batch_run(im_batch* b, im_batch_stats* stats) {
         stats->tile_edges = b->cfg.tile_edges;
         stats->heavy_degree = b->cfg.heavy_degree;
         stats->piece_edges = b->cfg.piece_edges;
-        stats->workgroups = b->cfg.workgroups;
+        stats->workgroups = b->grid;
         stats->candidates = b->candidates;
     }
     return IM_OK;
@@ -1293,9 +1420,8 @@ im_status im_batch_get_result(const im_batch* b, int32_t job, int32_t* out_seeds
     if (!b) return fail(IM_ERR_INVALID_ARG, "null batch");
     if (job < 0 || job >= (int32_t)b->jobs.size()) return fail(IM_ERR_INVALID_ARG, "job index out of range");
     if (!b->ran) return fail(IM_ERR_STATE, "the batch has not run");
-    const int i = b->order_of[job];
-    const HostJob& h = b->jobs[i];
-    const BCtl& c = b->h_ctl[i];
+    const HostJob& h = b->jobs[job];
+    const BCtl& c = b->h_ctl[job];
     if (res) {
         res->status = c.r.status;
         res->build_sweeps = (int32_t)c.r.build_sweeps;
@@ -1337,9 +1463,8 @@ im_status im_batch_get_registers(const im_batch* b, int32_t job, int32_t which, 
     if (job < 0 || job >= (int32_t)b->jobs.size()) return fail(IM_ERR_INVALID_ARG, "job index out of range");
     if (which != 0 && which != 1) return fail(IM_ERR_INVALID_ARG, "which must be 0 or 1");
     if (!b->ran) return fail(IM_ERR_STATE, "the batch has not run");
-    const int i = b->order_of[job];
-    const HostJob& h = b->jobs[i];
-    const BCtl& c = b->h_ctl[i];
+    const HostJob& h = b->jobs[job];
+    const BCtl& c = b->h_ctl[job];
     const int buf = which == 0 ? c.d.build_buf : (int)c.r.sel_buf;
     if (buf < 0 || buf > 2) return fail(IM_ERR_STATE, "no registers recorded");
     if (hipMemcpy(out, h.dj.M[buf], (size_t)h.n * h.J, hipMemcpyDeviceToHost) != hipSuccess)

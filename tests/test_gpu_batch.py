@@ -124,6 +124,9 @@ def _check_batch(b, specs):
     dict(lanes_per_row=64),
     dict(tile_edges=256, heavy_degree=16, piece_edges=8, workgroups=64),
     dict(tile_edges=64, heavy_degree=4, piece_edges=3, workgroups=7),
+    dict(pin_edges=-1),
+    dict(pin_edges=1 << 30, tile_edges=128),
+    dict(pin_edges=3000, workgroups=40),
 ])
 def test_mixed_batch_matches_oracle(hf, ctx, cfg):
     """Uneven graphs, all three edge models, R from 4 to 256 and K up to n in one launch."""
