@@ -317,6 +317,70 @@ IM_API im_status im_batch_get_registers(const im_batch* b, int32_t job, int32_t 
 IM_API size_t im_batch_device_bytes(const im_batch* b);
 IM_API void im_batch_free(im_batch* b);
 
+/*
+ * ---------------------------------------------------------------------------
+ * Serving: requests (graph, edge model, R, K) over a pool of resident graphs,
+ * answered by `slots` concurrent slots.  Each slot has its own host thread and
+ * HIP stream, so requests of different slots overlap on the device; requests
+ * that arrive while the slots are busy wait in a queue and start as soon as
+ * their slot is free.  A slot keeps the sketches it built resident and reuses
+ * them for later requests with the same (graph, model, p, R, hash seed,
+ * eps_c); every request runs its own greedy selection, so its result equals
+ * im_build_sketches + im_select_seeds run alone.  hbm_budget (0 = none) bounds
+ * the device memory of the resident graphs plus all sketches; each slot holds
+ * at most an equal share of what the graphs leave and evicts its least
+ * recently used idle sketches to admit a new build.
+ * ---------------------------------------------------------------------------
+ */
+typedef struct im_server_opts {
+    int32_t slots;      /* concurrent requests, in [1, 64] */
+    int32_t reserved;
+    size_t hbm_budget;  /* device bytes for graphs and sketches; 0 = no bound */
+} im_server_opts;
+
+typedef struct im_request {
+    int32_t graph;       /* id from im_server_add_graph */
+    im_prob_kind kind;   /* IM_PROB_CONSTANT or IM_PROB_WEIGHTED_CASCADE */
+    float p;             /* constant probability (kind IM_PROB_CONSTANT) */
+    int32_t R;           /* multiple of 4 in [4, 1024] */
+    int32_t K;           /* in [1, n] */
+    uint32_t hash_seed;
+    double eps_c;        /* as im_build_opts.eps_c */
+    double eps_g, eps_l; /* as im_select_opts (no defaults are substituted) */
+} im_request;
+
+typedef struct im_response {
+    int32_t status;        /* IM_OK, or the error of this request */
+    int32_t slot;          /* slot that served it */
+    int32_t sketch_reused; /* 1 if its sketches were resident already */
+    int32_t rebuilds;      /* rebuilds of its greedy selection */
+    double queue_ms;       /* submit to start */
+    double build_ms;       /* sketch build (0 when reused) */
+    double select_ms;      /* greedy selection */
+    double latency_ms;     /* submit to completion */
+} im_response;
+
+typedef struct im_server_stats {
+    int64_t submitted, completed, failed;
+    int64_t sketches_built, evictions, resident_sketches;
+    size_t device_bytes;   /* graphs plus resident sketches */
+} im_server_stats;
+
+typedef struct im_server im_server;
+
+IM_API im_status im_server_create(int32_t device, const im_server_opts* opts, im_server** out);
+/* Copies a CSR (host or device) into the resident pool; all graphs are added
+ * before the first request.  *out_graph receives its id. */
+IM_API im_status im_server_add_graph(im_server* sv, const im_csr* graph, int32_t* out_graph);
+/* Queues a request; out_seeds (K entries, host) must stay valid until
+ * im_server_wait returns for *out_ticket.  Thread-safe. */
+IM_API im_status im_server_submit(im_server* sv, const im_request* rq, int32_t* out_seeds, int64_t* out_ticket);
+/* Blocks until the request is done; fills *out (may be NULL) and returns its status. */
+IM_API im_status im_server_wait(im_server* sv, int64_t ticket, im_response* out);
+IM_API im_status im_server_get_stats(im_server* sv, im_server_stats* out);
+/* Finishes the queued requests, then frees every resource of the server. */
+IM_API void im_server_free(im_server* sv);
+
 /* Thread-local message of the last failed call on this thread ("" if none). */
 IM_API const char* im_last_error(void);
 

@@ -14,7 +14,7 @@ import numpy as np
 
 from . import _binding as B
 
-__all__ = ["Context", "Sketch", "Batch", "BatchJob", "im_build_sketches", "im_estimate", "im_estimate_all",
+__all__ = ["Context", "Sketch", "Batch", "BatchJob", "Server", "im_build_sketches", "im_estimate", "im_estimate_all",
            "im_select_seeds", "im_batch_create", "ImError"]
 
 ImError = B.ImError
@@ -312,3 +312,65 @@ def im_batch_create(ctx: Context, jobs, autotune: bool = False, lanes_per_row: i
                                     ctypes.byref(h)))
     del keep
     return Batch(ctx, h, jobs)
+
+
+class Server:
+    """Serving engine of the library (im_server_*): resident graphs, concurrent slots, sketch reuse,
+    admission by an HBM budget.  submit() returns a ticket; wait() blocks for its seeds and response."""
+
+    def __init__(self, device: int = 0, slots: int = 4, hbm_budget: int = 0):
+        self.lib = B.load()
+        h = ctypes.c_void_p()
+        B.check(self.lib.im_server_create(device, ctypes.byref(B.im_server_opts(slots, 0, hbm_budget)),
+                                          ctypes.byref(h)))
+        self.handle = h
+        self._ns = []
+        self._pending = {}
+
+    def add_graph(self, xadj, adj, n: int) -> int:
+        torch = _torch()
+        xp, xdev, xk = _ptr_and_residency(xadj, (np.int64, torch.int64))
+        ap, adev, ak = _ptr_and_residency(adj, (np.int32, torch.int32))
+        if xdev != adev:
+            raise ValueError("xadj and adj must both be host arrays or both device tensors")
+        m = int(len(adj)) if not isinstance(adj, torch.Tensor) else int(adj.numel())
+        gid = ctypes.c_int32()
+        B.check(self.lib.im_server_add_graph(self.handle, ctypes.byref(B.im_csr(n, m, xp, ap, xdev)),
+                                             ctypes.byref(gid)))
+        self._ns.append(n)
+        return gid.value
+
+    def submit(self, graph: int, R: int, K: int, model: str = "const", p: float = 0.0, hash_seed: int = 0,
+               eps_c: float = 0.0, eps_g: float = 0.01, eps_l: float = 0.3) -> int:
+        if model not in ("const", "wc"):
+            raise ValueError("requests take model 'const' or 'wc'")
+        seeds = np.zeros(K, dtype=np.int32)
+        rq = B.im_request(graph, _KIND[model], p, R, K, hash_seed & 0xFFFFFFFF, eps_c, eps_g, eps_l)
+        t = ctypes.c_int64()
+        B.check(self.lib.im_server_submit(self.handle, ctypes.byref(rq), seeds.ctypes.data, ctypes.byref(t)))
+        self._pending[t.value] = seeds
+        return t.value
+
+    def wait(self, ticket: int):
+        """(seeds, response dict); raises ImError if the request failed."""
+        resp = B.im_response()
+        st = self.lib.im_server_wait(self.handle, ticket, ctypes.byref(resp))
+        seeds = self._pending.pop(ticket)
+        B.check(st)
+        return seeds, {f: getattr(resp, f) for f, _ in B.im_response._fields_}
+
+    def stats(self) -> dict:
+        s = B.im_server_stats()
+        B.check(self.lib.im_server_get_stats(self.handle, ctypes.byref(s)))
+        return {f: getattr(s, f) for f, _ in B.im_server_stats._fields_}
+
+    def close(self):
+        if self.handle:
+            self.lib.im_server_free(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

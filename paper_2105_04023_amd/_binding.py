@@ -22,7 +22,8 @@ EXPORTED = [
     "im_estimate", "im_estimate_all", "im_select_seeds", "im_sketch_get_info", "im_sketch_get_trace",
     "im_sketch_get_registers", "im_sketch_get_blocked", "im_sketch_free", "im_last_error", "im_version",
     "im_sketch_get_sweep_log", "im_sketch_clear_sweep_log", "im_batch_create", "im_batch_run", "im_batch_get_result",
-    "im_batch_get_registers", "im_batch_device_bytes", "im_batch_free",
+    "im_batch_get_registers", "im_batch_device_bytes", "im_batch_free", "im_server_create", "im_server_add_graph",
+    "im_server_submit", "im_server_wait", "im_server_get_stats", "im_server_free",
 ]
 
 
@@ -102,6 +103,28 @@ class im_batch_stats(ctypes.Structure):
                 ("candidates", ctypes.c_int32)]
 
 
+class im_server_opts(ctypes.Structure):
+    _fields_ = [("slots", ctypes.c_int32), ("reserved", ctypes.c_int32), ("hbm_budget", ctypes.c_size_t)]
+
+
+class im_request(ctypes.Structure):
+    _fields_ = [("graph", ctypes.c_int32), ("kind", ctypes.c_int), ("p", ctypes.c_float), ("R", ctypes.c_int32),
+                ("K", ctypes.c_int32), ("hash_seed", ctypes.c_uint32), ("eps_c", ctypes.c_double),
+                ("eps_g", ctypes.c_double), ("eps_l", ctypes.c_double)]
+
+
+class im_response(ctypes.Structure):
+    _fields_ = [("status", ctypes.c_int32), ("slot", ctypes.c_int32), ("sketch_reused", ctypes.c_int32),
+                ("rebuilds", ctypes.c_int32), ("queue_ms", ctypes.c_double), ("build_ms", ctypes.c_double),
+                ("select_ms", ctypes.c_double), ("latency_ms", ctypes.c_double)]
+
+
+class im_server_stats(ctypes.Structure):
+    _fields_ = [("submitted", ctypes.c_int64), ("completed", ctypes.c_int64), ("failed", ctypes.c_int64),
+                ("sketches_built", ctypes.c_int64), ("evictions", ctypes.c_int64),
+                ("resident_sketches", ctypes.c_int64), ("device_bytes", ctypes.c_size_t)]
+
+
 ALLOC_FN = ctypes.CFUNCTYPE(ctypes.c_void_p, ctypes.c_size_t, ctypes.c_void_p)
 FREE_FN = ctypes.CFUNCTYPE(None, ctypes.c_void_p, ctypes.c_void_p)
 
@@ -143,6 +166,12 @@ def load(path: str = LIB_PATH):
         "im_batch_get_registers": ([p, i32, i32, p], ctypes.c_int),
         "im_batch_device_bytes": ([p], sz),
         "im_batch_free": ([p], None),
+        "im_server_create": ([i32, ctypes.POINTER(im_server_opts), ctypes.POINTER(p)], ctypes.c_int),
+        "im_server_add_graph": ([p, ctypes.POINTER(im_csr), ctypes.POINTER(i32)], ctypes.c_int),
+        "im_server_submit": ([p, ctypes.POINTER(im_request), p, ctypes.POINTER(i64)], ctypes.c_int),
+        "im_server_wait": ([p, i64, ctypes.POINTER(im_response)], ctypes.c_int),
+        "im_server_get_stats": ([p, ctypes.POINTER(im_server_stats)], ctypes.c_int),
+        "im_server_free": ([p], None),
     }
     for name, (args, res) in sig.items():
         fn = getattr(lib, name)

@@ -10,7 +10,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 OBJDIR = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "libhipfuser.so")
-SOURCES = ["hfr_kernels.hip", "hfr_api.hip", "hfr_batch.hip"]
+SOURCES = ["hfr_kernels.hip", "hfr_api.hip", "hfr_batch.hip", "hfr_server.hip"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 
 # -ffp-contract=off keeps the FP64 estimate and decision free of fused multiply-adds;

@@ -82,7 +82,7 @@ def test_ctypes_structs_match_the_c_layout(tmp_path):
 
     structs = [B.im_csr, B.im_probs, B.im_build_opts, B.im_select_opts, B.im_step, B.im_sketch_info,
                B.im_sweep_rec, B.im_select_stats, B.im_batch_job, B.im_batch_opts, B.im_batch_job_result,
-               B.im_batch_stats]
+               B.im_batch_stats, B.im_server_opts, B.im_request, B.im_response, B.im_server_stats]
     lines = ['#include <stdio.h>', '#include <stddef.h>', '#include "im.h"', "int main(void) {"]
     for s in structs:
         lines.append(f'printf("{s.__name__} %zu\\n", sizeof({s.__name__}));')
