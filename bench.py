@@ -139,6 +139,57 @@ def batch_leg(hf, ctx, steps: int, warmup: int):
     }
 
 
+def serve_leg(hf, n_requests: int, slots: int = 4, budget_gb: int = 200):
+    """Poisson stream (mean 200 requests/s, seed 5) over 16 resident R-MAT graphs (log2 n in 14..22,
+    degree 16); each request: IC p=0.01, IC p=0.1 or weighted cascade, R in {64, 256}, K in 10..100.
+    The stream is replayed in real time against the library's serving engine under a 200 GB budget;
+    latency is submit-to-completion as the engine measures it."""
+    import numpy as np
+
+    import synth
+
+    t = time.perf_counter()
+    pool, stream = synth.serving_recipe(requests=n_requests)
+    graphs = [synth.rmat(scale, draws, seed=seed) for scale, draws, seed in pool]
+    log(f"serving workload: {len(graphs)} graphs (n={sum(g.n for g in graphs)}, m={sum(g.m for g in graphs)}), "
+        f"{len(stream)} requests over {stream[-1][0]:.1f} s, generated in {time.perf_counter() - t:.1f} s")
+    sv = hf.Server(0, slots=slots, hbm_budget=budget_gb << 30)
+    try:
+        for g in graphs:
+            sv.add_graph(g.xadj, g.adj, g.n)
+        t0 = time.perf_counter()
+        tickets = []
+        for i, (arr, gi, model, p, R, K) in enumerate(stream):
+            delay = t0 + arr - time.perf_counter()
+            if delay > 0:
+                time.sleep(delay)
+            tickets.append(sv.submit(gi, R, K, model=model, p=p))
+            if (i + 1) % 500 == 0:
+                log(f"serving: {i + 1} submitted")
+        lat, reused, qms = [], 0, []
+        for i, tk in enumerate(tickets):
+            _, resp = sv.wait(tk)
+            lat.append(resp["latency_ms"])
+            qms.append(resp["queue_ms"])
+            reused += resp["sketch_reused"]
+            if (i + 1) % 500 == 0:
+                log(f"serving: {i + 1} completed")
+        wall = time.perf_counter() - t0
+        st = sv.stats()
+    finally:
+        sv.close()
+    lat = np.asarray(lat)
+    return {
+        "workload": "serve_16rmat_log2n14-22_deg16_poisson200_" + str(n_requests),
+        "requests": len(stream), "slots": slots, "hbm_budget_gb": budget_gb,
+        "throughput_req_s": len(stream) / wall, "wall_s": wall,
+        "latency_ms_p50": float(np.percentile(lat, 50)), "latency_ms_p99": float(np.percentile(lat, 99)),
+        "latency_ms_mean": float(lat.mean()), "queue_ms_p50": float(np.percentile(qms, 50)),
+        "sketch_reuse_frac": reused / len(stream), "sketches_built": st["sketches_built"],
+        "evictions": st["evictions"], "peak_resident_sketches": st["resident_sketches"],
+    }
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -147,6 +198,8 @@ def main():
     ap.add_argument("--workload", default="rmat24_wc_J256_K50", choices=sorted(WORKLOADS))
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-batch", action="store_true", help="skip the batched-vs-plain comparison")
+    ap.add_argument("--serve-requests", type=int, default=400,
+                    help="requests of the serving leg (the full stream has 2000; 0 skips the leg)")
     ap.add_argument("--K", type=int, default=0, help="override K")
     ap.add_argument("--sparse-div", type=int, default=0)
     ap.add_argument("--heavy-degree", type=int, default=0)
@@ -255,6 +308,8 @@ def main():
     }
     if not args.no_batch:
         out["batched"] = batch_leg(hf, ctx, args.steps, args.warmup)
+    if args.serve_requests > 0:
+        out["serving"] = serve_leg(hf, args.serve_requests)
     if args.dump_sweeps:
         with open(args.dump_sweeps, "w") as fh:
             json.dump(results[-1]["sweep_log"], fh)

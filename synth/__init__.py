@@ -12,6 +12,7 @@ R-MAT and Erdos-Renyi graphs with the same degree range stand in for them.
 from __future__ import annotations
 
 import ctypes
+import math
 import os
 import subprocess
 import threading
@@ -174,3 +175,28 @@ def batch_recipe(master_seed: int = 4, count: int = 64):
         p = (0.005, 0.01, 0.05)[int(r2 % 3)]
         out.append((scale, int(round(deg * (1 << scale))), p, 1000 * master_seed + i))
     return out
+
+
+def serving_recipe(master_seed: int = 5, graphs: int = 16, requests: int = 2000, rate: float = 200.0):
+    """The serving workload: a pool of R-MAT graphs and a Poisson request stream.
+
+    Graphs: log2 n uniform over the integers 14..22, average degree 16 (draws = 16 n),
+    graph seed 100 * master_seed + index.  Requests: exponential inter-arrival gaps
+    with mean 1/rate seconds; graph uniform over the pool; model uniform over
+    {IC p=0.01, IC p=0.1, weighted cascade}; R uniform over {64, 256}; K uniform
+    over the integers 10..100.  Returns (pool, stream) with pool entries
+    (scale, draws, seed) and stream entries (arrival_s, graph, model, p, R, K).
+    """
+    pool = []
+    for i in range(graphs):
+        scale = 14 + int(rand64(master_seed, i) % 9)
+        pool.append((scale, 16 << scale, 100 * master_seed + i))
+    stream, t = [], 0.0
+    base = graphs
+    for i in range(requests):
+        r = [rand64(master_seed, base + 5 * i + k) for k in range(5)]
+        u = (r[0] >> 11) / float(1 << 53)
+        t += -math.log1p(-u) / rate
+        model, p = [("const", 0.01), ("const", 0.1), ("wc", 0.0)][int(r[2] % 3)]
+        stream.append((t, int(r[1] % graphs), model, p, (64, 256)[int(r[3] % 2)], 10 + int(r[4] % 91)))
+    return pool, stream
