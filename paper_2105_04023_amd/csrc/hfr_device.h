@@ -6,6 +6,8 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include <type_traits>
+
 #include "hfr_internal.h"
 
 namespace hfr {
@@ -200,28 +202,31 @@ DEVI uint32_t merge_edges64(int64_t eb, int64_t ee, const int32_t* __restrict__ 
         in_n = w0 + 64 + lane < ee;
         v_n = in_n ? adj[w0 + 64 + lane] : 0;
         const bool lv = in && (first || bit_of(Lcur, v) != 0u);
+        uint64_t mask = __ballot(lv);
+        if (!mask) continue;  // no live head: the window needs no hash or threshold
+        vis += (uint32_t)__builtin_popcountll(mask);
         const uint32_t hh = in ? eh[e] : 0u;
         uint32_t tt = 0u;
         if constexpr (KIND == THR_TARGET) tt = in ? thr[v] : 0u;
         if constexpr (KIND == THR_EDGE) tt = in ? thr[e] : 0u;
-        uint64_t mask = __ballot(lv);
-        vis += (uint32_t)__builtin_popcountll(mask);
-        while (mask) {
-            // up to UB live edges; unused slots repeat the last one (max-merge is
-            // idempotent), so every load is issued without a branch
-            int idx[UB];
+        // batches of NB live edges, NB the smallest of 1, 2, 4, UB that covers the
+        // edges left (capped at UB): unused slots repeat the last edge (max-merge is
+        // idempotent), so every load of a batch is issued without a branch
+        auto batch = [&](auto nbc) {
+            constexpr int NB = decltype(nbc)::value;
+            int idx[NB];
             int last = __builtin_ctzll(mask);
 #pragma unroll
-            for (int b = 0; b < UB; ++b) {
+            for (int b = 0; b < NB; ++b) {
                 if (mask) last = __builtin_ctzll(mask);
                 idx[b] = last;
                 mask &= mask - 1;
             }
-            // lanes past the row (q >= P) load a valid dword of it instead; their
+            // lanes past the row (q >= P) load a valid dword of it; their
             // results are never stored
-            uint32_t d[UB][DW];
+            uint32_t d[NB][DW];
 #pragma unroll
-            for (int b = 0; b < UB; ++b) {
+            for (int b = 0; b < NB; ++b) {
                 const int64_t vb = __builtin_amdgcn_readlane(v, idx[b]);
                 const uint32_t* __restrict__ row = A + vb * P;
 #pragma unroll
@@ -232,13 +237,24 @@ DEVI uint32_t merge_edges64(int64_t eb, int64_t ee, const int32_t* __restrict__ 
             }
             __builtin_amdgcn_sched_barrier(0);
 #pragma unroll
-            for (int b = 0; b < UB; ++b) {
+            for (int b = 0; b < NB; ++b) {
                 const uint32_t hb = (uint32_t)__builtin_amdgcn_readlane((int)hh, idx[b]);
                 uint32_t nt = ntv;
                 if constexpr (KIND != THR_CONST) nt = 0u - (uint32_t)__builtin_amdgcn_readlane((int)tt, idx[b]);
 #pragma unroll
                 for (int i = 0; i < DW; ++i) merge_live(acc[i], d[b][i], x[i][0], x[i][1], x[i][2], x[i][3], hb, nt);
             }
+        };
+        while (mask) {
+            const int nl = __builtin_popcountll(mask);
+            if (nl > 4)
+                batch(std::integral_constant<int, UB>{});
+            else if (nl > 2)
+                batch(std::integral_constant<int, 4>{});
+            else if (nl == 2)
+                batch(std::integral_constant<int, 2>{});
+            else
+                batch(std::integral_constant<int, 1>{});
         }
     }
     return vis;
@@ -262,24 +278,27 @@ DEVI uint32_t merge_edges_grp(int64_t eb, int64_t ee, const int32_t* __restrict_
         const int64_t ec = in ? e : ee - 1;  // lanes past the row re-read its last edge
         const int32_t v = adj[ec];
         const bool lv = in && (first || bit_of(Lcur, v) != 0u);
+        uint64_t mask = (__ballot(lv) >> gbase) & GM;
+        if (!mask) continue;  // no live head: the window needs no hash or threshold
+        vis += (uint32_t)__builtin_popcountll(mask);
         const uint32_t hh = eh[ec];
         uint32_t tt = 0u;
         if constexpr (KIND == THR_TARGET) tt = thr[v];
         if constexpr (KIND == THR_EDGE) tt = thr[ec];
-        uint64_t mask = (__ballot(lv) >> gbase) & GM;
-        vis += (uint32_t)__builtin_popcountll(mask);
-        while (mask) {
-            int idx[UB];
+        // batches as in merge_edges64, sized per group
+        auto batch = [&](auto nbc) {
+            constexpr int NB = decltype(nbc)::value;
+            int idx[NB];
             int last = __builtin_ctzll(mask);
 #pragma unroll
-            for (int b = 0; b < UB; ++b) {
+            for (int b = 0; b < NB; ++b) {
                 if (mask) last = __builtin_ctzll(mask);
                 idx[b] = last;
                 mask &= mask - 1;
             }
-            uint32_t d[UB][DW];
+            uint32_t d[NB][DW];
 #pragma unroll
-            for (int b = 0; b < UB; ++b) {
+            for (int b = 0; b < NB; ++b) {
                 const int64_t vb = __shfl(v, gbase + idx[b], 64);
                 const uint32_t* __restrict__ row = A + vb * P;
 #pragma unroll
@@ -290,13 +309,24 @@ DEVI uint32_t merge_edges_grp(int64_t eb, int64_t ee, const int32_t* __restrict_
             }
             __builtin_amdgcn_sched_barrier(0);
 #pragma unroll
-            for (int b = 0; b < UB; ++b) {
+            for (int b = 0; b < NB; ++b) {
                 const uint32_t hb = (uint32_t)__shfl((int)hh, gbase + idx[b], 64);
                 uint32_t nt = ntv;
                 if constexpr (KIND != THR_CONST) nt = 0u - (uint32_t)__shfl((int)tt, gbase + idx[b], 64);
 #pragma unroll
                 for (int i = 0; i < DW; ++i) merge_live(acc[i], d[b][i], x[i][0], x[i][1], x[i][2], x[i][3], hb, nt);
             }
+        };
+        while (mask) {
+            const int nl = __builtin_popcountll(mask);
+            if (nl > 4)
+                batch(std::integral_constant<int, UB>{});
+            else if (nl > 2)
+                batch(std::integral_constant<int, 4>{});
+            else if (nl == 2)
+                batch(std::integral_constant<int, 2>{});
+            else
+                batch(std::integral_constant<int, 1>{});
         }
     }
     return vis;

@@ -632,27 +632,30 @@ __global__ __launch_bounds__(256) void k_sweep_rows64(
             in_n = fn < total;
             v_n = in_n ? adj[e_n] : 0;
             const bool lv = valid && (first || bit_of(Lcur, v) != 0u);
+            uint64_t mask = __ballot(lv);
+            if (!mask) continue;  // no live head: the window needs no hash or threshold
+            vis += (uint32_t)__builtin_popcountll(mask);
             const uint32_t hh = valid ? eh[e] : 0u;
             uint32_t tt = 0u;
             if constexpr (KIND == THR_TARGET) tt = valid ? thr[v] : 0u;
             if constexpr (KIND == THR_EDGE) tt = valid ? thr[e] : 0u;
-            uint64_t mask = __ballot(lv);
-            vis += (uint32_t)__builtin_popcountll(mask);
-            while (mask) {
-                // up to UB live edges; unused slots repeat the last one (max-merge
-                // is idempotent), so every load is issued without a branch
-                int idx[UB], rb[UB];
+            // batches of NB live edges, NB the smallest of 1, 2, 4, UB that covers
+            // the edges left (capped at UB); unused slots repeat the last one
+            // (max-merge is idempotent), so every load is issued without a branch
+            auto batch = [&](auto nbc) {
+                constexpr int NB = decltype(nbc)::value;
+                int idx[NB], rb[NB];
                 int last = __builtin_ctzll(mask);
 #pragma unroll
-                for (int b = 0; b < UB; ++b) {
+                for (int b = 0; b < NB; ++b) {
                     if (mask) last = __builtin_ctzll(mask);
                     idx[b] = last;
                     mask &= mask - 1;
                     rb[b] = __builtin_amdgcn_readlane(r, idx[b]);
                 }
-                uint32_t d[UB][DW], own[UB][DW], oub[UB][DW];
+                uint32_t d[NB][DW], own[NB][DW], oub[NB][DW];
 #pragma unroll
-                for (int b = 0; b < UB; ++b) {
+                for (int b = 0; b < NB; ++b) {
                     const int64_t vb = __builtin_amdgcn_readlane(v, idx[b]);
                     const int64_t ub_ = __builtin_amdgcn_readlane((int)u, rb[b]);
                     const uint32_t* __restrict__ row = A + vb * P;
@@ -670,7 +673,7 @@ __global__ __launch_bounds__(256) void k_sweep_rows64(
                 // keep the batch's loads ahead of the merges (no sinking to the uses)
                 __builtin_amdgcn_sched_barrier(0);
 #pragma unroll
-                for (int b = 0; b < UB; ++b) {
+                for (int b = 0; b < NB; ++b) {
                     if (rb[b] != cur) {
                         if (cur >= 0) {
                             bool ch = false;
@@ -708,6 +711,17 @@ __global__ __launch_bounds__(256) void k_sweep_rows64(
                     for (int i = 0; i < DW; ++i)
                         merge_live(acc[i], d[b][i], x[i][0], x[i][1], x[i][2], x[i][3], hb, nt);
                 }
+            };
+            while (mask) {
+                const int nl = __builtin_popcountll(mask);
+                if (nl > 4)
+                    batch(std::integral_constant<int, UB>{});
+                else if (nl > 2)
+                    batch(std::integral_constant<int, 4>{});
+                else if (nl == 2)
+                    batch(std::integral_constant<int, 2>{});
+                else
+                    batch(std::integral_constant<int, 1>{});
             }
         }
         if (cur >= 0) {
