@@ -184,7 +184,7 @@ size_t bytes_needed(int64_t n, int64_t m, int32_t R, im_prob_kind kind) {
     auto al = [](size_t b) { return (std::max<size_t>(b, 1) + 255) & ~size_t(255); };
     size_t t = 0;
     t += al(8 * (n + 1)) + al(4 * m) + al(4 * m);  // xadj, adj, edge hashes
-    t += al(8 * (n + 1)) + 2 * al(4 * m) + al(4 * n);  // reverse CSR with pieces, heavy slots
+    t += al(8 * (n + 1)) + 2 * al(4 * m) + 2 * al(4 * n);  // reverse CSR with pieces, heavy slots, light rows
     t += al(4 * ((n + 31) / 32 + 1)) + al(8 * (n + m / 256 + 64)) + al(4 * n) + al(32);  // sparse lists
     if (kind == IM_PROB_WEIGHTED_CASCADE) t += al(4 * n);
     if (kind == IM_PROB_PER_EDGE) t += al(4 * m);
@@ -283,6 +283,8 @@ im_status run_simulate(im_sketch* sk, int ia, int ib, const uint32_t* blk, SimRe
     HIP_TRY(hipEventRecord(sk->ev_a, s));
     HIP_TRY(launch_init(sk->L, n, sk->HJ, sk->seed, blk, buf[0], buf[1], s));
     if (blk) HIP_TRY(launch_full_blocked(sk->L, n, blk, sk->gb.fullblk, s));
+    // the row kernel sets L_{t+1} bits with atomics: every bitmap starts zeroed
+    for (int i = 0; i < 3; ++i) HIP_TRY(launch_fill_u32(sk->Lbm[i], 0u, (n + 31) / 32 + 1, s));
     HIP_TRY(launch_fill_u32(sk->fr.mark, 0u, (n + 31) / 32 + 1, s));
     HIP_TRY(launch_fill_u32(sk->fr.counts, 0u, 8, s));
     int final_sweeps = -1;
@@ -520,7 +522,7 @@ im_status im_build_sketches(im_ctx* ctx, const im_csr* graph, const im_probs* pr
     ok = ok && sk_alloc(sk, &sk->Lbm[0], words) && sk_alloc(sk, &sk->Lbm[1], words) &&
          sk_alloc(sk, &sk->Lbm[2], words);
     ok = ok && sk_alloc(sk, &g.rxadj, n + 1) && sk_alloc(sk, &g.radj, m) && sk_alloc(sk, &g.rpiece, m) &&
-         sk_alloc(sk, &g.hslot, n);
+         sk_alloc(sk, &g.hslot, n) && sk_alloc(sk, &g.lrows, n);
     ok = ok && sk_alloc(sk, &sk->fr.mark, words) && sk_alloc(sk, &sk->fr.items, n + m / 256 + 64) &&
          sk_alloc(sk, &sk->fr.W, n) && sk_alloc(sk, &sk->fr.counts, 8);
     ok = ok && sk_alloc(sk, &sk->cnt_ring, (size_t)RING * NSLOT * SLOT_U32) &&
@@ -637,6 +639,10 @@ im_status im_build_sketches(im_ctx* ctx, const im_csr* graph, const im_probs* pr
             HIP_TRY(launch_indegree(g, indeg, s));
             if (g.kind == THR_TARGET) HIP_TRY(launch_wc_thresholds(indeg, g.thr, n, s));
             HIP_TRY(launch_reverse_csr(g, indeg, cursor, scan_tmp, s));
+            // the row kernel's list of rows with 1..heavy_deg out-edges (the buffers
+            // of the in-degree pass are reused once the reverse CSR is done)
+            HIP_TRY(launch_light_rows(g, indeg, cursor, scan_tmp, s));
+            HIP_TRY(hipMemcpyAsync(&g.nlight, cursor + n, 8, hipMemcpyDeviceToHost, s));
             HIP_TRY(hipStreamSynchronize(s));
             ctx_free(ctx, p);
         }

@@ -51,6 +51,8 @@ struct DevGraph {
     int32_t* radj = nullptr;    // [m]
     int32_t* hslot = nullptr;   // heavy slot of each row, -1 for rows processed whole [n]
     int32_t* rpiece = nullptr;  // per in-edge: piece of its split source row, -1 otherwise [m]
+    int32_t* lrows = nullptr;   // rows with 1..heavy_deg out-edges, ascending [nlight]
+    int64_t nlight = 0;
     int64_t piece_edges = 256;
 };
 
@@ -137,6 +139,7 @@ hipError_t launch_sweep(const Layout& L, const DevGraph& g, const uint32_t* X, c
 hipError_t launch_reverse_csr(const DevGraph& g, const uint32_t* indeg, int64_t* cursor, uint32_t* scan_tmp,
                               hipStream_t s);
 hipError_t launch_heavy_slots(const DevGraph& g, hipStream_t s);
+hipError_t launch_light_rows(const DevGraph& g, uint32_t* flags, int64_t* pos, uint32_t* scan_tmp, hipStream_t s);
 hipError_t launch_full_blocked(const Layout& L, int64_t n, const uint32_t* blk, uint32_t* fullblk, hipStream_t s);
 hipError_t launch_argmax(const Layout& L, int64_t n, const uint32_t* M, const GreedyBufs& b, hipStream_t s);
 hipError_t launch_select(const Layout& L, const DevGraph& g, const uint32_t* M, const GreedyBufs& b,

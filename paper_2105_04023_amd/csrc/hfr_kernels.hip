@@ -549,7 +549,7 @@ __global__ __launch_bounds__(256) void k_sweep_rows64(
     uint32_t gate_thresh, uint32_t* __restrict__ cnt_out, unsigned long long* __restrict__ vis_out,
     const unsigned long long* __restrict__ sgate, unsigned long long* __restrict__ sum_out,
     const int64_t* __restrict__ rxadj, int64_t n, int64_t m, int P, int PW, int64_t heavy_deg, int first, Frontier fr,
-    int parity, const uint32_t* __restrict__ fullblk) {
+    int parity, const uint32_t* __restrict__ fullblk, const int32_t* __restrict__ lrows, int64_t nlight) {
     __shared__ unsigned long long sh64[4];
     __shared__ uint32_t sh32[4];
     __shared__ uint32_t s_off[4][33];
@@ -563,14 +563,16 @@ __global__ __launch_bounds__(256) void k_sweep_rows64(
     const uint32_t ntv = to_vgpr(0u - thr_const);
     uint32_t my_cnt = 0;
     unsigned long long my_vis = 0, my_sum = 0;
-    const int64_t nrows = sparse ? (int64_t)fr.counts[4 * parity + 1] : n;
+    // dense: every row with 1..heavy_deg out-edges (rows without out-edges never
+    // change and are never in L_t); sparse: the listed rows
+    const int64_t nrows = sparse ? (int64_t)fr.counts[4 * parity + 1] : nlight;
     const int64_t nbatch = (nrows + 31) >> 5;
     for (int64_t c = wave_index(); c < nbatch; c += wave_count()) {
-        // ---- the batch's rows: one per lane i < 32
+        // ---- the batch's rows: one per lane i < 32 (ascending in a dense sweep)
         int64_t u = -1;
         if (lane < 32) {
             const int64_t idx = c * 32 + lane;
-            if (idx < nrows) u = sparse ? (int64_t)fr.W[idx] : idx;
+            if (idx < nrows) u = sparse ? (int64_t)fr.W[idx] : (int64_t)lrows[idx];
         }
         int64_t eb = 0, ee = 0;
         bool inL = false;
@@ -653,21 +655,17 @@ __global__ __launch_bounds__(256) void k_sweep_rows64(
                     mask &= mask - 1;
                     rb[b] = __builtin_amdgcn_readlane(r, idx[b]);
                 }
-                uint32_t d[NB][DW], own[NB][DW], oub[NB][DW];
+                uint32_t d[NB][DW];
 #pragma unroll
                 for (int b = 0; b < NB; ++b) {
                     const int64_t vb = __builtin_amdgcn_readlane(v, idx[b]);
-                    const int64_t ub_ = __builtin_amdgcn_readlane((int)u, rb[b]);
                     const uint32_t* __restrict__ row = A + vb * P;
 #pragma unroll
                     for (int i = 0; i < DW; ++i) {
                         // lanes past the row (q >= P) read a valid dword of it; their
                         // results are masked from the change test and never stored
                         const int q = i * 64 + lane;
-                        const int qc = q < P ? q : P - 1;
-                        d[b][i] = row[qc];
-                        own[b][i] = A[ub_ * P + qc];
-                        oub[b][i] = BLK ? unblocked_mask(blk, ub_, qc, PW) : 0xFFFFFFFFu;
+                        d[b][i] = row[q < P ? q : P - 1];
                     }
                 }
                 // keep the batch's loads ahead of the merges (no sinking to the uses)
@@ -697,10 +695,13 @@ __global__ __launch_bounds__(256) void k_sweep_rows64(
                         cur = rb[b];
                         cur_u = __builtin_amdgcn_readlane((int)u, cur);
                         touched |= 1u << cur;
+                        // the row's own registers are first needed when it is finished
 #pragma unroll
                         for (int i = 0; i < DW; ++i) {
-                            cur_a[i] = own[b][i];
-                            cur_ub[i] = oub[b][i];
+                            const int q = i * 64 + lane;
+                            const int qc = q < P ? q : P - 1;
+                            cur_a[i] = A[cur_u * P + qc];
+                            cur_ub[i] = BLK ? unblocked_mask(blk, cur_u, qc, PW) : 0xFFFFFFFFu;
                             acc[i].e = acc[i].o = 0u;
                         }
                     }
@@ -753,10 +754,21 @@ __global__ __launch_bounds__(256) void k_sweep_rows64(
                 if (q < P) B[uu * P + q] = A[uu * P + q];
             }
         }
-        if (!sparse) {
-            if (lane == 0) Lnext[c] = word;
-        } else if (lane < 32 && ((word >> lane) & 1u)) {
-            atomicOr(&Lnext[u >> 5], 1u << (u & 31));
+        {
+            // L_{t+1} starts zeroed; lanes that share an L word (the rows are sorted
+            // in a dense sweep) OR their bits into the run's first lane, which
+            // issues one atomic for the word
+            const bool chg = lane < 32 && ((word >> lane) & 1u);
+            const int32_t wd = u >= 0 ? (int32_t)(u >> 5) : -1 - lane;
+            uint32_t bits = chg ? 1u << (u & 31) : 0u;
+#pragma unroll
+            for (int k = 1; k < 32; k <<= 1) {
+                const uint32_t ob = __shfl_down(bits, k, 64);
+                const int32_t ow = __shfl_down(wd, k, 64);
+                if (lane + k < 32 && ow == wd) bits |= ob;
+            }
+            const int32_t pw = __shfl_up(wd, 1, 64);
+            if (lane < 32 && bits && (lane == 0 || pw != wd)) atomicOr(&Lnext[wd], bits);
         }
         if (lane < 32 && ((word >> lane) & 1u)) my_sum += (unsigned long long)(rxadj[u + 1] - rxadj[u]);
         if (lane == 0) {
@@ -905,7 +917,8 @@ hipError_t launch_sweep(const Layout& L, const DevGraph& g, const uint32_t* X, c
                                                                         sp.blk, sp.gate, sp.gate_thresh, sp.cnt_out,  \
                                                                         sp.vis_out, sp.sgate, sp.sum_out, g.rxadj,    \
                                                                         g.n, g.m, L.P, L.PW, g.heavy_deg, sp.first,   \
-                                                                        sp.fr, sp.parity, sp.fullblk)))
+                                                                        sp.fr, sp.parity, sp.fullblk, g.lrows,        \
+                                                                        g.nlight)))
         if (sp.blk)
             HFR_ROWS64(true);
         else
@@ -1043,6 +1056,32 @@ hipError_t launch_reverse_csr(const DevGraph& g, const uint32_t* indeg, int64_t*
     if (g.m > 0)
         hipLaunchKernelGGL(k_rev_scatter, dim3(8192), dim3(256), 0, s, g.xadj, g.adj, n, cursor, g.radj, g.rpiece,
                            g.hslot, g.hpb, g.piece_edges);
+    return hipGetLastError();
+}
+
+// Rows with 1..heavy_deg out-edges, ascending: flag pass, scan, scatter.
+__global__ void k_light_flags(const int64_t* __restrict__ xadj, int64_t n, int64_t heavy_deg, uint32_t* flags) {
+    for (int64_t u = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; u < n; u += (int64_t)gridDim.x * blockDim.x) {
+        const int64_t d = xadj[u + 1] - xadj[u];
+        flags[u] = (d >= 1 && d <= heavy_deg) ? 1u : 0u;
+    }
+}
+
+__global__ void k_light_scatter(const uint32_t* __restrict__ flags, const int64_t* __restrict__ pos, int64_t n,
+                                int32_t* lrows) {
+    for (int64_t u = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; u < n; u += (int64_t)gridDim.x * blockDim.x)
+        if (flags[u]) lrows[pos[u]] = (int32_t)u;
+}
+
+hipError_t launch_light_rows(const DevGraph& g, uint32_t* flags, int64_t* pos, uint32_t* scan_tmp, hipStream_t s) {
+    const int64_t n = g.n;
+    const int64_t nb = (n + SCAN_BLOCK - 1) / SCAN_BLOCK;
+    int64_t* sums = reinterpret_cast<int64_t*>(scan_tmp);  // nb + 1 entries
+    hipLaunchKernelGGL(k_light_flags, dim3(4096), dim3(256), 0, s, g.xadj, n, g.heavy_deg, flags);
+    hipLaunchKernelGGL(k_scan_block_sums, dim3((unsigned)nb), dim3(256), 0, s, flags, n, sums);
+    hipLaunchKernelGGL(k_scan_sums, dim3(1), dim3(64), 0, s, sums, nb);
+    hipLaunchKernelGGL(k_scan_apply, dim3((unsigned)nb), dim3(256), 0, s, flags, n, sums, pos);
+    hipLaunchKernelGGL(k_light_scatter, dim3(4096), dim3(256), 0, s, flags, pos, n, g.lrows);
     return hipGetLastError();
 }
 
