@@ -186,7 +186,7 @@ size_t bytes_needed(int64_t n, int64_t m, int32_t R, im_prob_kind kind) {
     t += al(8 * (n + 1)) + al(4 * m) + al(4 * m);  // xadj, adj, edge hashes
     t += al(8 * (n + 1)) + 2 * al(4 * m) + 2 * al(4 * n);  // reverse CSR with pieces, heavy slots, light rows
     t += al(4 * ((n + 31) / 32 + 1)) + al(8 * (n + m / 256 + 64)) + al(4 * n) + al(32);  // sparse lists
-    if (kind == IM_PROB_WEIGHTED_CASCADE) t += al(4 * n);
+    if (kind == IM_PROB_WEIGHTED_CASCADE) t += al(4 * n) + al(4 * m);  // per target, then per edge
     if (kind == IM_PROB_PER_EDGE) t += al(4 * m);
     t += al(4 * R) * 2 + al(8 * R);               // X, HJ, T
     t += 3 * al((size_t)n * L.P * 4);             // register buffers
@@ -530,7 +530,8 @@ im_status im_build_sketches(im_ctx* ctx, const im_csr* graph, const im_probs* pr
     ok = ok && sk_alloc(sk, &sk->d_err, 4) && sk_alloc(sk, &sk->d_heavy_counts, 4) && sk_alloc(sk, &sk->d_flag, 4);
     sk->fr.chunk = 256;
     sk->fr.sparse_div = o.sparse_div < 0 ? 0u : (o.sparse_div == 0 ? 96u : (uint32_t)o.sparse_div);
-    if (probs->kind == IM_PROB_WEIGHTED_CASCADE) ok = ok && sk_alloc(sk, &g.thr, n);
+    uint32_t* wc_target = nullptr;
+    if (probs->kind == IM_PROB_WEIGHTED_CASCADE) ok = ok && sk_alloc(sk, &wc_target, n) && sk_alloc(sk, &g.thr, m);
     if (probs->kind == IM_PROB_PER_EDGE) ok = ok && sk_alloc(sk, &g.thr, m);
     if (!ok) {
         sk_release(sk);
@@ -637,7 +638,13 @@ im_status im_build_sketches(im_ctx* ctx, const im_csr* graph, const im_probs* pr
             uint32_t* scan_tmp = (uint32_t*)((char*)cursor + ((8 * (n + 1) + 255) & ~int64_t(255)));
             HIP_TRY(launch_fill_u32(indeg, 0u, n, s));
             HIP_TRY(launch_indegree(g, indeg, s));
-            if (g.kind == THR_TARGET) HIP_TRY(launch_wc_thresholds(indeg, g.thr, n, s));
+            if (g.kind == THR_TARGET) {
+                // w_uv depends on the target only; the kernels read it per edge, as a
+                // coalesced array beside the edge hashes instead of a gather by target
+                HIP_TRY(launch_wc_thresholds(indeg, wc_target, n, s));
+                HIP_TRY(launch_gather_u32(wc_target, g.adj, m, g.thr, s));
+                g.kind = THR_EDGE;
+            }
             HIP_TRY(launch_reverse_csr(g, indeg, cursor, scan_tmp, s));
             // the row kernel's list of rows with 1..heavy_deg out-edges (the buffers
             // of the in-degree pass are reused once the reverse CSR is done)

@@ -180,7 +180,7 @@ DEVI double estimate_from_sum(uint32_t s, int J, const double* __restrict__ T) {
 // Merge of a row's out-edges (Alg. 2): for every out-neighbour v in L_t and
 // every live sample, acc = max(acc, M^t[v]).
 // ----------------------------------------------------------------------------
-constexpr int UB = 8;  // neighbour rows in flight per wave
+constexpr int UB = 8;  // neighbour rows in flight per wave (twice that with one dword per lane)
 
 // G = 64 (one row per wave): the row's out-edges are read 64 at a time with
 // one coalesced load per array, the heads in L_t are found with one ballot,
@@ -247,7 +247,9 @@ DEVI uint32_t merge_edges64(int64_t eb, int64_t ee, const int32_t* __restrict__ 
         };
         while (mask) {
             const int nl = __builtin_popcountll(mask);
-            if (nl > 4)
+            if (DW == 1 && nl > UB)
+                batch(std::integral_constant<int, 2 * UB>{});
+            else if (nl > 4)
                 batch(std::integral_constant<int, UB>{});
             else if (nl > 2)
                 batch(std::integral_constant<int, 4>{});
@@ -319,7 +321,9 @@ DEVI uint32_t merge_edges_grp(int64_t eb, int64_t ee, const int32_t* __restrict_
         };
         while (mask) {
             const int nl = __builtin_popcountll(mask);
-            if (nl > 4)
+            if (DW == 1 && nl > UB)
+                batch(std::integral_constant<int, 2 * UB>{});
+            else if (nl > 4)
                 batch(std::integral_constant<int, UB>{});
             else if (nl > 2)
                 batch(std::integral_constant<int, 4>{});

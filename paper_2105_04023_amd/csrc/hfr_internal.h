@@ -126,6 +126,7 @@ hipError_t launch_validate(const DevGraph& g, uint32_t* err, hipStream_t s);
 hipError_t launch_edge_hash(const DevGraph& g, uint32_t seed, hipStream_t s);
 hipError_t launch_indegree(const DevGraph& g, uint32_t* indeg, hipStream_t s);
 hipError_t launch_wc_thresholds(const uint32_t* indeg, uint32_t* thr, int64_t n, hipStream_t s);
+hipError_t launch_gather_u32(const uint32_t* src, const int32_t* idx, int64_t m, uint32_t* out, hipStream_t s);
 hipError_t launch_edge_thresholds(const float* w, uint32_t* thr, int64_t m, uint32_t* err, hipStream_t s);
 hipError_t launch_sim_words(uint32_t* X, uint32_t* HJ, int J, uint32_t seed, hipStream_t s);
 hipError_t launch_heavy_count(const DevGraph& g, int64_t piece_edges, unsigned long long* counts, hipStream_t s);

@@ -87,6 +87,19 @@ __global__ void k_wc_thresholds(const uint32_t* __restrict__ indeg, uint32_t* th
         thr[v] = wc_threshold(indeg[v]);
 }
 
+// out[e] = src[idx[e]].
+__global__ void k_gather_u32(const uint32_t* __restrict__ src, const int32_t* __restrict__ idx, int64_t m,
+                             uint32_t* out) {
+    for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < m; e += (int64_t)gridDim.x * blockDim.x)
+        out[e] = src[idx[e]];
+}
+
+hipError_t launch_gather_u32(const uint32_t* src, const int32_t* idx, int64_t m, uint32_t* out, hipStream_t s) {
+    if (m == 0) return hipSuccess;
+    hipLaunchKernelGGL(k_gather_u32, dim3(8192), dim3(256), 0, s, src, idx, m, out);
+    return hipGetLastError();
+}
+
 hipError_t launch_wc_thresholds(const uint32_t* indeg, uint32_t* thr, int64_t n, hipStream_t s) {
     hipLaunchKernelGGL(k_wc_thresholds, dim3(4096), dim3(256), 0, s, indeg, thr, n);
     return hipGetLastError();
@@ -715,7 +728,9 @@ __global__ __launch_bounds__(256) void k_sweep_rows64(
             };
             while (mask) {
                 const int nl = __builtin_popcountll(mask);
-                if (nl > 4)
+                if (DW == 1 && nl > UB)
+                    batch(std::integral_constant<int, 2 * UB>{});
+                else if (nl > 4)
                     batch(std::integral_constant<int, UB>{});
                 else if (nl > 2)
                     batch(std::integral_constant<int, 4>{});
