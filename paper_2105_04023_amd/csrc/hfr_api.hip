@@ -115,6 +115,12 @@ struct im_sketch {
 
     hipEvent_t ev_a = nullptr, ev_b = nullptr;
     hipEvent_t ev_batch[2] = {nullptr, nullptr};
+    // the reverse CSR is built on `aux` while the first (dense) sweeps run;
+    // sweeps may go sparse only once ev_rev has completed
+    hipStream_t aux = nullptr;
+    hipEvent_t ev_indeg = nullptr, ev_rev = nullptr;
+    bool rev_ready = false;
+    void* rev_tmp = nullptr;  // in-degrees and cursors of the reverse CSR build
     std::vector<hipEvent_t> sweep_ev;
     bool time_sweeps = false;
 
@@ -145,6 +151,7 @@ bool sk_alloc(im_sketch* sk, T** out, size_t count) {
 
 void sk_release(im_sketch* sk) {
     if (!sk) return;
+    if (sk->aux) (void)hipStreamSynchronize(sk->aux);  // the reverse CSR build writes sketch buffers
     if (sk->ctx) {
         (void)hipStreamSynchronize(sk->ctx->stream);
         for (auto& b : sk->bufs) {
@@ -156,8 +163,10 @@ void sk_release(im_sketch* sk) {
     if (sk->h_gather[0]) (void)hipHostFree(sk->h_gather[0]);
     if (sk->h_gather[1]) (void)hipHostFree(sk->h_gather[1]);
     if (sk->h_small) (void)hipHostFree(sk->h_small);
-    for (hipEvent_t e : {sk->ev_a, sk->ev_b, sk->ev_batch[0], sk->ev_batch[1]})
+    if (sk->rev_tmp && sk->ctx) ctx_free(sk->ctx, sk->rev_tmp);
+    for (hipEvent_t e : {sk->ev_a, sk->ev_b, sk->ev_batch[0], sk->ev_batch[1], sk->ev_indeg, sk->ev_rev})
         if (e) (void)hipEventDestroy(e);
+    if (sk->aux) (void)hipStreamDestroy(sk->aux);
     for (hipEvent_t e : sk->sweep_ev) (void)hipEventDestroy(e);
     delete sk;
 }
@@ -267,6 +276,22 @@ struct SimResult {
     std::vector<char> sparse;
 };
 
+// True once the reverse CSR built on the aux stream is complete (then the
+// context stream is ordered after it and its temporaries are freed); with
+// wait, blocks until it is.
+hipError_t rev_csr_ready(im_sketch* sk, bool wait) {
+    if (sk->rev_ready) return hipSuccess;
+    hipError_t e = wait ? hipEventSynchronize(sk->ev_rev) : hipEventQuery(sk->ev_rev);
+    if (e == hipErrorNotReady) return hipSuccess;
+    if (e != hipSuccess) return e;
+    e = hipStreamWaitEvent(sk->ctx->stream, sk->ev_rev, 0);
+    if (e != hipSuccess) return e;
+    ctx_free(sk->ctx, sk->rev_tmp);
+    sk->rev_tmp = nullptr;
+    sk->rev_ready = true;
+    return hipSuccess;
+}
+
 // Simulate (Alg. 2) on buffers ia/ib: init (with blocked pairs if blk), then
 // synchronous sweeps until |L_t| <= floor(eps_c * n).
 im_status run_simulate(im_sketch* sk, int ia, int ib, const uint32_t* blk, SimResult* res) {
@@ -297,13 +322,16 @@ im_status run_simulate(im_sketch* sk, int ia, int ib, const uint32_t* blk, SimRe
     int batch_slot = 0;
     int timer_idx = 0;
     std::vector<int> timer_of_sweep;
+    std::vector<bool> sparse_ok;  // per launched sweep: sparse mode allowed
     while (final_sweeps < 0) {
         // synchronous sweeps reach the fixed point within n + 1 sweeps
         if (t > n + 2 + 2 * MAX_BATCH) {
             sk->poisoned = true;
             return fail(IM_ERR_DEVICE, "sweep count exceeded n + 1 without convergence");
         }
-        // launch one batch
+        // launch one batch; its sweeps may go sparse only once the reverse CSR exists
+        HIP_TRY(rev_csr_ready(sk, false));
+        const bool may_sparse = sk->rev_ready;
         hipLaunchKernelGGL(k_ring_zero, dim3(nb), dim3(256), 0, s, sk->cnt_ring, sk->vis_ring, t, nb);
         HIP_TRY(hipGetLastError());
         for (int64_t st = t; st < t + nb; ++st) {
@@ -314,6 +342,8 @@ im_status run_simulate(im_sketch* sk, int ia, int ib, const uint32_t* blk, SimRe
             sp.Lnext = sk->Lbm[(st + 1) % 3];
             sp.Lclear = sk->Lbm[(st + 2) % 3];
             sp.fr = sk->fr;
+            if (!may_sparse) sp.fr.sparse_div = 0;
+            sparse_ok.push_back(may_sparse);
             // piece flags of earlier sweeps never equal this sweep's stamp
             if (++sk->stamp_ctr == 0u) {
                 if (sk->g.npieces > 0) HIP_TRY(launch_fill_u32(sk->part_any, 0u, sk->g.npieces, s));
@@ -372,7 +402,7 @@ im_status run_simulate(im_sketch* sk, int ia, int ib, const uint32_t* blk, SimRe
             const int64_t tt = batch_t0[rs] + i;
             res->vis.push_back(vis);
             res->vis_light.push_back(vis_l);
-            res->sparse.push_back(tt > 0 && sk->fr.sparse_div != 0 &&
+            res->sparse.push_back(tt > 0 && sparse_ok[tt] && sk->fr.sparse_div != 0 &&
                                   (uint64_t)st_sum * sk->fr.sparse_div <= (uint64_t)sk->g.m);
             res->live.push_back(live);
             if ((uint64_t)live <= thresh) {
@@ -544,7 +574,10 @@ im_status im_build_sketches(im_ctx* ctx, const im_csr* graph, const im_probs* pr
         return fail(IM_ERR_DEVICE, "pinned host allocation failed");
     }
     if (hipEventCreate(&sk->ev_a) != hipSuccess || hipEventCreate(&sk->ev_b) != hipSuccess ||
-        hipEventCreate(&sk->ev_batch[0]) != hipSuccess || hipEventCreate(&sk->ev_batch[1]) != hipSuccess) {
+        hipEventCreate(&sk->ev_batch[0]) != hipSuccess || hipEventCreate(&sk->ev_batch[1]) != hipSuccess ||
+        hipEventCreateWithFlags(&sk->ev_indeg, hipEventDisableTiming) != hipSuccess ||
+        hipEventCreateWithFlags(&sk->ev_rev, hipEventDisableTiming) != hipSuccess ||
+        hipStreamCreateWithFlags(&sk->aux, hipStreamNonBlocking) != hipSuccess) {
         sk_release(sk);
         return fail(IM_ERR_DEVICE, "event creation failed");
     }
@@ -627,17 +660,29 @@ im_status im_build_sketches(im_ctx* ctx, const im_csr* graph, const im_probs* pr
             HIP_TRY(launch_fill_u32(sk->fr.pmark, 0u, g.npieces / 32 + 1, s));
         }
         HIP_TRY(launch_heavy_slots(g, s));
-        // in-degrees: weighted-cascade thresholds and the reverse CSR (whose in-edges
-        // carry the piece of their split source row)
+        // in-degrees: weighted-cascade thresholds (main stream) and the reverse CSR,
+        // whose in-edges carry the piece of their split source row (aux stream)
         {
             const int64_t nb = (n + 1023) / 1024;
-            void* p = ctx_alloc(ctx, 4 * n + 8 * (n + 1) + 8 * (nb + 2) + 512);
-            if (!p) return fail(IM_ERR_OUT_OF_BUDGET, "temporary allocation failed");
-            uint32_t* indeg = (uint32_t*)p;
-            int64_t* cursor = (int64_t*)((char*)p + ((4 * n + 255) & ~int64_t(255)));
-            uint32_t* scan_tmp = (uint32_t*)((char*)cursor + ((8 * (n + 1) + 255) & ~int64_t(255)));
+            const size_t a4n = (4 * n + 255) & ~size_t(255), a8n = (8 * (n + 1) + 255) & ~size_t(255);
+            const size_t asc = (8 * (nb + 2) + 255) & ~size_t(255);
+            // main: flags, positions and scan sums of the light-row list
+            void* pm_ = ctx_alloc(ctx, a4n + a8n + asc);
+            // kept until the reverse CSR is done: in-degrees, cursors, scan sums
+            sk->rev_tmp = ctx_alloc(ctx, a4n + a8n + asc);
+            if (!pm_ || !sk->rev_tmp) {
+                if (pm_) ctx_free(ctx, pm_);
+                return fail(IM_ERR_OUT_OF_BUDGET, "temporary allocation failed");
+            }
+            uint32_t* indeg = (uint32_t*)sk->rev_tmp;
+            int64_t* cursor = (int64_t*)((char*)sk->rev_tmp + a4n);
+            uint32_t* scan_tmp = (uint32_t*)((char*)cursor + a8n);
             HIP_TRY(launch_fill_u32(indeg, 0u, n, s));
             HIP_TRY(launch_indegree(g, indeg, s));
+            HIP_TRY(hipEventRecord(sk->ev_indeg, s));
+            HIP_TRY(hipStreamWaitEvent(sk->aux, sk->ev_indeg, 0));
+            HIP_TRY(launch_reverse_csr(g, indeg, cursor, scan_tmp, sk->aux));
+            HIP_TRY(hipEventRecord(sk->ev_rev, sk->aux));
             if (g.kind == THR_TARGET) {
                 // w_uv depends on the target only; the kernels read it per edge, as a
                 // coalesced array beside the edge hashes instead of a gather by target
@@ -645,13 +690,14 @@ im_status im_build_sketches(im_ctx* ctx, const im_csr* graph, const im_probs* pr
                 HIP_TRY(launch_gather_u32(wc_target, g.adj, m, g.thr, s));
                 g.kind = THR_EDGE;
             }
-            HIP_TRY(launch_reverse_csr(g, indeg, cursor, scan_tmp, s));
-            // the row kernel's list of rows with 1..heavy_deg out-edges (the buffers
-            // of the in-degree pass are reused once the reverse CSR is done)
-            HIP_TRY(launch_light_rows(g, indeg, cursor, scan_tmp, s));
-            HIP_TRY(hipMemcpyAsync(&g.nlight, cursor + n, 8, hipMemcpyDeviceToHost, s));
+            // the row kernel's list of rows with 1..heavy_deg out-edges
+            uint32_t* lflags = (uint32_t*)pm_;
+            int64_t* lpos = (int64_t*)((char*)pm_ + a4n);
+            uint32_t* lscan = (uint32_t*)((char*)lpos + a8n);
+            HIP_TRY(launch_light_rows(g, lflags, lpos, lscan, s));
+            HIP_TRY(hipMemcpyAsync(&g.nlight, lpos + n, 8, hipMemcpyDeviceToHost, s));
             HIP_TRY(hipStreamSynchronize(s));
-            ctx_free(ctx, p);
+            ctx_free(ctx, pm_);
         }
         // greedy buffers
         const size_t W = 4 * (size_t)L.PW;
@@ -678,6 +724,7 @@ im_status im_build_sketches(im_ctx* ctx, const im_csr* graph, const im_probs* pr
         SimResult r;
         im_status rs = run_simulate(sk, 0, 1, nullptr, &r);
         if (rs != IM_OK) return rs;
+        HIP_TRY(rev_csr_ready(sk, true));
         sk->build_buf = r.buf;
         sk->sel_buf = r.buf;
         sk->sweeps = r.sweeps;

@@ -55,14 +55,33 @@ hipError_t launch_validate(const DevGraph& g, uint32_t* err, hipStream_t s) {
     return hipGetLastError();
 }
 
-// Eq. (hash): h(u, v) = Murmur3(LE32(u) || LE32(v)) mod 2^31.  One wave per
-// row, lanes stride over its edges.
+// Eq. (hash): h(u, v) = Murmur3(LE32(u) || LE32(v)) mod 2^31.  A wave takes
+// 64 consecutive rows and walks their edges as one flat range, 64 at a time;
+// the source row of a flat edge is found by a binary search over the row
+// starts held one per lane.
 __global__ void k_edge_hash(const int64_t* __restrict__ xadj, const int32_t* __restrict__ adj, uint32_t* eh,
                             int64_t n, uint32_t seed) {
     const int lane = threadIdx.x & 63;
-    for (int64_t u = wave_index(); u < n; u += wave_count()) {
-        const int64_t eb = xadj[u], ee = xadj[u + 1];
-        for (int64_t e = eb + lane; e < ee; e += 64) eh[e] = mm3_key8((uint32_t)u, (uint32_t)adj[e], seed) & 0x7FFFFFFFu;
+    for (int64_t u0 = wave_index() * 64; u0 < n; u0 += wave_count() * 64) {
+        const int nr = n - u0 < 64 ? (int)(n - u0) : 64;
+        const int64_t start = xadj[u0 + (lane < nr ? lane : nr - 1)];
+        const int64_t e0 = __shfl(start, 0, 64), e1 = xadj[u0 + nr];
+        for (int64_t base = e0; base < e1; base += 64) {
+            const int64_t e = base + lane;
+            int lo = 0, hi = nr - 1;  // largest row i with start_i <= e
+#pragma unroll
+            for (int k = 0; k < 6; ++k) {
+                const int mid = (lo + hi + 1) >> 1;
+                const int64_t sm = __shfl(start, mid, 64);
+                if (lo < hi) {
+                    if (sm <= e)
+                        lo = mid;
+                    else
+                        hi = mid - 1;
+                }
+            }
+            if (e < e1) eh[e] = mm3_key8((uint32_t)(u0 + lo), (uint32_t)adj[e], seed) & 0x7FFFFFFFu;
+        }
     }
 }
 
