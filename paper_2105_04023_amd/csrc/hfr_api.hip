@@ -603,7 +603,6 @@ im_status im_build_sketches(im_ctx* ctx, const im_csr* graph, const im_probs* pr
         if (sk->h_small[0] & 1u) return fail(IM_ERR_INVALID_GRAPH, "xadj is not nondecreasing");
         if (sk->h_small[0] & 2u) return fail(IM_ERR_INVALID_GRAPH, "adj holds an id outside [0, n)");
 
-        HIP_TRY(launch_edge_hash(g, hash_seed, s));
         HIP_TRY(launch_sim_words(sk->X, sk->HJ, R, hash_seed, s));
         // exp2(r/J) table for the estimate (host libm), uploaded once
         std::vector<double> T(R);
@@ -660,6 +659,7 @@ im_status im_build_sketches(im_ctx* ctx, const im_csr* graph, const im_probs* pr
             HIP_TRY(launch_fill_u32(sk->fr.pmark, 0u, g.npieces / 32 + 1, s));
         }
         HIP_TRY(launch_heavy_slots(g, s));
+        HIP_TRY(launch_edge_hash(g, hash_seed, s));  // split rows are hashed by piece
         // in-degrees: weighted-cascade thresholds (main stream) and the reverse CSR,
         // whose in-edges carry the piece of their split source row (aux stream)
         {

@@ -55,49 +55,92 @@ hipError_t launch_validate(const DevGraph& g, uint32_t* err, hipStream_t s) {
     return hipGetLastError();
 }
 
-// Eq. (hash): h(u, v) = Murmur3(LE32(u) || LE32(v)) mod 2^31.  A wave takes
-// 64 consecutive rows and walks their edges as one flat range, 64 at a time;
-// the source row of a flat edge is found by a binary search over the row
-// starts held one per lane.
-__global__ void k_edge_hash(const int64_t* __restrict__ xadj, const int32_t* __restrict__ adj, uint32_t* eh,
-                            int64_t n, uint32_t seed) {
+// Eq. (hash): h(u, v) = Murmur3(LE32(u) || LE32(v)) mod 2^31, in two
+// balanced parts.  Rows with at most heavy_deg out-edges: a wave takes 64
+// consecutive rows and walks their edges as one flat range, 64 at a time (the
+// source row of a flat edge is found by a binary search over the row starts
+// held one per lane; split rows count as empty here).  Split rows: one wave
+// per piece of piece_edges edges.
+__global__ void k_edge_hash_light(const int64_t* __restrict__ xadj, const int32_t* __restrict__ adj, uint32_t* eh,
+                                  int64_t n, int64_t heavy_deg, uint32_t seed) {
     const int lane = threadIdx.x & 63;
     for (int64_t u0 = wave_index() * 64; u0 < n; u0 += wave_count() * 64) {
         const int nr = n - u0 < 64 ? (int)(n - u0) : 64;
-        const int64_t start = xadj[u0 + (lane < nr ? lane : nr - 1)];
-        const int64_t e0 = __shfl(start, 0, 64), e1 = xadj[u0 + nr];
-        for (int64_t base = e0; base < e1; base += 64) {
-            const int64_t e = base + lane;
-            int lo = 0, hi = nr - 1;  // largest row i with start_i <= e
+        const int64_t u = u0 + (lane < nr ? lane : nr - 1);
+        const int64_t rb = xadj[u], re = xadj[u + 1];
+        const int64_t len = (lane < nr && re - rb <= heavy_deg) ? re - rb : 0;
+        // flat offsets of the light edges of the chunk
+        int64_t off = len;
+#pragma unroll
+        for (int k = 1; k < 64; k <<= 1) {
+            const int64_t o = __shfl_up(off, k, 64);
+            if (lane >= k) off += o;
+        }
+        const int64_t total = __shfl(off, 63, 64);
+        const int64_t start = off - len;  // exclusive prefix
+        for (int64_t base = 0; base < total; base += 64) {
+            const int64_t f = base + lane;
+            int lo = 0, hi = nr - 1;  // largest row i with start_i <= f
 #pragma unroll
             for (int k = 0; k < 6; ++k) {
                 const int mid = (lo + hi + 1) >> 1;
                 const int64_t sm = __shfl(start, mid, 64);
                 if (lo < hi) {
-                    if (sm <= e)
+                    if (sm <= f)
                         lo = mid;
                     else
                         hi = mid - 1;
                 }
             }
-            if (e < e1) eh[e] = mm3_key8((uint32_t)(u0 + lo), (uint32_t)adj[e], seed) & 0x7FFFFFFFu;
+            const int64_t e = __shfl(rb, lo, 64) + (f - __shfl(start, lo, 64));
+            if (f < total) eh[e] = mm3_key8((uint32_t)(u0 + lo), (uint32_t)adj[e], seed) & 0x7FFFFFFFu;
         }
     }
 }
 
+__global__ void k_edge_hash_pieces(const int32_t* __restrict__ adj, const int32_t* __restrict__ hrow,
+                                   const int32_t* __restrict__ prow, const int64_t* __restrict__ pe0,
+                                   const int64_t* __restrict__ pe1, int64_t npieces, uint32_t* eh, uint32_t seed) {
+    const int lane = threadIdx.x & 63;
+    for (int64_t pc = wave_index(); pc < npieces; pc += wave_count()) {
+        const uint32_t u = (uint32_t)hrow[prow[pc]];
+        const int64_t e1 = pe1[pc];
+        for (int64_t e = pe0[pc] + lane; e < e1; e += 64) eh[e] = mm3_key8(u, (uint32_t)adj[e], seed) & 0x7FFFFFFFu;
+    }
+}
+
 hipError_t launch_edge_hash(const DevGraph& g, uint32_t seed, hipStream_t s) {
-    hipLaunchKernelGGL(k_edge_hash, dim3(8192), dim3(256), 0, s, g.xadj, g.adj, g.eh, g.n, seed);
+    hipLaunchKernelGGL(k_edge_hash_light, dim3(8192), dim3(256), 0, s, g.xadj, g.adj, g.eh, g.n, g.heavy_deg, seed);
+    if (g.npieces > 0)
+        hipLaunchKernelGGL(k_edge_hash_pieces, dim3(8192), dim3(256), 0, s, g.adj, g.hrow, g.prow, g.pe0, g.pe1,
+                           g.npieces, g.eh, seed);
     return hipGetLastError();
 }
 
-__global__ void k_indegree(const int32_t* __restrict__ adj, int64_t m, uint32_t* indeg) {
-    for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < m; e += (int64_t)gridDim.x * blockDim.x)
-        atomicAdd(&indeg[adj[e]], 1u);
+// In-degrees.  R-MAT-like graphs put their highest in-degrees on the lowest
+// ids, so the counts of ids below HOT_IDS are first gathered per block in LDS.
+constexpr int HOT_IDS = 8192;
+
+__global__ __launch_bounds__(256) void k_indegree(const int32_t* __restrict__ adj, int64_t m, int64_t n,
+                                                  uint32_t* indeg) {
+    __shared__ uint32_t hot[HOT_IDS];
+    for (int i = threadIdx.x; i < HOT_IDS; i += blockDim.x) hot[i] = 0u;
+    __syncthreads();
+    for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < m; e += (int64_t)gridDim.x * blockDim.x) {
+        const int32_t v = adj[e];
+        if (v < HOT_IDS)
+            atomicAdd(&hot[v], 1u);
+        else
+            atomicAdd(&indeg[v], 1u);
+    }
+    __syncthreads();
+    for (int i = threadIdx.x; i < HOT_IDS && i < n; i += blockDim.x)
+        if (hot[i]) atomicAdd(&indeg[i], hot[i]);
 }
 
 hipError_t launch_indegree(const DevGraph& g, uint32_t* indeg, hipStream_t s) {
     if (g.m == 0) return hipSuccess;
-    hipLaunchKernelGGL(k_indegree, dim3(8192), dim3(256), 0, s, g.adj, g.m, indeg);
+    hipLaunchKernelGGL(k_indegree, dim3(1024), dim3(256), 0, s, g.adj, g.m, g.n, indeg);
     return hipGetLastError();
 }
 
@@ -1033,23 +1076,35 @@ __global__ void k_scan_sums(int64_t* sums, int64_t nb) {
     }
 }
 
-__global__ void k_scan_apply(const uint32_t* __restrict__ in, int64_t n, const int64_t* __restrict__ sums,
-                             int64_t* out) {
-    __shared__ int64_t sh[SCAN_BLOCK];
-    const int64_t i0 = (int64_t)blockIdx.x * SCAN_BLOCK;
-    for (int k = threadIdx.x; k < SCAN_BLOCK; k += 256) sh[k] = i0 + k < n ? (int64_t)in[i0 + k] : 0;
-    __syncthreads();
-    if (threadIdx.x == 0) {
-        int64_t run = sums[blockIdx.x];
-        for (int k = 0; k < SCAN_BLOCK; ++k) {
-            const int64_t v = sh[k];
-            sh[k] = run;
-            run += v;
-        }
+__global__ __launch_bounds__(256) void k_scan_apply(const uint32_t* __restrict__ in, int64_t n,
+                                                    const int64_t* __restrict__ sums, int64_t* out) {
+    // exclusive prefix of the block's SCAN_BLOCK values: 4 per thread, then a
+    // scan of the thread totals across the block
+    __shared__ int64_t sh_wave[4];
+    const int64_t i0 = (int64_t)blockIdx.x * SCAN_BLOCK + 4 * threadIdx.x;
+    int64_t v[4], t = 0;
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+        v[k] = i0 + k < n ? (int64_t)in[i0 + k] : 0;
+        t += v[k];
     }
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    int64_t incl = t;
+#pragma unroll
+    for (int k = 1; k < 64; k <<= 1) {
+        const int64_t o = __shfl_up(incl, k, 64);
+        if (lane >= k) incl += o;
+    }
+    if (lane == 63) sh_wave[w] = incl;
     __syncthreads();
-    for (int k = threadIdx.x; k < SCAN_BLOCK; k += 256)
-        if (i0 + k < n) out[i0 + k] = sh[k];
+    int64_t base = sums[blockIdx.x];
+    for (int k = 0; k < w; ++k) base += sh_wave[k];
+    int64_t run = base + incl - t;
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+        if (i0 + k < n) out[i0 + k] = run;
+        run += v[k];
+    }
     const int64_t nb = (n + SCAN_BLOCK - 1) / SCAN_BLOCK;
     if (blockIdx.x == nb - 1 && threadIdx.x == 0) out[n] = sums[nb];
 }
