@@ -52,6 +52,88 @@ def heavy_launch_bytes(rec, J, wc, m_heavy, npieces):
     return b
 
 
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "k_sweep_heavy__rmat24_wc_J256_K50__traffic.md")
+KERNEL_SOURCES = ["paper_2105_04023_amd/csrc/hfr_kernels.hip", "paper_2105_04023_amd/csrc/hfr_device.h",
+                  "paper_2105_04023_amd/csrc/hfr_internal.h", "paper_2105_04023_amd/csrc/hfr_api.hip"]
+COPY_BYTES = 1 << 30
+
+
+def kernel_source_hash() -> str:
+    """sha256 over the sources the sweep kernels and their launches are built from."""
+    import hashlib
+
+    h = hashlib.sha256()
+    for f in KERNEL_SOURCES:
+        with open(os.path.join(ROOT, f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()
+
+
+def measured_traffic():
+    """HBM bytes per k_sweep_heavy launch from the committed counter summary, or None when the
+    summary is missing or was taken from other kernel sources."""
+    try:
+        kv = {}
+        for line in open(TRAFFIC_FILE):
+            if line.startswith("- ") and ": " in line:
+                k, v = line[2:].split(": ", 1)
+                kv[k.strip()] = v.strip().strip("`")
+        if kv.get("source_sha256") != kernel_source_hash():
+            return None
+        return float(kv["traffic_bytes_per_launch"])
+    except (OSError, KeyError, ValueError):
+        return None
+
+
+def summarize_pmc(fetch_dir: str, write_dir: str, command: str):
+    """Writes the traffic summary from two rocprofv3 --pmc runs of the same command (FETCH_SIZE, then
+    WRITE_SIZE; KiB per dispatch).  Each counter is scaled by what it reads for the 1 GiB device copy
+    that bench.py --calibrate-copy performs: factor = copied bytes / (counter KiB * 1024)."""
+    import csv
+
+    def per_dispatch(d):
+        out = {}
+        path = os.path.join(d, "run_counter_collection.csv")
+        for r in csv.DictReader(open(path)):
+            k = int(r["Dispatch_Id"])
+            e = out.setdefault(k, {"name": r["Kernel_Name"], "v": 0.0})
+            e["v"] += float(r["Counter_Value"])
+        return out
+
+    res = {}
+    for tag, d in (("FETCH_SIZE", fetch_dir), ("WRITE_SIZE", write_dir)):
+        disp = per_dispatch(d)
+        heavy = [e["v"] for e in disp.values() if e["name"].startswith("void hfr::k_sweep_heavy<")]
+        copies = [e["v"] for e in disp.values() if "copyBuffer" in e["name"]]
+        if not heavy or not copies:
+            raise SystemExit(f"{d}: no k_sweep_heavy or copy dispatches")
+        cal = max(copies)  # the 1 GiB calibration copy is the largest copy
+        factor = COPY_BYTES / (cal * 1024.0)
+        res[tag] = (sum(heavy) / len(heavy), len(heavy), cal, factor)
+    fetch_kib, n_f, cal_f, fac_f = res["FETCH_SIZE"]
+    write_kib, n_w, cal_w, fac_w = res["WRITE_SIZE"]
+    traffic = fetch_kib * 1024 * fac_f + write_kib * 1024 * fac_w
+    lines = [
+        "# k_sweep_heavy on rmat24_wc_J256_K50: HBM traffic from counters",
+        "",
+        "Commands (run from the repository root on the GPU box, `cd /tmp && export TMPDIR=/tmp` first):",
+        "",
+        f"    {command.format(counter='FETCH_SIZE', out=fetch_dir)}",
+        f"    {command.format(counter='WRITE_SIZE', out=write_dir)}",
+        "",
+        f"k_sweep_heavy dispatches: {n_f} (FETCH_SIZE run), {n_w} (WRITE_SIZE run); averages per dispatch:",
+        f"FETCH_SIZE {fetch_kib:.1f} KiB, WRITE_SIZE {write_kib:.1f} KiB.",
+        f"Calibration: a {COPY_BYTES} B device copy read FETCH_SIZE {cal_f:.1f} KiB and WRITE_SIZE {cal_w:.1f} KiB,",
+        f"so the factors are {fac_f:.4f} (fetch) and {fac_w:.4f} (write).",
+        "",
+        f"- fetch_bytes_per_launch: {fetch_kib * 1024 * fac_f:.0f}",
+        f"- write_bytes_per_launch: {write_kib * 1024 * fac_w:.0f}",
+        f"- traffic_bytes_per_launch: {traffic:.0f}",
+        f"- source_sha256: `{kernel_source_hash()}`",
+    ]
+    return "\n".join(lines) + "\n"
+
+
 def cpu_baseline(seconds_hint: float = 15.0):
     """The oracle's Simulate, single-threaded, on a bounded sample: the same R-MAT recipe at scale 16."""
     import oracle
@@ -204,7 +286,17 @@ def main():
     ap.add_argument("--sparse-div", type=int, default=0)
     ap.add_argument("--heavy-degree", type=int, default=0)
     ap.add_argument("--dump-sweeps", default="", help="write the sweep log of the last step to this JSON file")
+    ap.add_argument("--calibrate-copy", action="store_true",
+                    help="start with one 1 GiB device copy (the counter calibration of the traffic summary)")
+    ap.add_argument("--summarize-pmc", nargs=2, metavar=("FETCH_DIR", "WRITE_DIR"),
+                    help="print the traffic summary of two rocprofv3 --pmc output folders and exit")
     args = ap.parse_args()
+    if args.summarize_pmc:
+        cmd = ("timeout -s KILL 600 rocprofv3 --kernel-trace --pmc {counter} --output-format csv -d {out} -o run "
+               "-- python3 bench.py --steps 1 --warmup 0 --no-batch --serve-requests 0 --no-cpu-baseline "
+               "--calibrate-copy")
+        sys.stdout.write(summarize_pmc(args.summarize_pmc[0], args.summarize_pmc[1], cmd))
+        return
     if args.gpus != 1:
         print(json.dumps({"error": "this path runs on one GPU; multi-GPU runs are not part of this build",
                           "n_gpus": args.gpus}))
@@ -226,6 +318,12 @@ def main():
     m_heavy = int(deg[deg > heavy_deg].sum())
     xd = torch.from_numpy(g.xadj).cuda()
     ad = torch.from_numpy(g.adj).cuda()
+    if args.calibrate_copy:
+        a = torch.ones(COPY_BYTES // 4, dtype=torch.int32, device="cuda")
+        b = torch.empty_like(a)
+        b.copy_(a)
+        torch.cuda.synchronize()
+        del a, b
     torch.cuda.synchronize()
     ctx = hf.Context(0)
 
@@ -300,7 +398,8 @@ def main():
         "sigma": results[-1]["sigma"],
         "seeds_head": results[-1]["seeds"][:8],
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": achieved / HBM_PEAK_GBS, "traffic": None, "kernel": "k_sweep_heavy",
+                     "frac": achieved / HBM_PEAK_GBS, "traffic": measured_traffic(), "traffic_unit": "bytes/launch",
+                     "kernel": "k_sweep_heavy",
                      "launches": nlaunch, "avg_launch_ms": tot_ms / max(nlaunch, 1),
                      "algorithmic_bytes_per_launch": tot_bytes / max(nlaunch, 1)},
         "row_kernel": {"kernel": "k_sweep_rows64", "ms": row_ms,
