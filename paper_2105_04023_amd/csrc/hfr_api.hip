@@ -101,6 +101,7 @@ struct im_sketch {
     unsigned long long* gather = nullptr;  // device [2][3 * MAX_BATCH]
     uint32_t* part = nullptr;
     uint32_t* part_any = nullptr;
+    uint32_t* rtouch = nullptr;
     GreedyBufs gb{};
     StepRec* d_steps = nullptr;
     int32_t* d_seeds = nullptr;
@@ -205,7 +206,7 @@ size_t bytes_needed(int64_t n, int64_t m, int32_t R, im_prob_kind kind) {
     // split rows: bounded by m / heavy_degree rows and m / piece + rows pieces
     const int64_t nh = m / DEFAULT_HEAVY + 1, np = m / DEFAULT_PIECE + nh + 1;
     t += al(4 * nh) + al(8 * (nh + 1)) + al(8 * nh) + al(4 * np) + 2 * al(8 * np) + al((size_t)np * L.P * 4) +
-         al(4 * np) + al(4 * nh) + al(4 * np) + al(4 * (np / 32 + 1));
+         al(4 * np) + 2 * al(4 * nh) + al(4 * np) + al(4 * (np / 32 + 1));
     // greedy
     const size_t W = 4 * (size_t)L.PW;
     t += 3 * al((size_t)n * W * 4) + al(4 * words);
@@ -347,6 +348,7 @@ im_status run_simulate(im_sketch* sk, int ia, int ib, const uint32_t* blk, SimRe
             // piece flags of earlier sweeps never equal this sweep's stamp
             if (++sk->stamp_ctr == 0u) {
                 if (sk->g.npieces > 0) HIP_TRY(launch_fill_u32(sk->part_any, 0u, sk->g.npieces, s));
+                if (sk->g.nheavy > 0) HIP_TRY(launch_fill_u32(sk->rtouch, 0u, sk->g.nheavy, s));
                 sk->stamp_ctr = 1u;
             }
             sp.fr.stamp = sk->stamp_ctr;
@@ -362,6 +364,7 @@ im_status run_simulate(im_sketch* sk, int ia, int ib, const uint32_t* blk, SimRe
             sp.sum_out = sum_slots(sk, st + 1);
             sp.part = sk->part;
             sp.part_any = sk->part_any;
+            sp.rtouch = sk->rtouch;
             sp.first = st == 0;
             hipEvent_t e0 = nullptr, e1 = nullptr, ea = nullptr, eb = nullptr, e2 = nullptr, e3 = nullptr;
             if (sk->time_sweeps && timer_idx + 5 < (int)sk->sweep_ev.size()) {
@@ -648,7 +651,8 @@ im_status im_build_sketches(im_ctx* ctx, const im_csr* graph, const im_probs* pr
             bool ok2 = sk_alloc(sk, &g.hrow, g.nheavy) && sk_alloc(sk, &g.hpb, g.nheavy) &&
                        sk_alloc(sk, &g.hpn, g.nheavy) && sk_alloc(sk, &g.prow, g.npieces) &&
                        sk_alloc(sk, &g.pe0, g.npieces) && sk_alloc(sk, &g.pe1, g.npieces) &&
-                       sk_alloc(sk, &sk->part, (size_t)g.npieces * L.P) && sk_alloc(sk, &sk->part_any, g.npieces);
+                       sk_alloc(sk, &sk->part, (size_t)g.npieces * L.P) && sk_alloc(sk, &sk->part_any, g.npieces) &&
+                       sk_alloc(sk, &sk->rtouch, g.nheavy);
             if (!ok2) return fail(IM_ERR_OUT_OF_BUDGET, "device allocation failed (split rows)");
             HIP_TRY(launch_heavy_assign(g, piece, sk->d_heavy_counts, s));
             HIP_TRY(launch_heavy_pieces(g, piece, s));
@@ -656,6 +660,7 @@ im_status im_build_sketches(im_ctx* ctx, const im_csr* graph, const im_probs* pr
                 !sk_alloc(sk, &sk->fr.pmark, g.npieces / 32 + 1))
                 return fail(IM_ERR_OUT_OF_BUDGET, "device allocation failed (sparse lists)");
             HIP_TRY(launch_fill_u32(sk->part_any, 0u, g.npieces, s));
+            HIP_TRY(launch_fill_u32(sk->rtouch, 0u, g.nheavy, s));
             HIP_TRY(launch_fill_u32(sk->fr.pmark, 0u, g.npieces / 32 + 1, s));
         }
         HIP_TRY(launch_heavy_slots(g, s));

@@ -432,6 +432,13 @@ DEVI bool fix_row(int64_t r, int64_t u, const uint32_t* __restrict__ A, uint32_t
         const int q = k * G + p;
         ub[k] = (blk && q < P) ? unblocked_mask(blk, u, q, PW) : 0xFFFFFFFFu;
     }
+    // the row's own registers are first needed after the pieces: load them now
+    uint32_t a[DW];
+#pragma unroll
+    for (int k = 0; k < DW; ++k) {
+        const int q = k * G + p;
+        a[k] = A[u * P + (q < P ? q : P - 1)];
+    }
     const int64_t pb = hpb[r], np = hpn[r];
     uint32_t acc[DW];
     bool any = false;
@@ -487,9 +494,8 @@ DEVI bool fix_row(int64_t r, int64_t u, const uint32_t* __restrict__ A, uint32_t
         const int q = k * G + p;
         nw[k] = 0;
         if (q < P) {
-            const uint32_t a = A[u * P + q];
-            nw[k] = byte_max(a, acc[k]) & ub[k];
-            ch = ch || nw[k] != a;
+            nw[k] = byte_max(a[k], acc[k]) & ub[k];
+            ch = ch || nw[k] != a[k];
         }
     }
     const bool changed = group_any<G>(ch);
@@ -690,7 +696,10 @@ DEVI unsigned long long bfs_expand_entries(int64_t b0, int64_t b1, int64_t bstep
         int nb = 0;
         auto flush = [&]() {
             uint32_t nbits = 0;
-            if (myval) {
+            // blocked bits are only ever set: a plain read that already shows every
+            // candidate bit means the atomic could add nothing (a stale read only
+            // costs an atomic)
+            if (myval && (myval & ~blk[myw * W + sw]) != 0u) {
                 const uint32_t old = atomicOr(&blk[myw * W + sw], myval);
                 nbits = myval & ~old;
                 if (nbits) {

@@ -89,6 +89,7 @@ struct SweepParams {
     const unsigned long long* sgate;  // slots of S_t = sum of in-degrees over L_t (nullptr on the first sweep)
     unsigned long long* sum_out;      // slots of S_{t+1}
     const uint32_t* fullblk;   // n bits: vertex blocked in every sample (nullptr with blk)
+    uint32_t* rtouch;          // per split row: serial of the last sweep that merged one of its pieces
     Frontier fr;
     int parity;                // t & 1
     int first;

@@ -876,7 +876,7 @@ __global__ __launch_bounds__(256) void k_sweep_heavy(
     const int32_t* __restrict__ prow, const int64_t* __restrict__ pe0, const int64_t* __restrict__ pe1,
     uint32_t* __restrict__ part, uint32_t* __restrict__ part_any, int64_t npieces, int64_t n, int P, int PW,
     int first, Frontier fr, int parity, const unsigned long long* __restrict__ sgate, int64_t m,
-    const uint32_t* __restrict__ fullblk) {
+    const uint32_t* __restrict__ fullblk, uint32_t* __restrict__ rtouch) {
     __shared__ unsigned long long sh64[4];
     const uint32_t live = sweep_live(gate, gate_thresh, first, n);
     if (!live) return;
@@ -892,7 +892,8 @@ __global__ __launch_bounds__(256) void k_sweep_heavy(
         const int64_t i = base + grp;
         if (i >= count) continue;
         const int64_t pc = sparse ? (int64_t)fr.HP[i] : i;
-        const bool skip = fullblk && bit_of(fullblk, hrow[prow[pc]]) != 0u;
+        const int32_t r = prow[pc];
+        const bool skip = fullblk && bit_of(fullblk, hrow[r]) != 0u;
         Acc acc[DW];
 #pragma unroll
         for (int k = 0; k < DW; ++k) acc[k].e = acc[k].o = 0u;
@@ -908,6 +909,7 @@ __global__ __launch_bounds__(256) void k_sweep_heavy(
         }
         if (p == 0) {
             part_any[pc] = vis > 0 ? fr.stamp : 0u;
+            if (vis > 0) rtouch[r] = fr.stamp;  // the row has a piece to combine in this sweep
             my_vis += vis;
         }
     }
@@ -925,7 +927,8 @@ __global__ __launch_bounds__(256) void k_sweep_heavy_fix(
     const int64_t* __restrict__ hpb, const int64_t* __restrict__ hpn, const uint32_t* __restrict__ part,
     const uint32_t* __restrict__ part_any, int64_t nheavy, int64_t n, int P, int PW, int first, Frontier fr,
     int parity, const unsigned long long* __restrict__ sgate, unsigned long long* __restrict__ sum_out,
-    const int64_t* __restrict__ rxadj, int64_t m, const uint32_t* __restrict__ fullblk) {
+    const int64_t* __restrict__ rxadj, int64_t m, const uint32_t* __restrict__ fullblk,
+    const uint32_t* __restrict__ rtouch) {
     __shared__ uint32_t sh32[4];
     __shared__ unsigned long long sh64[4];
     const uint32_t live = sweep_live(gate, gate_thresh, first, n);
@@ -937,18 +940,52 @@ __global__ __launch_bounds__(256) void k_sweep_heavy_fix(
     const int lane = threadIdx.x & 63, grp = lane / G, p = lane % G;
     uint32_t my_cnt = 0;
     unsigned long long my_sum = 0;
-    for (int64_t base = wave_index() * RPW; base < count; base += wave_count() * RPW) {
-        const int64_t i = base + grp;
-        if (i >= count) continue;
-        const int64_t r = sparse ? (int64_t)fr.HW[i] : i;
-        const int64_t u = hrow[r];
-        if (fullblk && bit_of(fullblk, u)) continue;
-        const bool changed =
-            fix_row<G, DW>(r, u, A, B, Lcur, blk, hpb, hpn, part, part_any, stamp, P, PW, first, lane, p);
-        if (changed && p == 0) {
-            atomicOr(&Lnext[u >> 5], 1u << (u & 31));
-            my_cnt += 1;
-            my_sum += (unsigned long long)(rxadj[u + 1] - rxadj[u]);
+    // A row needs work only if a piece merged a live edge in this sweep (touch
+    // stamp) or it is in L_t (copy rule); fix_row would leave any other row
+    // untouched.  Rows are filtered with one ballot per wave-sized group.
+    auto needs = [&](int64_t r, int64_t u) {
+        return !(fullblk && bit_of(fullblk, u)) && (rtouch[r] == stamp || (!first && bit_of(Lcur, u)));
+    };
+    if constexpr (G == 64) {
+        // each wave filters `span` rows at a time, span = its share of the rows (<= 64)
+        int64_t span = (count + wave_count() - 1) / wave_count();
+        span = span < 1 ? 1 : (span > 64 ? 64 : span);
+        for (int64_t base = wave_index() * span; base < count; base += wave_count() * span) {
+            const int64_t i = base + lane;
+            int64_t r = 0, u = 0;
+            bool need = false;
+            if (lane < span && i < count) {
+                r = sparse ? (int64_t)fr.HW[i] : i;
+                u = hrow[r];
+                need = needs(r, u);
+            }
+            for (uint64_t mask = __ballot(need); mask; mask &= mask - 1) {
+                const int j = __builtin_ctzll(mask);
+                const int64_t rr = __builtin_amdgcn_readlane((int)r, j);
+                const int64_t uu = __builtin_amdgcn_readlane((int)u, j);
+                const bool changed =
+                    fix_row<G, DW>(rr, uu, A, B, Lcur, blk, hpb, hpn, part, part_any, stamp, P, PW, first, lane, p);
+                if (changed && lane == 0) {
+                    atomicOr(&Lnext[uu >> 5], 1u << (uu & 31));
+                    my_cnt += 1;
+                    my_sum += (unsigned long long)(rxadj[uu + 1] - rxadj[uu]);
+                }
+            }
+        }
+    } else {
+        for (int64_t base = wave_index() * RPW; base < count; base += wave_count() * RPW) {
+            const int64_t i = base + grp;
+            if (i >= count) continue;
+            const int64_t r = sparse ? (int64_t)fr.HW[i] : i;
+            const int64_t u = hrow[r];
+            if (!needs(r, u)) continue;
+            const bool changed =
+                fix_row<G, DW>(r, u, A, B, Lcur, blk, hpb, hpn, part, part_any, stamp, P, PW, first, lane, p);
+            if (changed && p == 0) {
+                atomicOr(&Lnext[u >> 5], 1u << (u & 31));
+                my_cnt += 1;
+                my_sum += (unsigned long long)(rxadj[u + 1] - rxadj[u]);
+            }
         }
     }
     const uint32_t bc = block_sum256(my_cnt, sh32);
@@ -1025,7 +1062,8 @@ hipError_t launch_sweep(const Layout& L, const DevGraph& g, const uint32_t* X, c
                                                                             sp.vis_heavy_out, g.hrow, g.prow, g.pe0,
                                                                             g.pe1, sp.part, sp.part_any, g.npieces,
                                                                             g.n, L.P, L.PW, sp.first, sp.fr,
-                                                                            sp.parity, sp.sgate, g.m, sp.fullblk)));
+                                                                            sp.parity, sp.sgate, g.m, sp.fullblk,
+                                                                            sp.rtouch)));
         err = hipGetLastError();
         if (err != hipSuccess) return err;
         if (ev3) (void)hipEventRecord(ev3, s);
@@ -1034,7 +1072,7 @@ hipError_t launch_sweep(const Layout& L, const DevGraph& g, const uint32_t* X, c
                                                   sp.Lcur, sp.Lnext, sp.blk, sp.gate, sp.gate_thresh, sp.cnt_out,
                                                   g.hrow, g.hpb, g.hpn, sp.part, sp.part_any, g.nheavy, g.n, L.P,
                                                   L.PW, sp.first, sp.fr, sp.parity, sp.sgate, sp.sum_out, g.rxadj,
-                                                  g.m, sp.fullblk));
+                                                  g.m, sp.fullblk, sp.rtouch));
         err = hipGetLastError();
         if (err != hipSuccess) return err;
     } else if (ev3) {
