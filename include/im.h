@@ -236,6 +236,21 @@ IM_API im_status im_sketch_get_blocked(const im_sketch* sk, uint8_t* out);
 IM_API void im_sketch_free(im_sketch* sk);
 
 /*
+ * Independent Monte-Carlo evaluation of a seed set: sigma(S) = (1/R) sum_j
+ * |vertices reachable from S in sample j| over R samples drawn with
+ * hash_seed (use a seed other than the selection's for samples independent of
+ * the sketches): live-edge samples as in Eq. (hash_prob), then one
+ * multi-source reach search over all samples at once (Alg. 1's reach step
+ * from the whole set).  graph and probs as in im_build_sketches; seeds holds
+ * count >= 1 host vertex ids (repeats allowed).  *out_sigma receives sigma,
+ * *out_reach (may be NULL) the reached (vertex, sample) pairs.  Temporary
+ * device memory comes from the context and is released before returning.
+ */
+IM_API im_status im_evaluate_influence(im_ctx* ctx, const im_csr* graph, const im_probs* probs, int32_t R,
+                                       uint32_t hash_seed, const int32_t* seeds, int32_t count, double* out_sigma,
+                                       int64_t* out_reach);
+
+/*
  * ---------------------------------------------------------------------------
  * Batched solve: many independent problems (graphs of uneven sizes, edge
  * models and R) solved together by ONE persistent kernel launch, captured

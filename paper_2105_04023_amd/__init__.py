@@ -15,7 +15,7 @@ import numpy as np
 from . import _binding as B
 
 __all__ = ["Context", "Sketch", "Batch", "BatchJob", "Server", "im_build_sketches", "im_estimate", "im_estimate_all",
-           "im_select_seeds", "im_batch_create", "ImError"]
+           "im_select_seeds", "im_batch_create", "im_evaluate_influence", "ImError"]
 
 ImError = B.ImError
 _KIND = {"const": B.IM_PROB_CONSTANT, "wc": B.IM_PROB_WEIGHTED_CASCADE, "edge": B.IM_PROB_PER_EDGE}
@@ -183,6 +183,33 @@ def im_build_sketches(ctx: Context, xadj, adj, n: int, R: int, model: str = "con
                                       ctypes.byref(opts), ctypes.byref(h)))
     del keep
     return Sketch(ctx, h, n, R)
+
+
+def im_evaluate_influence(ctx: Context, xadj, adj, n: int, seeds, R: int, model: str = "const", p: float = 0.0,
+                          per_edge=None, hash_seed: int = 0):
+    """Monte-Carlo influence of a seed set over R fresh samples: (sigma, reached pairs)."""
+    torch = _torch()
+    xp, xdev, xk = _ptr_and_residency(xadj, (np.int64, torch.int64))
+    ap, adev, ak = _ptr_and_residency(adj, (np.int32, torch.int32))
+    if xdev != adev:
+        raise ValueError("xadj and adj must both be host arrays or both device tensors")
+    m = int(len(adj)) if not isinstance(adj, torch.Tensor) else int(adj.numel())
+    keep = [xk, ak]
+    pe_ptr = None
+    if model == "edge":
+        pp, pdev, pk = _ptr_and_residency(per_edge, (np.float32, torch.float32))
+        if pdev != xdev:
+            raise ValueError("per-edge probabilities must reside where the CSR resides")
+        pe_ptr = pp
+        keep.append(pk)
+    sv = np.ascontiguousarray(seeds, dtype=np.int32).ravel()
+    sigma, reach = ctypes.c_double(), ctypes.c_int64()
+    B.check(ctx.lib.im_evaluate_influence(ctx.handle, ctypes.byref(B.im_csr(n, m, xp, ap, xdev)),
+                                          ctypes.byref(B.im_probs(_KIND[model], float(p), pe_ptr)), R,
+                                          hash_seed & 0xFFFFFFFF, sv.ctypes.data, len(sv), ctypes.byref(sigma),
+                                          ctypes.byref(reach)))
+    del keep
+    return sigma.value, reach.value
 
 
 def im_estimate(sk: Sketch, verts) -> float:

@@ -23,7 +23,7 @@ EXPORTED = [
     "im_sketch_get_registers", "im_sketch_get_blocked", "im_sketch_free", "im_last_error", "im_version",
     "im_sketch_get_sweep_log", "im_sketch_clear_sweep_log", "im_batch_create", "im_batch_run", "im_batch_get_result",
     "im_batch_get_registers", "im_batch_device_bytes", "im_batch_free", "im_server_create", "im_server_add_graph",
-    "im_server_submit", "im_server_wait", "im_server_get_stats", "im_server_free",
+    "im_server_submit", "im_server_wait", "im_server_get_stats", "im_server_free", "im_evaluate_influence",
 ]
 
 
@@ -172,6 +172,8 @@ def load(path: str = LIB_PATH):
         "im_server_wait": ([p, i64, ctypes.POINTER(im_response)], ctypes.c_int),
         "im_server_get_stats": ([p, ctypes.POINTER(im_server_stats)], ctypes.c_int),
         "im_server_free": ([p], None),
+        "im_evaluate_influence": ([p, ctypes.POINTER(im_csr), ctypes.POINTER(im_probs), i32, ctypes.c_uint32, p, i32,
+                                   ctypes.POINTER(ctypes.c_double), ctypes.POINTER(i64)], ctypes.c_int),
     }
     for name, (args, res) in sig.items():
         fn = getattr(lib, name)

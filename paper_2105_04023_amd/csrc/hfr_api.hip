@@ -134,6 +134,7 @@ struct im_sketch {
     int32_t simulate_count = 0;
     int32_t level_id = 1;
     bool selected = false;
+    bool has_registers = true;
 };
 
 namespace {
@@ -276,6 +277,33 @@ struct SimResult {
     std::vector<int64_t> live, vis, vis_light;
     std::vector<char> sparse;
 };
+
+// Runs the multi-sample reach BFS from the level-0 queue (qsize[0] entries,
+// frontier bits in F[0]) until a level finds nothing new.  Levels are launched
+// in growing batches; the host reads the queue sizes after each batch.
+// *levels: levels launched; *with_work += levels that had entries.
+im_status run_reach(im_sketch* sk, int32_t lvl0, int* levels, int64_t* with_work) {
+    hipStream_t s = sk->ctx->stream;
+    const int64_t n = sk->g.n;
+    GreedyBufs& b = sk->gb;
+    int level = 0, nb = 4;
+    while (true) {
+        const int64_t bfs_grid = 2048;
+        for (int i = 0; i < nb; ++i, ++level)
+            HIP_TRY(launch_bfs_level(sk->L, sk->g, sk->X, b, level, lvl0 + level + 1, (int)bfs_grid, s));
+        HIP_TRY(hipMemcpyAsync(sk->h_small, b.qsize, 16, hipMemcpyDeviceToHost, s));
+        HIP_TRY(hipStreamSynchronize(s));
+        if ((sk->h_small[0] | sk->h_small[1] | sk->h_small[2]) == 0u) break;
+        if (level > n + 2) {
+            sk->poisoned = true;
+            return fail(IM_ERR_DEVICE, "reach search exceeded n levels");
+        }
+        nb = std::min(nb * 2, 64);
+    }
+    *levels = level;
+    *with_work += sk->h_small[3];
+    return IM_OK;
+}
 
 // True once the reverse CSR built on the aux stream is complete (then the
 // context stream is ordered after it and its temporaries are freed); with
@@ -499,8 +527,16 @@ size_t im_sketch_bytes_needed(int64_t n, int64_t m, int32_t R, im_prob_kind kind
     return bytes_needed(n, m, R, kind);
 }
 
-im_status im_build_sketches(im_ctx* ctx, const im_csr* graph, const im_probs* probs, int32_t R, uint32_t hash_seed,
-                            const im_build_opts* opts, im_sketch** out) {
+}  // extern "C"
+
+namespace {
+
+// Builds a sketch (graph copy, hashes, thresholds, split rows, reverse CSR,
+// greedy buffers) and, with `simulate`, its registers (Alg. 2).  Without
+// `simulate` no register buffer is allocated: the handle serves Monte-Carlo
+// reach only.
+im_status build_sketch(im_ctx* ctx, const im_csr* graph, const im_probs* probs, int32_t R, uint32_t hash_seed,
+                       const im_build_opts* opts, bool simulate, im_sketch** out) {
     im_sketch* sk = nullptr;
     if (!ctx || !graph || !probs || !out) return fail(IM_ERR_INVALID_ARG, "null argument");
     if (R < 4 || R > 1024 || R % 4) return fail(IM_ERR_INVALID_ARG, "R must be a multiple of 4 in [4, 1024] (got %d)", R);
@@ -550,7 +586,7 @@ im_status im_build_sketches(im_ctx* ctx, const im_csr* graph, const im_probs* pr
     bool ok = true;
     ok = ok && sk_alloc(sk, &g.xadj, n + 1) && sk_alloc(sk, &g.adj, m) && sk_alloc(sk, &g.eh, m);
     ok = ok && sk_alloc(sk, &sk->X, R) && sk_alloc(sk, &sk->HJ, R) && sk_alloc(sk, &sk->T, R);
-    for (int i = 0; i < 3 && ok; ++i) ok = sk_alloc(sk, &sk->M[i], (size_t)n * L.P);
+    for (int i = 0; i < 3 && ok && simulate; ++i) ok = sk_alloc(sk, &sk->M[i], (size_t)n * L.P);
     const int64_t words = (n + 31) / 32 + 1;
     ok = ok && sk_alloc(sk, &sk->Lbm[0], words) && sk_alloc(sk, &sk->Lbm[1], words) &&
          sk_alloc(sk, &sk->Lbm[2], words);
@@ -726,6 +762,10 @@ im_status im_build_sketches(im_ctx* ctx, const im_csr* graph, const im_probs* pr
         HIP_TRY(hipEventElapsedTime(&pm, sk->ev_a, sk->ev_b));
         sk->prep_ms = pm;
 
+        if (!simulate) {
+            HIP_TRY(rev_csr_ready(sk, true));
+            return IM_OK;
+        }
         SimResult r;
         im_status rs = run_simulate(sk, 0, 1, nullptr, &r);
         if (rs != IM_OK) return rs;
@@ -744,8 +784,18 @@ im_status im_build_sketches(im_ctx* ctx, const im_csr* graph, const im_probs* pr
         sk_release(sk);
         return st;
     }
+    sk->has_registers = simulate;
     *out = sk;
     return IM_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+im_status im_build_sketches(im_ctx* ctx, const im_csr* graph, const im_probs* probs, int32_t R, uint32_t hash_seed,
+                            const im_build_opts* opts, im_sketch** out) {
+    return build_sketch(ctx, graph, probs, R, hash_seed, opts, true, out);
 }
 
 void im_sketch_free(im_sketch* sk) { sk_release(sk); }
@@ -909,24 +959,12 @@ im_status im_select_seeds(im_sketch* sk, int32_t K, const im_select_opts* opts, 
             HIP_TRY(hipMemsetAsync(b.qsize, 0, 16, s));
             const int32_t lvl0 = sk->level_id;
             HIP_TRY(launch_select(L, sk->g, sk->M[cur], b, d_steps + (k - 1), d_seeds, k - 1, lvl0, s));
-            // BFS levels in batches; the decision kernel is enqueued after every
-            // batch and reports -1 while the frontier is not empty.
-            int level = 0, nb = 4;
             int32_t flag = -1;
-            while (true) {
-                const int64_t bfs_grid = 2048;
-                for (int i = 0; i < nb; ++i, ++level)
-                    HIP_TRY(launch_bfs_level(L, sk->g, sk->X, b, level, lvl0 + level + 1, (int)bfs_grid, s));
-                HIP_TRY(hipMemcpyAsync(sk->h_small, b.qsize, 16, hipMemcpyDeviceToHost, s));
-                HIP_TRY(hipStreamSynchronize(s));
-                if ((sk->h_small[0] | sk->h_small[1] | sk->h_small[2]) == 0u) break;
-                if (level > n + 2) {
-                    sk->poisoned = true;
-                    return fail(IM_ERR_DEVICE, "reach search exceeded n levels");
-                }
-                nb = std::min(nb * 2, 64);
+            int level = 0;
+            {
+                const im_status rs = run_reach(sk, lvl0, &level, &levels_total);
+                if (rs != IM_OK) return rs;
             }
-            levels_total += sk->h_small[3];
             sk->level_id = lvl0 + level + 2;
             {
                 int32_t chosen = 0;
@@ -1004,6 +1042,50 @@ im_status im_select_seeds(im_sketch* sk, int32_t K, const im_select_opts* opts, 
         stats->wall_ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - wall0).count();
     }
     return IM_OK;
+}
+
+
+im_status im_evaluate_influence(im_ctx* ctx, const im_csr* graph, const im_probs* probs, int32_t R,
+                                uint32_t hash_seed, const int32_t* seeds, int32_t count, double* out_sigma,
+                                int64_t* out_reach) {
+    if (!seeds || !out_sigma) return fail(IM_ERR_INVALID_ARG, "null argument");
+    if (count < 1) return fail(IM_ERR_INVALID_ARG, "count must be >= 1");
+    if (graph)
+        for (int32_t i = 0; i < count; ++i)
+            if (seeds[i] < 0 || seeds[i] >= graph->n)
+                return fail(IM_ERR_INVALID_ARG, "seed %d is not a vertex id", (int)seeds[i]);
+    im_sketch* sk = nullptr;
+    im_status st = build_sketch(ctx, graph, probs, R, hash_seed, nullptr, false, &sk);
+    if (st != IM_OK) return st;
+    hipStream_t s = ctx->stream;
+    const int64_t n = sk->g.n;
+    const size_t W = 4 * (size_t)sk->L.PW;
+    GreedyBufs& b = sk->gb;
+    int32_t* d_seeds = (int32_t*)ctx_alloc(ctx, 4 * (size_t)count);
+    auto body = [&]() -> im_status {
+        if (!d_seeds) return fail(IM_ERR_OUT_OF_BUDGET, "temporary allocation failed");
+        HIP_TRY(hipMemcpyAsync(d_seeds, seeds, 4 * (size_t)count, hipMemcpyHostToDevice, s));
+        HIP_TRY(launch_fill_u32(b.blk, 0u, (int64_t)(n * W), s));
+        HIP_TRY(launch_fill_u32(reinterpret_cast<uint32_t*>(b.R), 0u, 2 * NSLOT * SLOT_U64, s));
+        HIP_TRY(launch_fill_u32(b.qsize, 0u, 4, s));
+        HIP_TRY(launch_reach_start(sk->L, sk->g, b, d_seeds, count, 1, s));
+        int level = 0;
+        int64_t with_work = 0;
+        const im_status rs = run_reach(sk, 1, &level, &with_work);
+        if (rs != IM_OK) return rs;
+        unsigned long long slots[NSLOT * SLOT_U64];
+        HIP_TRY(hipMemcpyAsync(slots, b.R, sizeof(slots), hipMemcpyDeviceToHost, s));
+        HIP_TRY(hipStreamSynchronize(s));
+        unsigned long long reach = 0;
+        for (int i = 0; i < NSLOT; ++i) reach += slots[i * SLOT_U64];
+        *out_sigma = (double)reach / (double)R;
+        if (out_reach) *out_reach = (int64_t)reach;
+        return IM_OK;
+    };
+    st = body();
+    if (d_seeds) ctx_free(ctx, d_seeds);
+    sk_release(sk);
+    return st;
 }
 
 }  // extern "C"

@@ -148,6 +148,8 @@ hipError_t launch_select(const Layout& L, const DevGraph& g, const uint32_t* M, 
                          StepRec* rec, int32_t* seeds_dev, int k, int32_t level_id, hipStream_t s);
 hipError_t launch_bfs_level(const Layout& L, const DevGraph& g, const uint32_t* X, const GreedyBufs& b, int level,
                             int32_t level_id_next, int grid, hipStream_t s);
+hipError_t launch_reach_start(const Layout& L, const DevGraph& g, const GreedyBufs& b, const int32_t* verts,
+                              int count, int32_t level_id, hipStream_t s);
 hipError_t launch_decide(const Layout& L, const GreedyBufs& b, StepRec* rec, int k, int K, double eps_g,
                          double eps_l, int32_t* rebuild_flag, hipStream_t s);
 hipError_t launch_estimate_all(const Layout& L, int64_t n, const uint32_t* M, const double* T, float* out,

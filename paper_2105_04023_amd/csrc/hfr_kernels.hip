@@ -1302,6 +1302,42 @@ hipError_t launch_select(const Layout& L, const DevGraph& g, const uint32_t* M, 
     return hipGetLastError();
 }
 
+// Level 0 of a reach search from a vertex set: one wave per listed vertex s
+// blocks every pair (s, j) not blocked yet, makes the new pairs its frontier
+// and queues its out-edges once (stamp); repeated vertices add nothing.
+__global__ void k_reach_start(const int64_t* __restrict__ xadj, GreedyBufs b, const int32_t* __restrict__ verts,
+                              int count, int P, int PW, int32_t level_id) {
+    const int lane = threadIdx.x & 63;
+    const int W = 4 * PW;
+    for (int64_t i = wave_index(); i < count; i += wave_count()) {
+        const int64_t s = verts[i];
+        const int64_t deg = xadj[s + 1] - xadj[s];
+        uint32_t newcnt = 0;
+        for (int w = lane; w < W; w += 64) {
+            const uint32_t valid = plane_valid_mask(w, P, PW);
+            const uint32_t nb = valid & ~atomicOr(&b.blk[s * W + w], valid);
+            newcnt += __builtin_popcount(nb);
+            if (deg > 0 && nb) atomicOr(&b.F[0][s * W + w], nb);
+        }
+        newcnt = wave_sum(newcnt);
+        if (lane == 0 && newcnt) {
+            atomicAdd(&b.R[0], (unsigned long long)newcnt);
+            if (deg > 0 && atomicMax(&b.stamp[s], level_id) < level_id) {
+                const int64_t nch = (deg + b.bfs_chunk - 1) / b.bfs_chunk;
+                const uint32_t pos = atomicAdd(&b.qsize[0], (uint32_t)nch);
+                for (int64_t c = 0; c < nch; ++c) b.Q[0][pos + c] = make_int2((int)s, (int)c);
+            }
+        }
+    }
+}
+
+hipError_t launch_reach_start(const Layout& L, const DevGraph& g, const GreedyBufs& b, const int32_t* verts,
+                              int count, int32_t level_id, hipStream_t s) {
+    const int grid = (count + 3) / 4 < 1024 ? (count + 3) / 4 : 1024;
+    hipLaunchKernelGGL(k_reach_start, dim3(grid), dim3(256), 0, s, g.xadj, b, verts, count, L.P, L.PW, level_id);
+    return hipGetLastError();
+}
+
 // One BFS level over the queue of level `cur` (see bfs_expand_entries).
 template <int G, int DW, int KIND>
 __global__ __launch_bounds__(256) void k_bfs_expand(const int64_t* __restrict__ xadj, const int32_t* __restrict__ adj,
