@@ -272,6 +272,38 @@ def serve_leg(hf, n_requests: int, slots: int = 4, budget_gb: int = 200):
     }
 
 
+def quality_leg(hf, ctx, eval_R: int = 1024, eval_seed: int = 0x5EED):
+    """Seed quality against rebuild policy on the 2^20-vertex R-MAT (IC p = 0.01, R = 256, K = 50):
+    error-adaptive rebuild (eps_g = 0.01, eps_l = 0.3) against rebuilding after every step
+    (eps = 0) and never rebuilding (eps = inf).  Each seed set is scored by the independent
+    Monte-Carlo evaluator on eval_R fresh samples (hash seed eval_seed)."""
+    import torch
+
+    import synth
+
+    w = synth.workload_rmat20()
+    g = w.graph
+    xd = torch.from_numpy(g.xadj).cuda()
+    ad = torch.from_numpy(g.adj).cuda()
+    sk = hf.im_build_sketches(ctx, xd, ad, g.n, w.J, model=w.model, p=w.p)
+    out = {"workload": w.name, "eval_R": eval_R, "eval_hash_seed": eval_seed, "modes": {}}
+    try:
+        for name, (eg, el) in (("adaptive", (w.eps_g, w.eps_l)), ("always_rebuild", (0.0, 0.0)),
+                               ("never_rebuild", (float("inf"), float("inf")))):
+            t0 = time.perf_counter()
+            seeds, steps, stats = hf.im_select_seeds(sk, w.K, eps_g=eg, eps_l=el)
+            sel_ms = (time.perf_counter() - t0) * 1e3
+            sigma_eval, _ = hf.im_evaluate_influence(ctx, xd, ad, g.n, seeds, eval_R, model=w.model, p=w.p,
+                                                     hash_seed=eval_seed)
+            out["modes"][name] = {"sigma_eval": sigma_eval, "sigma_sketch_samples": steps[-1].sigma,
+                                  "rebuilds": stats["rebuilds"], "select_ms": sel_ms}
+            log(f"quality {name}: sigma {sigma_eval:.1f} (fresh samples), rebuilds {stats['rebuilds']}, "
+                f"select {sel_ms:.0f} ms")
+    finally:
+        sk.free()
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -280,6 +312,7 @@ def main():
     ap.add_argument("--workload", default="rmat24_wc_J256_K50", choices=sorted(WORKLOADS))
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-batch", action="store_true", help="skip the batched-vs-plain comparison")
+    ap.add_argument("--no-quality", action="store_true", help="skip the rebuild-policy quality comparison")
     ap.add_argument("--serve-requests", type=int, default=400,
                     help="requests of the serving leg (the full stream has 2000; 0 skips the leg)")
     ap.add_argument("--K", type=int, default=0, help="override K")
@@ -409,6 +442,8 @@ def main():
         out["batched"] = batch_leg(hf, ctx, args.steps, args.warmup)
     if args.serve_requests > 0:
         out["serving"] = serve_leg(hf, args.serve_requests)
+    if not args.no_quality:
+        out["quality"] = quality_leg(hf, ctx)
     if args.dump_sweeps:
         with open(args.dump_sweeps, "w") as fh:
             json.dump(results[-1]["sweep_log"], fh)
