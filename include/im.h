@@ -78,6 +78,13 @@ typedef struct im_probs {
  * sweeping stops once |L| <= eps_c * n (0 = run to the fixed point).  The
  * tuning fields select the work decomposition only; results do not depend on
  * them.  Zero means "library default". */
+#define IM_BUILD_TIME_SWEEPS 1 /* record HIP-event timings of every sweep (im_sketch_get_sweep_log) */
+#define IM_BUILD_IN_PLACE 2    /* in-place sweeps: a sweep reads registers this sweep already raised
+                                  (the paper's own update order, Sec. 3.3).  Every Simulate, build
+                                  and rebuilds, then reaches the same fixed point in at most as many
+                                  sweeps; registers, estimates and seeds equal those of synchronous
+                                  sweeps when eps_c = 0, while sweep and visit counts depend on the
+                                  schedule (not reproducible). */
 typedef struct im_build_opts {
     double eps_c;
     int32_t heavy_degree; /* rows with more out-edges are split across waves */
@@ -85,7 +92,7 @@ typedef struct im_build_opts {
     int32_t sparse_div;   /* sweep t > 0 visits only the rows next to L_t when the
                              in-degrees of L_t sum to at most m / sparse_div
                              (0: 96; < 0: never) */
-    int32_t reserved;
+    int32_t flags;        /* IM_BUILD_* bits */
 } im_build_opts;
 
 /* Thresholds of the error-adaptive rebuild (Sec. 3.2.1): the sketches are
@@ -198,7 +205,7 @@ IM_API im_status im_sketch_get_trace(const im_sketch* sk, int64_t* live_counts, 
                               int32_t* written);
 
 /* One sweep, recorded when the build was asked to time sweeps
- * (im_build_opts.reserved != 0): kernel_ms is the device time of the row
+ * (IM_BUILD_TIME_SWEEPS): kernel_ms is the device time of the row
  * kernel, heavy_ms that of the split-row piece kernel, sweep_ms that of all
  * kernels of the sweep, from HIP events on the context stream; light_visits the edges
  * with a live head the row kernel visited, visits those of the whole sweep, live_next

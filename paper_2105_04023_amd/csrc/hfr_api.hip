@@ -124,6 +124,7 @@ struct im_sketch {
     void* rev_tmp = nullptr;  // in-degrees and cursors of the reverse CSR build
     std::vector<hipEvent_t> sweep_ev;
     bool time_sweeps = false;
+    bool in_place = false;  // sweeps read and write one register buffer
 
     // build statistics
     int sweeps = 0;
@@ -326,6 +327,9 @@ hipError_t rev_csr_ready(im_sketch* sk, bool wait) {
 im_status run_simulate(im_sketch* sk, int ia, int ib, const uint32_t* blk, SimResult* res) {
     hipStream_t s = sk->ctx->stream;
     const int64_t n = sk->g.n;
+    // synchronous sweeps alternate two buffers; in-place sweeps use one for both
+    // (the copy rule then rewrites a row with its own values)
+    if (sk->in_place) ib = ia;
     uint32_t* buf[2] = {sk->M[ia], sk->M[ib]};
     const double lim = floor(sk->eps_c * (double)n);
     const uint32_t thresh = lim >= (double)n ? (uint32_t)n : (uint32_t)lim;
@@ -554,6 +558,7 @@ im_status build_sketch(im_ctx* ctx, const im_csr* graph, const im_probs* probs, 
     if (opts) o = *opts;
     if (!(o.eps_c >= 0.0)) return fail(IM_ERR_INVALID_ARG, "eps_c must be >= 0");
     if (o.heavy_degree < 0 || o.piece_edges < 0) return fail(IM_ERR_INVALID_ARG, "negative tuning value");
+    if (o.flags & ~(IM_BUILD_TIME_SWEEPS | IM_BUILD_IN_PLACE)) return fail(IM_ERR_INVALID_ARG, "unknown build flag");
     const size_t need = bytes_needed(n, m, R, probs->kind);
     if (ctx->budget && ctx->in_use + need > ctx->budget)
         return fail(IM_ERR_OUT_OF_BUDGET, "sketch needs %zu bytes, %zu of %zu in use", need, ctx->in_use, ctx->budget);
@@ -578,7 +583,8 @@ im_status build_sketch(im_ctx* ctx, const im_csr* graph, const im_probs* probs, 
     sk->L = make_layout(R);
     sk->seed = hash_seed;
     sk->eps_c = o.eps_c;
-    sk->time_sweeps = o.reserved != 0;
+    sk->time_sweeps = (o.flags & IM_BUILD_TIME_SWEEPS) != 0;
+    sk->in_place = (o.flags & IM_BUILD_IN_PLACE) != 0;
     DevGraph& g = sk->g;
     g.n = n;
     g.m = m;

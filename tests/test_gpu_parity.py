@@ -264,3 +264,35 @@ def test_budget_admission(hf):
     assert 0 < ok.bytes_in_use() <= need + (1 << 20)
     sk.free()
     assert ok.bytes_in_use() == 0
+
+
+@pytest.mark.parametrize("gname,model,p,J,K,sparse_div,heavy", [
+    ("er300", "const", 0.1, 64, 10, 0, 0),
+    ("rmat10", "wc", 0.0, 256, 12, 0, 0),
+    ("rmat10", "const", 0.1, 128, 12, 1, 8),
+    ("star", "edge", 0.0, 64, 6, 0, 0),
+])
+def test_in_place_reaches_the_same_fixed_point(hf, ctx, gname, model, p, J, K, sparse_div, heavy):
+    """In-place sweeps: same registers, estimates, reach and seeds as the synchronous form (eps_c = 0),
+    in at most as many sweeps; sweep and visit counts are not compared (they depend on the schedule)."""
+    g = GRAPHS[gname]
+    pe = _per_edge(g) if model == "edge" else None
+    thr = _thr(g, model, p, pe)
+    res = oracle.greedy(g, thr, J, K, want_blk=True)
+    sk = _build(hf, ctx, g, model, p, J, per_edge=pe, sparse_div=sparse_div, heavy_degree=heavy, in_place=True)
+    try:
+        assert sk.info()["sweeps"] <= res["build_sweeps"]
+        M, *_ = oracle.simulate(g, thr, J)
+        assert np.array_equal(sk.registers(0), M)
+        seeds, steps, stats = hf.im_select_seeds(sk, K)
+        assert list(seeds) == res["seeds"]
+        for k in range(K):
+            o, s = res["steps"][k], steps[k]
+            for f in ("seed", "rebuilt", "fresh", "score", "reach", "e", "sigma", "delta", "err_l", "err_g"):
+                assert getattr(s, f) == o[f], (k, f)
+            if o["rebuilt"]:
+                assert s.sweeps <= o["sweeps"]
+        assert np.array_equal(sk.registers(1), res["M"])
+        assert np.array_equal(sk.blocked(), res["blk"])
+    finally:
+        sk.free()
