@@ -208,7 +208,7 @@ size_t bytes_needed(int64_t n, int64_t m, int32_t R, im_prob_kind kind) {
     // split rows: bounded by m / heavy_degree rows and m / piece + rows pieces
     const int64_t nh = m / DEFAULT_HEAVY + 1, np = m / DEFAULT_PIECE + nh + 1;
     t += al(4 * nh) + al(8 * (nh + 1)) + al(8 * nh) + al(4 * np) + 2 * al(8 * np) + al((size_t)np * L.P * 4) +
-         al(4 * np) + 2 * al(4 * nh) + al(4 * np) + al(4 * (np / 32 + 1));
+         al(4 * np) + 2 * al(4 * nh) + 2 * al(4 * np) + al(4 * (np / 32 + 1));
     // greedy
     const size_t W = 4 * (size_t)L.PW;
     t += 3 * al((size_t)n * W * 4) + al(4 * words);
@@ -558,6 +558,7 @@ im_status build_sketch(im_ctx* ctx, const im_csr* graph, const im_probs* probs, 
     if (opts) o = *opts;
     if (!(o.eps_c >= 0.0)) return fail(IM_ERR_INVALID_ARG, "eps_c must be >= 0");
     if (o.heavy_degree < 0 || o.piece_edges < 0) return fail(IM_ERR_INVALID_ARG, "negative tuning value");
+    if (o.piece_edges > 2048) return fail(IM_ERR_INVALID_ARG, "piece_edges must be at most 2048");
     if (o.flags & ~(IM_BUILD_TIME_SWEEPS | IM_BUILD_IN_PLACE)) return fail(IM_ERR_INVALID_ARG, "unknown build flag");
     const size_t need = bytes_needed(n, m, R, probs->kind);
     if (ctx->budget && ctx->in_use + need > ctx->budget)
@@ -689,6 +690,9 @@ im_status build_sketch(im_ctx* ctx, const im_csr* graph, const im_probs* probs, 
         HIP_TRY(hipStreamSynchronize(s));
         g.nheavy = (int64_t)hc[0];
         g.npieces = (int64_t)hc[1];
+        // the reverse CSR names the 64-edge windows of the pieces with int32
+        if (g.npieces * ((piece + 63) / 64) >= (1ll << 31))
+            return fail(IM_ERR_INVALID_GRAPH, "too many split-row windows (%lld pieces)", (long long)g.npieces);
         if (g.nheavy > 0) {
             bool ok2 = sk_alloc(sk, &g.hrow, g.nheavy) && sk_alloc(sk, &g.hpb, g.nheavy) &&
                        sk_alloc(sk, &g.hpn, g.nheavy) && sk_alloc(sk, &g.prow, g.npieces) &&
@@ -699,11 +703,12 @@ im_status build_sketch(im_ctx* ctx, const im_csr* graph, const im_probs* probs, 
             HIP_TRY(launch_heavy_assign(g, piece, sk->d_heavy_counts, s));
             HIP_TRY(launch_heavy_pieces(g, piece, s));
             if (!sk_alloc(sk, &sk->fr.HW, g.nheavy) || !sk_alloc(sk, &sk->fr.HP, g.npieces) ||
-                !sk_alloc(sk, &sk->fr.pmark, g.npieces / 32 + 1))
+                !sk_alloc(sk, &sk->fr.pmark, g.npieces / 32 + 1) || !sk_alloc(sk, &sk->fr.wmask, g.npieces))
                 return fail(IM_ERR_OUT_OF_BUDGET, "device allocation failed (sparse lists)");
             HIP_TRY(launch_fill_u32(sk->part_any, 0u, g.npieces, s));
             HIP_TRY(launch_fill_u32(sk->rtouch, 0u, g.nheavy, s));
             HIP_TRY(launch_fill_u32(sk->fr.pmark, 0u, g.npieces / 32 + 1, s));
+            HIP_TRY(launch_fill_u32(sk->fr.wmask, 0u, g.npieces, s));
         }
         HIP_TRY(launch_heavy_slots(g, s));
         HIP_TRY(launch_edge_hash(g, hash_seed, s));  // split rows are hashed by piece

@@ -50,7 +50,8 @@ struct DevGraph {
     int64_t* rxadj = nullptr;   // [n + 1]
     int32_t* radj = nullptr;    // [m]
     int32_t* hslot = nullptr;   // heavy slot of each row, -1 for rows processed whole [n]
-    int32_t* rpiece = nullptr;  // per in-edge: piece of its split source row, -1 otherwise [m]
+    int32_t* rpiece = nullptr;  // per in-edge of a split source row: its 64-edge window, piece * wpp +
+                                // window in the piece (wpp = ceil(piece_edges / 64)); -1 otherwise [m]
     int32_t* lrows = nullptr;   // rows with 1..heavy_deg out-edges, ascending [nlight]
     int64_t nlight = 0;
     int64_t piece_edges = 256;
@@ -66,6 +67,7 @@ struct Frontier {
     int32_t* HP = nullptr;      // pieces of listed heavy rows
     uint32_t* counts = nullptr; // [2][4]: items, W, HW, HP
     uint32_t* pmark = nullptr;  // npieces bits: piece already listed in this sweep
+    uint32_t* wmask = nullptr;  // per piece: its 64-edge windows holding an edge into L_t
     uint32_t stamp = 0;         // unique per sweep (never 0): piece flags of this sweep
     int32_t chunk = 256;        // in-edges per item
     uint32_t sparse_div = 8;    // sweep t > 0 is sparse iff S_t * sparse_div <= m (0: never)

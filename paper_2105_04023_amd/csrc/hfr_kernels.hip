@@ -471,15 +471,16 @@ __global__ __launch_bounds__(256) void k_sweep_frontier(const uint32_t* __restri
 }
 
 // Sparse sweep: marks the in-neighbours of L_t and lists the new ones.  A
-// split source row is listed once (HW) and only the pieces holding an edge
-// into L_t are listed (HP).
+// split source row is listed once (HW), only the pieces holding an edge into
+// L_t are listed (HP), and within them only the 64-edge windows holding such
+// an edge are marked (wmask).
 __global__ __launch_bounds__(256) void k_sweep_expand(const uint32_t* __restrict__ gate, uint32_t gate_thresh,
                                                       const unsigned long long* __restrict__ sgate, int64_t m,
                                                       int first, int64_t n, Frontier fr, int parity,
                                                       const int64_t* __restrict__ rxadj,
                                                       const int32_t* __restrict__ radj,
                                                       const int32_t* __restrict__ rpiece,
-                                                      const int32_t* __restrict__ hslot) {
+                                                      const int32_t* __restrict__ hslot, int32_t wpp) {
     const uint32_t live = sweep_live(gate, gate_thresh, first, n);
     if (!live || !sweep_sparse(sgate, first, m, fr.sparse_div)) return;
     uint32_t* cnt = fr.counts + 4 * parity;
@@ -502,7 +503,11 @@ __global__ __launch_bounds__(256) void k_sweep_expand(const uint32_t* __restrict
                 // before paying for the atomic
                 if ((fr.mark[u >> 5] & bit) == 0u) fresh = (atomicOr(&fr.mark[u >> 5], bit) & bit) == 0u;
                 if (r >= 0) {
-                    const int32_t pc = rpiece[e];
+                    // the window of the edge within its piece, then the piece
+                    const int32_t wi = rpiece[e];
+                    const int32_t pc = wi / wpp;
+                    const uint32_t wbit = 1u << (wi - pc * wpp);
+                    if ((fr.wmask[pc] & wbit) == 0u) atomicOr(&fr.wmask[pc], wbit);
                     const uint32_t pbit = 1u << (pc & 31);
                     if ((fr.pmark[pc >> 5] & pbit) == 0u && (atomicOr(&fr.pmark[pc >> 5], pbit) & pbit) == 0u)
                         fr.HP[atomicAdd(&cnt[3], 1u)] = pc;
@@ -537,7 +542,10 @@ __global__ __launch_bounds__(256) void k_sweep_cleanup(const uint32_t* __restric
     const int64_t nw = cnt[1], nh = cnt[2], np = cnt[3];
     for (int64_t i = tid; i < nw; i += stride) fr.mark[fr.W[i] >> 5] = 0u;
     for (int64_t i = tid; i < nh; i += stride) fr.mark[hrow[fr.HW[i]] >> 5] = 0u;
-    for (int64_t i = tid; i < np; i += stride) fr.pmark[fr.HP[i] >> 5] = 0u;
+    for (int64_t i = tid; i < np; i += stride) {
+        fr.pmark[fr.HP[i] >> 5] = 0u;
+        fr.wmask[fr.HP[i]] = 0u;
+    }
 }
 
 template <int G, int DW, int KIND>
@@ -898,7 +906,19 @@ __global__ __launch_bounds__(256) void k_sweep_heavy(
 #pragma unroll
         for (int k = 0; k < DW; ++k) acc[k].e = acc[k].o = 0u;
         uint32_t vis = 0;
-        if (!skip) vis = merge_edges<G, DW, KIND>(pe0[pc], pe1[pc], adj, eh, thr, ntv, A, Lcur, first, P, lane, p, x, acc);
+        if (!skip) {
+            if (sparse) {
+                // only the windows holding an edge into L_t
+                const int64_t b0 = pe0[pc], b1 = pe1[pc];
+                for (uint32_t wm = fr.wmask[pc]; wm; wm &= wm - 1) {
+                    const int64_t w0 = b0 + 64 * (int64_t)__builtin_ctz(wm);
+                    const int64_t w1 = w0 + 64 < b1 ? w0 + 64 : b1;
+                    vis += merge_edges<G, DW, KIND>(w0, w1, adj, eh, thr, ntv, A, Lcur, first, P, lane, p, x, acc);
+                }
+            } else {
+                vis = merge_edges<G, DW, KIND>(pe0[pc], pe1[pc], adj, eh, thr, ntv, A, Lcur, first, P, lane, p, x, acc);
+            }
+        }
         // vis is uniform over the group; a partial without live edges is never read
         if (vis > 0) {
 #pragma unroll
@@ -1018,7 +1038,7 @@ hipError_t launch_sweep(const Layout& L, const DevGraph& g, const uint32_t* X, c
     hipLaunchKernelGGL(k_sweep_frontier, dim3(sg), dim3(256), 0, s, sp.gate, sp.gate_thresh, sp.sgate, g.m, sp.first,
                        g.n, sp.Lcur, sp.Lclear, sp.fr, sp.parity, g.rxadj, g.hslot);
     hipLaunchKernelGGL(k_sweep_expand, dim3(sg), dim3(256), 0, s, sp.gate, sp.gate_thresh, sp.sgate, g.m, sp.first, g.n,
-                       sp.fr, sp.parity, g.rxadj, g.radj, g.rpiece, g.hslot);
+                       sp.fr, sp.parity, g.rxadj, g.radj, g.rpiece, g.hslot, (int32_t)((g.piece_edges + 63) / 64));
     hipError_t err = hipGetLastError();
     if (err != hipSuccess) return err;
     if (ev0) (void)hipEventRecord(ev0, s);
@@ -1151,7 +1171,7 @@ __global__ __launch_bounds__(256) void k_scan_apply(const uint32_t* __restrict__
 // depends on scheduling, the set does not.
 __global__ void k_rev_scatter(const int64_t* __restrict__ xadj, const int32_t* __restrict__ adj, int64_t n,
                               int64_t* cursor, int32_t* radj, int32_t* rpiece, const int32_t* __restrict__ hslot,
-                              const int64_t* __restrict__ hpb, int64_t piece) {
+                              const int64_t* __restrict__ hpb, int64_t piece, int32_t wpp) {
     const int lane = threadIdx.x & 63;
     for (int64_t u = wave_index(); u < n; u += wave_count()) {
         const int64_t eb = xadj[u], ee = xadj[u + 1];
@@ -1161,7 +1181,9 @@ __global__ void k_rev_scatter(const int64_t* __restrict__ xadj, const int32_t* _
             const int32_t v = adj[e];
             const unsigned long long pos = atomicAdd((unsigned long long*)&cursor[v], 1ull);
             radj[pos] = (int32_t)u;
-            rpiece[pos] = r >= 0 ? (int32_t)(base + (e - eb) / piece) : -1;
+            // 64-edge window of the edge within its piece (windows of piece c are
+            // c * wpp .. c * wpp + wpp - 1)
+            rpiece[pos] = r >= 0 ? (int32_t)((base + (e - eb) / piece) * wpp + ((e - eb) % piece) / 64) : -1;
         }
     }
 }
@@ -1182,7 +1204,7 @@ hipError_t launch_reverse_csr(const DevGraph& g, const uint32_t* indeg, int64_t*
     hipLaunchKernelGGL(k_copy_i64, dim3(4096), dim3(256), 0, s, g.rxadj, cursor, n);
     if (g.m > 0)
         hipLaunchKernelGGL(k_rev_scatter, dim3(8192), dim3(256), 0, s, g.xadj, g.adj, n, cursor, g.radj, g.rpiece,
-                           g.hslot, g.hpb, g.piece_edges);
+                           g.hslot, g.hpb, g.piece_edges, (int32_t)((g.piece_edges + 63) / 64));
     return hipGetLastError();
 }
 

@@ -88,9 +88,11 @@ def test_build_registers_and_trace(hf, ctx, gname, J, sparse_div):
 @pytest.mark.parametrize("sparse_div", [0, 1, -1])
 @pytest.mark.parametrize("model", ["const", "wc", "edge"])
 @pytest.mark.parametrize("gname", ["er300", "rmat10", "star"])
-@pytest.mark.parametrize("J,heavy,piece", [(64, 0, 0), (256, 0, 0), (256, 8, 4), (64, 16, 16), (128, 5, 3)])
+@pytest.mark.parametrize("J,heavy,piece", [(64, 0, 0), (256, 0, 0), (256, 8, 4), (64, 16, 16), (128, 5, 3),
+                                           (128, 64, 200), (64, 40, 2048)])
 def test_build_models_and_split_rows(hf, ctx, gname, model, J, heavy, piece, sparse_div):
-    """sparse_div 1: every sweep after the first visits only the rows next to L_t; -1: all rows."""
+    """sparse_div 1: every sweep after the first visits only the rows next to L_t (and within a
+    piece of a split row only the 64-edge windows holding an edge into L_t); -1: all rows."""
     g = GRAPHS[gname]
     pe = _per_edge(g) if model == "edge" else None
     thr = _thr(g, model, 0.1, pe)
@@ -240,6 +242,9 @@ def test_invalid_inputs_rejected(hf, ctx):
     pe[0] = 2.0
     with pytest.raises(hf.ImError) as e:
         _build(hf, ctx, g, "edge", 0.0, 8, per_edge=pe)
+    assert e.value.status == -1
+    with pytest.raises(hf.ImError) as e:
+        _build(hf, ctx, g, "const", 0.1, 8, heavy_degree=2, piece_edges=2049)
     assert e.value.status == -1
     sk = _build(hf, ctx, g, "const", 0.1, 8)
     try:
