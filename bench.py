@@ -40,15 +40,16 @@ def heavy_launch_bytes(rec, J, wc, m_heavy, npieces):
     Per edge visited with a live head: the neighbour's row (J bytes), the edge hash (4)
     and, for the weighted cascade, the target's threshold (4).  A dense launch also reads
     every split-row out-edge id (4 m_heavy) and its piece table (20 B per piece) and
-    writes one partial row plus a flag per piece (J + 4).  A launch past the stopping
-    rule moves nothing.
+    writes a flag per piece (4).  The partial rows (J bytes per piece with a live edge)
+    are not counted: how many pieces had one is not logged, and even when all do they
+    are under 1% of the bytes.  A launch past the stopping rule moves nothing.
     """
     if not rec["ran"]:
         return 0
     hv = rec["visits"] - rec["light_visits"]
     b = hv * (J + 4 + (4 if wc else 0))
     if not rec["sparse"]:
-        b += 4 * m_heavy + 20 * npieces + npieces * (J + 4)
+        b += 4 * m_heavy + 24 * npieces
     return b
 
 
@@ -331,7 +332,7 @@ def main():
         sys.stdout.write(summarize_pmc(args.summarize_pmc[0], args.summarize_pmc[1], cmd))
         return
     if args.gpus != 1:
-        print(json.dumps({"error": "this path runs on one GPU; multi-GPU runs are not part of this build",
+        print(json.dumps({"error": "this path runs on one GPU: --gpus above 1 is not supported",
                           "n_gpus": args.gpus}))
         sys.exit(2)
 
@@ -347,7 +348,7 @@ def main():
     K = args.K or w.K
     log(f"workload {w.name}: n={g.n} m={g.m} generated in {time.perf_counter() - t:.1f} s")
     deg = np.diff(g.xadj)
-    heavy_deg = args.heavy_degree or 32
+    heavy_deg = args.heavy_degree or 64  # the library's default split threshold
     m_heavy = int(deg[deg > heavy_deg].sum())
     xd = torch.from_numpy(g.xadj).cuda()
     ad = torch.from_numpy(g.adj).cuda()
@@ -399,6 +400,7 @@ def main():
     recs = [rec for r in results for rec in r["sweep_log"]]
     wc = w.model == "wc"
     npieces = results[-1]["info"]["heavy_pieces"]
+    assert results[-1]["info"]["heavy_rows"] == int((deg > heavy_deg).sum()), "split threshold mismatch"
     tot_bytes = sum(heavy_launch_bytes(rec, J, wc, m_heavy, npieces) for rec in recs)
     tot_ms = sum(rec["heavy_ms"] for rec in recs)
     nlaunch = len(recs)

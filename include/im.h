@@ -87,8 +87,8 @@ typedef struct im_probs {
                                   schedule (not reproducible). */
 typedef struct im_build_opts {
     double eps_c;
-    int32_t heavy_degree; /* rows with more out-edges are split across waves */
-    int32_t piece_edges;  /* edges per piece of a split row, at most 2048 */
+    int32_t heavy_degree; /* rows with more out-edges are split across waves (0: 64) */
+    int32_t piece_edges;  /* edges per piece of a split row, at most 2048 (0: 256) */
     int32_t sparse_div;   /* sweep t > 0 visits only the rows next to L_t when the
                              in-degrees of L_t sum to at most m / sparse_div
                              (0: 96; < 0: never) */

@@ -66,7 +66,7 @@ namespace {
 
 constexpr int RING = 256;         // sweeps held by the counter ring
 constexpr int MAX_BATCH = 64;     // sweeps per batch
-constexpr int DEFAULT_HEAVY = 32;
+constexpr int DEFAULT_HEAVY = 64;
 constexpr int DEFAULT_PIECE = 256;
 constexpr int BFS_CHUNK = 256;
 constexpr int SWEEP_TIMERS = 6 * RING;
@@ -197,7 +197,7 @@ size_t bytes_needed(int64_t n, int64_t m, int32_t R, im_prob_kind kind) {
     size_t t = 0;
     t += al(8 * (n + 1)) + al(4 * m) + al(4 * m);  // xadj, adj, edge hashes
     t += al(8 * (n + 1)) + 2 * al(4 * m) + 2 * al(4 * n);  // reverse CSR with pieces, heavy slots, light rows
-    t += al(4 * ((n + 31) / 32 + 1)) + al(8 * (n + m / 256 + 64)) + al(4 * n) + al(32);  // sparse lists
+    t += al(4 * ((n + 31) / 32 + 1)) + al(8 * (n + m / 256 + 64)) + al(4 * n) + al(32);  // sparse marks, lists
     if (kind == IM_PROB_WEIGHTED_CASCADE) t += al(4 * n) + al(4 * m);  // per target, then per edge
     if (kind == IM_PROB_PER_EDGE) t += al(4 * m);
     t += al(4 * R) * 2 + al(8 * R);               // X, HJ, T
@@ -208,7 +208,7 @@ size_t bytes_needed(int64_t n, int64_t m, int32_t R, im_prob_kind kind) {
     // split rows: bounded by m / heavy_degree rows and m / piece + rows pieces
     const int64_t nh = m / DEFAULT_HEAVY + 1, np = m / DEFAULT_PIECE + nh + 1;
     t += al(4 * nh) + al(8 * (nh + 1)) + al(8 * nh) + al(4 * np) + 2 * al(8 * np) + al((size_t)np * L.P * 4) +
-         al(4 * np) + 2 * al(4 * nh) + 2 * al(4 * np) + al(4 * (np / 32 + 1));
+         al(4 * np) + al(4 * nh) + al(4 * np);
     // greedy
     const size_t W = 4 * (size_t)L.PW;
     t += 3 * al((size_t)n * W * 4) + al(4 * words);
@@ -702,12 +702,10 @@ im_status build_sketch(im_ctx* ctx, const im_csr* graph, const im_probs* probs, 
             if (!ok2) return fail(IM_ERR_OUT_OF_BUDGET, "device allocation failed (split rows)");
             HIP_TRY(launch_heavy_assign(g, piece, sk->d_heavy_counts, s));
             HIP_TRY(launch_heavy_pieces(g, piece, s));
-            if (!sk_alloc(sk, &sk->fr.HW, g.nheavy) || !sk_alloc(sk, &sk->fr.HP, g.npieces) ||
-                !sk_alloc(sk, &sk->fr.pmark, g.npieces / 32 + 1) || !sk_alloc(sk, &sk->fr.wmask, g.npieces))
+            if (!sk_alloc(sk, &sk->fr.wmask, g.npieces))
                 return fail(IM_ERR_OUT_OF_BUDGET, "device allocation failed (sparse lists)");
             HIP_TRY(launch_fill_u32(sk->part_any, 0u, g.npieces, s));
             HIP_TRY(launch_fill_u32(sk->rtouch, 0u, g.nheavy, s));
-            HIP_TRY(launch_fill_u32(sk->fr.pmark, 0u, g.npieces / 32 + 1, s));
             HIP_TRY(launch_fill_u32(sk->fr.wmask, 0u, g.npieces, s));
         }
         HIP_TRY(launch_heavy_slots(g, s));

@@ -182,81 +182,91 @@ DEVI double estimate_from_sum(uint32_t s, int J, const double* __restrict__ T) {
 // ----------------------------------------------------------------------------
 constexpr int UB = 8;  // neighbour rows in flight per wave (twice that with one dword per lane)
 
-// G = 64 (one row per wave): the row's out-edges are read 64 at a time with
-// one coalesced load per array, the heads in L_t are found with one ballot,
-// and the rows of up to UB live heads are loaded back-to-back before they are
-// merged.  Returns the number of edges with a live head.
+// G = 64 (one row per wave): the row's out-edges are read NW windows of 64
+// at a time, with one coalesced load per window and array; the L_t tests of
+// the NW windows are issued together, so that a sweep with few live heads
+// waits on one round of dependent loads per NW windows.  The rows of up to UB
+// live heads of a window are loaded back-to-back before they are merged.
+// Returns the number of edges with a live head.
+constexpr int NW = 4;
 template <int DW, int KIND>
 DEVI uint32_t merge_edges64(int64_t eb, int64_t ee, const int32_t* __restrict__ adj, const uint32_t* __restrict__ eh,
                             const uint32_t* __restrict__ thr, uint32_t ntv, const uint32_t* __restrict__ A,
                             const uint32_t* __restrict__ Lcur, int first, int P, int lane,
                             const uint32_t (&x)[DW][4], Acc (&acc)[DW]) {
     uint32_t vis = 0;
-    // the next window's edge ids are loaded while the current one is merged
-    bool in_n = eb + lane < ee;
-    int32_t v_n = in_n ? adj[eb + lane] : 0;
-    for (int64_t w0 = eb; w0 < ee; w0 += 64) {
-        const int64_t e = w0 + lane;
-        const bool in = in_n;
-        const int32_t v = v_n;
-        in_n = w0 + 64 + lane < ee;
-        v_n = in_n ? adj[w0 + 64 + lane] : 0;
-        const bool lv = in && (first || bit_of(Lcur, v) != 0u);
-        uint64_t mask = __ballot(lv);
-        if (!mask) continue;  // no live head: the window needs no hash or threshold
-        vis += (uint32_t)__builtin_popcountll(mask);
-        const uint32_t hh = in ? eh[e] : 0u;
-        uint32_t tt = 0u;
-        if constexpr (KIND == THR_TARGET) tt = in ? thr[v] : 0u;
-        if constexpr (KIND == THR_EDGE) tt = in ? thr[e] : 0u;
-        // batches of NB live edges, NB the smallest of 1, 2, 4, UB that covers the
-        // edges left (capped at UB): unused slots repeat the last edge (max-merge is
-        // idempotent), so every load of a batch is issued without a branch
-        auto batch = [&](auto nbc) {
-            constexpr int NB = decltype(nbc)::value;
-            int idx[NB];
-            int last = __builtin_ctzll(mask);
+    for (int64_t c0 = eb; c0 < ee; c0 += 64 * NW) {
+        int32_t vw[NW];
+        bool inw[NW];
 #pragma unroll
-            for (int b = 0; b < NB; ++b) {
-                if (mask) last = __builtin_ctzll(mask);
-                idx[b] = last;
-                mask &= mask - 1;
-            }
-            // lanes past the row (q >= P) load a valid dword of it; their
-            // results are never stored
-            uint32_t d[NB][DW];
+        for (int w = 0; w < NW; ++w) {
+            inw[w] = c0 + 64 * w + lane < ee;
+            vw[w] = inw[w] ? adj[c0 + 64 * w + lane] : 0;
+        }
+        uint64_t mw[NW];
 #pragma unroll
-            for (int b = 0; b < NB; ++b) {
-                const int64_t vb = __builtin_amdgcn_readlane(v, idx[b]);
-                const uint32_t* __restrict__ row = A + vb * P;
+        for (int w = 0; w < NW; ++w) mw[w] = __ballot(inw[w] && (first || bit_of(Lcur, vw[w]) != 0u));
 #pragma unroll
-                for (int i = 0; i < DW; ++i) {
-                    const int q = i * 64 + lane;
-                    d[b][i] = row[q < P ? q : P - 1];
+        for (int w = 0; w < NW; ++w) {
+            uint64_t mask = mw[w];
+            if (!mask) continue;  // no live head: the window needs no hash or threshold
+            const int64_t e = c0 + 64 * w + lane;
+            const bool in = inw[w];
+            const int32_t v = vw[w];
+            vis += (uint32_t)__builtin_popcountll(mask);
+            const uint32_t hh = in ? eh[e] : 0u;
+            uint32_t tt = 0u;
+            if constexpr (KIND == THR_TARGET) tt = in ? thr[v] : 0u;
+            if constexpr (KIND == THR_EDGE) tt = in ? thr[e] : 0u;
+            // batches of NB live edges, NB the smallest of 1, 2, 4, UB that covers the
+            // edges left (capped at UB): unused slots repeat the last edge (max-merge is
+            // idempotent), so every load of a batch is issued without a branch
+            auto batch = [&](auto nbc) {
+                constexpr int NB = decltype(nbc)::value;
+                int idx[NB];
+                int last = __builtin_ctzll(mask);
+    #pragma unroll
+                for (int b = 0; b < NB; ++b) {
+                    if (mask) last = __builtin_ctzll(mask);
+                    idx[b] = last;
+                    mask &= mask - 1;
                 }
+                // lanes past the row (q >= P) load a valid dword of it; their
+                // results are never stored
+                uint32_t d[NB][DW];
+    #pragma unroll
+                for (int b = 0; b < NB; ++b) {
+                    const int64_t vb = __builtin_amdgcn_readlane(v, idx[b]);
+                    const uint32_t* __restrict__ row = A + vb * P;
+    #pragma unroll
+                    for (int i = 0; i < DW; ++i) {
+                        const int q = i * 64 + lane;
+                        d[b][i] = row[q < P ? q : P - 1];
+                    }
+                }
+                __builtin_amdgcn_sched_barrier(0);
+    #pragma unroll
+                for (int b = 0; b < NB; ++b) {
+                    const uint32_t hb = (uint32_t)__builtin_amdgcn_readlane((int)hh, idx[b]);
+                    uint32_t nt = ntv;
+                    if constexpr (KIND != THR_CONST) nt = 0u - (uint32_t)__builtin_amdgcn_readlane((int)tt, idx[b]);
+    #pragma unroll
+                    for (int i = 0; i < DW; ++i) merge_live(acc[i], d[b][i], x[i][0], x[i][1], x[i][2], x[i][3], hb, nt);
+                }
+            };
+            while (mask) {
+                const int nl = __builtin_popcountll(mask);
+                if (DW == 1 && nl > UB)
+                    batch(std::integral_constant<int, 2 * UB>{});
+                else if (nl > 4)
+                    batch(std::integral_constant<int, UB>{});
+                else if (nl > 2)
+                    batch(std::integral_constant<int, 4>{});
+                else if (nl == 2)
+                    batch(std::integral_constant<int, 2>{});
+                else
+                    batch(std::integral_constant<int, 1>{});
             }
-            __builtin_amdgcn_sched_barrier(0);
-#pragma unroll
-            for (int b = 0; b < NB; ++b) {
-                const uint32_t hb = (uint32_t)__builtin_amdgcn_readlane((int)hh, idx[b]);
-                uint32_t nt = ntv;
-                if constexpr (KIND != THR_CONST) nt = 0u - (uint32_t)__builtin_amdgcn_readlane((int)tt, idx[b]);
-#pragma unroll
-                for (int i = 0; i < DW; ++i) merge_live(acc[i], d[b][i], x[i][0], x[i][1], x[i][2], x[i][3], hb, nt);
-            }
-        };
-        while (mask) {
-            const int nl = __builtin_popcountll(mask);
-            if (DW == 1 && nl > UB)
-                batch(std::integral_constant<int, 2 * UB>{});
-            else if (nl > 4)
-                batch(std::integral_constant<int, UB>{});
-            else if (nl > 2)
-                batch(std::integral_constant<int, 4>{});
-            else if (nl == 2)
-                batch(std::integral_constant<int, 2>{});
-            else
-                batch(std::integral_constant<int, 1>{});
         }
     }
     return vis;

@@ -60,14 +60,12 @@ struct DevGraph {
 // Work lists of a sparse sweep.  Counters come in two sets selected by the
 // sweep parity; a sweep zeroes the other set for the next sweep.
 struct Frontier {
-    uint32_t* mark = nullptr;   // n bits: row already listed in this sweep
+    uint32_t* mark = nullptr;   // n bits: rows to merge in a sparse sweep; zero outside one
     int2* items = nullptr;      // (live vertex, chunk of its in-edges)
-    int32_t* W = nullptr;       // rows processed whole
-    int32_t* HW = nullptr;      // heavy row slots
-    int32_t* HP = nullptr;      // pieces of listed heavy rows
-    uint32_t* counts = nullptr; // [2][4]: items, W, HW, HP
-    uint32_t* pmark = nullptr;  // npieces bits: piece already listed in this sweep
-    uint32_t* wmask = nullptr;  // per piece: its 64-edge windows holding an edge into L_t
+    int32_t* W = nullptr;       // the marked rows, listed (split rows among them are skipped)
+    uint32_t* counts = nullptr; // [2][4]: items and W of the sweep of each parity (rest unused)
+    uint32_t* wmask = nullptr;  // per piece: its 64-edge windows holding an edge into L_t; zero
+                                // outside a sparse sweep
     uint32_t stamp = 0;         // unique per sweep (never 0): piece flags of this sweep
     int32_t chunk = 256;        // in-edges per item
     uint32_t sparse_div = 8;    // sweep t > 0 is sparse iff S_t * sparse_div <= m (0: never)

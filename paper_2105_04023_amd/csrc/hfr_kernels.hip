@@ -416,14 +416,13 @@ DEVI uint32_t wave_excl_scan(uint32_t c, uint32_t* total) {
 
 
 // First kernel of every sweep.  Zeroes the bitmap that will hold L_{t+2}; in a
-// sparse sweep also lists L_t (marked, for the copy rule; split rows go to HW
-// without pieces) and the in-edge chunks of every vertex of L_t.
+// sparse sweep also marks the rows of L_t (the copy rule needs them) and lists
+// the in-edge chunks of every vertex of L_t.
 __global__ __launch_bounds__(256) void k_sweep_frontier(const uint32_t* __restrict__ gate, uint32_t gate_thresh,
                                                         const unsigned long long* __restrict__ sgate, int64_t m,
                                                         int first, int64_t n, const uint32_t* __restrict__ Lcur,
                                                         uint32_t* __restrict__ Lclear, Frontier fr, int parity,
-                                                        const int64_t* __restrict__ rxadj,
-                                                        const int32_t* __restrict__ hslot) {
+                                                        const int64_t* __restrict__ rxadj) {
     const uint32_t live = sweep_live(gate, gate_thresh, first, n);
     if (!live) return;
     const int64_t nwords = (n + 31) >> 5;
@@ -433,36 +432,25 @@ __global__ __launch_bounds__(256) void k_sweep_frontier(const uint32_t* __restri
     if (!sweep_sparse(sgate, first, m, fr.sparse_div)) return;
     uint32_t* cnt = fr.counts + 4 * parity;
     const int lane = threadIdx.x & 63;
-    // uniform trip count per wave so that every lane takes part in the scans
+    // uniform trip count per wave so that every lane takes part in the scan
     const int64_t span = ((nwords + stride - 1) / stride) * stride;
     for (int64_t w0 = tid - lane; w0 < span; w0 += stride) {
         const int64_t w = w0 + lane;
         const uint32_t bits = w < nwords ? Lcur[w] : 0u;
-        uint32_t nlight = 0, nitems = 0;
+        uint32_t nitems = 0;
         for (uint32_t b = bits; b; b &= b - 1) {
             const int64_t v = w * 32 + __builtin_ctz(b);
-            if (hslot[v] < 0) ++nlight;
             nitems += (uint32_t)((rxadj[v + 1] - rxadj[v] + fr.chunk - 1) / fr.chunk);
         }
-        uint32_t tl, ti;
-        const uint32_t ol = wave_excl_scan(nlight, &tl);
+        uint32_t ti;
         const uint32_t oi = wave_excl_scan(nitems, &ti);
-        uint32_t bl = 0, bi = 0;
-        if (lane == 0) {
-            if (tl) bl = atomicAdd(&cnt[1], tl);
-            if (ti) bi = atomicAdd(&cnt[0], ti);
-        }
-        bl = __shfl(bl, 0, 64) + ol;
+        uint32_t bi = 0;
+        if (lane == 0 && ti) bi = atomicAdd(&cnt[0], ti);
         bi = __shfl(bi, 0, 64) + oi;
         if (bits) {
-            fr.mark[w] = bits;
+            fr.mark[w] = bits;  // the mark words are zero outside a sparse sweep
             for (uint32_t b = bits; b; b &= b - 1) {
                 const int64_t v = w * 32 + __builtin_ctz(b);
-                const int32_t r = hslot[v];
-                if (r < 0)
-                    fr.W[bl++] = (int32_t)v;
-                else
-                    fr.HW[atomicAdd(&cnt[2], 1u)] = r;
                 const int64_t nc = (rxadj[v + 1] - rxadj[v] + fr.chunk - 1) / fr.chunk;
                 for (int64_t c = 0; c < nc; ++c) fr.items[bi++] = make_int2((int)v, (int)c);
             }
@@ -470,82 +458,82 @@ __global__ __launch_bounds__(256) void k_sweep_frontier(const uint32_t* __restri
     }
 }
 
-// Sparse sweep: marks the in-neighbours of L_t and lists the new ones.  A
-// split source row is listed once (HW), only the pieces holding an edge into
-// L_t are listed (HP), and within them only the 64-edge windows holding such
-// an edge are marked (wmask).
+// Sparse sweep: marks the source rows of the in-edges of L_t.  An in-edge from
+// a row that is not split sets the row's bit in `mark`; an in-edge from a
+// split row sets the bit of its 64-edge window in its piece's window mask.
+// Nothing is listed here: the marked rows are listed afterwards with one
+// atomic per wave, and the piece kernel finds its pieces by scanning the
+// window masks, so each in-edge costs one random access and no shared counter
+// is contended.
 __global__ __launch_bounds__(256) void k_sweep_expand(const uint32_t* __restrict__ gate, uint32_t gate_thresh,
                                                       const unsigned long long* __restrict__ sgate, int64_t m,
                                                       int first, int64_t n, Frontier fr, int parity,
                                                       const int64_t* __restrict__ rxadj,
                                                       const int32_t* __restrict__ radj,
-                                                      const int32_t* __restrict__ rpiece,
-                                                      const int32_t* __restrict__ hslot, int32_t wpp) {
+                                                      const int32_t* __restrict__ rpiece, int32_t wpp) {
     const uint32_t live = sweep_live(gate, gate_thresh, first, n);
     if (!live || !sweep_sparse(sgate, first, m, fr.sparse_div)) return;
-    uint32_t* cnt = fr.counts + 4 * parity;
-    const uint32_t nitems = cnt[0];
+    const uint32_t nitems = fr.counts[4 * parity];
     const int lane = threadIdx.x & 63;
     for (int64_t it = wave_index(); it < (int64_t)nitems; it += wave_count()) {
         const int2 item = fr.items[it];
         const int64_t vb = rxadj[item.x], ve = rxadj[item.x + 1];
         const int64_t e0 = vb + (int64_t)item.y * fr.chunk;
         const int64_t e1 = e0 + fr.chunk < ve ? e0 + fr.chunk : ve;
-        for (int64_t w0 = e0; w0 < e1; w0 += 64) {
-            const int64_t e = w0 + lane;
-            bool fresh = false;
-            int32_t u = 0, r = -1;
-            if (e < e1) {
-                u = radj[e];
-                r = hslot[u];
-                const uint32_t bit = 1u << (u & 31);
-                // most in-neighbours are reached from several live vertices: test
-                // before paying for the atomic
-                if ((fr.mark[u >> 5] & bit) == 0u) fresh = (atomicOr(&fr.mark[u >> 5], bit) & bit) == 0u;
-                if (r >= 0) {
-                    // the window of the edge within its piece, then the piece
-                    const int32_t wi = rpiece[e];
-                    const int32_t pc = wi / wpp;
-                    const uint32_t wbit = 1u << (wi - pc * wpp);
-                    if ((fr.wmask[pc] & wbit) == 0u) atomicOr(&fr.wmask[pc], wbit);
-                    const uint32_t pbit = 1u << (pc & 31);
-                    if ((fr.pmark[pc >> 5] & pbit) == 0u && (atomicOr(&fr.pmark[pc >> 5], pbit) & pbit) == 0u)
-                        fr.HP[atomicAdd(&cnt[3], 1u)] = pc;
-                    if (fresh) fr.HW[atomicAdd(&cnt[2], 1u)] = r;
-                }
+        for (int64_t e = e0 + lane; e < e1; e += 64) {
+            const int32_t u = radj[e];
+            const int32_t wi = rpiece[e];
+            // most rows are reached from several live vertices: test before
+            // paying for the atomic
+            uint32_t* word;
+            uint32_t bit;
+            if (wi < 0) {
+                word = &fr.mark[u >> 5];
+                bit = 1u << (u & 31);
+            } else {
+                const int32_t pc = wi / wpp;
+                word = &fr.wmask[pc];
+                bit = 1u << (wi - pc * wpp);
             }
-            const bool lt = fresh && r < 0;
-            const uint64_t bal = __ballot(lt);
-            if (bal) {
-                uint32_t base = 0;
-                if (lane == 0) base = atomicAdd(&cnt[1], (uint32_t)__builtin_popcountll(bal));
-                base = __shfl(base, 0, 64);
-                if (lt) fr.W[base + (uint32_t)__builtin_popcountll(bal & ((1ull << lane) - 1ull))] = u;
-            }
+            if ((*word & bit) == 0u) atomicOr(word, bit);
         }
     }
 }
 
-// Last kernel of every sweep: unmarks the rows listed in a sparse sweep and
-// zeroes the list counters of the next sweep.
-__global__ __launch_bounds__(256) void k_sweep_cleanup(const uint32_t* __restrict__ gate, uint32_t gate_thresh,
+// Sparse sweep: lists the marked rows (W) for the row kernels and clears the
+// marks, with one counter atomic per wave.
+__global__ __launch_bounds__(256) void k_sweep_compact(const uint32_t* __restrict__ gate, uint32_t gate_thresh,
                                                        const unsigned long long* __restrict__ sgate, int64_t m,
-                                                       int first, int64_t n, Frontier fr, int parity,
-                                                       const int32_t* __restrict__ hrow) {
+                                                       int first, int64_t n, Frontier fr, int parity) {
     const uint32_t live = sweep_live(gate, gate_thresh, first, n);
-    if (!live) return;
+    if (!live || !sweep_sparse(sgate, first, m, fr.sparse_div)) return;
+    uint32_t* cnt = fr.counts + 4 * parity;
+    const int64_t nwords = (n + 31) >> 5;
     const int64_t stride = (int64_t)gridDim.x * blockDim.x;
     const int64_t tid = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
-    if (tid < 4) fr.counts[4 * (parity ^ 1) + tid] = 0u;
-    if (!sweep_sparse(sgate, first, m, fr.sparse_div)) return;
-    const uint32_t* cnt = fr.counts + 4 * parity;
-    const int64_t nw = cnt[1], nh = cnt[2], np = cnt[3];
-    for (int64_t i = tid; i < nw; i += stride) fr.mark[fr.W[i] >> 5] = 0u;
-    for (int64_t i = tid; i < nh; i += stride) fr.mark[hrow[fr.HW[i]] >> 5] = 0u;
-    for (int64_t i = tid; i < np; i += stride) {
-        fr.pmark[fr.HP[i] >> 5] = 0u;
-        fr.wmask[fr.HP[i]] = 0u;
+    const int lane = threadIdx.x & 63;
+    // uniform trip count per wave so that every lane takes part in the scan
+    const int64_t span = ((nwords + stride - 1) / stride) * stride;
+    for (int64_t w0 = tid - lane; w0 < span; w0 += stride) {
+        const int64_t w = w0 + lane;
+        const uint32_t bits = w < nwords ? fr.mark[w] : 0u;
+        if (bits) fr.mark[w] = 0u;
+        uint32_t tot;
+        const uint32_t off = wave_excl_scan((uint32_t)__builtin_popcount(bits), &tot);
+        if (!tot) continue;
+        uint32_t base = 0;
+        if (lane == 0) base = atomicAdd(&cnt[1], tot);
+        base = __shfl(base, 0, 64) + off;
+        for (uint32_t b = bits; b; b &= b - 1) fr.W[base++] = (int32_t)(w * 32 + __builtin_ctz(b));
     }
+}
+
+// Last kernel of every sweep: zeroes the item counter of the next sweep.
+__global__ __launch_bounds__(64) void k_sweep_cleanup(const uint32_t* __restrict__ gate, uint32_t gate_thresh,
+                                                      int first, int64_t n, Frontier fr, int parity) {
+    const uint32_t live = sweep_live(gate, gate_thresh, first, n);
+    if (!live) return;
+    if (threadIdx.x < 4) fr.counts[4 * (parity ^ 1) + threadIdx.x] = 0u;
 }
 
 template <int G, int DW, int KIND>
@@ -889,17 +877,15 @@ __global__ __launch_bounds__(256) void k_sweep_heavy(
     const uint32_t live = sweep_live(gate, gate_thresh, first, n);
     if (!live) return;
     const bool sparse = sweep_sparse(sgate, first, m, fr.sparse_div);
-    const int64_t count = sparse ? (int64_t)fr.counts[4 * parity + 3] : npieces;
     constexpr int RPW = 64 / G;
     const int lane = threadIdx.x & 63, grp = lane / G, p = lane % G;
     uint32_t x[DW][4];
     load_sim_words<G, DW>(X, P, p, x);
     const uint32_t ntv = to_vgpr(0u - thr_const);
     unsigned long long my_vis = 0;
-    for (int64_t base = wave_index() * RPW; base < count; base += wave_count() * RPW) {
-        const int64_t i = base + grp;
-        if (i >= count) continue;
-        const int64_t pc = sparse ? (int64_t)fr.HP[i] : i;
+    // merges piece pc (uniform over the group); wm: its 64-edge windows to scan,
+    // all of them when 0
+    auto piece = [&](const int64_t pc, const uint32_t wm) {
         const int32_t r = prow[pc];
         const bool skip = fullblk && bit_of(fullblk, hrow[r]) != 0u;
         Acc acc[DW];
@@ -907,11 +893,10 @@ __global__ __launch_bounds__(256) void k_sweep_heavy(
         for (int k = 0; k < DW; ++k) acc[k].e = acc[k].o = 0u;
         uint32_t vis = 0;
         if (!skip) {
-            if (sparse) {
-                // only the windows holding an edge into L_t
+            if (wm) {
                 const int64_t b0 = pe0[pc], b1 = pe1[pc];
-                for (uint32_t wm = fr.wmask[pc]; wm; wm &= wm - 1) {
-                    const int64_t w0 = b0 + 64 * (int64_t)__builtin_ctz(wm);
+                for (uint32_t left = wm; left; left &= left - 1) {
+                    const int64_t w0 = b0 + 64 * (int64_t)__builtin_ctz(left);
                     const int64_t w1 = w0 + 64 < b1 ? w0 + 64 : b1;
                     vis += merge_edges<G, DW, KIND>(w0, w1, adj, eh, thr, ntv, A, Lcur, first, P, lane, p, x, acc);
                 }
@@ -931,6 +916,34 @@ __global__ __launch_bounds__(256) void k_sweep_heavy(
             part_any[pc] = vis > 0 ? fr.stamp : 0u;
             if (vis > 0) rtouch[r] = fr.stamp;  // the row has a piece to combine in this sweep
             my_vis += vis;
+        }
+    };
+    if (!sparse) {
+        for (int64_t base = wave_index() * RPW; base < npieces; base += wave_count() * RPW) {
+            const int64_t i = base + grp;
+            if (i < npieces) piece(i, 0u);
+        }
+    } else {
+        // the pieces with a marked window: each wave scans `span` window masks
+        // (its share, <= 64), clears the nonzero ones (this kernel is their last
+        // reader in the sweep) and merges those pieces, RPW at a time
+        int64_t span = (npieces + wave_count() - 1) / wave_count();
+        span = span < 1 ? 1 : (span > 64 ? 64 : span);
+        for (int64_t base = wave_index() * span; base < npieces; base += wave_count() * span) {
+            uint32_t wm = 0;
+            if (lane < span && base + lane < npieces) {
+                wm = fr.wmask[base + lane];
+                if (wm) fr.wmask[base + lane] = 0u;
+            }
+            for (uint64_t nz = __ballot(wm != 0u); nz;) {
+                // group grp takes the grp-th marked piece left
+                uint64_t t = nz;
+                for (int k = 0; k < grp && t; ++k) t &= t - 1;
+                const int j = t ? __builtin_ctzll(t) : 0;
+                const uint32_t wj = (uint32_t)__shfl((int)wm, j, 64);
+                for (int k = 0; k < RPW && nz; ++k) nz &= nz - 1;
+                if (t) piece(base + j, wj);
+            }
         }
     }
     const unsigned long long bv = block_sum256(my_vis, sh64);
@@ -953,8 +966,8 @@ __global__ __launch_bounds__(256) void k_sweep_heavy_fix(
     __shared__ unsigned long long sh64[4];
     const uint32_t live = sweep_live(gate, gate_thresh, first, n);
     if (!live) return;
-    const bool sparse = sweep_sparse(sgate, first, m, fr.sparse_div);
-    const int64_t count = sparse ? (int64_t)fr.counts[4 * parity + 2] : nheavy;
+    // dense and sparse sweeps alike: every split row, filtered by needs()
+    const int64_t count = nheavy;
     const uint32_t stamp = fr.stamp;
     constexpr int RPW = 64 / G;
     const int lane = threadIdx.x & 63, grp = lane / G, p = lane % G;
@@ -975,7 +988,7 @@ __global__ __launch_bounds__(256) void k_sweep_heavy_fix(
             int64_t r = 0, u = 0;
             bool need = false;
             if (lane < span && i < count) {
-                r = sparse ? (int64_t)fr.HW[i] : i;
+                r = i;
                 u = hrow[r];
                 need = needs(r, u);
             }
@@ -996,7 +1009,7 @@ __global__ __launch_bounds__(256) void k_sweep_heavy_fix(
         for (int64_t base = wave_index() * RPW; base < count; base += wave_count() * RPW) {
             const int64_t i = base + grp;
             if (i >= count) continue;
-            const int64_t r = sparse ? (int64_t)fr.HW[i] : i;
+            const int64_t r = i;
             const int64_t u = hrow[r];
             if (!needs(r, u)) continue;
             const bool changed =
@@ -1036,9 +1049,11 @@ hipError_t launch_sweep(const Layout& L, const DevGraph& g, const uint32_t* X, c
     const int lg = grid > 0 ? grid : grid_for_rows(words);
     const int sg = 2048;  // grid of the list kernels
     hipLaunchKernelGGL(k_sweep_frontier, dim3(sg), dim3(256), 0, s, sp.gate, sp.gate_thresh, sp.sgate, g.m, sp.first,
-                       g.n, sp.Lcur, sp.Lclear, sp.fr, sp.parity, g.rxadj, g.hslot);
+                       g.n, sp.Lcur, sp.Lclear, sp.fr, sp.parity, g.rxadj);
     hipLaunchKernelGGL(k_sweep_expand, dim3(sg), dim3(256), 0, s, sp.gate, sp.gate_thresh, sp.sgate, g.m, sp.first, g.n,
-                       sp.fr, sp.parity, g.rxadj, g.radj, g.rpiece, g.hslot, (int32_t)((g.piece_edges + 63) / 64));
+                       sp.fr, sp.parity, g.rxadj, g.radj, g.rpiece, (int32_t)((g.piece_edges + 63) / 64));
+    hipLaunchKernelGGL(k_sweep_compact, dim3(sg), dim3(256), 0, s, sp.gate, sp.gate_thresh, sp.sgate, g.m, sp.first,
+                       g.n, sp.fr, sp.parity);
     hipError_t err = hipGetLastError();
     if (err != hipSuccess) return err;
     if (ev0) (void)hipEventRecord(ev0, s);
@@ -1098,8 +1113,8 @@ hipError_t launch_sweep(const Layout& L, const DevGraph& g, const uint32_t* X, c
     } else if (ev3) {
         (void)hipEventRecord(ev3, s);
     }
-    hipLaunchKernelGGL(k_sweep_cleanup, dim3(sg), dim3(256), 0, s, sp.gate, sp.gate_thresh, sp.sgate, g.m, sp.first,
-                       g.n, sp.fr, sp.parity, g.hrow);
+    hipLaunchKernelGGL(k_sweep_cleanup, dim3(1), dim3(64), 0, s, sp.gate, sp.gate_thresh, sp.first, g.n, sp.fr,
+                       sp.parity);
     return hipGetLastError();
 }
 
