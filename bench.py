@@ -327,8 +327,8 @@ def main():
     args = ap.parse_args()
     if args.summarize_pmc:
         cmd = ("timeout -s KILL 600 rocprofv3 --kernel-trace --pmc {counter} --output-format csv -d {out} -o run "
-               "-- python3 bench.py --steps 1 --warmup 0 --no-batch --serve-requests 0 --no-cpu-baseline "
-               "--calibrate-copy")
+               "-- python3 bench.py --steps 1 --warmup 0 --no-batch --no-quality --serve-requests 0 "
+               "--no-cpu-baseline --calibrate-copy")
         sys.stdout.write(summarize_pmc(args.summarize_pmc[0], args.summarize_pmc[1], cmd))
         return
     if args.gpus != 1:

@@ -605,7 +605,7 @@ im_status build_sketch(im_ctx* ctx, const im_csr* graph, const im_probs* probs, 
          sk_alloc(sk, &sk->vis_ring, (size_t)3 * RING * NSLOT * SLOT_U64) && sk_alloc(sk, &sk->gather, 8 * MAX_BATCH);
     ok = ok && sk_alloc(sk, &sk->d_err, 4) && sk_alloc(sk, &sk->d_heavy_counts, 4) && sk_alloc(sk, &sk->d_flag, 4);
     sk->fr.chunk = 256;
-    sk->fr.sparse_div = o.sparse_div < 0 ? 0u : (o.sparse_div == 0 ? 96u : (uint32_t)o.sparse_div);
+    sk->fr.sparse_div = o.sparse_div < 0 ? 0u : (o.sparse_div == 0 ? 48u : (uint32_t)o.sparse_div);
     uint32_t* wc_target = nullptr;
     if (probs->kind == IM_PROB_WEIGHTED_CASCADE) ok = ok && sk_alloc(sk, &wc_target, n) && sk_alloc(sk, &g.thr, m);
     if (probs->kind == IM_PROB_PER_EDGE) ok = ok && sk_alloc(sk, &g.thr, m);
