@@ -702,10 +702,15 @@ DEVI unsigned long long bfs_expand_entries(int64_t b0, int64_t b1, int64_t bstep
             }
         }
         uint32_t myval = 0;
-        int64_t myw = 0, mywdeg = 0;
+        int64_t myw = 0;
+        bool myslot = false;  // an edge was put in this lane's slot of the batch
         int nb = 0;
         auto flush = [&]() {
             uint32_t nbits = 0;
+            // out-degree of the slot's target, loaded only for edges with a
+            // candidate bit (it decides whether the target is queued)
+            int64_t mywdeg = 0;
+            if (myslot) mywdeg = xadj[myw + 1] - xadj[myw];
             // blocked bits are only ever set: a plain read that already shows every
             // candidate bit means the atomic could add nothing (a stale read only
             // costs an atomic)
@@ -727,6 +732,7 @@ DEVI unsigned long long bfs_expand_entries(int64_t b0, int64_t b1, int64_t bstep
                 }
             }
             myval = 0;
+            myslot = false;
         };
         for (int64_t w0 = e0; w0 < e1; w0 += G) {
             const int64_t e = w0 + p;
@@ -736,22 +742,18 @@ DEVI unsigned long long bfs_expand_entries(int64_t b0, int64_t b1, int64_t bstep
             uint32_t tt = 0u;
             if constexpr (KIND == THR_TARGET) tt = in ? thr[wv] : 0u;
             if constexpr (KIND == THR_EDGE) tt = in ? thr[e] : 0u;
-            const int64_t wd = in ? xadj[wv + 1] - xadj[wv] : 0;
             const int nwin = (int)(e1 - w0 < G ? e1 - w0 : G);
             for (int j = 0; j < nwin; ++j) {
                 uint32_t hb, nt = ntv;
                 int32_t wj;
-                int64_t wdj;
                 if constexpr (G == 64) {
                     hb = (uint32_t)__builtin_amdgcn_readlane((int)hh, j);
                     if constexpr (KIND != THR_CONST) nt = 0u - (uint32_t)__builtin_amdgcn_readlane((int)tt, j);
                     wj = __builtin_amdgcn_readlane(wv, j);
-                    wdj = __builtin_amdgcn_readlane((int)wd, j);
                 } else {
                     hb = __shfl(hh, grp * G + j, 64);
                     if constexpr (KIND != THR_CONST) nt = 0u - __shfl(tt, grp * G + j, 64);
                     wj = __shfl(wv, grp * G + j, 64);
-                    wdj = __shfl((int)wd, grp * G + j, 64);
                 }
                 uint32_t cw = 0;
                 bool anyc = false;
@@ -777,7 +779,7 @@ DEVI unsigned long long bfs_expand_entries(int64_t b0, int64_t b1, int64_t bstep
                 if (sb == nb) {
                     myval = cw;
                     myw = wj;
-                    mywdeg = wdj;
+                    myslot = slot_ok;
                 }
                 if (++nb == EPB) {
                     flush();

@@ -883,10 +883,9 @@ __global__ __launch_bounds__(256) void k_sweep_heavy(
     load_sim_words<G, DW>(X, P, p, x);
     const uint32_t ntv = to_vgpr(0u - thr_const);
     unsigned long long my_vis = 0;
-    // merges piece pc (uniform over the group); wm: its 64-edge windows to scan,
-    // all of them when 0
-    auto piece = [&](const int64_t pc, const uint32_t wm) {
-        const int32_t r = prow[pc];
+    // merges piece pc of split row r, edges [b0, b1) (uniform over the group);
+    // wm: its 64-edge windows to scan, all of them when 0
+    auto piece = [&](const int64_t pc, const int32_t r, const int64_t b0, const int64_t b1, const uint32_t wm) {
         const bool skip = fullblk && bit_of(fullblk, hrow[r]) != 0u;
         Acc acc[DW];
 #pragma unroll
@@ -894,14 +893,13 @@ __global__ __launch_bounds__(256) void k_sweep_heavy(
         uint32_t vis = 0;
         if (!skip) {
             if (wm) {
-                const int64_t b0 = pe0[pc], b1 = pe1[pc];
                 for (uint32_t left = wm; left; left &= left - 1) {
                     const int64_t w0 = b0 + 64 * (int64_t)__builtin_ctz(left);
                     const int64_t w1 = w0 + 64 < b1 ? w0 + 64 : b1;
                     vis += merge_edges<G, DW, KIND>(w0, w1, adj, eh, thr, ntv, A, Lcur, first, P, lane, p, x, acc);
                 }
             } else {
-                vis = merge_edges<G, DW, KIND>(pe0[pc], pe1[pc], adj, eh, thr, ntv, A, Lcur, first, P, lane, p, x, acc);
+                vis = merge_edges<G, DW, KIND>(b0, b1, adj, eh, thr, ntv, A, Lcur, first, P, lane, p, x, acc);
             }
         }
         // vis is uniform over the group; a partial without live edges is never read
@@ -919,9 +917,26 @@ __global__ __launch_bounds__(256) void k_sweep_heavy(
         }
     };
     if (!sparse) {
-        for (int64_t base = wave_index() * RPW; base < npieces; base += wave_count() * RPW) {
-            const int64_t i = base + grp;
-            if (i < npieces) piece(i, 0u);
+        // a group's pieces are i, i + stride, ...; the next piece's table entry is
+        // loaded while the current piece is merged
+        const int64_t stride = wave_count() * RPW;
+        int64_t i = wave_index() * RPW + grp;
+        int32_t r_n = 0;
+        int64_t b0_n = 0, b1_n = 0;
+        if (i < npieces) {
+            r_n = prow[i];
+            b0_n = pe0[i];
+            b1_n = pe1[i];
+        }
+        for (; i - grp < npieces; i += stride) {
+            const int32_t r = r_n;
+            const int64_t b0 = b0_n, b1 = b1_n;
+            if (i + stride < npieces) {
+                r_n = prow[i + stride];
+                b0_n = pe0[i + stride];
+                b1_n = pe1[i + stride];
+            }
+            if (i < npieces) piece(i, r, b0, b1, 0u);
         }
     } else {
         // the pieces with a marked window: each wave scans `span` window masks
@@ -942,7 +957,10 @@ __global__ __launch_bounds__(256) void k_sweep_heavy(
                 const int j = t ? __builtin_ctzll(t) : 0;
                 const uint32_t wj = (uint32_t)__shfl((int)wm, j, 64);
                 for (int k = 0; k < RPW && nz; ++k) nz &= nz - 1;
-                if (t) piece(base + j, wj);
+                if (t) {
+                    const int64_t pc = base + j;
+                    piece(pc, prow[pc], pe0[pc], pe1[pc], wj);
+                }
             }
         }
     }
