@@ -159,7 +159,8 @@ IM_API void im_ctx_free(im_ctx* ctx);
 /* Device bytes currently held by sketches of the context. */
 IM_API size_t im_ctx_bytes_in_use(const im_ctx* ctx);
 
-/* Device bytes a sketch of this shape would hold (for admission by budget). */
+/* Device bytes a sketch of this shape would hold at its peak, the temporaries
+ * of its preparation included (for admission by budget). */
 IM_API size_t im_sketch_bytes_needed(int64_t n, int64_t m, int32_t R, im_prob_kind kind);
 
 /*

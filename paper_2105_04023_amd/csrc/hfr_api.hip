@@ -215,6 +215,10 @@ size_t bytes_needed(int64_t n, int64_t m, int32_t R, im_prob_kind kind) {
     t += 2 * al(8 * qcap_for(n, m)) + al(64) + al(4 * n) + al(n) + 2 * al(4 * L.P) + al(8) +
          al(NSLOT * SLOT_U64 * 8) + al(8);
     t += al(sizeof(StepRec) * 64) + al(4 * 64) + al(16) + al(16) + al(64);
+    // preparation temporaries: the light-row list's, and the reverse CSR's
+    const int64_t nb = (n + 1023) / 1024;
+    const size_t list_tmp = al(4 * n) + al(8 * (n + 1)) + al(8 * (nb + 2));
+    t += list_tmp + (rb_fits(n, m) ? rb_temp_bytes(n, m) : list_tmp);
     return t;
 }
 
@@ -710,29 +714,38 @@ im_status build_sketch(im_ctx* ctx, const im_csr* graph, const im_probs* probs, 
         }
         HIP_TRY(launch_heavy_slots(g, s));
         HIP_TRY(launch_edge_hash(g, hash_seed, s));  // split rows are hashed by piece
-        // in-degrees: weighted-cascade thresholds (main stream) and the reverse CSR,
-        // whose in-edges carry the piece of their split source row (aux stream)
+        // in-degrees (weighted-cascade thresholds) and the reverse CSR, whose
+        // in-edges carry the 64-edge window of their split source row's piece
         {
             const int64_t nb = (n + 1023) / 1024;
             const size_t a4n = (4 * n + 255) & ~size_t(255), a8n = (8 * (n + 1) + 255) & ~size_t(255);
             const size_t asc = (8 * (nb + 2) + 255) & ~size_t(255);
             // main: flags, positions and scan sums of the light-row list
             void* pm_ = ctx_alloc(ctx, a4n + a8n + asc);
-            // kept until the reverse CSR is done: in-degrees, cursors, scan sums
-            sk->rev_tmp = ctx_alloc(ctx, a4n + a8n + asc);
+            // in-degrees and the reverse CSR's temporaries (freed below when the
+            // reverse CSR is built on this stream, else once the aux stream is done)
+            const bool one_stream = rb_fits(n, m);
+            sk->rev_tmp = ctx_alloc(ctx, one_stream ? rb_temp_bytes(n, m) : a4n + a8n + asc);
             if (!pm_ || !sk->rev_tmp) {
                 if (pm_) ctx_free(ctx, pm_);
                 return fail(IM_ERR_OUT_OF_BUDGET, "temporary allocation failed");
             }
-            uint32_t* indeg = (uint32_t*)sk->rev_tmp;
-            int64_t* cursor = (int64_t*)((char*)sk->rev_tmp + a4n);
-            uint32_t* scan_tmp = (uint32_t*)((char*)cursor + a8n);
-            HIP_TRY(launch_fill_u32(indeg, 0u, n, s));
-            HIP_TRY(launch_indegree(g, indeg, s));
-            HIP_TRY(hipEventRecord(sk->ev_indeg, s));
-            HIP_TRY(hipStreamWaitEvent(sk->aux, sk->ev_indeg, 0));
-            HIP_TRY(launch_reverse_csr(g, indeg, cursor, scan_tmp, sk->aux));
-            HIP_TRY(hipEventRecord(sk->ev_rev, sk->aux));
+            uint32_t* indeg = nullptr;
+            if (one_stream) {
+                // a counting sort on the target, with LDS counters only
+                HIP_TRY(launch_reverse_csr_buckets(g, sk->rev_tmp, &indeg, s));
+            } else {
+                // global atomics, the scatter on the aux stream beside the sweeps
+                indeg = (uint32_t*)sk->rev_tmp;
+                int64_t* cursor = (int64_t*)((char*)sk->rev_tmp + a4n);
+                uint32_t* scan_tmp = (uint32_t*)((char*)cursor + a8n);
+                HIP_TRY(launch_fill_u32(indeg, 0u, n, s));
+                HIP_TRY(launch_indegree(g, indeg, s));
+                HIP_TRY(hipEventRecord(sk->ev_indeg, s));
+                HIP_TRY(hipStreamWaitEvent(sk->aux, sk->ev_indeg, 0));
+                HIP_TRY(launch_reverse_csr(g, indeg, cursor, scan_tmp, sk->aux));
+                HIP_TRY(hipEventRecord(sk->ev_rev, sk->aux));
+            }
             if (g.kind == THR_TARGET) {
                 // w_uv depends on the target only; the kernels read it per edge, as a
                 // coalesced array beside the edge hashes instead of a gather by target
@@ -748,6 +761,11 @@ im_status build_sketch(im_ctx* ctx, const im_csr* graph, const im_probs* probs, 
             HIP_TRY(hipMemcpyAsync(&g.nlight, lpos + n, 8, hipMemcpyDeviceToHost, s));
             HIP_TRY(hipStreamSynchronize(s));
             ctx_free(ctx, pm_);
+            if (one_stream) {
+                ctx_free(ctx, sk->rev_tmp);
+                sk->rev_tmp = nullptr;
+                sk->rev_ready = true;
+            }
         }
         // greedy buffers
         const size_t W = 4 * (size_t)L.PW;

@@ -140,6 +140,11 @@ hipError_t launch_sweep(const Layout& L, const DevGraph& g, const uint32_t* X, c
                         hipEvent_t ev_heavy_begin, hipEvent_t ev_heavy_end);
 hipError_t launch_reverse_csr(const DevGraph& g, const uint32_t* indeg, int64_t* cursor, uint32_t* scan_tmp,
                               hipStream_t s);
+// Reverse CSR and in-degrees by a counting sort on the target, on one stream
+// (graphs with n <= 2^25 and m < 2^31: rb_fits).
+bool rb_fits(int64_t n, int64_t m);
+size_t rb_temp_bytes(int64_t n, int64_t m);
+hipError_t launch_reverse_csr_buckets(const DevGraph& g, void* tmp, uint32_t** indeg, hipStream_t s);
 hipError_t launch_heavy_slots(const DevGraph& g, hipStream_t s);
 hipError_t launch_light_rows(const DevGraph& g, uint32_t* flags, int64_t* pos, uint32_t* scan_tmp, hipStream_t s);
 hipError_t launch_full_blocked(const Layout& L, int64_t n, const uint32_t* blk, uint32_t* fullblk, hipStream_t s);

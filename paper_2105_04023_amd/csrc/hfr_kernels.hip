@@ -55,14 +55,13 @@ hipError_t launch_validate(const DevGraph& g, uint32_t* err, hipStream_t s) {
     return hipGetLastError();
 }
 
-// Eq. (hash): h(u, v) = Murmur3(LE32(u) || LE32(v)) mod 2^31, in two
-// balanced parts.  Rows with at most heavy_deg out-edges: a wave takes 64
-// consecutive rows and walks their edges as one flat range, 64 at a time (the
-// source row of a flat edge is found by a binary search over the row starts
-// held one per lane; split rows count as empty here).  Split rows: one wave
-// per piece of piece_edges edges.
-__global__ void k_edge_hash_light(const int64_t* __restrict__ xadj, const int32_t* __restrict__ adj, uint32_t* eh,
-                                  int64_t n, int64_t heavy_deg, uint32_t seed) {
+// Calls f(u, e) once for every out-edge e of every row u with at most
+// heavy_deg out-edges, on the lane that owns it (lanes diverge around the
+// call).  A wave takes 64 consecutive rows at a time and walks their edges as
+// one flat range, 64 per window; the row of a flat edge is found by a binary
+// search over the rows' starts, held one per lane.
+template <class F>
+DEVI void for_light_edges(const int64_t* __restrict__ xadj, int64_t n, int64_t heavy_deg, F&& f) {
     const int lane = threadIdx.x & 63;
     for (int64_t u0 = wave_index() * 64; u0 < n; u0 += wave_count() * 64) {
         const int nr = n - u0 < 64 ? (int)(n - u0) : 64;
@@ -79,34 +78,54 @@ __global__ void k_edge_hash_light(const int64_t* __restrict__ xadj, const int32_
         const int64_t total = __shfl(off, 63, 64);
         const int64_t start = off - len;  // exclusive prefix
         for (int64_t base = 0; base < total; base += 64) {
-            const int64_t f = base + lane;
-            int lo = 0, hi = nr - 1;  // largest row i with start_i <= f
+            const int64_t f_ = base + lane;
+            int lo = 0, hi = nr - 1;  // largest row i with start_i <= f_
 #pragma unroll
             for (int k = 0; k < 6; ++k) {
                 const int mid = (lo + hi + 1) >> 1;
                 const int64_t sm = __shfl(start, mid, 64);
                 if (lo < hi) {
-                    if (sm <= f)
+                    if (sm <= f_)
                         lo = mid;
                     else
                         hi = mid - 1;
                 }
             }
-            const int64_t e = __shfl(rb, lo, 64) + (f - __shfl(start, lo, 64));
-            if (f < total) eh[e] = mm3_key8((uint32_t)(u0 + lo), (uint32_t)adj[e], seed) & 0x7FFFFFFFu;
+            const int64_t e = __shfl(rb, lo, 64) + (f_ - __shfl(start, lo, 64));
+            if (f_ < total) f(u0 + lo, e);
         }
     }
+}
+
+// Calls f(u, e, pc, b0) once for every edge e of every piece pc (of split row
+// u, edges [b0, pe1[pc])); one wave per piece.
+template <class F>
+DEVI void for_piece_edges(const int32_t* __restrict__ hrow, const int32_t* __restrict__ prow,
+                          const int64_t* __restrict__ pe0, const int64_t* __restrict__ pe1, int64_t npieces, F&& f) {
+    const int lane = threadIdx.x & 63;
+    for (int64_t pc = wave_index(); pc < npieces; pc += wave_count()) {
+        const int64_t u = hrow[prow[pc]];
+        const int64_t b0 = pe0[pc], e1 = pe1[pc];
+        for (int64_t e = b0 + lane; e < e1; e += 64) f(u, e, pc, b0);
+    }
+}
+
+// Eq. (hash): h(u, v) = Murmur3(LE32(u) || LE32(v)) mod 2^31, in two balanced
+// parts: the rows with at most heavy_deg out-edges, then the pieces of the
+// split rows.
+__global__ void k_edge_hash_light(const int64_t* __restrict__ xadj, const int32_t* __restrict__ adj, uint32_t* eh,
+                                  int64_t n, int64_t heavy_deg, uint32_t seed) {
+    for_light_edges(xadj, n, heavy_deg, [&](int64_t u, int64_t e) {
+        eh[e] = mm3_key8((uint32_t)u, (uint32_t)adj[e], seed) & 0x7FFFFFFFu;
+    });
 }
 
 __global__ void k_edge_hash_pieces(const int32_t* __restrict__ adj, const int32_t* __restrict__ hrow,
                                    const int32_t* __restrict__ prow, const int64_t* __restrict__ pe0,
                                    const int64_t* __restrict__ pe1, int64_t npieces, uint32_t* eh, uint32_t seed) {
-    const int lane = threadIdx.x & 63;
-    for (int64_t pc = wave_index(); pc < npieces; pc += wave_count()) {
-        const uint32_t u = (uint32_t)hrow[prow[pc]];
-        const int64_t e1 = pe1[pc];
-        for (int64_t e = pe0[pc] + lane; e < e1; e += 64) eh[e] = mm3_key8(u, (uint32_t)adj[e], seed) & 0x7FFFFFFFu;
-    }
+    for_piece_edges(hrow, prow, pe0, pe1, npieces, [&](int64_t u, int64_t e, int64_t, int64_t) {
+        eh[e] = mm3_key8((uint32_t)u, (uint32_t)adj[e], seed) & 0x7FFFFFFFu;
+    });
 }
 
 hipError_t launch_edge_hash(const DevGraph& g, uint32_t seed, hipStream_t s) {
@@ -1154,17 +1173,32 @@ __global__ void k_scan_block_sums(const uint32_t* __restrict__ in, int64_t n, in
     if (threadIdx.x == 0) sums[blockIdx.x] = s;
 }
 
-__global__ void k_scan_sums(int64_t* sums, int64_t nb) {
-    // one thread: nb is at most n / 1024
-    if (threadIdx.x == 0 && blockIdx.x == 0) {
-        int64_t run = 0;
-        for (int64_t b = 0; b < nb; ++b) {
-            const int64_t v = sums[b];
-            sums[b] = run;
-            run += v;
-        }
-        sums[nb] = run;
+// Exclusive scan of the nb block sums in place (sums[nb] = total), one block of
+// 1024 threads: each thread scans a contiguous run of ceil(nb / 1024) sums,
+// offset by the scan of the run totals across the block.
+__global__ __launch_bounds__(1024) void k_scan_sums(int64_t* sums, int64_t nb) {
+    __shared__ int64_t sh[1024];
+    const int t = threadIdx.x;
+    const int64_t per = (nb + 1023) / 1024;
+    const int64_t b0 = t * per;
+    const int64_t b1 = b0 + per < nb ? b0 + per : nb;
+    int64_t loc = 0;
+    for (int64_t b = b0; b < b1; ++b) loc += sums[b];
+    sh[t] = loc;
+    __syncthreads();
+    for (int off = 1; off < 1024; off <<= 1) {
+        const int64_t y = t >= off ? sh[t - off] : 0;
+        __syncthreads();
+        sh[t] += y;
+        __syncthreads();
     }
+    int64_t run = sh[t] - loc;
+    for (int64_t b = b0; b < b1; ++b) {
+        const int64_t v = sums[b];
+        sums[b] = run;
+        run += v;
+    }
+    if (t == 1023) sums[nb] = sh[1023];
 }
 
 __global__ __launch_bounds__(256) void k_scan_apply(const uint32_t* __restrict__ in, int64_t n,
@@ -1201,7 +1235,8 @@ __global__ __launch_bounds__(256) void k_scan_apply(const uint32_t* __restrict__
 }
 
 // radj[cursor[v]++] = u for every edge (u, v); the order inside an in-row
-// depends on scheduling, the set does not.
+// depends on scheduling, the set does not (graphs too large for the counting
+// sort below).
 __global__ void k_rev_scatter(const int64_t* __restrict__ xadj, const int32_t* __restrict__ adj, int64_t n,
                               int64_t* cursor, int32_t* radj, int32_t* rpiece, const int32_t* __restrict__ hslot,
                               const int64_t* __restrict__ hpb, int64_t piece, int32_t wpp) {
@@ -1232,12 +1267,295 @@ hipError_t launch_reverse_csr(const DevGraph& g, const uint32_t* indeg, int64_t*
     const int64_t nb = (n + SCAN_BLOCK - 1) / SCAN_BLOCK;
     int64_t* sums = reinterpret_cast<int64_t*>(scan_tmp);  // nb + 1 entries
     hipLaunchKernelGGL(k_scan_block_sums, dim3((unsigned)nb), dim3(256), 0, s, indeg, n, sums);
-    hipLaunchKernelGGL(k_scan_sums, dim3(1), dim3(64), 0, s, sums, nb);
+    hipLaunchKernelGGL(k_scan_sums, dim3(1), dim3(1024), 0, s, sums, nb);
     hipLaunchKernelGGL(k_scan_apply, dim3((unsigned)nb), dim3(256), 0, s, indeg, n, sums, g.rxadj);
     hipLaunchKernelGGL(k_copy_i64, dim3(4096), dim3(256), 0, s, g.rxadj, cursor, n);
     if (g.m > 0)
         hipLaunchKernelGGL(k_rev_scatter, dim3(8192), dim3(256), 0, s, g.xadj, g.adj, n, cursor, g.radj, g.rpiece,
                            g.hslot, g.hpb, g.piece_edges, (int32_t)((g.piece_edges + 63) / 64));
+    return hipGetLastError();
+}
+
+// ----------------------------------------------------------------------------
+// Reverse CSR by a two-level counting sort on the target, without global
+// atomics: (1) every workgroup counts its edges per bucket of 2^RB_SHIFT
+// consecutive targets in LDS; (2) a scan of the counts, bucket-major, gives
+// each workgroup its slice of every bucket; (3) the workgroups re-walk the same
+// edges and write (target, source, window) records into their slices; (4) one
+// workgroup per bucket counts the in-degrees of its targets in LDS, turns them
+// into the offsets rxadj and places the records.  The edges of a workgroup are
+// the same in (1) and (3): both walk the rows with at most heavy_deg edges,
+// then the pieces of the split rows, with the same grids.  Step (4) shares a
+// bucket with many records among several workgroups (chunks).
+// ----------------------------------------------------------------------------
+constexpr int RB_SHIFT = 13;          // targets per bucket: 8192 (32 KiB of LDS counters)
+constexpr int RB_MAX_BUCKETS = 4096;  // so n <= 2^25
+constexpr int RB_BLOCKS = 1024;       // workgroups per walk (light rows, then pieces)
+
+template <bool PIECES>
+__global__ __launch_bounds__(256) void k_rb_count(const int64_t* __restrict__ xadj, const int32_t* __restrict__ adj,
+                                                  int64_t n, int64_t heavy_deg, const int32_t* __restrict__ hrow,
+                                                  const int32_t* __restrict__ prow, const int64_t* __restrict__ pe0,
+                                                  const int64_t* __restrict__ pe1, int64_t npieces, int nbk, int ncol,
+                                                  int col, uint32_t* __restrict__ hist) {
+    __shared__ uint32_t h[RB_MAX_BUCKETS];
+    for (int i = threadIdx.x; i < nbk; i += blockDim.x) h[i] = 0u;
+    __syncthreads();
+    if constexpr (PIECES)
+        for_piece_edges(hrow, prow, pe0, pe1, npieces,
+                        [&](int64_t, int64_t e, int64_t, int64_t) { atomicAdd(&h[adj[e] >> RB_SHIFT], 1u); });
+    else
+        for_light_edges(xadj, n, heavy_deg, [&](int64_t, int64_t e) { atomicAdd(&h[adj[e] >> RB_SHIFT], 1u); });
+    __syncthreads();
+    for (int i = threadIdx.x; i < nbk; i += blockDim.x) hist[(int64_t)i * ncol + col + blockIdx.x] = h[i];
+}
+
+template <bool PIECES>
+__global__ __launch_bounds__(256) void k_rb_scatter(const int64_t* __restrict__ xadj, const int32_t* __restrict__ adj,
+                                                    int64_t n, int64_t heavy_deg, const int32_t* __restrict__ hrow,
+                                                    const int32_t* __restrict__ prow, const int64_t* __restrict__ pe0,
+                                                    const int64_t* __restrict__ pe1, int64_t npieces, int nbk,
+                                                    int ncol, int col, const int64_t* __restrict__ off, int32_t wpp,
+                                                    int32_t* __restrict__ tv, int32_t* __restrict__ tu,
+                                                    int32_t* __restrict__ tw) {
+    __shared__ int64_t base[RB_MAX_BUCKETS];
+    __shared__ uint32_t cur[RB_MAX_BUCKETS];
+    for (int i = threadIdx.x; i < nbk; i += blockDim.x) {
+        base[i] = off[(int64_t)i * ncol + col + blockIdx.x];
+        cur[i] = 0u;
+    }
+    __syncthreads();
+    auto put = [&](int64_t u, int64_t e, int32_t w) {
+        const int32_t v = adj[e];
+        const int b = v >> RB_SHIFT;
+        const int64_t pos = base[b] + atomicAdd(&cur[b], 1u);
+        tv[pos] = v;
+        tu[pos] = (int32_t)u;
+        tw[pos] = w;
+    };
+    if constexpr (PIECES)
+        // the 64-edge window of the edge within its piece: windows of piece pc
+        // are pc * wpp .. pc * wpp + wpp - 1
+        for_piece_edges(hrow, prow, pe0, pe1, npieces, [&](int64_t u, int64_t e, int64_t pc, int64_t b0) {
+            put(u, e, (int32_t)(pc * wpp + (e - b0) / 64));
+        });
+    else
+        for_light_edges(xadj, n, heavy_deg, [&](int64_t u, int64_t e) { put(u, e, -1); });
+}
+
+// The records of bucket b are [off[b * ncol], off[(b + 1) * ncol]); the
+// bucket is cut into chunks of at most RB_CHUNK records (at least one chunk,
+// also when empty), so that the hub buckets of skewed graphs are shared by
+// many workgroups.  cstart[b] = first chunk of bucket b, cstart[nbk] = total.
+constexpr int64_t RB_CHUNK = 1 << 17;
+
+__global__ __launch_bounds__(1024) void k_rb_chunks(const int64_t* __restrict__ off, int ncol, int nbk,
+                                                    int64_t* __restrict__ cstart) {
+    __shared__ int64_t part[1024];
+    const int t = threadIdx.x;
+    const int per = (nbk + 1023) / 1024;
+    int64_t loc = 0;
+    for (int k = 0; k < per; ++k) {
+        const int64_t b = (int64_t)t * per + k;
+        if (b < nbk) {
+            const int64_t len = off[(b + 1) * ncol] - off[b * ncol];
+            loc += len > 0 ? (len + RB_CHUNK - 1) / RB_CHUNK : 1;
+        }
+    }
+    part[t] = loc;
+    __syncthreads();
+    for (int o = 1; o < 1024; o <<= 1) {
+        const int64_t y = t >= o ? part[t - o] : 0;
+        __syncthreads();
+        part[t] += y;
+        __syncthreads();
+    }
+    int64_t run = part[t] - loc;
+    for (int k = 0; k < per; ++k) {
+        const int64_t b = (int64_t)t * per + k;
+        if (b < nbk) {
+            cstart[b] = run;
+            const int64_t len = off[(b + 1) * ncol] - off[b * ncol];
+            run += len > 0 ? (len + RB_CHUNK - 1) / RB_CHUNK : 1;
+        }
+    }
+    if (t == 1023) cstart[nbk] = part[1023];
+}
+
+// Chunk c of the grid: its bucket b, target base v0 and records [r0, r1), and
+// the bucket's first record s0.  False past the last chunk.
+struct RbChunk {
+    int64_t b, v0, s0, r0, r1;
+};
+DEVI bool rb_chunk(int64_t c, const int64_t* __restrict__ off, int ncol, int nbk, const int64_t* __restrict__ cstart,
+                   RbChunk& ch) {
+    if (c >= cstart[nbk]) return false;
+    int lo = 0, hi = nbk - 1;  // last bucket with cstart <= c
+    while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (cstart[mid] <= c) lo = mid; else hi = mid - 1;
+    }
+    ch.b = lo;
+    ch.v0 = (int64_t)lo << RB_SHIFT;
+    ch.s0 = off[(int64_t)lo * ncol];
+    const int64_t s1 = off[(int64_t)(lo + 1) * ncol];
+    ch.r0 = ch.s0 + (c - cstart[lo]) * RB_CHUNK;
+    ch.r1 = ch.r0 + RB_CHUNK < s1 ? ch.r0 + RB_CHUNK : s1;
+    return true;
+}
+
+// Per chunk: the in-degree counts of its records' targets, ctab[c][t].
+__global__ __launch_bounds__(1024) void k_rb_fcount(const int64_t* __restrict__ off, int ncol, int nbk,
+                                                    const int64_t* __restrict__ cstart, const int32_t* __restrict__ tv,
+                                                    uint32_t* __restrict__ ctab) {
+    constexpr int BT = 1 << RB_SHIFT;
+    __shared__ uint32_t cnt[BT];
+    RbChunk ch;
+    if (!rb_chunk(blockIdx.x, off, ncol, nbk, cstart, ch)) return;
+    for (int i = threadIdx.x; i < BT; i += 1024) cnt[i] = 0u;
+    __syncthreads();
+    for (int64_t i = ch.r0 + threadIdx.x; i < ch.r1; i += 1024) atomicAdd(&cnt[tv[i] - ch.v0], 1u);
+    __syncthreads();
+    for (int i = threadIdx.x; i < BT; i += 1024) ctab[(int64_t)blockIdx.x * BT + i] = cnt[i];
+}
+
+// Per bucket: in-degrees and rxadj of its targets, and ctab[c][t] turned into
+// the first slot (relative to the bucket's first record) of chunk c's records
+// of target t.
+__global__ __launch_bounds__(1024) void k_rb_fscan(const int64_t* __restrict__ off, int ncol, int nbk, int64_t n,
+                                                   const int64_t* __restrict__ cstart, uint32_t* __restrict__ ctab,
+                                                   uint32_t* __restrict__ indeg, int64_t* __restrict__ rxadj) {
+    constexpr int BT = 1 << RB_SHIFT, PER = BT / 1024;
+    __shared__ int64_t part[1024];
+    const int t = threadIdx.x;
+    const int64_t b = blockIdx.x;
+    const int64_t c0 = cstart[b], c1 = cstart[b + 1];
+    const int64_t s0 = off[b * ncol], v0 = b << RB_SHIFT;
+    uint32_t deg[PER];
+#pragma unroll
+    for (int k = 0; k < PER; ++k) deg[k] = 0u;
+    for (int64_t c = c0; c < c1; ++c)
+#pragma unroll
+        for (int k = 0; k < PER; ++k) deg[k] += ctab[c * BT + k * 1024 + t];
+    // targets are k * 1024 + t: scan in that order, PER rounds of 1024
+    int64_t base = 0;
+    uint32_t first[PER];
+#pragma unroll
+    for (int k = 0; k < PER; ++k) {
+        part[t] = deg[k];
+        __syncthreads();
+        for (int o = 1; o < 1024; o <<= 1) {
+            const int64_t y = t >= o ? part[t - o] : 0;
+            __syncthreads();
+            part[t] += y;
+            __syncthreads();
+        }
+        const int64_t loc = base + part[t] - deg[k];
+        first[k] = (uint32_t)loc;
+        const int64_t v = v0 + k * 1024 + t;
+        if (v < n) {
+            indeg[v] = deg[k];
+            rxadj[v] = s0 + loc;
+        }
+        base += part[1023];
+        __syncthreads();
+    }
+    if (b == nbk - 1 && t == 0) rxadj[n] = off[(int64_t)nbk * ncol];
+    for (int64_t c = c0; c < c1; ++c)
+#pragma unroll
+        for (int k = 0; k < PER; ++k) {
+            const int64_t i = c * BT + k * 1024 + t;
+            const uint32_t x = ctab[i];
+            ctab[i] = first[k];
+            first[k] += x;
+        }
+}
+
+// Per chunk: places its records at their slots (radj, rpiece).
+__global__ __launch_bounds__(1024) void k_rb_fplace(const int64_t* __restrict__ off, int ncol, int nbk,
+                                                    const int64_t* __restrict__ cstart,
+                                                    const uint32_t* __restrict__ ctab, const int32_t* __restrict__ tv,
+                                                    const int32_t* __restrict__ tu, const int32_t* __restrict__ tw,
+                                                    int32_t* __restrict__ radj, int32_t* __restrict__ rpiece) {
+    constexpr int BT = 1 << RB_SHIFT;
+    __shared__ uint32_t cur[BT];
+    RbChunk ch;
+    if (!rb_chunk(blockIdx.x, off, ncol, nbk, cstart, ch)) return;
+    for (int i = threadIdx.x; i < BT; i += 1024) cur[i] = ctab[(int64_t)blockIdx.x * BT + i];
+    __syncthreads();
+    for (int64_t i = ch.r0 + threadIdx.x; i < ch.r1; i += 1024) {
+        const int64_t p = ch.s0 + atomicAdd(&cur[tv[i] - ch.v0], 1u);
+        radj[p] = tu[i];
+        rpiece[p] = tw[i];
+    }
+}
+
+static int64_t rb_max_chunks(int64_t n, int64_t m) {
+    const int64_t nbk = (n + (1 << RB_SHIFT) - 1) >> RB_SHIFT;
+    return m / RB_CHUNK + nbk + 1;
+}
+
+bool rb_fits(int64_t n, int64_t m) {
+    return n <= (int64_t)RB_MAX_BUCKETS << RB_SHIFT && m < (1ll << 31);
+}
+
+size_t rb_temp_bytes(int64_t n, int64_t m) {
+    const int64_t nbk = (n + (1 << RB_SHIFT) - 1) >> RB_SHIFT;
+    const int64_t cells = nbk * 2 * RB_BLOCKS;
+    const int64_t nsb = (cells + SCAN_BLOCK - 1) / SCAN_BLOCK;
+    auto al = [](int64_t b) { return (size_t)((b + 255) & ~int64_t(255)); };
+    return al(4 * n) + 3 * al(4 * (m > 0 ? m : 1)) + al(4 * cells) + al(8 * (cells + 1)) + al(8 * (nsb + 2)) +
+           al(8 * (nbk + 1)) + al(4 * rb_max_chunks(n, m) * (1 << RB_SHIFT));
+}
+
+// In-degrees (indeg) and the reverse CSR of g (rxadj, radj, rpiece) on stream
+// s; tmp holds rb_temp_bytes(n, m) bytes, indeg at its start.
+hipError_t launch_reverse_csr_buckets(const DevGraph& g, void* tmp, uint32_t** indeg_out, hipStream_t s) {
+    const int64_t n = g.n, m = g.m;
+    const int nbk = (int)((n + (1 << RB_SHIFT) - 1) >> RB_SHIFT);
+    const int ncol = 2 * RB_BLOCKS;
+    const int64_t cells = (int64_t)nbk * ncol;
+    const int64_t nsb = (cells + SCAN_BLOCK - 1) / SCAN_BLOCK;
+    auto al = [](int64_t b) { return (int64_t)((b + 255) & ~int64_t(255)); };
+    char* p = static_cast<char*>(tmp);
+    uint32_t* indeg = reinterpret_cast<uint32_t*>(p);
+    p += al(4 * n);
+    int32_t* tv = reinterpret_cast<int32_t*>(p);
+    p += al(4 * (m > 0 ? m : 1));
+    int32_t* tu = reinterpret_cast<int32_t*>(p);
+    p += al(4 * (m > 0 ? m : 1));
+    int32_t* tw = reinterpret_cast<int32_t*>(p);
+    p += al(4 * (m > 0 ? m : 1));
+    uint32_t* hist = reinterpret_cast<uint32_t*>(p);
+    p += al(4 * cells);
+    int64_t* off = reinterpret_cast<int64_t*>(p);
+    p += al(8 * (cells + 1));
+    int64_t* sums = reinterpret_cast<int64_t*>(p);
+    p += al(8 * (nsb + 2));
+    int64_t* cstart = reinterpret_cast<int64_t*>(p);
+    p += al(8 * (nbk + 1));
+    uint32_t* ctab = reinterpret_cast<uint32_t*>(p);
+    const int64_t maxch = rb_max_chunks(n, m);
+    *indeg_out = indeg;
+    const int32_t wpp = (int32_t)((g.piece_edges + 63) / 64);
+    // a workgroup that walks no edge still writes its (zero) counts
+    hipLaunchKernelGGL((k_rb_count<false>), dim3(RB_BLOCKS), dim3(256), 0, s, g.xadj, g.adj, n, g.heavy_deg, g.hrow,
+                       g.prow, g.pe0, g.pe1, g.npieces, nbk, ncol, 0, hist);
+    hipLaunchKernelGGL((k_rb_count<true>), dim3(RB_BLOCKS), dim3(256), 0, s, g.xadj, g.adj, n, g.heavy_deg, g.hrow,
+                       g.prow, g.pe0, g.pe1, g.npieces, nbk, ncol, RB_BLOCKS, hist);
+    hipLaunchKernelGGL(k_scan_block_sums, dim3((unsigned)nsb), dim3(256), 0, s, hist, cells, sums);
+    hipLaunchKernelGGL(k_scan_sums, dim3(1), dim3(1024), 0, s, sums, nsb);
+    hipLaunchKernelGGL(k_scan_apply, dim3((unsigned)nsb), dim3(256), 0, s, hist, cells, sums, off);
+    hipLaunchKernelGGL((k_rb_scatter<false>), dim3(RB_BLOCKS), dim3(256), 0, s, g.xadj, g.adj, n, g.heavy_deg, g.hrow,
+                       g.prow, g.pe0, g.pe1, g.npieces, nbk, ncol, 0, off, wpp, tv, tu, tw);
+    hipLaunchKernelGGL((k_rb_scatter<true>), dim3(RB_BLOCKS), dim3(256), 0, s, g.xadj, g.adj, n, g.heavy_deg, g.hrow,
+                       g.prow, g.pe0, g.pe1, g.npieces, nbk, ncol, RB_BLOCKS, off, wpp, tv, tu, tw);
+    hipLaunchKernelGGL(k_rb_chunks, dim3(1), dim3(1024), 0, s, off, ncol, nbk, cstart);
+    hipLaunchKernelGGL(k_rb_fcount, dim3((unsigned)maxch), dim3(1024), 0, s, off, ncol, nbk, cstart, tv, ctab);
+    hipLaunchKernelGGL(k_rb_fscan, dim3((unsigned)nbk), dim3(1024), 0, s, off, ncol, nbk, n, cstart, ctab, indeg,
+                       g.rxadj);
+    hipLaunchKernelGGL(k_rb_fplace, dim3((unsigned)maxch), dim3(1024), 0, s, off, ncol, nbk, cstart, ctab, tv, tu, tw,
+                       g.radj, g.rpiece);
     return hipGetLastError();
 }
 
@@ -1261,7 +1579,7 @@ hipError_t launch_light_rows(const DevGraph& g, uint32_t* flags, int64_t* pos, u
     int64_t* sums = reinterpret_cast<int64_t*>(scan_tmp);  // nb + 1 entries
     hipLaunchKernelGGL(k_light_flags, dim3(4096), dim3(256), 0, s, g.xadj, n, g.heavy_deg, flags);
     hipLaunchKernelGGL(k_scan_block_sums, dim3((unsigned)nb), dim3(256), 0, s, flags, n, sums);
-    hipLaunchKernelGGL(k_scan_sums, dim3(1), dim3(64), 0, s, sums, nb);
+    hipLaunchKernelGGL(k_scan_sums, dim3(1), dim3(1024), 0, s, sums, nb);
     hipLaunchKernelGGL(k_scan_apply, dim3((unsigned)nb), dim3(256), 0, s, flags, n, sums, pos);
     hipLaunchKernelGGL(k_light_scatter, dim3(4096), dim3(256), 0, s, flags, pos, n, g.lrows);
     return hipGetLastError();
