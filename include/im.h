@@ -85,6 +85,11 @@ typedef struct im_probs {
                                   sweeps; registers, estimates and seeds equal those of synchronous
                                   sweeps when eps_c = 0, while sweep and visit counts depend on the
                                   schedule (not reproducible). */
+#define IM_BUILD_ATOMIC_REVERSE 4 /* build the reverse CSR (in-edges, for sparse sweeps) with global
+                                     atomics on an auxiliary stream beside the first sweeps, the
+                                     method used anyway when n > 2^25 or m >= 2^31; otherwise it
+                                     is a counting sort on the build's stream.  Results are the
+                                     same either way. */
 typedef struct im_build_opts {
     double eps_c;
     int32_t heavy_degree; /* rows with more out-edges are split across waves (0: 64) */

@@ -160,9 +160,10 @@ def _ptr_and_residency(a, dtype):
 def im_build_sketches(ctx: Context, xadj, adj, n: int, R: int, model: str = "const", p: float = 0.0,
                       per_edge=None, hash_seed: int = 0, eps_c: float = 0.0, heavy_degree: int = 0,
                       piece_edges: int = 0, sparse_div: int = 0, time_sweeps: bool = False,
-                      in_place: bool = False) -> Sketch:
+                      in_place: bool = False, atomic_reverse: bool = False) -> Sketch:
     """Alg. 1 initialisation + Alg. 2: builds the per-vertex rank registers of R samples.
-    in_place selects in-place sweeps (IM_BUILD_IN_PLACE) for the build and every rebuild."""
+    in_place selects in-place sweeps (IM_BUILD_IN_PLACE) for the build and every rebuild;
+    atomic_reverse the atomic reverse-CSR construction (IM_BUILD_ATOMIC_REVERSE)."""
     torch = _torch()
     xp, xdev, xk = _ptr_and_residency(xadj, (np.int64, torch.int64))
     ap, adev, ak = _ptr_and_residency(adj, (np.int32, torch.int32))
@@ -179,7 +180,8 @@ def im_build_sketches(ctx: Context, xadj, adj, n: int, R: int, model: str = "con
         pe_ptr = pp
         keep.append(pk)
     probs = B.im_probs(_KIND[model], float(p), pe_ptr)
-    flags = (B.IM_BUILD_TIME_SWEEPS if time_sweeps else 0) | (B.IM_BUILD_IN_PLACE if in_place else 0)
+    flags = ((B.IM_BUILD_TIME_SWEEPS if time_sweeps else 0) | (B.IM_BUILD_IN_PLACE if in_place else 0) |
+             (B.IM_BUILD_ATOMIC_REVERSE if atomic_reverse else 0))
     opts = B.im_build_opts(eps_c, heavy_degree, piece_edges, sparse_div, flags)
     h = ctypes.c_void_p()
     B.check(ctx.lib.im_build_sketches(ctx.handle, ctypes.byref(g), ctypes.byref(probs), R, hash_seed & 0xFFFFFFFF,

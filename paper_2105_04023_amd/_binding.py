@@ -15,7 +15,7 @@ IM_OK = 0
 STATUS_NAMES = {0: "IM_OK", -1: "IM_ERR_INVALID_ARG", -2: "IM_ERR_INVALID_GRAPH", -3: "IM_ERR_OUT_OF_BUDGET",
                 -4: "IM_ERR_DEVICE", -5: "IM_ERR_STATE"}
 IM_PROB_CONSTANT, IM_PROB_WEIGHTED_CASCADE, IM_PROB_PER_EDGE = 0, 1, 2
-IM_BUILD_TIME_SWEEPS, IM_BUILD_IN_PLACE = 1, 2
+IM_BUILD_TIME_SWEEPS, IM_BUILD_IN_PLACE, IM_BUILD_ATOMIC_REVERSE = 1, 2, 4
 
 # Every symbol include/im.h declares (checked by the CPU test suite).
 EXPORTED = [

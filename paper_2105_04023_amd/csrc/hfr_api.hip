@@ -563,7 +563,8 @@ im_status build_sketch(im_ctx* ctx, const im_csr* graph, const im_probs* probs, 
     if (!(o.eps_c >= 0.0)) return fail(IM_ERR_INVALID_ARG, "eps_c must be >= 0");
     if (o.heavy_degree < 0 || o.piece_edges < 0) return fail(IM_ERR_INVALID_ARG, "negative tuning value");
     if (o.piece_edges > 2048) return fail(IM_ERR_INVALID_ARG, "piece_edges must be at most 2048");
-    if (o.flags & ~(IM_BUILD_TIME_SWEEPS | IM_BUILD_IN_PLACE)) return fail(IM_ERR_INVALID_ARG, "unknown build flag");
+    if (o.flags & ~(IM_BUILD_TIME_SWEEPS | IM_BUILD_IN_PLACE | IM_BUILD_ATOMIC_REVERSE))
+        return fail(IM_ERR_INVALID_ARG, "unknown build flag");
     const size_t need = bytes_needed(n, m, R, probs->kind);
     if (ctx->budget && ctx->in_use + need > ctx->budget)
         return fail(IM_ERR_OUT_OF_BUDGET, "sketch needs %zu bytes, %zu of %zu in use", need, ctx->in_use, ctx->budget);
@@ -724,7 +725,7 @@ im_status build_sketch(im_ctx* ctx, const im_csr* graph, const im_probs* probs, 
             void* pm_ = ctx_alloc(ctx, a4n + a8n + asc);
             // in-degrees and the reverse CSR's temporaries (freed below when the
             // reverse CSR is built on this stream, else once the aux stream is done)
-            const bool one_stream = rb_fits(n, m);
+            const bool one_stream = rb_fits(n, m) && !(o.flags & IM_BUILD_ATOMIC_REVERSE);
             sk->rev_tmp = ctx_alloc(ctx, one_stream ? rb_temp_bytes(n, m) : a4n + a8n + asc);
             if (!pm_ || !sk->rev_tmp) {
                 if (pm_) ctx_free(ctx, pm_);
