@@ -182,12 +182,74 @@ DEVI double estimate_from_sum(uint32_t s, int J, const double* __restrict__ T) {
 // ----------------------------------------------------------------------------
 constexpr int UB = 8;  // neighbour rows in flight per wave (twice that with one dword per lane)
 
+// G = 64: merges one window of up to 64 out-edges, lane l holding edge e (in:
+// the edge exists) with head v, `mask` the lanes whose head is in L_t (not
+// empty).  The rows of up to UB live heads are loaded back-to-back before they
+// are merged.
+template <int DW, int KIND>
+DEVI void merge_window64(uint64_t mask, int64_t e, bool in, int32_t v, const uint32_t* __restrict__ eh,
+                         const uint32_t* __restrict__ thr, uint32_t ntv, const uint32_t* __restrict__ A, int P,
+                         int lane, const uint32_t (&x)[DW][4], Acc (&acc)[DW]) {
+    const uint32_t hh = in ? eh[e] : 0u;
+    uint32_t tt = 0u;
+    if constexpr (KIND == THR_TARGET) tt = in ? thr[v] : 0u;
+    if constexpr (KIND == THR_EDGE) tt = in ? thr[e] : 0u;
+    // batches of NB live edges, NB the smallest of 1, 2, 4, UB that covers the
+    // edges left (capped at UB): unused slots repeat the last edge (max-merge is
+    // idempotent), so every load of a batch is issued without a branch
+    auto batch = [&](auto nbc) {
+        constexpr int NB = decltype(nbc)::value;
+        int idx[NB];
+        int last = __builtin_ctzll(mask);
+#pragma unroll
+        for (int b = 0; b < NB; ++b) {
+            if (mask) last = __builtin_ctzll(mask);
+            idx[b] = last;
+            mask &= mask - 1;
+        }
+        // lanes past the row (q >= P) load a valid dword of it; their
+        // results are never stored
+        uint32_t d[NB][DW];
+#pragma unroll
+        for (int b = 0; b < NB; ++b) {
+            const int64_t vb = __builtin_amdgcn_readlane(v, idx[b]);
+            const uint32_t* __restrict__ row = A + vb * P;
+#pragma unroll
+            for (int i = 0; i < DW; ++i) {
+                const int q = i * 64 + lane;
+                d[b][i] = row[q < P ? q : P - 1];
+            }
+        }
+        __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+        for (int b = 0; b < NB; ++b) {
+            const uint32_t hb = (uint32_t)__builtin_amdgcn_readlane((int)hh, idx[b]);
+            uint32_t nt = ntv;
+            if constexpr (KIND != THR_CONST) nt = 0u - (uint32_t)__builtin_amdgcn_readlane((int)tt, idx[b]);
+#pragma unroll
+            for (int i = 0; i < DW; ++i) merge_live(acc[i], d[b][i], x[i][0], x[i][1], x[i][2], x[i][3], hb, nt);
+        }
+    };
+    while (mask) {
+        const int nl = __builtin_popcountll(mask);
+        if (DW == 1 && nl > UB)
+            batch(std::integral_constant<int, 2 * UB>{});
+        else if (nl > 4)
+            batch(std::integral_constant<int, UB>{});
+        else if (nl > 2)
+            batch(std::integral_constant<int, 4>{});
+        else if (nl == 2)
+            batch(std::integral_constant<int, 2>{});
+        else
+            batch(std::integral_constant<int, 1>{});
+    }
+}
+
 // G = 64 (one row per wave): the row's out-edges are read NW windows of 64
 // at a time, with one coalesced load per window and array; the L_t tests of
 // the NW windows are issued together, so that a sweep with few live heads
-// waits on one round of dependent loads per NW windows.  The rows of up to UB
-// live heads of a window are loaded back-to-back before they are merged.
-// Returns the number of edges with a live head.
+// waits on one round of dependent loads per NW windows.  Returns the number
+// of edges with a live head.
 constexpr int NW = 4;
 template <int DW, int KIND>
 DEVI uint32_t merge_edges64(int64_t eb, int64_t ee, const int32_t* __restrict__ adj, const uint32_t* __restrict__ eh,
@@ -208,65 +270,9 @@ DEVI uint32_t merge_edges64(int64_t eb, int64_t ee, const int32_t* __restrict__ 
         for (int w = 0; w < NW; ++w) mw[w] = __ballot(inw[w] && (first || bit_of(Lcur, vw[w]) != 0u));
 #pragma unroll
         for (int w = 0; w < NW; ++w) {
-            uint64_t mask = mw[w];
-            if (!mask) continue;  // no live head: the window needs no hash or threshold
-            const int64_t e = c0 + 64 * w + lane;
-            const bool in = inw[w];
-            const int32_t v = vw[w];
-            vis += (uint32_t)__builtin_popcountll(mask);
-            const uint32_t hh = in ? eh[e] : 0u;
-            uint32_t tt = 0u;
-            if constexpr (KIND == THR_TARGET) tt = in ? thr[v] : 0u;
-            if constexpr (KIND == THR_EDGE) tt = in ? thr[e] : 0u;
-            // batches of NB live edges, NB the smallest of 1, 2, 4, UB that covers the
-            // edges left (capped at UB): unused slots repeat the last edge (max-merge is
-            // idempotent), so every load of a batch is issued without a branch
-            auto batch = [&](auto nbc) {
-                constexpr int NB = decltype(nbc)::value;
-                int idx[NB];
-                int last = __builtin_ctzll(mask);
-    #pragma unroll
-                for (int b = 0; b < NB; ++b) {
-                    if (mask) last = __builtin_ctzll(mask);
-                    idx[b] = last;
-                    mask &= mask - 1;
-                }
-                // lanes past the row (q >= P) load a valid dword of it; their
-                // results are never stored
-                uint32_t d[NB][DW];
-    #pragma unroll
-                for (int b = 0; b < NB; ++b) {
-                    const int64_t vb = __builtin_amdgcn_readlane(v, idx[b]);
-                    const uint32_t* __restrict__ row = A + vb * P;
-    #pragma unroll
-                    for (int i = 0; i < DW; ++i) {
-                        const int q = i * 64 + lane;
-                        d[b][i] = row[q < P ? q : P - 1];
-                    }
-                }
-                __builtin_amdgcn_sched_barrier(0);
-    #pragma unroll
-                for (int b = 0; b < NB; ++b) {
-                    const uint32_t hb = (uint32_t)__builtin_amdgcn_readlane((int)hh, idx[b]);
-                    uint32_t nt = ntv;
-                    if constexpr (KIND != THR_CONST) nt = 0u - (uint32_t)__builtin_amdgcn_readlane((int)tt, idx[b]);
-    #pragma unroll
-                    for (int i = 0; i < DW; ++i) merge_live(acc[i], d[b][i], x[i][0], x[i][1], x[i][2], x[i][3], hb, nt);
-                }
-            };
-            while (mask) {
-                const int nl = __builtin_popcountll(mask);
-                if (DW == 1 && nl > UB)
-                    batch(std::integral_constant<int, 2 * UB>{});
-                else if (nl > 4)
-                    batch(std::integral_constant<int, UB>{});
-                else if (nl > 2)
-                    batch(std::integral_constant<int, 4>{});
-                else if (nl == 2)
-                    batch(std::integral_constant<int, 2>{});
-                else
-                    batch(std::integral_constant<int, 1>{});
-            }
+            if (!mw[w]) continue;  // no live head: the window needs no hash or threshold
+            vis += (uint32_t)__builtin_popcountll(mw[w]);
+            merge_window64<DW, KIND>(mw[w], c0 + 64 * w + lane, inw[w], vw[w], eh, thr, ntv, A, P, lane, x, acc);
         }
     }
     return vis;
