@@ -138,6 +138,19 @@ DEVI bool group_all(bool c) {
     return !group_any<G>(!c);
 }
 
+// Exclusive prefix of c over the wave and the wave total.
+DEVI uint32_t wave_excl_scan(uint32_t c, uint32_t* total) {
+    const int lane = threadIdx.x & 63;
+    uint32_t x = c;
+#pragma unroll
+    for (int off = 1; off < 64; off <<= 1) {
+        const uint32_t y = __shfl_up(x, off, 64);
+        if (lane >= off) x += y;
+    }
+    *total = __shfl(x, 63, 64);
+    return x - c;
+}
+
 DEVI int64_t wave_index() { return __builtin_amdgcn_readfirstlane((int)((blockIdx.x * blockDim.x + threadIdx.x) >> 6)); }
 DEVI int64_t wave_count() { return (int64_t)(gridDim.x * blockDim.x) >> 6; }
 
@@ -729,7 +742,22 @@ DEVI unsigned long long bfs_expand_entries(int64_t b0, int64_t b1, int64_t bstep
                 }
             }
             const uint64_t bal = __ballot(nbits != 0u);
-            if (sw == 0 && slot_ok && mywdeg > 0 && ((bal >> (grp * G + sb * W)) & wmask) != 0ull) {
+            const bool want = sw == 0 && slot_ok && mywdeg > 0 && ((bal >> (grp * G + sb * W)) & wmask) != 0ull;
+            if constexpr (G == 64) {
+                // the whole wave flushes together: the targets it queues take one
+                // range of the next queue, with a single counter atomic
+                uint32_t nch = 0;
+                if (want && atomicMax(&stamp[myw], level_id_next) < level_id_next)
+                    nch = (uint32_t)((mywdeg + bfs_chunk - 1) / bfs_chunk);
+                uint32_t tot;
+                const uint32_t off = wave_excl_scan(nch, &tot);
+                if (tot) {
+                    uint32_t pos = 0;
+                    if (lane == 0) pos = atomicAdd(qn, tot);
+                    pos = __shfl(pos, 0, 64) + off;
+                    for (uint32_t c = 0; c < nch; ++c) Qn[pos + c] = make_int2((int)myw, (int)c);
+                }
+            } else if (want) {
                 const int32_t old = atomicMax(&stamp[myw], level_id_next);
                 if (old < level_id_next) {
                     const int64_t nch = (mywdeg + bfs_chunk - 1) / bfs_chunk;

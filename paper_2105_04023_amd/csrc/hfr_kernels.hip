@@ -420,19 +420,6 @@ DEVI bool sweep_sparse(const unsigned long long* __restrict__ sgate, int first, 
     return s * div <= (unsigned long long)m;
 }
 
-// Exclusive prefix of c over the wave and the wave total.
-DEVI uint32_t wave_excl_scan(uint32_t c, uint32_t* total) {
-    const int lane = threadIdx.x & 63;
-    uint32_t x = c;
-#pragma unroll
-    for (int off = 1; off < 64; off <<= 1) {
-        const uint32_t y = __shfl_up(x, off, 64);
-        if (lane >= off) x += y;
-    }
-    *total = __shfl(x, 63, 64);
-    return x - c;
-}
-
 
 // First kernel of every sweep.  Zeroes the bitmap that will hold L_{t+2}; in a
 // sparse sweep also marks the rows of L_t (the copy rule needs them) and lists
