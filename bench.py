@@ -117,7 +117,7 @@ def summarize_pmc(fetch_dir: str, write_dir: str, command: str):
     lines = [
         "# k_sweep_heavy on rmat24_wc_J256_K50: HBM traffic from counters",
         "",
-        "Commands (run from the repository root on the GPU box, `cd /tmp && export TMPDIR=/tmp` first):",
+        "Commands (run from the repository root on an MI355X, `cd /tmp && export TMPDIR=/tmp` first):",
         "",
         f"    {command.format(counter='FETCH_SIZE', out=fetch_dir)}",
         f"    {command.format(counter='WRITE_SIZE', out=write_dir)}",
