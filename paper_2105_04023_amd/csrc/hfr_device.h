@@ -291,6 +291,43 @@ DEVI uint32_t merge_edges64(int64_t eb, int64_t ee, const int32_t* __restrict__ 
     return vis;
 }
 
+// G = 64: merges the 64-edge windows of [eb, ee) named by the bits of wm
+// (window i starts at eb + 64 i), NW of them at a time with their loads and
+// L_t tests issued together.  Returns the number of edges with a live head.
+template <int DW, int KIND>
+DEVI uint32_t merge_marked_windows64(int64_t eb, int64_t ee, uint32_t wm, const int32_t* __restrict__ adj,
+                                     const uint32_t* __restrict__ eh, const uint32_t* __restrict__ thr, uint32_t ntv,
+                                     const uint32_t* __restrict__ A, const uint32_t* __restrict__ Lcur, int first,
+                                     int P, int lane, const uint32_t (&x)[DW][4], Acc (&acc)[DW]) {
+    uint32_t vis = 0;
+    while (wm) {
+        int64_t w0[NW];
+#pragma unroll
+        for (int w = 0; w < NW; ++w) {
+            // past the last marked window: an empty window
+            w0[w] = wm ? eb + 64 * (int64_t)__builtin_ctz(wm) : ee;
+            wm &= wm - 1;
+        }
+        int32_t vw[NW];
+        bool inw[NW];
+#pragma unroll
+        for (int w = 0; w < NW; ++w) {
+            inw[w] = w0[w] + lane < ee && w0[w] < ee;
+            vw[w] = inw[w] ? adj[w0[w] + lane] : 0;
+        }
+        uint64_t mw[NW];
+#pragma unroll
+        for (int w = 0; w < NW; ++w) mw[w] = __ballot(inw[w] && (first || bit_of(Lcur, vw[w]) != 0u));
+#pragma unroll
+        for (int w = 0; w < NW; ++w) {
+            if (!mw[w]) continue;
+            vis += (uint32_t)__builtin_popcountll(mw[w]);
+            merge_window64<DW, KIND>(mw[w], w0[w] + lane, inw[w], vw[w], eh, thr, ntv, A, P, lane, x, acc);
+        }
+    }
+    return vis;
+}
+
 // G < 64 (several rows per wave): each G-lane group reads its row's out-edges
 // G at a time, finds the heads in L_t with one ballot and merges the rows of
 // up to UB live heads per batch of loads.  Groups may diverge; shuffles only

@@ -890,19 +890,25 @@ __global__ __launch_bounds__(256) void k_sweep_heavy(
     const uint32_t ntv = to_vgpr(0u - thr_const);
     unsigned long long my_vis = 0;
     // merges piece pc of split row r, edges [b0, b1) (uniform over the group);
-    // wm: its 64-edge windows to scan, all of them when 0
-    auto piece = [&](const int64_t pc, const int32_t r, const int64_t b0, const int64_t b1, const uint32_t wm) {
-        const bool skip = fullblk && bit_of(fullblk, hrow[r]) != 0u;
+    // wm: its 64-edge windows to scan, all of them when 0; skip: the row is
+    // blocked in every sample
+    auto piece = [&](const int64_t pc, const int32_t r, const int64_t b0, const int64_t b1, const uint32_t wm,
+                     const bool skip) {
         Acc acc[DW];
 #pragma unroll
         for (int k = 0; k < DW; ++k) acc[k].e = acc[k].o = 0u;
         uint32_t vis = 0;
         if (!skip) {
             if (wm) {
-                for (uint32_t left = wm; left; left &= left - 1) {
-                    const int64_t w0 = b0 + 64 * (int64_t)__builtin_ctz(left);
-                    const int64_t w1 = w0 + 64 < b1 ? w0 + 64 : b1;
-                    vis += merge_edges<G, DW, KIND>(w0, w1, adj, eh, thr, ntv, A, Lcur, first, P, lane, p, x, acc);
+                if constexpr (G == 64) {
+                    vis = merge_marked_windows64<DW, KIND>(b0, b1, wm, adj, eh, thr, ntv, A, Lcur, first, P, lane, x,
+                                                           acc);
+                } else {
+                    for (uint32_t left = wm; left; left &= left - 1) {
+                        const int64_t w0 = b0 + 64 * (int64_t)__builtin_ctz(left);
+                        const int64_t w1 = w0 + 64 < b1 ? w0 + 64 : b1;
+                        vis += merge_edges<G, DW, KIND>(w0, w1, adj, eh, thr, ntv, A, Lcur, first, P, lane, p, x, acc);
+                    }
                 }
             } else {
                 vis = merge_edges<G, DW, KIND>(b0, b1, adj, eh, thr, ntv, A, Lcur, first, P, lane, p, x, acc);
@@ -942,7 +948,7 @@ __global__ __launch_bounds__(256) void k_sweep_heavy(
                 b0_n = pe0[i + stride];
                 b1_n = pe1[i + stride];
             }
-            if (i < npieces) piece(i, r, b0, b1, 0u);
+            if (i < npieces) piece(i, r, b0, b1, 0u, fullblk && bit_of(fullblk, hrow[r]) != 0u);
         }
     } else {
         // the pieces with a marked window: each wave scans `span` window masks
@@ -956,17 +962,27 @@ __global__ __launch_bounds__(256) void k_sweep_heavy(
                 wm = fr.wmask[base + lane];
                 if (wm) fr.wmask[base + lane] = 0u;
             }
+            // the table entries of every marked piece of the span, loaded at once
+            int32_t rl = 0;
+            int64_t b0l = 0, b1l = 0;
+            bool skl = false;
+            if (wm) {
+                rl = prow[base + lane];
+                b0l = pe0[base + lane];
+                b1l = pe1[base + lane];
+                skl = fullblk && bit_of(fullblk, hrow[rl]) != 0u;
+            }
             for (uint64_t nz = __ballot(wm != 0u); nz;) {
                 // group grp takes the grp-th marked piece left
                 uint64_t t = nz;
                 for (int k = 0; k < grp && t; ++k) t &= t - 1;
                 const int j = t ? __builtin_ctzll(t) : 0;
                 const uint32_t wj = (uint32_t)__shfl((int)wm, j, 64);
+                const int32_t r = __shfl(rl, j, 64);
+                const int64_t b0 = __shfl(b0l, j, 64), b1 = __shfl(b1l, j, 64);
+                const bool sk = __shfl((int)skl, j, 64) != 0;
                 for (int k = 0; k < RPW && nz; ++k) nz &= nz - 1;
-                if (t) {
-                    const int64_t pc = base + j;
-                    piece(pc, prow[pc], pe0[pc], pe1[pc], wj);
-                }
+                if (t) piece(base + j, r, b0, b1, wj, sk);
             }
         }
     }
