@@ -198,6 +198,7 @@ size_t bytes_needed(int64_t n, int64_t m, int32_t R, im_prob_kind kind) {
     t += al(8 * (n + 1)) + al(4 * m) + al(4 * m);  // xadj, adj, edge hashes
     t += al(8 * (n + 1)) + 2 * al(4 * m) + 2 * al(4 * n);  // reverse CSR with pieces, heavy slots, light rows
     t += al(4 * ((n + 31) / 32 + 1)) + al(8 * (n + m / 256 + 64)) + al(4 * n) + al(32);  // sparse marks, lists
+    t += al(4 * COARSE_WORDS);                                                          // coarse L_t
     if (kind == IM_PROB_WEIGHTED_CASCADE) t += al(4 * n) + al(4 * m);  // per target, then per edge
     if (kind == IM_PROB_PER_EDGE) t += al(4 * m);
     t += al(4 * R) * 2 + al(8 * R);               // X, HJ, T
@@ -611,6 +612,18 @@ im_status build_sketch(im_ctx* ctx, const im_csr* graph, const im_probs* probs, 
     ok = ok && sk_alloc(sk, &sk->d_err, 4) && sk_alloc(sk, &sk->d_heavy_counts, 4) && sk_alloc(sk, &sk->d_flag, 4);
     sk->fr.chunk = 256;
     sk->fr.sparse_div = o.sparse_div < 0 ? 0u : (o.sparse_div == 0 ? 48u : (uint32_t)o.sparse_div);
+    {
+        // coarse copy of L_t: at least 256 vertices per bit, at most COARSE_WORDS
+        // words; used by the one-row-per-wave kernels while at most 1/8 of its
+        // bits (or 64 of them, on small graphs) can be set
+        int cs = 8;
+        while (((n - 1) >> (cs + 5)) + 1 > COARSE_WORDS) ++cs;
+        sk->fr.coarse_shift = cs;
+        sk->fr.coarse_words = (int32_t)(((n - 1) >> (cs + 5)) + 1);
+        const uint32_t cbits = (uint32_t)(((n - 1) >> cs) + 1);
+        sk->fr.coarse_live = L.G == 64 ? std::max(cbits / 8u, 64u) : 0u;
+        ok = ok && sk_alloc(sk, &sk->fr.coarse, sk->fr.coarse_words);
+    }
     uint32_t* wc_target = nullptr;
     if (probs->kind == IM_PROB_WEIGHTED_CASCADE) ok = ok && sk_alloc(sk, &wc_target, n) && sk_alloc(sk, &g.thr, m);
     if (probs->kind == IM_PROB_PER_EDGE) ok = ok && sk_alloc(sk, &g.thr, m);

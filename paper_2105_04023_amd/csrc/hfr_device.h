@@ -85,6 +85,14 @@ DEVI uint32_t acc_max(uint32_t a, const Acc& acc) {
 
 DEVI uint32_t bit_of(const uint32_t* __restrict__ bm, int64_t v) { return (bm[v >> 5] >> (v & 31)) & 1u; }
 
+// Whether head v is in L_t.  With cl set (a coarse copy of L_t in LDS, one bit
+// per 2^cs vertices, set if any of them is in L_t), a head whose coarse bit is
+// clear is answered without the load from the bitmap in memory.
+DEVI bool in_L(const uint32_t* __restrict__ Lcur, const uint32_t* cl, int cs, int64_t v) {
+    if (cl && ((cl[v >> (cs + 5)] >> ((v >> cs) & 31)) & 1u) == 0u) return false;
+    return bit_of(Lcur, v) != 0u;
+}
+
 // Byte mask of the unblocked registers of dword q of vertex u.
 DEVI uint32_t unblocked_mask(const uint32_t* __restrict__ blk, int64_t u, int q, int PW) {
     const uint32_t* b = blk + u * 4 * PW + (q >> 5);
@@ -268,7 +276,7 @@ template <int DW, int KIND>
 DEVI uint32_t merge_edges64(int64_t eb, int64_t ee, const int32_t* __restrict__ adj, const uint32_t* __restrict__ eh,
                             const uint32_t* __restrict__ thr, uint32_t ntv, const uint32_t* __restrict__ A,
                             const uint32_t* __restrict__ Lcur, int first, int P, int lane,
-                            const uint32_t (&x)[DW][4], Acc (&acc)[DW]) {
+                            const uint32_t (&x)[DW][4], Acc (&acc)[DW], const uint32_t* cl = nullptr, int cs = 0) {
     uint32_t vis = 0;
     for (int64_t c0 = eb; c0 < ee; c0 += 64 * NW) {
         int32_t vw[NW];
@@ -280,7 +288,7 @@ DEVI uint32_t merge_edges64(int64_t eb, int64_t ee, const int32_t* __restrict__ 
         }
         uint64_t mw[NW];
 #pragma unroll
-        for (int w = 0; w < NW; ++w) mw[w] = __ballot(inw[w] && (first || bit_of(Lcur, vw[w]) != 0u));
+        for (int w = 0; w < NW; ++w) mw[w] = __ballot(inw[w] && (first || in_L(Lcur, cl, cs, vw[w])));
 #pragma unroll
         for (int w = 0; w < NW; ++w) {
             if (!mw[w]) continue;  // no live head: the window needs no hash or threshold
@@ -298,7 +306,8 @@ template <int DW, int KIND>
 DEVI uint32_t merge_marked_windows64(int64_t eb, int64_t ee, uint32_t wm, const int32_t* __restrict__ adj,
                                      const uint32_t* __restrict__ eh, const uint32_t* __restrict__ thr, uint32_t ntv,
                                      const uint32_t* __restrict__ A, const uint32_t* __restrict__ Lcur, int first,
-                                     int P, int lane, const uint32_t (&x)[DW][4], Acc (&acc)[DW]) {
+                                     int P, int lane, const uint32_t (&x)[DW][4], Acc (&acc)[DW],
+                                     const uint32_t* cl = nullptr, int cs = 0) {
     uint32_t vis = 0;
     while (wm) {
         int64_t w0[NW];
@@ -317,7 +326,7 @@ DEVI uint32_t merge_marked_windows64(int64_t eb, int64_t ee, uint32_t wm, const 
         }
         uint64_t mw[NW];
 #pragma unroll
-        for (int w = 0; w < NW; ++w) mw[w] = __ballot(inw[w] && (first || bit_of(Lcur, vw[w]) != 0u));
+        for (int w = 0; w < NW; ++w) mw[w] = __ballot(inw[w] && (first || in_L(Lcur, cl, cs, vw[w])));
 #pragma unroll
         for (int w = 0; w < NW; ++w) {
             if (!mw[w]) continue;
@@ -406,9 +415,9 @@ template <int G, int DW, int KIND>
 DEVI uint32_t merge_edges(int64_t eb, int64_t ee, const int32_t* __restrict__ adj, const uint32_t* __restrict__ eh,
                           const uint32_t* __restrict__ thr, uint32_t ntv, const uint32_t* __restrict__ A,
                           const uint32_t* __restrict__ Lcur, int first, int P, int lane, int p,
-                          const uint32_t (&x)[DW][4], Acc (&acc)[DW]) {
+                          const uint32_t (&x)[DW][4], Acc (&acc)[DW], const uint32_t* cl = nullptr, int cs = 0) {
     if constexpr (G == 64)
-        return merge_edges64<DW, KIND>(eb, ee, adj, eh, thr, ntv, A, Lcur, first, P, lane, x, acc);
+        return merge_edges64<DW, KIND>(eb, ee, adj, eh, thr, ntv, A, Lcur, first, P, lane, x, acc, cl, cs);
     else
         return merge_edges_grp<G, DW, KIND>(eb, ee, adj, eh, thr, ntv, A, Lcur, first, P, lane, p, x, acc);
 }

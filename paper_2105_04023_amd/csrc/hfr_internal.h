@@ -57,6 +57,8 @@ struct DevGraph {
     int64_t piece_edges = 256;
 };
 
+constexpr int COARSE_WORDS = 2048;  // coarse copy of L_t: 8 KiB of LDS per workgroup
+
 // Work lists of a sparse sweep.  Counters come in two sets selected by the
 // sweep parity; a sweep zeroes the other set for the next sweep.
 struct Frontier {
@@ -66,6 +68,11 @@ struct Frontier {
     uint32_t* counts = nullptr; // [2][4]: items and W of the sweep of each parity (rest unused)
     uint32_t* wmask = nullptr;  // per piece: its 64-edge windows holding an edge into L_t; zero
                                 // outside a sparse sweep
+    uint32_t* coarse = nullptr; // coarse copy of L_t for dense sweeps with few live vertices: bit c set
+                                // iff a vertex of [c << coarse_shift, (c + 1) << coarse_shift) is in L_t
+    int32_t coarse_shift = 8;   // so that the copy has at most COARSE_WORDS words
+    int32_t coarse_words = 0;
+    uint32_t coarse_live = 0;   // largest |L_t| for which the copy is built and used (0: never)
     uint32_t stamp = 0;         // unique per sweep (never 0): piece flags of this sweep
     int32_t chunk = 256;        // in-edges per item
     uint32_t sparse_div = 8;    // sweep t > 0 is sparse iff S_t * sparse_div <= m (0: never)

@@ -420,6 +420,22 @@ DEVI bool sweep_sparse(const unsigned long long* __restrict__ sgate, int first, 
     return s * div <= (unsigned long long)m;
 }
 
+// A dense sweep after the first with at most coarse_live vertices in L_t tests
+// heads against the coarse copy of L_t first (built by the frontier kernel).
+DEVI bool sweep_coarse(uint32_t live, int first, bool sparse, const Frontier& fr) {
+    return !first && !sparse && fr.coarse_live > 0 && live <= fr.coarse_live;
+}
+
+// Copies the coarse L_t of the sweep into LDS (cl[COARSE_WORDS]); returns the
+// pointer the merges test against, nullptr when the sweep does not use it.
+// Uniform over the workgroup.
+DEVI const uint32_t* load_coarse(bool use, const Frontier& fr, uint32_t* cl) {
+    if (!use) return nullptr;
+    for (int i = threadIdx.x; i < fr.coarse_words; i += blockDim.x) cl[i] = fr.coarse[i];
+    __syncthreads();
+    return cl;
+}
+
 
 // First kernel of every sweep.  Zeroes the bitmap that will hold L_{t+2}; in a
 // sparse sweep also marks the rows of L_t (the copy rule needs them) and lists
@@ -435,9 +451,27 @@ __global__ __launch_bounds__(256) void k_sweep_frontier(const uint32_t* __restri
     const int64_t stride = (int64_t)gridDim.x * blockDim.x;
     const int64_t tid = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
     for (int64_t w = tid; w < nwords + 1; w += stride) Lclear[w] = 0u;
-    if (!sweep_sparse(sgate, first, m, fr.sparse_div)) return;
-    uint32_t* cnt = fr.counts + 4 * parity;
+    const bool sparse = sweep_sparse(sgate, first, m, fr.sparse_div);
     const int lane = threadIdx.x & 63;
+    if (sweep_coarse(live, first, sparse, fr)) {
+        // coarse word cw covers the 2^cs L_t words from cw << cs: lane l ORs k =
+        // 2^cs / 64 of them, so coarse bit b is lanes 2b and 2b + 1
+        const int cs = fr.coarse_shift;
+        const int64_t k = (int64_t)1 << (cs - 6);
+        for (int64_t cw = wave_index(); cw < fr.coarse_words; cw += wave_count()) {
+            const int64_t w0 = (cw << cs) + lane * k;
+            uint32_t any = 0;
+            for (int64_t i = 0; i < k; ++i)
+                if (w0 + i < nwords) any |= Lcur[w0 + i];
+            const uint64_t bal = __ballot(any != 0u);
+            uint32_t bits = 0;
+#pragma unroll
+            for (int b = 0; b < 32; ++b) bits |= (uint32_t)(((bal >> (2 * b)) | (bal >> (2 * b + 1))) & 1ull) << b;
+            if (lane == 0) fr.coarse[cw] = bits;
+        }
+    }
+    if (!sparse) return;
+    uint32_t* cnt = fr.counts + 4 * parity;
     // uniform trip count per wave so that every lane takes part in the scan
     const int64_t span = ((nwords + stride - 1) / stride) * stride;
     for (int64_t w0 = tid - lane; w0 < span; w0 += stride) {
@@ -631,9 +665,12 @@ __global__ __launch_bounds__(256) void k_sweep_rows64(
     __shared__ uint32_t sh32[4];
     __shared__ uint32_t s_off[4][33];
     __shared__ int64_t s_x[4][32];
+    __shared__ uint32_t s_coarse[COARSE_WORDS];
     const uint32_t live = sweep_live(gate, gate_thresh, first, n);
     if (!live) return;
     const bool sparse = sweep_sparse(sgate, first, m, fr.sparse_div);
+    const uint32_t* cl = load_coarse(sweep_coarse(live, first, sparse, fr), fr, s_coarse);
+    const int cs = fr.coarse_shift;
     const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
     uint32_t x[DW][4];
     load_sim_words<64, DW>(X, P, lane, x);
@@ -710,7 +747,7 @@ __global__ __launch_bounds__(256) void k_sweep_rows64(
             locate(fn, r_n, e_n);
             in_n = fn < total;
             v_n = in_n ? adj[e_n] : 0;
-            const bool lv = valid && (first || bit_of(Lcur, v) != 0u);
+            const bool lv = valid && (first || in_L(Lcur, cl, cs, v));
             uint64_t mask = __ballot(lv);
             if (!mask) continue;  // no live head: the window needs no hash or threshold
             vis += (uint32_t)__builtin_popcountll(mask);
@@ -880,9 +917,12 @@ __global__ __launch_bounds__(256) void k_sweep_heavy(
     int first, Frontier fr, int parity, const unsigned long long* __restrict__ sgate, int64_t m,
     const uint32_t* __restrict__ fullblk, uint32_t* __restrict__ rtouch) {
     __shared__ unsigned long long sh64[4];
+    __shared__ uint32_t s_coarse[COARSE_WORDS];
     const uint32_t live = sweep_live(gate, gate_thresh, first, n);
     if (!live) return;
     const bool sparse = sweep_sparse(sgate, first, m, fr.sparse_div);
+    const uint32_t* cl = load_coarse(G == 64 && sweep_coarse(live, first, sparse, fr), fr, s_coarse);
+    const int cs = fr.coarse_shift;
     constexpr int RPW = 64 / G;
     const int lane = threadIdx.x & 63, grp = lane / G, p = lane % G;
     uint32_t x[DW][4];
@@ -911,7 +951,7 @@ __global__ __launch_bounds__(256) void k_sweep_heavy(
                     }
                 }
             } else {
-                vis = merge_edges<G, DW, KIND>(b0, b1, adj, eh, thr, ntv, A, Lcur, first, P, lane, p, x, acc);
+                vis = merge_edges<G, DW, KIND>(b0, b1, adj, eh, thr, ntv, A, Lcur, first, P, lane, p, x, acc, cl, cs);
             }
         }
         // vis is uniform over the group; a partial without live edges is never read
