@@ -614,14 +614,14 @@ im_status build_sketch(im_ctx* ctx, const im_csr* graph, const im_probs* probs, 
     sk->fr.sparse_div = o.sparse_div < 0 ? 0u : (o.sparse_div == 0 ? 48u : (uint32_t)o.sparse_div);
     {
         // coarse copy of L_t: at least 256 vertices per bit, at most COARSE_WORDS
-        // words; used by the one-row-per-wave kernels while at most 1/8 of its
+        // words; used by the one-row-per-wave kernels while at most half of its
         // bits (or 64 of them, on small graphs) can be set
         int cs = 8;
         while (((n - 1) >> (cs + 5)) + 1 > COARSE_WORDS) ++cs;
         sk->fr.coarse_shift = cs;
         sk->fr.coarse_words = (int32_t)(((n - 1) >> (cs + 5)) + 1);
         const uint32_t cbits = (uint32_t)(((n - 1) >> cs) + 1);
-        sk->fr.coarse_live = L.G == 64 ? std::max(cbits / 8u, 64u) : 0u;
+        sk->fr.coarse_live = L.G == 64 ? std::max(cbits / 2u, 64u) : 0u;
         ok = ok && sk_alloc(sk, &sk->fr.coarse, sk->fr.coarse_words);
     }
     uint32_t* wc_target = nullptr;
