@@ -541,30 +541,39 @@ __global__ __launch_bounds__(256) void k_sweep_expand(const uint32_t* __restrict
 }
 
 // Sparse sweep: lists the marked rows (W) for the row kernels and clears the
-// marks, with one counter atomic per wave.
+// marks, with one counter atomic per workgroup.
 __global__ __launch_bounds__(256) void k_sweep_compact(const uint32_t* __restrict__ gate, uint32_t gate_thresh,
                                                        const unsigned long long* __restrict__ sgate, int64_t m,
                                                        int first, int64_t n, Frontier fr, int parity) {
     const uint32_t live = sweep_live(gate, gate_thresh, first, n);
     if (!live || !sweep_sparse(sgate, first, m, fr.sparse_div)) return;
     uint32_t* cnt = fr.counts + 4 * parity;
+    __shared__ uint32_t s_wtot[4];
+    __shared__ uint32_t s_base;
     const int64_t nwords = (n + 31) >> 5;
-    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
-    const int64_t tid = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
-    const int lane = threadIdx.x & 63;
-    // uniform trip count per wave so that every lane takes part in the scan
-    const int64_t span = ((nwords + stride - 1) / stride) * stride;
-    for (int64_t w0 = tid - lane; w0 < span; w0 += stride) {
-        const int64_t w = w0 + lane;
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    // 256 words per workgroup and round, one counter atomic per workgroup
+    for (int64_t c0 = (int64_t)blockIdx.x * 256; c0 < nwords; c0 += (int64_t)gridDim.x * 256) {
+        const int64_t w = c0 + threadIdx.x;
         const uint32_t bits = w < nwords ? fr.mark[w] : 0u;
         if (bits) fr.mark[w] = 0u;
-        uint32_t tot;
-        const uint32_t off = wave_excl_scan((uint32_t)__builtin_popcount(bits), &tot);
-        if (!tot) continue;
-        uint32_t base = 0;
-        if (lane == 0) base = atomicAdd(&cnt[1], tot);
-        base = __shfl(base, 0, 64) + off;
-        for (uint32_t b = bits; b; b &= b - 1) fr.W[base++] = (int32_t)(w * 32 + __builtin_ctz(b));
+        uint32_t wtot;
+        const uint32_t off = wave_excl_scan((uint32_t)__builtin_popcount(bits), &wtot);
+        if (lane == 0) s_wtot[wv] = wtot;
+        __syncthreads();
+        uint32_t before = 0, tot = 0;
+#pragma unroll
+        for (int k = 0; k < 4; ++k) {
+            if (k < wv) before += s_wtot[k];
+            tot += s_wtot[k];
+        }
+        if (threadIdx.x == 0 && tot) s_base = atomicAdd(&cnt[1], tot);
+        __syncthreads();
+        if (tot) {
+            uint32_t pos = s_base + before + off;
+            for (uint32_t b = bits; b; b &= b - 1) fr.W[pos++] = (int32_t)(w * 32 + __builtin_ctz(b));
+        }
+        __syncthreads();  // s_wtot and s_base are reused by the next round
     }
 }
 
