@@ -122,6 +122,7 @@ struct im_sketch {
     hipEvent_t ev_indeg = nullptr, ev_rev = nullptr;
     bool rev_ready = false;
     void* rev_tmp = nullptr;  // in-degrees and cursors of the reverse CSR build
+    void* list_tmp = nullptr; // a preparation temporary (per-edge weights, light-row list build)
     std::vector<hipEvent_t> sweep_ev;
     bool time_sweeps = false;
     bool in_place = false;  // sweeps read and write one register buffer
@@ -167,6 +168,7 @@ void sk_release(im_sketch* sk) {
     if (sk->h_gather[1]) (void)hipHostFree(sk->h_gather[1]);
     if (sk->h_small) (void)hipHostFree(sk->h_small);
     if (sk->rev_tmp && sk->ctx) ctx_free(sk->ctx, sk->rev_tmp);
+    if (sk->list_tmp && sk->ctx) ctx_free(sk->ctx, sk->list_tmp);
     for (hipEvent_t e : {sk->ev_a, sk->ev_b, sk->ev_batch[0], sk->ev_batch[1], sk->ev_indeg, sk->ev_rev})
         if (e) (void)hipEventDestroy(e);
     if (sk->aux) (void)hipStreamDestroy(sk->aux);
@@ -683,7 +685,7 @@ im_status build_sketch(im_ctx* ctx, const im_csr* graph, const im_probs* probs, 
                 const float* w = probs->per_edge;
                 void* tmp = nullptr;
                 if (!graph->on_device) {
-                    tmp = ctx_alloc(ctx, 4 * m);
+                    tmp = sk->list_tmp = ctx_alloc(ctx, 4 * m);  // released with the sketch on error
                     if (!tmp) return fail(IM_ERR_OUT_OF_BUDGET, "temporary allocation failed");
                     HIP_TRY(hipMemcpyAsync(tmp, probs->per_edge, 4 * m, hipMemcpyHostToDevice, s));
                     w = (const float*)tmp;
@@ -692,7 +694,10 @@ im_status build_sketch(im_ctx* ctx, const im_csr* graph, const im_probs* probs, 
                 HIP_TRY(launch_edge_thresholds(w, g.thr, m, sk->d_err, s));
                 HIP_TRY(hipMemcpyAsync(sk->h_small, sk->d_err, 4, hipMemcpyDeviceToHost, s));
                 HIP_TRY(hipStreamSynchronize(s));
-                if (tmp) ctx_free(ctx, tmp);
+                if (tmp) {
+                    ctx_free(ctx, tmp);
+                    sk->list_tmp = nullptr;
+                }
                 if (sk->h_small[0] & 4u) return fail(IM_ERR_INVALID_ARG, "a per-edge probability is outside [0, 1]");
             }
         }
@@ -735,15 +740,13 @@ im_status build_sketch(im_ctx* ctx, const im_csr* graph, const im_probs* probs, 
             const size_t a4n = (4 * n + 255) & ~size_t(255), a8n = (8 * (n + 1) + 255) & ~size_t(255);
             const size_t asc = (8 * (nb + 2) + 255) & ~size_t(255);
             // main: flags, positions and scan sums of the light-row list
-            void* pm_ = ctx_alloc(ctx, a4n + a8n + asc);
+            // (held by the sketch, so that an error on the way releases it too)
+            void* pm_ = sk->list_tmp = ctx_alloc(ctx, a4n + a8n + asc);
             // in-degrees and the reverse CSR's temporaries (freed below when the
             // reverse CSR is built on this stream, else once the aux stream is done)
             const bool one_stream = rb_fits(n, m) && !(o.flags & IM_BUILD_ATOMIC_REVERSE);
             sk->rev_tmp = ctx_alloc(ctx, one_stream ? rb_temp_bytes(n, m) : a4n + a8n + asc);
-            if (!pm_ || !sk->rev_tmp) {
-                if (pm_) ctx_free(ctx, pm_);
-                return fail(IM_ERR_OUT_OF_BUDGET, "temporary allocation failed");
-            }
+            if (!pm_ || !sk->rev_tmp) return fail(IM_ERR_OUT_OF_BUDGET, "temporary allocation failed");
             uint32_t* indeg = nullptr;
             if (one_stream) {
                 // a counting sort on the target, with LDS counters only
@@ -775,6 +778,7 @@ im_status build_sketch(im_ctx* ctx, const im_csr* graph, const im_probs* probs, 
             HIP_TRY(hipMemcpyAsync(&g.nlight, lpos + n, 8, hipMemcpyDeviceToHost, s));
             HIP_TRY(hipStreamSynchronize(s));
             ctx_free(ctx, pm_);
+            sk->list_tmp = nullptr;
             if (one_stream) {
                 ctx_free(ctx, sk->rev_tmp);
                 sk->rev_tmp = nullptr;

@@ -222,6 +222,7 @@ def test_er_small_workload(hf, ctx):
 
 def test_invalid_inputs_rejected(hf, ctx):
     g = GRAPHS["er40"]
+    held = ctx.bytes_in_use()
     with pytest.raises(hf.ImError) as e:
         _build(hf, ctx, g, "const", 0.1, 6)
     assert e.value.status == -1
@@ -246,6 +247,8 @@ def test_invalid_inputs_rejected(hf, ctx):
     with pytest.raises(hf.ImError) as e:
         _build(hf, ctx, g, "const", 0.1, 8, heavy_degree=2, piece_edges=2049)
     assert e.value.status == -1
+    # a rejected build leaves nothing allocated, temporaries included
+    assert ctx.bytes_in_use() == held
     sk = _build(hf, ctx, g, "const", 0.1, 8)
     try:
         with pytest.raises(hf.ImError):
