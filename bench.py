@@ -344,6 +344,8 @@ def main():
                     help="start with one 1 GiB device copy (the counter calibration of the traffic summary)")
     ap.add_argument("--summarize-pmc", nargs=2, metavar=("FETCH_DIR", "WRITE_DIR"),
                     help="print the traffic summary of two rocprofv3 --pmc output folders and exit")
+    ap.add_argument("--batch-only", action="store_true",
+                    help="run only the batched-vs-plain comparison and print its object (for profiling)")
     args = ap.parse_args()
     if args.summarize_pmc:
         cmd = ("timeout -s KILL 600 rocprofv3 --kernel-trace --pmc {counter} --output-format csv -d {out} -o run "
@@ -360,6 +362,10 @@ def main():
     import torch
 
     import paper_2105_04023_amd as hf
+
+    if args.batch_only:
+        print(json.dumps({"batched": batch_leg(hf, hf.Context(0), args.steps, args.warmup)}), flush=True)
+        return
     import synth
 
     t = time.perf_counter()
