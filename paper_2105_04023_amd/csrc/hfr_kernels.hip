@@ -938,6 +938,27 @@ __global__ __launch_bounds__(256) void k_sweep_heavy(
     load_sim_words<G, DW>(X, P, p, x);
     const uint32_t ntv = to_vgpr(0u - thr_const);
     unsigned long long my_vis = 0;
+    // writes the partial row of piece pc of split row r (the merge of its live
+    // edges, or of a run of consecutive pieces of r that starts at pc) and its
+    // flag; vis is uniform over the group, a partial without live edges is
+    // never read and a piece without a flag of this sweep is skipped by the
+    // fix-up
+    auto finish_piece = [&](const int64_t pc, const int32_t r, const uint32_t vis, const Acc (&acc)[DW]) {
+        if (vis > 0) {
+#pragma unroll
+            for (int k = 0; k < DW; ++k) {
+                const int q = k * G + p;
+                if (q < P) part[pc * P + q] = acc[k].e | acc[k].o;
+            }
+        }
+        if (p == 0) {
+            if (vis > 0) {
+                part_any[pc] = fr.stamp;
+                rtouch[r] = fr.stamp;  // the row has a piece to combine in this sweep
+            }
+            my_vis += vis;
+        }
+    };
     // merges piece pc of split row r, edges [b0, b1) (uniform over the group);
     // wm: its 64-edge windows to scan, all of them when 0; skip: the row is
     // blocked in every sample
@@ -963,21 +984,50 @@ __global__ __launch_bounds__(256) void k_sweep_heavy(
                 vis = merge_edges<G, DW, KIND>(b0, b1, adj, eh, thr, ntv, A, Lcur, first, P, lane, p, x, acc, cl, cs);
             }
         }
-        // vis is uniform over the group; a partial without live edges is never read
-        if (vis > 0) {
-#pragma unroll
-            for (int k = 0; k < DW; ++k) {
-                const int q = k * G + p;
-                if (q < P) part[pc * P + q] = acc[k].e | acc[k].o;
-            }
-        }
-        if (p == 0) {
-            part_any[pc] = vis > 0 ? fr.stamp : 0u;
-            if (vis > 0) rtouch[r] = fr.stamp;  // the row has a piece to combine in this sweep
-            my_vis += vis;
-        }
+        finish_piece(pc, r, vis, acc);
     };
-    if (!sparse) {
+    if (!sparse && G == 64) {
+        // each wave takes `span` consecutive pieces (its share, <= 64), with their
+        // table entries loaded lane-parallel; a run of consecutive pieces of one
+        // row is merged into one partial row (the run's first piece's), so the
+        // fix-up of a row with many pieces reads a few partials
+        int64_t span = (npieces + wave_count() - 1) / wave_count();
+        span = span < 1 ? 1 : (span > 64 ? 64 : span);
+        for (int64_t base = wave_index() * span; base < npieces; base += wave_count() * span) {
+            const int cnt = (int)(npieces - base < span ? npieces - base : span);
+            int32_t rl = 0;
+            int64_t b0l = 0, b1l = 0;
+            bool skl = false;
+            if (lane < cnt) {
+                rl = prow[base + lane];
+                b0l = pe0[base + lane];
+                b1l = pe1[base + lane];
+                skl = fullblk && bit_of(fullblk, hrow[rl]) != 0u;
+            }
+            const uint64_t skipm = __ballot(skl);
+            Acc acc[DW];
+#pragma unroll
+            for (int k = 0; k < DW; ++k) acc[k].e = acc[k].o = 0u;
+            uint32_t vis = 0;
+            int first_j = 0;
+            int32_t run_r = __shfl(rl, 0, 64);
+            for (int j = 0; j < cnt; ++j) {
+                const int32_t r = __shfl(rl, j, 64);
+                if (r != run_r) {
+                    finish_piece(base + first_j, run_r, vis, acc);
+#pragma unroll
+                    for (int k = 0; k < DW; ++k) acc[k].e = acc[k].o = 0u;
+                    vis = 0;
+                    first_j = j;
+                    run_r = r;
+                }
+                if (!((skipm >> j) & 1ull))
+                    vis += merge_edges<G, DW, KIND>(__shfl(b0l, j, 64), __shfl(b1l, j, 64), adj, eh, thr, ntv, A,
+                                                    Lcur, first, P, lane, p, x, acc, cl, cs);
+            }
+            finish_piece(base + first_j, run_r, vis, acc);
+        }
+    } else if (!sparse) {
         // a group's pieces are i, i + stride, ...; the next piece's table entry is
         // loaded while the current piece is merged
         const int64_t stride = wave_count() * RPW;
