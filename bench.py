@@ -39,17 +39,17 @@ def heavy_launch_bytes(rec, J, wc, m_heavy, npieces):
 
     Per edge visited with a live head: the neighbour's row (J bytes), the edge hash (4)
     and, for the weighted cascade, the target's threshold (4).  A dense launch also reads
-    every split-row out-edge id (4 m_heavy) and its piece table (20 B per piece) and
-    writes a flag per piece (4).  The partial rows (J bytes per piece with a live edge)
-    are not counted: how many pieces had one is not logged, and even when all do they
-    are under 1% of the bytes.  A launch past the stopping rule moves nothing.
+    every split-row out-edge id (4 m_heavy) and its piece table (20 B per piece).  The
+    partial rows and flags it writes (J + 4 bytes per run of a row's pieces with a live
+    edge) are not counted: how many there were is not logged, and they are under 1% of the
+    bytes.  A launch past the stopping rule moves nothing.
     """
     if not rec["ran"]:
         return 0
     hv = rec["visits"] - rec["light_visits"]
     b = hv * (J + 4 + (4 if wc else 0))
     if not rec["sparse"]:
-        b += 4 * m_heavy + 24 * npieces
+        b += 4 * m_heavy + 20 * npieces
     return b
 
 

@@ -30,8 +30,8 @@ def test_heavy_launch_bytes(bench):
     # per live-head visit: the head's row, the edge hash and (weighted cascade) the threshold
     assert bench.heavy_launch_bytes(sparse, J, False, m_heavy, npieces) == 500 * (J + 4)
     assert bench.heavy_launch_bytes(sparse, J, True, m_heavy, npieces) == 500 * (J + 8)
-    # a dense launch also reads every split-row edge id and the piece table, writes the flags
-    assert bench.heavy_launch_bytes(dense, J, True, m_heavy, npieces) == 500 * (J + 8) + 4 * m_heavy + 24 * npieces
+    # a dense launch also reads every split-row edge id and the piece table
+    assert bench.heavy_launch_bytes(dense, J, True, m_heavy, npieces) == 500 * (J + 8) + 4 * m_heavy + 20 * npieces
     assert bench.heavy_launch_bytes(idle, J, True, m_heavy, npieces) == 0
 
 
