@@ -215,7 +215,9 @@ IM_API im_status im_sketch_get_trace(const im_sketch* sk, int64_t* live_counts, 
  * kernel, heavy_ms that of the split-row piece kernel, sweep_ms that of all
  * kernels of the sweep, from HIP events on the context stream; light_visits the edges
  * with a live head the row kernel visited, visits those of the whole sweep, live_next
- * |L_{t+1}|.  ran = 0 marks a launch past the stopping rule (it returned at
+ * |L_{t+1}|; light_merged and merged count the visited edges whose head's row was
+ * merged, i.e. those live in at least one of the R samples (an edge live in none is
+ * skipped after its live test, its head's row is not read).  ran = 0 marks a launch past the stopping rule (it returned at
  * once).  simulate numbers the Simulate calls of the sketch (0 = build,
  * later ones are rebuilds inside im_select_seeds). */
 typedef struct im_sweep_rec {
@@ -231,6 +233,8 @@ typedef struct im_sweep_rec {
     int64_t live_next; /* |L_{t+1}| */
     int32_t sparse;    /* 1 if the sweep visited only the rows next to L_t */
     int32_t reserved;
+    int64_t light_merged; /* edges of light_visits whose head's row was merged */
+    int64_t merged;       /* the same over the whole sweep */
 } im_sweep_rec;
 
 /* Copies up to cap records of the sweep log; returns the number copied. */

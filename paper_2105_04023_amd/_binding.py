@@ -70,7 +70,8 @@ class im_sweep_rec(ctypes.Structure):
     _fields_ = [("simulate", ctypes.c_int32), ("sweep", ctypes.c_int32), ("ran", ctypes.c_int32),
                 ("kernel_ms", ctypes.c_float), ("sweep_ms", ctypes.c_float), ("heavy_ms", ctypes.c_float),
                 ("light_visits", ctypes.c_int64), ("visits", ctypes.c_int64), ("live", ctypes.c_int64),
-                ("live_next", ctypes.c_int64), ("sparse", ctypes.c_int32), ("reserved", ctypes.c_int32)]
+                ("live_next", ctypes.c_int64), ("sparse", ctypes.c_int32), ("reserved", ctypes.c_int32),
+                ("light_merged", ctypes.c_int64), ("merged", ctypes.c_int64)]
 
 
 class im_select_stats(ctypes.Structure):

@@ -66,6 +66,7 @@ namespace {
 
 constexpr int RING = 256;         // sweeps held by the counter ring
 constexpr int MAX_BATCH = 64;     // sweeps per batch
+constexpr int GATHER = 6;         // counts gathered per sweep (k_gather_counts)
 constexpr int DEFAULT_HEAVY = 64;
 constexpr int DEFAULT_PIECE = 256;
 constexpr int BFS_CHUNK = 256;
@@ -98,7 +99,7 @@ struct im_sketch {
     Frontier fr{};
     uint32_t* cnt_ring = nullptr;
     unsigned long long* vis_ring = nullptr;
-    unsigned long long* gather = nullptr;  // device [2][3 * MAX_BATCH]
+    unsigned long long* gather = nullptr;  // device [2][GATHER * MAX_BATCH]
     uint32_t* part = nullptr;
     uint32_t* part_any = nullptr;
     uint32_t* rtouch = nullptr;
@@ -207,7 +208,7 @@ size_t bytes_needed(int64_t n, int64_t m, int32_t R, im_prob_kind kind) {
     t += 3 * al((size_t)n * L.P * 4);             // register buffers
     const int64_t words = (n + 31) / 32 + 1;
     t += 3 * al(4 * words);
-    t += al((size_t)RING * NSLOT * SLOT_U32 * 4) + al((size_t)3 * RING * NSLOT * SLOT_U64 * 8) + al(64 * MAX_BATCH);
+    t += al((size_t)RING * NSLOT * SLOT_U32 * 4) + al((size_t)3 * RING * NSLOT * SLOT_U64 * 8) + al(16 * GATHER * MAX_BATCH);
     // split rows: bounded by m / heavy_degree rows and m / piece + rows pieces
     const int64_t nh = m / DEFAULT_HEAVY + 1, np = m / DEFAULT_PIECE + nh + 1;
     t += al(4 * nh) + al(8 * (nh + 1)) + al(8 * nh) + al(4 * np) + 2 * al(8 * np) + al((size_t)np * L.P * 4) +
@@ -227,7 +228,8 @@ size_t bytes_needed(int64_t n, int64_t m, int32_t R, im_prob_kind kind) {
 
 // Sums of the live-count slots of sweeps [t0+1, t0+nb], of the row-kernel
 // and split-row-kernel visit slots and of S_t for sweeps [t0, t0+nb-1] into
-// out[4i..4i+3].
+// out[GATHER i .. GATHER i + 3], and of the rows merged by the two kernels
+// (word 1 of their visit slots) into out[GATHER i + 4], out[GATHER i + 5].
 // The visit ring holds RING row-kernel entries followed by RING split-row ones.
 __global__ void k_gather_counts(const uint32_t* __restrict__ cnt, const unsigned long long* __restrict__ vis,
                                 int64_t t0, int nb, unsigned long long* out) {
@@ -237,17 +239,22 @@ __global__ void k_gather_counts(const uint32_t* __restrict__ cnt, const unsigned
     const unsigned long long* v = vis + ((t0 + i) % RING) * NSLOT * SLOT_U64;
     const unsigned long long* vh = v + (size_t)RING * NSLOT * SLOT_U64;
     const unsigned long long* sm = vis + (2 * (size_t)RING + (t0 + i) % RING) * NSLOT * SLOT_U64;
-    unsigned long long sc = 0, sv = 0, sh = 0, ss = 0;
+    unsigned long long sc = 0, sv = 0, sh = 0, ss = 0, mv = 0, mh = 0;
     for (int k = 0; k < NSLOT; ++k) {
         sc += c[k * SLOT_U32];
         sv += v[k * SLOT_U64];
         sh += vh[k * SLOT_U64];
         ss += sm[k * SLOT_U64];
+        mv += v[k * SLOT_U64 + 1];
+        mh += vh[k * SLOT_U64 + 1];
     }
-    out[4 * i] = sc;
-    out[4 * i + 1] = sv;
-    out[4 * i + 2] = sh;
-    out[4 * i + 3] = ss;  // S_t, the in-degree sum of L_t (0 for t = 0)
+    unsigned long long* o = out + GATHER * i;
+    o[0] = sc;
+    o[1] = sv;
+    o[2] = sh;
+    o[3] = ss;  // S_t, the in-degree sum of L_t (0 for t = 0)
+    o[4] = mv;
+    o[5] = mh;
 }
 
 // Zeroes the live-count slots of sweeps [t0+1, t0+nb] and the visit slots of
@@ -282,7 +289,7 @@ struct SimResult {
     int sweeps;
     int64_t visits;
     double ms;
-    std::vector<int64_t> live, vis, vis_light;
+    std::vector<int64_t> live, vis, vis_light, mrg, mrg_light;  // mrg: rows merged
     std::vector<char> sparse;
 };
 
@@ -420,10 +427,10 @@ im_status run_simulate(im_sketch* sk, int ia, int ib, const uint32_t* blk, SimRe
             if (eb) HIP_TRY(hipEventRecord(eb, s));
         }
         hipLaunchKernelGGL(k_gather_counts, dim3(1), dim3(64), 0, s, sk->cnt_ring, sk->vis_ring, t, nb,
-                           sk->gather + 4 * MAX_BATCH * batch_slot);
+                           sk->gather + GATHER * MAX_BATCH * batch_slot);
         HIP_TRY(hipGetLastError());
-        HIP_TRY(hipMemcpyAsync(sk->h_gather[batch_slot], sk->gather + 4 * MAX_BATCH * batch_slot,
-                               sizeof(unsigned long long) * 4 * nb, hipMemcpyDeviceToHost, s));
+        HIP_TRY(hipMemcpyAsync(sk->h_gather[batch_slot], sk->gather + GATHER * MAX_BATCH * batch_slot,
+                               sizeof(unsigned long long) * GATHER * nb, hipMemcpyDeviceToHost, s));
         HIP_TRY(hipEventRecord(sk->ev_batch[batch_slot], s));
         batch_t0[batch_slot] = t;
         batch_nb[batch_slot] = nb;
@@ -437,10 +444,13 @@ im_status run_simulate(im_sketch* sk, int ia, int ib, const uint32_t* blk, SimRe
         HIP_TRY(hipEventSynchronize(sk->ev_batch[rs]));
         --inflight;
         for (int i = 0; i < batch_nb[rs]; ++i) {
-            const int64_t live = (int64_t)sk->h_gather[rs][4 * i];
-            const int64_t vis_l = (int64_t)sk->h_gather[rs][4 * i + 1];
-            const int64_t vis = vis_l + (int64_t)sk->h_gather[rs][4 * i + 2];
-            const int64_t st_sum = (int64_t)sk->h_gather[rs][4 * i + 3];
+            const unsigned long long* gi = sk->h_gather[rs] + GATHER * i;
+            const int64_t live = (int64_t)gi[0];
+            const int64_t vis_l = (int64_t)gi[1];
+            const int64_t vis = vis_l + (int64_t)gi[2];
+            const int64_t st_sum = (int64_t)gi[3];
+            res->mrg_light.push_back((int64_t)gi[4]);
+            res->mrg.push_back((int64_t)(gi[4] + gi[5]));
             const int64_t tt = batch_t0[rs] + i;
             res->vis.push_back(vis);
             res->vis_light.push_back(vis_l);
@@ -462,6 +472,8 @@ im_status run_simulate(im_sketch* sk, int ia, int ib, const uint32_t* blk, SimRe
     res->live.resize(final_sweeps + 1);
     res->vis.resize(final_sweeps);
     res->vis_light.resize(final_sweeps);
+    res->mrg.resize(final_sweeps);
+    res->mrg_light.resize(final_sweeps);
     res->sparse.resize(final_sweeps);
     res->visits = 0;
     for (int64_t v : res->vis) res->visits += v;
@@ -485,6 +497,8 @@ im_status run_simulate(im_sketch* sk, int ia, int ib, const uint32_t* blk, SimRe
             if (rec.ran) {
                 rec.light_visits = res->vis_light[t];
                 rec.visits = res->vis[t];
+                rec.light_merged = res->mrg_light[t];
+                rec.merged = res->mrg[t];
                 rec.live = res->live[t];
                 rec.live_next = res->live[t + 1];
                 rec.sparse = res->sparse[t];
@@ -610,7 +624,7 @@ im_status build_sketch(im_ctx* ctx, const im_csr* graph, const im_probs* probs, 
     ok = ok && sk_alloc(sk, &sk->fr.mark, words) && sk_alloc(sk, &sk->fr.items, n + m / 256 + 64) &&
          sk_alloc(sk, &sk->fr.W, n) && sk_alloc(sk, &sk->fr.counts, 8);
     ok = ok && sk_alloc(sk, &sk->cnt_ring, (size_t)RING * NSLOT * SLOT_U32) &&
-         sk_alloc(sk, &sk->vis_ring, (size_t)3 * RING * NSLOT * SLOT_U64) && sk_alloc(sk, &sk->gather, 8 * MAX_BATCH);
+         sk_alloc(sk, &sk->vis_ring, (size_t)3 * RING * NSLOT * SLOT_U64) && sk_alloc(sk, &sk->gather, 2 * GATHER * MAX_BATCH);
     ok = ok && sk_alloc(sk, &sk->d_err, 4) && sk_alloc(sk, &sk->d_heavy_counts, 4) && sk_alloc(sk, &sk->d_flag, 4);
     sk->fr.chunk = 256;
     sk->fr.sparse_div = o.sparse_div < 0 ? 0u : (o.sparse_div == 0 ? 48u : (uint32_t)o.sparse_div);
@@ -633,8 +647,8 @@ im_status build_sketch(im_ctx* ctx, const im_csr* graph, const im_probs* probs, 
         sk_release(sk);
         return fail(IM_ERR_OUT_OF_BUDGET, "device allocation failed");
     }
-    if (hipHostMalloc((void**)&sk->h_gather[0], 32 * MAX_BATCH) != hipSuccess ||
-        hipHostMalloc((void**)&sk->h_gather[1], 32 * MAX_BATCH) != hipSuccess ||
+    if (hipHostMalloc((void**)&sk->h_gather[0], 8 * GATHER * MAX_BATCH) != hipSuccess ||
+        hipHostMalloc((void**)&sk->h_gather[1], 8 * GATHER * MAX_BATCH) != hipSuccess ||
         hipHostMalloc((void**)&sk->h_small, 64) != hipSuccess) {
         sk_release(sk);
         return fail(IM_ERR_DEVICE, "pinned host allocation failed");
@@ -770,6 +784,8 @@ im_status build_sketch(im_ctx* ctx, const im_csr* graph, const im_probs* probs, 
                 HIP_TRY(launch_gather_u32(wc_target, g.adj, m, g.thr, s));
                 g.kind = THR_EDGE;
             }
+            // samples and thresholds are final: flag the edges live in no sample
+            HIP_TRY(launch_dead_edges(g, sk->X, R, s));
             // the row kernel's list of rows with 1..heavy_deg out-edges
             uint32_t* lflags = (uint32_t*)pm_;
             int64_t* lpos = (int64_t*)((char*)pm_ + a4n);

@@ -205,16 +205,27 @@ constexpr int UB = 8;  // neighbour rows in flight per wave (twice that with one
 
 // G = 64: merges one window of up to 64 out-edges, lane l holding edge e (in:
 // the edge exists) with head v, `mask` the lanes whose head is in L_t (not
-// empty).  The rows of up to UB live heads are loaded back-to-back before they
-// are merged.
+// empty).  Edges live in no sample are dropped from the mask; the rows of up
+// to UB remaining heads are loaded back-to-back before they are merged.
+// Returns the number of rows merged.
 template <int DW, int KIND>
-DEVI void merge_window64(uint64_t mask, int64_t e, bool in, int32_t v, const uint32_t* __restrict__ eh,
-                         const uint32_t* __restrict__ thr, uint32_t ntv, const uint32_t* __restrict__ A, int P,
+DEVI uint32_t merge_window64(uint64_t mask, int64_t e, bool in, int32_t v, const uint32_t* __restrict__ eh,
+                             const uint32_t* __restrict__ thr, uint32_t ntv, const uint32_t* __restrict__ A, int P,
                          int lane, const uint32_t (&x)[DW][4], Acc (&acc)[DW]) {
-    const uint32_t hh = in ? eh[e] : 0u;
-    uint32_t tt = 0u;
-    if constexpr (KIND == THR_TARGET) tt = in ? thr[v] : 0u;
-    if constexpr (KIND == THR_EDGE) tt = in ? thr[e] : 0u;
+    const uint32_t hraw = in ? eh[e] : 0u;
+    mask &= ~__ballot((hraw & DEAD_EDGE) != 0u);  // edges live in no sample merge nothing
+    if (!mask) return 0u;
+    const uint32_t merged = (uint32_t)__builtin_popcountll(mask);
+    const uint32_t hh = hraw & ~DEAD_EDGE;
+    uint32_t ntt = 0u;  // negated threshold
+    if constexpr (KIND == THR_TARGET) ntt = 0u - (in ? thr[v] : 0u);
+    if constexpr (KIND == THR_EDGE) ntt = 0u - (in ? thr[e] : 0u);
+    // dword of a neighbour row this lane loads (lanes past the row load its last dword; their
+    // results are never stored), unsigned so that a row load takes the row base as its
+    // scalar address
+    uint32_t qo[DW];
+#pragma unroll
+    for (int i = 0; i < DW; ++i) qo[i] = (uint32_t)(i * 64 + lane < P ? i * 64 + lane : P - 1);
     // batches of NB live edges, NB the smallest of 1, 2, 4, UB that covers the
     // edges left (capped at UB): unused slots repeat the last edge (max-merge is
     // idempotent), so every load of a batch is issued without a branch
@@ -228,25 +239,21 @@ DEVI void merge_window64(uint64_t mask, int64_t e, bool in, int32_t v, const uin
             idx[b] = last;
             mask &= mask - 1;
         }
-        // lanes past the row (q >= P) load a valid dword of it; their
-        // results are never stored
         uint32_t d[NB][DW];
 #pragma unroll
         for (int b = 0; b < NB; ++b) {
             const int64_t vb = __builtin_amdgcn_readlane(v, idx[b]);
             const uint32_t* __restrict__ row = A + vb * P;
 #pragma unroll
-            for (int i = 0; i < DW; ++i) {
-                const int q = i * 64 + lane;
-                d[b][i] = row[q < P ? q : P - 1];
-            }
+            for (int i = 0; i < DW; ++i) d[b][i] = row[qo[i]];
         }
         __builtin_amdgcn_sched_barrier(0);
 #pragma unroll
         for (int b = 0; b < NB; ++b) {
             const uint32_t hb = (uint32_t)__builtin_amdgcn_readlane((int)hh, idx[b]);
             uint32_t nt = ntv;
-            if constexpr (KIND != THR_CONST) nt = 0u - (uint32_t)__builtin_amdgcn_readlane((int)tt, idx[b]);
+            // in a VGPR, so that each live test is one v_xad_u32 with hb as its scalar operand
+            if constexpr (KIND != THR_CONST) nt = to_vgpr((uint32_t)__builtin_amdgcn_readlane((int)ntt, idx[b]));
 #pragma unroll
             for (int i = 0; i < DW; ++i) merge_live(acc[i], d[b][i], x[i][0], x[i][1], x[i][2], x[i][3], hb, nt);
         }
@@ -264,6 +271,7 @@ DEVI void merge_window64(uint64_t mask, int64_t e, bool in, int32_t v, const uin
         else
             batch(std::integral_constant<int, 1>{});
     }
+    return merged;
 }
 
 // G = 64 (one row per wave): the row's out-edges are read NW windows of 64
@@ -276,7 +284,8 @@ template <int DW, int KIND>
 DEVI uint32_t merge_edges64(int64_t eb, int64_t ee, const int32_t* __restrict__ adj, const uint32_t* __restrict__ eh,
                             const uint32_t* __restrict__ thr, uint32_t ntv, const uint32_t* __restrict__ A,
                             const uint32_t* __restrict__ Lcur, int first, int P, int lane,
-                            const uint32_t (&x)[DW][4], Acc (&acc)[DW], const uint32_t* cl = nullptr, int cs = 0) {
+                            const uint32_t (&x)[DW][4], Acc (&acc)[DW], const uint32_t* cl = nullptr, int cs = 0,
+                            unsigned long long* mrg = nullptr) {
     uint32_t vis = 0;
     for (int64_t c0 = eb; c0 < ee; c0 += 64 * NW) {
         int32_t vw[NW];
@@ -293,7 +302,9 @@ DEVI uint32_t merge_edges64(int64_t eb, int64_t ee, const int32_t* __restrict__ 
         for (int w = 0; w < NW; ++w) {
             if (!mw[w]) continue;  // no live head: the window needs no hash or threshold
             vis += (uint32_t)__builtin_popcountll(mw[w]);
-            merge_window64<DW, KIND>(mw[w], c0 + 64 * w + lane, inw[w], vw[w], eh, thr, ntv, A, P, lane, x, acc);
+            const uint32_t mg =
+                merge_window64<DW, KIND>(mw[w], c0 + 64 * w + lane, inw[w], vw[w], eh, thr, ntv, A, P, lane, x, acc);
+            if (mrg) *mrg += mg;
         }
     }
     return vis;
@@ -307,7 +318,7 @@ DEVI uint32_t merge_marked_windows64(int64_t eb, int64_t ee, uint32_t wm, const 
                                      const uint32_t* __restrict__ eh, const uint32_t* __restrict__ thr, uint32_t ntv,
                                      const uint32_t* __restrict__ A, const uint32_t* __restrict__ Lcur, int first,
                                      int P, int lane, const uint32_t (&x)[DW][4], Acc (&acc)[DW],
-                                     const uint32_t* cl = nullptr, int cs = 0) {
+                                     const uint32_t* cl = nullptr, int cs = 0, unsigned long long* mrg = nullptr) {
     uint32_t vis = 0;
     while (wm) {
         int64_t w0[NW];
@@ -331,7 +342,9 @@ DEVI uint32_t merge_marked_windows64(int64_t eb, int64_t ee, uint32_t wm, const 
         for (int w = 0; w < NW; ++w) {
             if (!mw[w]) continue;
             vis += (uint32_t)__builtin_popcountll(mw[w]);
-            merge_window64<DW, KIND>(mw[w], w0[w] + lane, inw[w], vw[w], eh, thr, ntv, A, P, lane, x, acc);
+            const uint32_t mg =
+                merge_window64<DW, KIND>(mw[w], w0[w] + lane, inw[w], vw[w], eh, thr, ntv, A, P, lane, x, acc);
+            if (mrg) *mrg += mg;
         }
     }
     return vis;
@@ -345,7 +358,8 @@ template <int G, int DW, int KIND>
 DEVI uint32_t merge_edges_grp(int64_t eb, int64_t ee, const int32_t* __restrict__ adj,
                               const uint32_t* __restrict__ eh, const uint32_t* __restrict__ thr, uint32_t ntv,
                               const uint32_t* __restrict__ A, const uint32_t* __restrict__ Lcur, int first, int P,
-                              int lane, int p, const uint32_t (&x)[DW][4], Acc (&acc)[DW]) {
+                              int lane, int p, const uint32_t (&x)[DW][4], Acc (&acc)[DW],
+                              unsigned long long* mrg = nullptr) {
     const int gbase = lane - p;
     constexpr uint64_t GM = (1ull << G) - 1ull;
     uint32_t vis = 0;
@@ -358,7 +372,11 @@ DEVI uint32_t merge_edges_grp(int64_t eb, int64_t ee, const int32_t* __restrict_
         uint64_t mask = (__ballot(lv) >> gbase) & GM;
         if (!mask) continue;  // no live head: the window needs no hash or threshold
         vis += (uint32_t)__builtin_popcountll(mask);
-        const uint32_t hh = eh[ec];
+        const uint32_t hraw = eh[ec];
+        mask &= ~(__ballot((hraw & DEAD_EDGE) != 0u) >> gbase);  // edges live in no sample merge nothing
+        if (!mask) continue;
+        if (mrg) *mrg += (uint32_t)__builtin_popcountll(mask);
+        const uint32_t hh = hraw & ~DEAD_EDGE;
         uint32_t tt = 0u;
         if constexpr (KIND == THR_TARGET) tt = thr[v];
         if constexpr (KIND == THR_EDGE) tt = thr[ec];
@@ -415,11 +433,12 @@ template <int G, int DW, int KIND>
 DEVI uint32_t merge_edges(int64_t eb, int64_t ee, const int32_t* __restrict__ adj, const uint32_t* __restrict__ eh,
                           const uint32_t* __restrict__ thr, uint32_t ntv, const uint32_t* __restrict__ A,
                           const uint32_t* __restrict__ Lcur, int first, int P, int lane, int p,
-                          const uint32_t (&x)[DW][4], Acc (&acc)[DW], const uint32_t* cl = nullptr, int cs = 0) {
+                          const uint32_t (&x)[DW][4], Acc (&acc)[DW], const uint32_t* cl = nullptr, int cs = 0,
+                          unsigned long long* mrg = nullptr) {
     if constexpr (G == 64)
-        return merge_edges64<DW, KIND>(eb, ee, adj, eh, thr, ntv, A, Lcur, first, P, lane, x, acc, cl, cs);
+        return merge_edges64<DW, KIND>(eb, ee, adj, eh, thr, ntv, A, Lcur, first, P, lane, x, acc, cl, cs, mrg);
     else
-        return merge_edges_grp<G, DW, KIND>(eb, ee, adj, eh, thr, ntv, A, Lcur, first, P, lane, p, x, acc);
+        return merge_edges_grp<G, DW, KIND>(eb, ee, adj, eh, thr, ntv, A, Lcur, first, P, lane, p, x, acc, mrg);
 }
 
 template <int G, int DW>
@@ -441,7 +460,8 @@ DEVI bool sweep_row(int64_t u, const int64_t* __restrict__ xadj, const int32_t* 
                     const uint32_t (&x)[DW][4], const uint32_t* __restrict__ A, uint32_t* __restrict__ B,
                     const uint32_t* __restrict__ Lcur, uint32_t* __restrict__ Lnext, const uint32_t* __restrict__ blk,
                     const uint32_t* __restrict__ fullblk, int64_t heavy_deg, int P, int PW, int first,
-                    bool dense_word, int lane, int p, unsigned long long& my_vis) {
+                    bool dense_word, int lane, int p, unsigned long long& my_vis,
+                    unsigned long long* my_mrg = nullptr) {
     const int64_t eb = xadj[u], ee = xadj[u + 1];
     const bool inL = first ? false : bit_of(Lcur, u) != 0;
     bool active = ee - eb <= heavy_deg && (ee > eb || inL) && !(fullblk && bit_of(fullblk, u));
@@ -464,8 +484,13 @@ DEVI bool sweep_row(int64_t u, const int64_t* __restrict__ xadj, const int32_t* 
     Acc acc[DW];
 #pragma unroll
     for (int i = 0; i < DW; ++i) acc[i].e = acc[i].o = 0u;
-    const uint32_t vis = merge_edges<G, DW, KIND>(eb, ee, adj, eh, thr, ntv, A, Lcur, first, P, lane, p, x, acc);
-    if (p == 0) my_vis += vis;
+    unsigned long long mg = 0;
+    const uint32_t vis =
+        merge_edges<G, DW, KIND>(eb, ee, adj, eh, thr, ntv, A, Lcur, first, P, lane, p, x, acc, nullptr, 0, &mg);
+    if (p == 0) {
+        my_vis += vis;
+        if (my_mrg) *my_mrg += mg;
+    }
     if (vis == 0 && !inL) return false;
     bool ch = false;
     uint32_t nw[DW];
@@ -818,12 +843,22 @@ DEVI unsigned long long bfs_expand_entries(int64_t b0, int64_t b1, int64_t bstep
             const int64_t e = w0 + p;
             const bool in = e < e1;
             const int32_t wv = in ? adj[e] : 0;
-            const uint32_t hh = in ? eh[e] : 0u;
+            const uint32_t hraw = in ? eh[e] : 0u;
+            const uint32_t hh = hraw & ~DEAD_EDGE;
             uint32_t tt = 0u;
             if constexpr (KIND == THR_TARGET) tt = in ? thr[wv] : 0u;
             if constexpr (KIND == THR_EDGE) tt = in ? thr[e] : 0u;
             const int nwin = (int)(e1 - w0 < G ? e1 - w0 : G);
-            for (int j = 0; j < nwin; ++j) {
+            // G = 64: only the window's edges live in some sample (an edge live in
+            // none reaches nothing); groups scan their whole window
+            uint64_t todo = 0;
+            if constexpr (G == 64) todo = __ballot(in && (hraw & DEAD_EDGE) == 0u);
+            for (int jj = 0; G == 64 ? todo != 0ull : jj < nwin; ++jj) {
+                int j = jj;
+                if constexpr (G == 64) {
+                    j = __builtin_ctzll(todo);
+                    todo &= todo - 1;
+                }
                 uint32_t hb, nt = ntv;
                 int32_t wj;
                 if constexpr (G == 64) {

@@ -33,7 +33,7 @@ struct DevGraph {
     int64_t n = 0, m = 0;
     int64_t* xadj = nullptr;
     int32_t* adj = nullptr;
-    uint32_t* eh = nullptr;   // 31-bit edge hash per edge
+    uint32_t* eh = nullptr;   // 31-bit edge hash per edge; bit 31 (DEAD_EDGE) marks an edge live in no sample
     uint32_t* thr = nullptr;  // per target vertex (WC) or per edge
     uint32_t thr_const = 0;
     int kind = THR_CONST;
@@ -56,6 +56,11 @@ struct DevGraph {
     int64_t nlight = 0;
     int64_t piece_edges = 256;
 };
+
+// Flag in an edge hash: the edge is live in none of the J samples (no j with
+// (X_j xor h) < its threshold), so no merge of the Simulate needs the head's row.
+// Every live test masks it off; hashes without it merge as usual.
+constexpr uint32_t DEAD_EDGE = 0x80000000u;
 
 constexpr int COARSE_WORDS = 2048;  // coarse copy of L_t: 8 KiB of LDS per workgroup
 
@@ -137,6 +142,8 @@ hipError_t launch_wc_thresholds(const uint32_t* indeg, uint32_t* thr, int64_t n,
 hipError_t launch_gather_u32(const uint32_t* src, const int32_t* idx, int64_t m, uint32_t* out, hipStream_t s);
 hipError_t launch_edge_thresholds(const float* w, uint32_t* thr, int64_t m, uint32_t* err, hipStream_t s);
 hipError_t launch_sim_words(uint32_t* X, uint32_t* HJ, int J, uint32_t seed, hipStream_t s);
+// Sets DEAD_EDGE in the hash of every edge live in no sample (thresholds final).
+hipError_t launch_dead_edges(const DevGraph& g, const uint32_t* X, int J, hipStream_t s);
 hipError_t launch_heavy_count(const DevGraph& g, int64_t piece_edges, unsigned long long* counts, hipStream_t s);
 hipError_t launch_heavy_assign(const DevGraph& g, int64_t piece_edges, unsigned long long* counts, hipStream_t s);
 hipError_t launch_heavy_pieces(const DevGraph& g, int64_t piece_edges, hipStream_t s);

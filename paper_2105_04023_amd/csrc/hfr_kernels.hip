@@ -217,6 +217,41 @@ hipError_t launch_sim_words(uint32_t* X, uint32_t* HJ, int J, uint32_t seed, hip
     return hipGetLastError();
 }
 
+// Marks the edges live in no sample: with h the edge's hash and t its
+// threshold, the edge is live in sample j iff (X_j xor h) < t (Sec. 3.1), so it is
+// dead in all J iff min_j (X_j xor h) >= t.  A wave stops scanning samples once
+// every lane has found one in which its edge is live.
+__global__ __launch_bounds__(256) void k_dead_edges(uint32_t* __restrict__ eh, const uint32_t* __restrict__ thr,
+                                                    uint32_t thr_const, int per_edge, const uint32_t* __restrict__ X,
+                                                    int J, int64_t m) {
+    __shared__ uint32_t sx[1024];
+    for (int j = threadIdx.x; j < J; j += blockDim.x) sx[j] = X[j];
+    __syncthreads();
+    for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e - threadIdx.x < m;
+         e += (int64_t)gridDim.x * blockDim.x) {
+        const bool in = e < m;
+        const uint32_t h = in ? eh[e] : 0u;
+        const uint32_t t = in ? (per_edge ? thr[e] : thr_const) : 0u;
+        uint32_t mn = 0xFFFFFFFFu;
+        for (int j0 = 0; j0 < J; j0 += 16) {
+            if (!__ballot(in && mn >= t)) break;  // every edge of the wave is live somewhere
+            const int j1 = j0 + 16 < J ? j0 + 16 : J;
+            for (int j = j0; j < j1; ++j) mn = min(mn, sx[j] ^ h);
+        }
+        if (in && mn >= t) eh[e] = h | DEAD_EDGE;
+    }
+}
+
+hipError_t launch_dead_edges(const DevGraph& g, const uint32_t* X, int J, hipStream_t s) {
+    if (g.m == 0) return hipSuccess;
+    if (J > 1024) return hipErrorInvalidValue;
+    int64_t blocks = (g.m + 255) / 256;
+    if (blocks > 8192) blocks = 8192;
+    hipLaunchKernelGGL(k_dead_edges, dim3((int)blocks), dim3(256), 0, s, g.eh, g.thr, g.thr_const,
+                       g.kind == THR_CONST ? 0 : 1, X, J, g.m);
+    return hipGetLastError();
+}
+
 // Rows with more than heavy_deg out-edges are split into pieces.
 // counts[0] = heavy rows, counts[1] = pieces.
 __global__ void k_heavy_count(const int64_t* __restrict__ xadj, int64_t n, int64_t heavy_deg, int64_t piece,
@@ -607,7 +642,7 @@ __global__ __launch_bounds__(256) void k_sweep_light(
     load_sim_words<G, DW>(X, P, p, x);
     const uint32_t ntv = to_vgpr(0u - thr_const);
     uint32_t my_cnt = 0;
-    unsigned long long my_vis = 0;
+    unsigned long long my_vis = 0, my_mrg = 0;
     if (!sparse) {
         const int64_t nwords = (n + 31) >> 5;
         for (int64_t c = wave_index(); c < nwords; c += wave_count()) {
@@ -617,7 +652,7 @@ __global__ __launch_bounds__(256) void k_sweep_light(
                 bool changed = false;
                 if (u < n)
                     changed = sweep_row<G, DW, KIND>(u, xadj, adj, eh, thr, ntv, x, A, B, Lcur, Lnext, blk, fullblk,
-                                                     heavy_deg, P, PW, first, true, lane, p, my_vis);
+                                                     heavy_deg, P, PW, first, true, lane, p, my_vis, &my_mrg);
                 if (changed && p == 0) my_sum += (unsigned long long)(rxadj[u + 1] - rxadj[u]);
                 const uint64_t bal = __ballot(changed && p == 0);
 #pragma unroll
@@ -635,7 +670,7 @@ __global__ __launch_bounds__(256) void k_sweep_light(
             bool changed = false;
             if (i < nw)
                 changed = sweep_row<G, DW, KIND>(fr.W[i], xadj, adj, eh, thr, ntv, x, A, B, Lcur, Lnext, blk,
-                                                 fullblk, heavy_deg, P, PW, first, false, lane, p, my_vis);
+                                                 fullblk, heavy_deg, P, PW, first, false, lane, p, my_vis, &my_mrg);
             if (changed && p == 0) {
                 my_cnt += 1;
                 my_sum += (unsigned long long)(rxadj[fr.W[i] + 1] - rxadj[fr.W[i]]);
@@ -644,11 +679,13 @@ __global__ __launch_bounds__(256) void k_sweep_light(
     }
     const uint32_t bc = block_sum256(my_cnt, sh32);
     const unsigned long long bv = block_sum256(my_vis, sh64);
+    const unsigned long long bm = block_sum256(my_mrg, sh64);
     const unsigned long long bs = block_sum256(my_sum, sh64);
     if (threadIdx.x == 0) {
         const int slot = blockIdx.x % NSLOT;
         if (bc) atomicAdd(&cnt_out[slot * SLOT_U32], bc);
         if (bv) atomicAdd(&vis_out[slot * SLOT_U64], bv);
+        if (bm) atomicAdd(&vis_out[slot * SLOT_U64 + 1], bm);  // rows merged, beside the visits
         if (bs) atomicAdd(&sum_out[slot * SLOT_U64], bs);
     }
 }
@@ -685,7 +722,7 @@ __global__ __launch_bounds__(256) void k_sweep_rows64(
     load_sim_words<64, DW>(X, P, lane, x);
     const uint32_t ntv = to_vgpr(0u - thr_const);
     uint32_t my_cnt = 0;
-    unsigned long long my_vis = 0, my_sum = 0;
+    unsigned long long my_vis = 0, my_sum = 0, my_mrg = 0;
     // dense: every row with 1..heavy_deg out-edges (rows without out-edges never
     // change and are never in L_t); sparse: the listed rows
     const int64_t nrows = sparse ? (int64_t)fr.counts[4 * parity + 1] : nlight;
@@ -730,7 +767,7 @@ __global__ __launch_bounds__(256) void k_sweep_rows64(
             cur_ub[i] = 0xFFFFFFFFu;
             acc[i].e = acc[i].o = 0u;
         }
-        uint32_t vis = 0;
+        uint32_t vis = 0, mrg = 0;  // edges with a live head; rows merged
         // flat edge f of the batch -> (row r, edge id e); the next window's ids
         // are fetched while the current window is merged
         auto locate = [&](uint32_t f, int& r, int64_t& e) {
@@ -760,7 +797,11 @@ __global__ __launch_bounds__(256) void k_sweep_rows64(
             uint64_t mask = __ballot(lv);
             if (!mask) continue;  // no live head: the window needs no hash or threshold
             vis += (uint32_t)__builtin_popcountll(mask);
-            const uint32_t hh = valid ? eh[e] : 0u;
+            const uint32_t hraw = valid ? eh[e] : 0u;
+            mask &= ~__ballot((hraw & DEAD_EDGE) != 0u);  // edges live in no sample merge nothing
+            if (!mask) continue;
+            mrg += (uint32_t)__builtin_popcountll(mask);
+            const uint32_t hh = hraw & ~DEAD_EDGE;
             uint32_t tt = 0u;
             if constexpr (KIND == THR_TARGET) tt = valid ? thr[v] : 0u;
             if constexpr (KIND == THR_EDGE) tt = valid ? thr[e] : 0u;
@@ -899,15 +940,18 @@ __global__ __launch_bounds__(256) void k_sweep_rows64(
         if (lane == 0) {
             my_cnt += __builtin_popcount(word);
             my_vis += vis;
+            my_mrg += mrg;
         }
     }
     const uint32_t bc = block_sum256(my_cnt, sh32);
     const unsigned long long bv = block_sum256(my_vis, sh64);
+    const unsigned long long bm = block_sum256(my_mrg, sh64);
     const unsigned long long bs = block_sum256(my_sum, sh64);
     if (threadIdx.x == 0) {
         const int slot = blockIdx.x % NSLOT;
         if (bc) atomicAdd(&cnt_out[slot * SLOT_U32], bc);
         if (bv) atomicAdd(&vis_out[slot * SLOT_U64], bv);
+        if (bm) atomicAdd(&vis_out[slot * SLOT_U64 + 1], bm);  // rows merged, beside the visits
         if (bs) atomicAdd(&sum_out[slot * SLOT_U64], bs);
     }
 }
@@ -938,6 +982,7 @@ __global__ __launch_bounds__(256) void k_sweep_heavy(
     load_sim_words<G, DW>(X, P, p, x);
     const uint32_t ntv = to_vgpr(0u - thr_const);
     unsigned long long my_vis = 0;
+    unsigned long long my_mrg = 0;  // rows merged (uniform over the group)
     // writes the partial row of piece pc of split row r (the merge of its live
     // edges, or of a run of consecutive pieces of r that starts at pc) and its
     // flag; vis is uniform over the group, a partial without live edges is
@@ -972,16 +1017,18 @@ __global__ __launch_bounds__(256) void k_sweep_heavy(
             if (wm) {
                 if constexpr (G == 64) {
                     vis = merge_marked_windows64<DW, KIND>(b0, b1, wm, adj, eh, thr, ntv, A, Lcur, first, P, lane, x,
-                                                           acc);
+                                                           acc, nullptr, 0, &my_mrg);
                 } else {
                     for (uint32_t left = wm; left; left &= left - 1) {
                         const int64_t w0 = b0 + 64 * (int64_t)__builtin_ctz(left);
                         const int64_t w1 = w0 + 64 < b1 ? w0 + 64 : b1;
-                        vis += merge_edges<G, DW, KIND>(w0, w1, adj, eh, thr, ntv, A, Lcur, first, P, lane, p, x, acc);
+                        vis += merge_edges<G, DW, KIND>(w0, w1, adj, eh, thr, ntv, A, Lcur, first, P, lane, p, x, acc,
+                                                        nullptr, 0, &my_mrg);
                     }
                 }
             } else {
-                vis = merge_edges<G, DW, KIND>(b0, b1, adj, eh, thr, ntv, A, Lcur, first, P, lane, p, x, acc, cl, cs);
+                vis = merge_edges<G, DW, KIND>(b0, b1, adj, eh, thr, ntv, A, Lcur, first, P, lane, p, x, acc, cl, cs,
+                                               &my_mrg);
             }
         }
         finish_piece(pc, r, vis, acc);
@@ -1023,7 +1070,7 @@ __global__ __launch_bounds__(256) void k_sweep_heavy(
                 }
                 if (!((skipm >> j) & 1ull))
                     vis += merge_edges<G, DW, KIND>(__shfl(b0l, j, 64), __shfl(b1l, j, 64), adj, eh, thr, ntv, A,
-                                                    Lcur, first, P, lane, p, x, acc, cl, cs);
+                                                    Lcur, first, P, lane, p, x, acc, cl, cs, &my_mrg);
             }
             finish_piece(base + first_j, run_r, vis, acc);
         }
@@ -1086,7 +1133,11 @@ __global__ __launch_bounds__(256) void k_sweep_heavy(
         }
     }
     const unsigned long long bv = block_sum256(my_vis, sh64);
-    if (threadIdx.x == 0 && bv) atomicAdd(&vis_out[(blockIdx.x % NSLOT) * SLOT_U64], bv);
+    const unsigned long long bm = block_sum256(p == 0 ? my_mrg : 0ull, sh64);
+    if (threadIdx.x == 0) {
+        if (bv) atomicAdd(&vis_out[(blockIdx.x % NSLOT) * SLOT_U64], bv);
+        if (bm) atomicAdd(&vis_out[(blockIdx.x % NSLOT) * SLOT_U64 + 1], bm);  // rows merged, beside the visits
+    }
 }
 
 // One G-lane group per split row: combine the pieces merged in this sweep

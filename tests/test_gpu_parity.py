@@ -351,3 +351,47 @@ def test_reverse_csr_on_hub_buckets(hf, ctx, model, p):
         assert np.array_equal(o[0], out[0][0]) and np.array_equal(o[1], out[0][1])
         assert np.array_equal(o[2], out[0][2])
         assert o[3] == out[0][3] and o[4] == out[0][4]
+
+
+# ---- rows merged: an edge live in none of the samples is skipped after its live test ----
+
+def _edges_live_somewhere(g, thr, J):
+    """Per edge: live in at least one of the J samples (Sec. 3.1), from the oracle's hashes and
+    sample words; the vectorised test is checked against the oracle's own live test."""
+    src = np.repeat(np.arange(g.n, dtype=np.int64), np.diff(g.xadj))
+    h = np.array([oracle.edge_hash(int(u), int(v)) for u, v in zip(src, g.adj)], dtype=np.uint64)
+    X = np.array([oracle.sim_word(j) for j in range(J)], dtype=np.uint64)
+    t = thr.astype(np.uint64)
+    rng = np.random.default_rng(5)
+    for e, j in zip(rng.integers(0, len(h), 200), rng.integers(0, J, 200)):
+        assert bool((X[j] ^ h[e]) < t[e]) == oracle.live(int(h[e]), int(X[j]), int(t[e]))
+    return ((X[None, :] ^ h[:, None]) < t[:, None]).any(axis=1)
+
+
+@pytest.mark.parametrize("model,p,J,heavy", [("wc", 0.0, 256, 8), ("const", 0.005, 256, 0), ("wc", 0.0, 64, 8),
+                                             ("wc", 0.0, 512, 16)])
+def test_first_sweep_merges_the_edges_live_somewhere(hf, ctx, model, p, J, heavy):
+    # in the first sweep every head is live, so the rows merged are exactly the edges live in
+    # at least one sample; split rows (heavy > 0) go through the piece kernel
+    g = synth.rmat(12, 40000, seed=7)
+    thr = oracle.edge_thresholds(g, model, np.float32(p))
+    sk = hf.im_build_sketches(ctx, g.xadj, g.adj, g.n, J, model=model, p=p, heavy_degree=heavy,
+                              piece_edges=64 if heavy else 0, time_sweeps=True)
+    try:
+        log = [r for r in sk.sweep_log() if r["ran"]]
+        M = sk.registers(0)
+    finally:
+        sk.free()
+    want = _edges_live_somewhere(g, thr, J)
+    deg = np.diff(g.xadj)
+    light = np.repeat(deg <= (heavy if heavy else 64), deg)
+    assert log[0]["sweep"] == 0 and log[0]["visits"] == g.m
+    assert log[0]["merged"] == int(want.sum())
+    assert log[0]["light_merged"] == int(want[light].sum())
+    assert 0 < log[0]["merged"] < g.m  # the workload has edges of both kinds
+    for r in log:
+        assert 0 <= r["light_merged"] <= r["light_visits"] and r["merged"] - r["light_merged"] <= r["visits"] - r["light_visits"]
+    # and the skip changes nothing: the registers and the visit trace are the oracle's
+    M_or, _, _, te = oracle.simulate(g, thr, J)
+    assert np.array_equal(M, M_or)
+    assert [r["visits"] for r in log] == [int(v) for v in te]
