@@ -135,6 +135,7 @@ struct im_sketch {
     std::vector<int64_t> trace_live, trace_vis;
     std::vector<im_sweep_rec> sweep_log;
     int32_t simulate_count = 0;
+    int64_t sweep_hint = 0;  // sweeps of the last Simulate: rebuilds batch their sweeps by it
     int32_t level_id = 1;
     bool selected = false;
     bool has_registers = true;
@@ -363,6 +364,12 @@ im_status run_simulate(im_sketch* sk, int ia, int ib, const uint32_t* blk, SimRe
     if ((uint64_t)n <= thresh) final_sweeps = 0;
     int64_t t = 0;
     int nb = 8;
+    // sweeps are launched in growing batches, two in flight, before the host sees
+    // where the fixed point falls; the sweeps past it return at once.  A rebuild
+    // converges in about as many sweeps as the Simulate before it, so below that
+    // count (less a margin) batches run at full size, and past it they restart at 4
+    const int64_t hint_safe = sk->sweep_hint > 0 ? sk->sweep_hint - 8 : 0;
+    bool tail = false;
     int inflight = 0;  // batches launched and not yet read
     int64_t batch_t0[2] = {0, 0};
     int batch_nb[2] = {0, 0};
@@ -375,6 +382,14 @@ im_status run_simulate(im_sketch* sk, int ia, int ib, const uint32_t* blk, SimRe
         if (t > n + 2 + 2 * MAX_BATCH) {
             sk->poisoned = true;
             return fail(IM_ERR_DEVICE, "sweep count exceeded n + 1 without convergence");
+        }
+        if (hint_safe > 0) {
+            if (t < hint_safe)
+                nb = (int)std::min<int64_t>(nb, hint_safe - t);
+            else if (!tail) {
+                tail = true;
+                nb = 4;
+            }
         }
         // launch one batch; its sweeps may go sparse only once the reverse CSR exists
         HIP_TRY(rev_csr_ready(sk, false));
@@ -469,6 +484,7 @@ im_status run_simulate(im_sketch* sk, int ia, int ib, const uint32_t* blk, SimRe
     HIP_TRY(hipEventElapsedTime(&ms, sk->ev_a, sk->ev_b));
     res->ms = ms;
     res->sweeps = final_sweeps;
+    sk->sweep_hint = final_sweeps;
     res->live.resize(final_sweeps + 1);
     res->vis.resize(final_sweeps);
     res->vis_light.resize(final_sweeps);

@@ -205,21 +205,21 @@ constexpr int UB = 8;  // neighbour rows in flight per wave (twice that with one
 
 // G = 64: merges one window of up to 64 out-edges, lane l holding edge e (in:
 // the edge exists) with head v, `mask` the lanes whose head is in L_t (not
-// empty).  Edges live in no sample are dropped from the mask; the rows of up
-// to UB remaining heads are loaded back-to-back before they are merged.
-// Returns the number of rows merged.
+// empty, edges live in no sample already dropped).  The rows of up to UB heads
+// are loaded back-to-back before they are merged.  Returns the number of rows
+// merged.
 template <int DW, int KIND>
 DEVI uint32_t merge_window64(uint64_t mask, int64_t e, bool in, int32_t v, const uint32_t* __restrict__ eh,
                              const uint32_t* __restrict__ thr, uint32_t ntv, const uint32_t* __restrict__ A, int P,
                          int lane, const uint32_t (&x)[DW][4], Acc (&acc)[DW]) {
-    const uint32_t hraw = in ? eh[e] : 0u;
-    mask &= ~__ballot((hraw & DEAD_EDGE) != 0u);  // edges live in no sample merge nothing
-    if (!mask) return 0u;
+    // hashes and thresholds of the merged edges only: a sparse mask then
+    // fetches only the cache lines it needs
     const uint32_t merged = (uint32_t)__builtin_popcountll(mask);
-    const uint32_t hh = hraw & ~DEAD_EDGE;
+    const bool mine = ((mask >> lane) & 1ull) != 0ull;
+    const uint32_t hh = mine ? eh[e] : 0u;
     uint32_t ntt = 0u;  // negated threshold
-    if constexpr (KIND == THR_TARGET) ntt = 0u - (in ? thr[v] : 0u);
-    if constexpr (KIND == THR_EDGE) ntt = 0u - (in ? thr[e] : 0u);
+    if constexpr (KIND == THR_TARGET) ntt = 0u - (mine ? thr[v] : 0u);
+    if constexpr (KIND == THR_EDGE) ntt = 0u - (mine ? thr[e] : 0u);
     // dword of a neighbour row this lane loads (lanes past the row load its last dword; their
     // results are never stored), unsigned so that a row load takes the row base as its
     // scalar address
@@ -290,10 +290,13 @@ DEVI uint32_t merge_edges64(int64_t eb, int64_t ee, const int32_t* __restrict__ 
     for (int64_t c0 = eb; c0 < ee; c0 += 64 * NW) {
         int32_t vw[NW];
         bool inw[NW];
+        uint64_t dm[NW];  // edges live in no sample
 #pragma unroll
         for (int w = 0; w < NW; ++w) {
             inw[w] = c0 + 64 * w + lane < ee;
-            vw[w] = inw[w] ? adj[c0 + 64 * w + lane] : 0;
+            const int32_t a = inw[w] ? adj[c0 + 64 * w + lane] : 0;
+            vw[w] = adj_target(a);
+            dm[w] = __ballot(adj_dead(a));
         }
         uint64_t mw[NW];
 #pragma unroll
@@ -302,8 +305,10 @@ DEVI uint32_t merge_edges64(int64_t eb, int64_t ee, const int32_t* __restrict__ 
         for (int w = 0; w < NW; ++w) {
             if (!mw[w]) continue;  // no live head: the window needs no hash or threshold
             vis += (uint32_t)__builtin_popcountll(mw[w]);
+            const uint64_t mm = mw[w] & ~dm[w];  // edges live in no sample merge nothing
+            if (!mm) continue;
             const uint32_t mg =
-                merge_window64<DW, KIND>(mw[w], c0 + 64 * w + lane, inw[w], vw[w], eh, thr, ntv, A, P, lane, x, acc);
+                merge_window64<DW, KIND>(mm, c0 + 64 * w + lane, inw[w], vw[w], eh, thr, ntv, A, P, lane, x, acc);
             if (mrg) *mrg += mg;
         }
     }
@@ -330,10 +335,13 @@ DEVI uint32_t merge_marked_windows64(int64_t eb, int64_t ee, uint32_t wm, const 
         }
         int32_t vw[NW];
         bool inw[NW];
+        uint64_t dm[NW];  // edges live in no sample
 #pragma unroll
         for (int w = 0; w < NW; ++w) {
             inw[w] = w0[w] + lane < ee && w0[w] < ee;
-            vw[w] = inw[w] ? adj[w0[w] + lane] : 0;
+            const int32_t a = inw[w] ? adj[w0[w] + lane] : 0;
+            vw[w] = adj_target(a);
+            dm[w] = __ballot(adj_dead(a));
         }
         uint64_t mw[NW];
 #pragma unroll
@@ -342,8 +350,10 @@ DEVI uint32_t merge_marked_windows64(int64_t eb, int64_t ee, uint32_t wm, const 
         for (int w = 0; w < NW; ++w) {
             if (!mw[w]) continue;
             vis += (uint32_t)__builtin_popcountll(mw[w]);
+            const uint64_t mm = mw[w] & ~dm[w];  // edges live in no sample merge nothing
+            if (!mm) continue;
             const uint32_t mg =
-                merge_window64<DW, KIND>(mw[w], w0[w] + lane, inw[w], vw[w], eh, thr, ntv, A, P, lane, x, acc);
+                merge_window64<DW, KIND>(mm, w0[w] + lane, inw[w], vw[w], eh, thr, ntv, A, P, lane, x, acc);
             if (mrg) *mrg += mg;
         }
     }
@@ -367,16 +377,16 @@ DEVI uint32_t merge_edges_grp(int64_t eb, int64_t ee, const int32_t* __restrict_
         const int64_t e = w0 + p;
         const bool in = e < ee;
         const int64_t ec = in ? e : ee - 1;  // lanes past the row re-read its last edge
-        const int32_t v = adj[ec];
+        const int32_t a = adj[ec];
+        const int32_t v = adj_target(a);
         const bool lv = in && (first || bit_of(Lcur, v) != 0u);
         uint64_t mask = (__ballot(lv) >> gbase) & GM;
         if (!mask) continue;  // no live head: the window needs no hash or threshold
         vis += (uint32_t)__builtin_popcountll(mask);
-        const uint32_t hraw = eh[ec];
-        mask &= ~(__ballot((hraw & DEAD_EDGE) != 0u) >> gbase);  // edges live in no sample merge nothing
+        mask &= ~(__ballot(in && adj_dead(a)) >> gbase);  // edges live in no sample merge nothing
         if (!mask) continue;
         if (mrg) *mrg += (uint32_t)__builtin_popcountll(mask);
-        const uint32_t hh = hraw & ~DEAD_EDGE;
+        const uint32_t hh = eh[ec];
         uint32_t tt = 0u;
         if constexpr (KIND == THR_TARGET) tt = thr[v];
         if constexpr (KIND == THR_EDGE) tt = thr[ec];
@@ -842,9 +852,9 @@ DEVI unsigned long long bfs_expand_entries(int64_t b0, int64_t b1, int64_t bstep
         for (int64_t w0 = e0; w0 < e1; w0 += G) {
             const int64_t e = w0 + p;
             const bool in = e < e1;
-            const int32_t wv = in ? adj[e] : 0;
-            const uint32_t hraw = in ? eh[e] : 0u;
-            const uint32_t hh = hraw & ~DEAD_EDGE;
+            const int32_t wa = in ? adj[e] : 0;
+            const int32_t wv = adj_target(wa);
+            const uint32_t hh = in ? eh[e] : 0u;
             uint32_t tt = 0u;
             if constexpr (KIND == THR_TARGET) tt = in ? thr[wv] : 0u;
             if constexpr (KIND == THR_EDGE) tt = in ? thr[e] : 0u;
@@ -852,7 +862,7 @@ DEVI unsigned long long bfs_expand_entries(int64_t b0, int64_t b1, int64_t bstep
             // G = 64: only the window's edges live in some sample (an edge live in
             // none reaches nothing); groups scan their whole window
             uint64_t todo = 0;
-            if constexpr (G == 64) todo = __ballot(in && (hraw & DEAD_EDGE) == 0u);
+            if constexpr (G == 64) todo = __ballot(in && !adj_dead(wa));
             for (int jj = 0; G == 64 ? todo != 0ull : jj < nwin; ++jj) {
                 int j = jj;
                 if constexpr (G == 64) {

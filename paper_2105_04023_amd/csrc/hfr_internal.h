@@ -32,8 +32,8 @@ enum ThrKind { THR_CONST = 0, THR_TARGET = 1, THR_EDGE = 2 };
 struct DevGraph {
     int64_t n = 0, m = 0;
     int64_t* xadj = nullptr;
-    int32_t* adj = nullptr;
-    uint32_t* eh = nullptr;   // 31-bit edge hash per edge; bit 31 (DEAD_EDGE) marks an edge live in no sample
+    int32_t* adj = nullptr;   // the sketch's copy; DEAD_EDGE may be set once the sweeps' inputs are final
+    uint32_t* eh = nullptr;   // 31-bit edge hash per edge
     uint32_t* thr = nullptr;  // per target vertex (WC) or per edge
     uint32_t thr_const = 0;
     int kind = THR_CONST;
@@ -57,10 +57,13 @@ struct DevGraph {
     int64_t piece_edges = 256;
 };
 
-// Flag in an edge hash: the edge is live in none of the J samples (no j with
-// (X_j xor h) < its threshold), so no merge of the Simulate needs the head's row.
-// Every live test masks it off; hashes without it merge as usual.
+// Flag in bit 31 of an edge's target id (ids are below 2^31): the edge is live in
+// none of the J samples (no j with (X_j xor h) < its threshold), so no merge or
+// reach step needs the head's row.  Every reader of the id masks it off (adj_target);
+// a graph without flags merges as usual.
 constexpr uint32_t DEAD_EDGE = 0x80000000u;
+__host__ __device__ inline int32_t adj_target(int32_t a) { return a & 0x7FFFFFFF; }
+__host__ __device__ inline bool adj_dead(int32_t a) { return a < 0; }
 
 constexpr int COARSE_WORDS = 2048;  // coarse copy of L_t: 8 KiB of LDS per workgroup
 
@@ -142,7 +145,7 @@ hipError_t launch_wc_thresholds(const uint32_t* indeg, uint32_t* thr, int64_t n,
 hipError_t launch_gather_u32(const uint32_t* src, const int32_t* idx, int64_t m, uint32_t* out, hipStream_t s);
 hipError_t launch_edge_thresholds(const float* w, uint32_t* thr, int64_t m, uint32_t* err, hipStream_t s);
 hipError_t launch_sim_words(uint32_t* X, uint32_t* HJ, int J, uint32_t seed, hipStream_t s);
-// Sets DEAD_EDGE in the hash of every edge live in no sample (thresholds final).
+// Sets DEAD_EDGE in the target id of every edge live in no sample (thresholds final).
 hipError_t launch_dead_edges(const DevGraph& g, const uint32_t* X, int J, hipStream_t s);
 hipError_t launch_heavy_count(const DevGraph& g, int64_t piece_edges, unsigned long long* counts, hipStream_t s);
 hipError_t launch_heavy_assign(const DevGraph& g, int64_t piece_edges, unsigned long long* counts, hipStream_t s);

@@ -146,7 +146,7 @@ __global__ __launch_bounds__(256) void k_indegree(const int32_t* __restrict__ ad
     for (int i = threadIdx.x; i < HOT_IDS; i += blockDim.x) hot[i] = 0u;
     __syncthreads();
     for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < m; e += (int64_t)gridDim.x * blockDim.x) {
-        const int32_t v = adj[e];
+        const int32_t v = adj_target(adj[e]);
         if (v < HOT_IDS)
             atomicAdd(&hot[v], 1u);
         else
@@ -219,35 +219,60 @@ hipError_t launch_sim_words(uint32_t* X, uint32_t* HJ, int J, uint32_t seed, hip
 
 // Marks the edges live in no sample: with h the edge's hash and t its
 // threshold, the edge is live in sample j iff (X_j xor h) < t (Sec. 3.1), so it is
-// dead in all J iff min_j (X_j xor h) >= t.  A wave stops scanning samples once
-// every lane has found one in which its edge is live.
-__global__ __launch_bounds__(256) void k_dead_edges(uint32_t* __restrict__ eh, const uint32_t* __restrict__ thr,
+// dead in all J iff min_j (X_j xor h) >= t.  The sample words are read at
+// wave-uniform addresses, four at a time (J is a multiple of 4), each load
+// serving four edges per lane; a wave stops scanning samples once every edge
+// it holds has one in which it is live.
+__global__ __launch_bounds__(256) void k_dead_edges(int32_t* __restrict__ adj, const uint32_t* __restrict__ eh,
+                                                    const uint32_t* __restrict__ thr,
                                                     uint32_t thr_const, int per_edge, const uint32_t* __restrict__ X,
                                                     int J, int64_t m) {
-    __shared__ uint32_t sx[1024];
-    for (int j = threadIdx.x; j < J; j += blockDim.x) sx[j] = X[j];
-    __syncthreads();
-    for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e - threadIdx.x < m;
-         e += (int64_t)gridDim.x * blockDim.x) {
-        const bool in = e < m;
-        const uint32_t h = in ? eh[e] : 0u;
-        const uint32_t t = in ? (per_edge ? thr[e] : thr_const) : 0u;
-        uint32_t mn = 0xFFFFFFFFu;
-        for (int j0 = 0; j0 < J; j0 += 16) {
-            if (!__ballot(in && mn >= t)) break;  // every edge of the wave is live somewhere
-            const int j1 = j0 + 16 < J ? j0 + 16 : J;
-            for (int j = j0; j < j1; ++j) mn = min(mn, sx[j] ^ h);
+    constexpr int EPT = 4;  // edges per lane (e0 + 256 k): one load of sample words serves EPT edges
+    const int64_t step = (int64_t)gridDim.x * blockDim.x * EPT;
+    for (int64_t e0 = (int64_t)blockIdx.x * blockDim.x * EPT + threadIdx.x; e0 - threadIdx.x < m; e0 += step) {
+        uint32_t h[EPT], t[EPT], mn[EPT];
+        bool in[EPT];
+#pragma unroll
+        for (int k = 0; k < EPT; ++k) {
+            const int64_t e = e0 + (int64_t)k * blockDim.x;
+            in[k] = e < m;
+            h[k] = in[k] ? eh[e] : 0u;
+            t[k] = in[k] ? (per_edge ? thr[e] : thr_const) : 0u;
+            mn[k] = 0xFFFFFFFFu;
         }
-        if (in && mn >= t) eh[e] = h | DEAD_EDGE;
+        for (int j0 = 0; j0 < J; j0 += 16) {
+            bool open = false;
+#pragma unroll
+            for (int k = 0; k < EPT; ++k) open = open || (in[k] && mn[k] >= t[k]);
+            if (!__ballot(open)) break;  // every edge of the wave is live somewhere
+#pragma unroll
+            for (int g = 0; g < 4; ++g) {
+                if (j0 + 4 * g < J) {
+                    const uint32_t* xg = X + j0 + 4 * g;
+                    const uint32_t x0 = xg[0], x1 = xg[1], x2 = xg[2], x3 = xg[3];
+#pragma unroll
+                    for (int k = 0; k < EPT; ++k) {
+                        mn[k] = min(min(mn[k], x0 ^ h[k]), x1 ^ h[k]);
+                        mn[k] = min(min(mn[k], x2 ^ h[k]), x3 ^ h[k]);
+                    }
+                }
+            }
+        }
+#pragma unroll
+        for (int k = 0; k < EPT; ++k)
+            if (in[k] && mn[k] >= t[k]) {
+                int32_t* a = adj + e0 + (int64_t)k * blockDim.x;
+                *a = (int32_t)((uint32_t)*a | DEAD_EDGE);
+            }
     }
 }
 
 hipError_t launch_dead_edges(const DevGraph& g, const uint32_t* X, int J, hipStream_t s) {
     if (g.m == 0) return hipSuccess;
-    if (J > 1024) return hipErrorInvalidValue;
-    int64_t blocks = (g.m + 255) / 256;
+    if (J > 1024 || J % 4) return hipErrorInvalidValue;
+    int64_t blocks = (g.m + 1023) / 1024;
     if (blocks > 8192) blocks = 8192;
-    hipLaunchKernelGGL(k_dead_edges, dim3((int)blocks), dim3(256), 0, s, g.eh, g.thr, g.thr_const,
+    hipLaunchKernelGGL(k_dead_edges, dim3((int)blocks), dim3(256), 0, s, g.adj, g.eh, g.thr, g.thr_const,
                        g.kind == THR_CONST ? 0 : 1, X, J, g.m);
     return hipGetLastError();
 }
@@ -698,7 +723,7 @@ __global__ __launch_bounds__(256) void k_sweep_light(
 // row loads; the first load of a row also fetches the row itself (and its
 // blocked bits), so finishing a row needs no extra round trip.
 template <int DW, int KIND, bool BLK>
-__global__ __launch_bounds__(256) void k_sweep_rows64(
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(5, 8))) void k_sweep_rows64(
     const int64_t* __restrict__ xadj, const int32_t* __restrict__ adj, const uint32_t* __restrict__ eh,
     const uint32_t* __restrict__ thr, uint32_t thr_const, const uint32_t* __restrict__ X,
     const uint32_t* __restrict__ A, uint32_t* __restrict__ B, const uint32_t* __restrict__ Lcur,
@@ -783,12 +808,13 @@ __global__ __launch_bounds__(256) void k_sweep_rows64(
         int64_t e_n;
         locate((uint32_t)lane, r_n, e_n);
         bool in_n = (uint32_t)lane < total;
-        int32_t v_n = in_n ? adj[e_n] : 0;
+        int32_t v_n = in_n ? adj[e_n] : 0;  // raw id (DEAD_EDGE possible)
         for (uint32_t f0 = 0; f0 < total; f0 += 64) {
             const int r = r_n;
             const int64_t e = e_n;
             const bool valid = in_n;
-            const int32_t v = v_n;
+            const int32_t v = adj_target(v_n);
+            const uint64_t dmask = __ballot(adj_dead(v_n));  // edges live in no sample
             const uint32_t fn = f0 + 64 + lane;
             locate(fn, r_n, e_n);
             in_n = fn < total;
@@ -797,14 +823,15 @@ __global__ __launch_bounds__(256) void k_sweep_rows64(
             uint64_t mask = __ballot(lv);
             if (!mask) continue;  // no live head: the window needs no hash or threshold
             vis += (uint32_t)__builtin_popcountll(mask);
-            const uint32_t hraw = valid ? eh[e] : 0u;
-            mask &= ~__ballot((hraw & DEAD_EDGE) != 0u);  // edges live in no sample merge nothing
+            mask &= ~dmask;  // edges live in no sample merge nothing
             if (!mask) continue;
             mrg += (uint32_t)__builtin_popcountll(mask);
-            const uint32_t hh = hraw & ~DEAD_EDGE;
+            // hashes and thresholds of the merged edges only
+            const bool mine = ((mask >> lane) & 1ull) != 0ull;
+            const uint32_t hh = mine ? eh[e] : 0u;
             uint32_t tt = 0u;
-            if constexpr (KIND == THR_TARGET) tt = valid ? thr[v] : 0u;
-            if constexpr (KIND == THR_EDGE) tt = valid ? thr[e] : 0u;
+            if constexpr (KIND == THR_TARGET) tt = mine ? thr[v] : 0u;
+            if constexpr (KIND == THR_EDGE) tt = mine ? thr[e] : 0u;
             // batches of NB live edges, NB the smallest of 1, 2, 4, UB that covers
             // the edges left (capped at UB); unused slots repeat the last one
             // (max-merge is idempotent), so every load is issued without a branch
@@ -960,7 +987,7 @@ __global__ __launch_bounds__(256) void k_sweep_rows64(
 // One G-lane group per piece of a split row: merge of the live rows of the
 // piece's out-neighbours in L_t, written to part[piece].
 template <int G, int DW, int KIND>
-__global__ __launch_bounds__(256) void k_sweep_heavy(
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(7, 8))) void k_sweep_heavy(
     const int32_t* __restrict__ adj, const uint32_t* __restrict__ eh, const uint32_t* __restrict__ thr,
     uint32_t thr_const, const uint32_t* __restrict__ X, const uint32_t* __restrict__ A,
     const uint32_t* __restrict__ Lcur, const uint32_t* __restrict__ blk, const uint32_t* __restrict__ gate,
@@ -1399,7 +1426,7 @@ __global__ void k_rev_scatter(const int64_t* __restrict__ xadj, const int32_t* _
         const int32_t r = hslot[u];
         const int64_t base = r >= 0 ? hpb[r] : 0;
         for (int64_t e = eb + lane; e < ee; e += 64) {
-            const int32_t v = adj[e];
+            const int32_t v = adj_target(adj[e]);  // may run beside the flagging of dead edges
             const unsigned long long pos = atomicAdd((unsigned long long*)&cursor[v], 1ull);
             radj[pos] = (int32_t)u;
             // 64-edge window of the edge within its piece (windows of piece c are
@@ -1796,7 +1823,84 @@ __global__ __launch_bounds__(256) void k_argmax(const uint32_t* __restrict__ M, 
     }
 }
 
+// The same argmax for rows of P = 16 DQ dwords: 16 lanes per row, lane p holding
+// dwords [p DQ, p DQ + DQ) (16-byte loads), so a wave scores 4 rows per step with
+// one 4-step reduction, two steps' loads in flight.
+template <int DQ>
+__global__ __launch_bounds__(256) void k_argmax16(const uint32_t* __restrict__ M, const uint32_t* __restrict__ MS,
+                                                  const uint8_t* __restrict__ inS, unsigned long long* key_out,
+                                                  int64_t n) {
+    __shared__ unsigned long long sh[4];
+    constexpr int P = 16 * DQ;
+    const int lane = threadIdx.x & 63, grp = lane >> 4, p = lane & 15;
+    uint32_t ms[DQ];
+#pragma unroll
+    for (int i = 0; i < DQ; ++i) ms[i] = MS[p * DQ + i];
+    unsigned long long best = 0;
+    const int64_t stride = wave_count() * 4;
+    for (int64_t base = wave_index() * 4; base < n; base += 2 * stride) {
+        const int64_t u0 = base + grp, u1 = base + stride + grp;
+        const bool ok0 = u0 < n && inS[u0] == 0, ok1 = u1 < n && inS[u1] == 0;
+        uint4 d0[DQ / 4], d1[DQ / 4];
+#pragma unroll
+        for (int c = 0; c < DQ / 4; ++c) {
+            d0[c] = ok0 ? reinterpret_cast<const uint4*>(M + u0 * P + p * DQ)[c] : make_uint4(0u, 0u, 0u, 0u);
+            d1[c] = ok1 ? reinterpret_cast<const uint4*>(M + u1 * P + p * DQ)[c] : make_uint4(0u, 0u, 0u, 0u);
+        }
+        uint32_t s0 = 0, s1 = 0;
+#pragma unroll
+        for (int c = 0; c < DQ / 4; ++c) {
+            s0 = __builtin_amdgcn_sad_u8(byte_max(ms[4 * c], d0[c].x), 0u, s0);
+            s0 = __builtin_amdgcn_sad_u8(byte_max(ms[4 * c + 1], d0[c].y), 0u, s0);
+            s0 = __builtin_amdgcn_sad_u8(byte_max(ms[4 * c + 2], d0[c].z), 0u, s0);
+            s0 = __builtin_amdgcn_sad_u8(byte_max(ms[4 * c + 3], d0[c].w), 0u, s0);
+            s1 = __builtin_amdgcn_sad_u8(byte_max(ms[4 * c], d1[c].x), 0u, s1);
+            s1 = __builtin_amdgcn_sad_u8(byte_max(ms[4 * c + 1], d1[c].y), 0u, s1);
+            s1 = __builtin_amdgcn_sad_u8(byte_max(ms[4 * c + 2], d1[c].z), 0u, s1);
+            s1 = __builtin_amdgcn_sad_u8(byte_max(ms[4 * c + 3], d1[c].w), 0u, s1);
+        }
+#pragma unroll
+        for (int off = 8; off > 0; off >>= 1) {
+            s0 += __shfl_xor(s0, off, 64);
+            s1 += __shfl_xor(s1, off, 64);
+        }
+        if (p == 0) {
+            if (ok0) {
+                const unsigned long long k0 = ((unsigned long long)s0 << 32) | (0xFFFFFFFFu - (uint32_t)u0);
+                best = k0 > best ? k0 : best;
+            }
+            if (ok1) {
+                const unsigned long long k1 = ((unsigned long long)s1 << 32) | (0xFFFFFFFFu - (uint32_t)u1);
+                best = k1 > best ? k1 : best;
+            }
+        }
+    }
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) {
+        const unsigned long long o = __shfl_xor(best, off, 64);
+        best = o > best ? o : best;
+    }
+    const int w = threadIdx.x >> 6;
+    if (lane == 0) sh[w] = best;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        unsigned long long bb = sh[0];
+        for (int i = 1; i < 4; ++i) bb = sh[i] > bb ? sh[i] : bb;
+        if (bb) atomicMax(key_out, bb);
+    }
+}
+
 hipError_t launch_argmax(const Layout& L, int64_t n, const uint32_t* M, const GreedyBufs& b, hipStream_t s) {
+    if (L.P == 64 || L.P == 128 || L.P == 256) {
+        const int grid = grid_for_rows((n + 7) / 8);  // 8 rows per wave and step pair
+        if (L.P == 64)
+            hipLaunchKernelGGL((k_argmax16<4>), dim3(grid), dim3(256), 0, s, M, b.MS, b.inS, b.key, n);
+        else if (L.P == 128)
+            hipLaunchKernelGGL((k_argmax16<8>), dim3(grid), dim3(256), 0, s, M, b.MS, b.inS, b.key, n);
+        else
+            hipLaunchKernelGGL((k_argmax16<16>), dim3(grid), dim3(256), 0, s, M, b.MS, b.inS, b.key, n);
+        return hipGetLastError();
+    }
     const int grid = grid_for_rows((n + (64 / L.G) - 1) / (64 / L.G));
     HFR_LAYOUT_DISPATCH(L, hipLaunchKernelGGL((k_argmax<G_, DW_>), dim3(grid), dim3(256), 0, s, M, b.MS, b.inS, b.key,
                                               n, L.P));
