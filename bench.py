@@ -37,20 +37,23 @@ WORKLOADS = {
 def heavy_launch_bytes(rec, J, wc, m_heavy, npieces):
     """Algorithmic HBM bytes of one launch of the split-row piece kernel (k_sweep_heavy).
 
-    Per edge visited with a live head: its hash (4 bytes), which also says whether the
-    edge is live in any sample; per such edge that is (a merged row): the neighbour's row
-    (J bytes) and, for the weighted cascade, the edge's threshold (4).  A dense launch also
-    reads every split-row out-edge id (4 m_heavy) and its piece table (20 B per piece).
-    The partial rows and flags it writes (J + 4 bytes per run of a row's pieces with a
-    live edge) are not counted: how many there were is not logged, and they are under 1%
-    of the bytes.  A launch past the stopping rule moves nothing.
+    Per merged edge (a visited edge live in some sample): the neighbour's row (J bytes),
+    the edge hash (4) and, for the weighted cascade, the edge's threshold (4); an edge live
+    in no sample is known to be so from its id (flag bit), which costs nothing more.  Edge
+    ids: a dense launch reads every split-row out-edge id (4 m_heavy) and the piece table
+    (20 B per piece), a sparse launch the ids of the edges it visits (4 each).  The partial
+    rows and flags written (J + 4 bytes per run of a row's pieces with a live edge) are not
+    counted: how many there were is not logged, and they are under 1% of the bytes.  A
+    launch past the stopping rule moves nothing.
     """
     if not rec["ran"]:
         return 0
     hv = rec["visits"] - rec["light_visits"]
     hm = rec["merged"] - rec["light_merged"]
-    b = hv * 4 + hm * (J + (4 if wc else 0))
-    if not rec["sparse"]:
+    b = hm * (J + 4 + (4 if wc else 0))
+    if rec["sparse"]:
+        b += 4 * hv
+    else:
         b += 4 * m_heavy + 20 * npieces
     return b
 
@@ -434,7 +437,7 @@ def main():
     nlaunch = len(recs)
     achieved = tot_bytes / (tot_ms * 1e-3) / 1e9 if tot_ms > 0 else 0.0
     row_ms = sum(rec["kernel_ms"] for rec in recs)
-    row_bytes = sum(rec["light_visits"] * 4 + rec["light_merged"] * (J + (4 if wc else 0))
+    row_bytes = sum(rec["light_visits"] * 4 + rec["light_merged"] * (J + 4 + (4 if wc else 0))
                     for rec in recs if rec["ran"])
     out = {
         "metric": "edge*simulation visits/s in sketch build (+ K-seed IM time; batched vs plain in 'batched')",

@@ -27,13 +27,12 @@ def test_heavy_launch_bytes(bench):
     dense = {"ran": 1, "sparse": 0, "visits": 700, "light_visits": 200, "merged": 400, "light_merged": 150}
     sparse = dict(dense, sparse=1)
     idle = dict(dense, ran=0)
-    # per live-head visit the edge hash; per merged row the head's row and (weighted cascade)
-    # the threshold
-    assert bench.heavy_launch_bytes(sparse, J, False, m_heavy, npieces) == 500 * 4 + 250 * J
-    assert bench.heavy_launch_bytes(sparse, J, True, m_heavy, npieces) == 500 * 4 + 250 * (J + 4)
-    # a dense launch also reads every split-row edge id and the piece table
-    assert bench.heavy_launch_bytes(dense, J, True, m_heavy, npieces) == (500 * 4 + 250 * (J + 4) + 4 * m_heavy
-                                                                        + 20 * npieces)
+    # per merged row the head's row, the edge hash and (weighted cascade) the threshold; a
+    # sparse launch reads the ids of the edges it visits
+    assert bench.heavy_launch_bytes(sparse, J, False, m_heavy, npieces) == 500 * 4 + 250 * (J + 4)
+    assert bench.heavy_launch_bytes(sparse, J, True, m_heavy, npieces) == 500 * 4 + 250 * (J + 8)
+    # a dense launch reads every split-row edge id and the piece table instead
+    assert bench.heavy_launch_bytes(dense, J, True, m_heavy, npieces) == 250 * (J + 8) + 4 * m_heavy + 20 * npieces
     assert bench.heavy_launch_bytes(idle, J, True, m_heavy, npieces) == 0
 
 
