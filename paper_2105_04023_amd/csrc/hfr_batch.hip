@@ -101,7 +101,7 @@ struct BCtl {
 struct BJob {
     int64_t n, m;
     const int64_t* xadj;
-    const int32_t* adj;
+    int32_t* adj;           // the batch's copy; bit 31 (DEAD_EDGE) flags an edge live in no sample
     uint32_t* eh;           // edge hashes, written by PH_INIT0
     uint32_t* thr;          // WC: per target (written by PH_INIT0); per edge: uploaded
     const uint32_t* indeg;  // WC in-degrees
@@ -241,9 +241,9 @@ DEVI void init_words_of(uint32_t seed, int P, int p, uint32_t (&hj)[DW][4]) {
 
 // Register init of rows [r0, r1) (Alg. 1): M_u[j] = clz(hash(u) xor hash(j)),
 // 0 for blocked pairs of a rebuild.  The first init of a run also clears the
-// run's per-vertex state of those rows, hashes their out-edges (Eq. hash),
-// derives their weighted-cascade thresholds and clears a slice of the piece
-// flags.
+// run's per-vertex state of those rows, hashes their out-edges (Eq. hash) and
+// flags those live in no sample, derives their weighted-cascade thresholds and
+// clears a slice of the piece flags.
 template <int G, int DW>
 DEVI void tile_init(const BJob& jb, const BDesc& d, int tile, bool first_run) {
     constexpr int RPW = 64 / G;
@@ -265,8 +265,25 @@ DEVI void tile_init(const BJob& jb, const BDesc& d, int tile, bool first_run) {
             const int64_t u = base + grp;
             if (u < r1) {
                 const int64_t eb = jb.xadj[u], ee = jb.xadj[u + 1];
-                for (int64_t e = eb + p; e < ee; e += G)
-                    jb.eh[e] = mm3_key8((uint32_t)u, (uint32_t)jb.adj[e], jb.seed) & 0x7FFFFFFFu;
+                for (int64_t e = eb + p; e < ee; e += G) {
+                    // the id may carry the flag of an earlier run of this batch
+                    const int32_t v = adj_target(jb.adj[e]);
+                    const uint32_t h = mm3_key8((uint32_t)u, (uint32_t)v, jb.seed) & 0x7FFFFFFFu;
+                    jb.eh[e] = h;
+                    // an edge live in no sample (min_j (X_j xor h) >= t, Sec. 3.1) is
+                    // flagged in its target id: the sweeps and the reach skip it.  X_j
+                    // is wave-uniform; a wave stops once all its edges are live somewhere
+                    const uint32_t t = jb.kind == THR_CONST    ? jb.thr_const
+                                       : jb.kind == THR_TARGET ? wc_threshold(jb.indeg[v])
+                                                               : jb.thr[e];
+                    uint32_t mn = 0xFFFFFFFFu;
+                    for (int j0 = 0; j0 < jb.J; j0 += 16) {
+                        if (!__ballot(mn >= t)) break;
+                        for (int j = j0; j < j0 + 16 && j < jb.J; ++j)
+                            mn = min(mn, (mm3_key4((uint32_t)j, jb.seed + 2u) & 0x7FFFFFFFu) ^ h);
+                    }
+                    if (mn >= t) jb.adj[e] = (int32_t)((uint32_t)v | DEAD_EDGE);
+                }
             }
         }
         if (jb.npieces > 0) {
