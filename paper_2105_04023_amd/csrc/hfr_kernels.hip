@@ -1970,7 +1970,7 @@ hipError_t launch_reach_start(const Layout& L, const DevGraph& g, const GreedyBu
 
 // One BFS level over the queue of level `cur` (see bfs_expand_entries).
 template <int G, int DW, int KIND>
-__global__ __launch_bounds__(256) void k_bfs_expand(const int64_t* __restrict__ xadj, const int32_t* __restrict__ adj,
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(8, 8))) void k_bfs_expand(const int64_t* __restrict__ xadj, const int32_t* __restrict__ adj,
                                                     const uint32_t* __restrict__ eh, const uint32_t* __restrict__ thr,
                                                     uint32_t thr_const, const uint32_t* __restrict__ X, GreedyBufs b,
                                                     int cur, int32_t level_id_next, int P, int PW) {
