@@ -216,8 +216,8 @@ IM_API im_status im_sketch_get_trace(const im_sketch* sk, int64_t* live_counts, 
  * kernels of the sweep, from HIP events on the context stream; light_visits the edges
  * with a live head the row kernel visited, visits those of the whole sweep, live_next
  * |L_{t+1}|; light_merged and merged count the visited edges whose head's row was
- * merged, i.e. those live in at least one of the R samples (an edge live in none is
- * skipped after its live test, its head's row is not read).  ran = 0 marks a launch past the stopping rule (it returned at
+ * merged, i.e. those live in at least one of the R samples (an edge live in none still
+ * counts as visited, but its head's row, hash and threshold are not read).  ran = 0 marks a launch past the stopping rule (it returned at
  * once).  simulate numbers the Simulate calls of the sketch (0 = build,
  * later ones are rebuilds inside im_select_seeds). */
 typedef struct im_sweep_rec {
