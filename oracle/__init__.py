@@ -47,6 +47,12 @@ class Step(ctypes.Structure):
     ]
 
 
+# int obs(k, const uint8_t* M, const uint8_t* blk, const orc_step* st, int64_t sweeps,
+#         const int64_t* trace_live, const int64_t* trace_edges, void* user)
+_OBSERVER = ctypes.CFUNCTYPE(ctypes.c_int, ctypes.c_int32, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p,
+                             ctypes.c_int64, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p)
+
+
 def build(force: bool = False) -> str:
     """Compile the oracle with gcc: -O2, no FMA contraction, no fast-math."""
     if force or not os.path.exists(_SO) or os.path.getmtime(_SO) < os.path.getmtime(_SRC):
@@ -89,6 +95,9 @@ def _load():
             lib.orc_greedy.argtypes = [i64, p, p, p, i32, u32, i32, ctypes.c_double, ctypes.c_double,
                                        ctypes.c_double, p, p, p, p, p]
             lib.orc_greedy.restype = ctypes.c_int
+            lib.orc_greedy_observed.argtypes = [i64, p, p, p, i32, u32, i32, ctypes.c_double, ctypes.c_double,
+                                                ctypes.c_double, p, p, p, p, p, _OBSERVER, p]
+            lib.orc_greedy_observed.restype = ctypes.c_int
             _lib = lib
     return _lib
 
@@ -186,8 +195,16 @@ def reach_add(graph, thr: np.ndarray, J: int, seed: int, blk: np.ndarray, s: int
 
 
 def greedy(graph, thr: np.ndarray, J: int, K: int, seed: int = 0, eps_g: float = 0.01, eps_l: float = 0.3,
-           eps_c: float = 0.0, want_blk: bool = False):
-    """Alg. 1.  Returns a dict: seeds, steps (list of dicts), M (final registers), blk, build_sweeps, build_visits."""
+           eps_c: float = 0.0, want_blk: bool = False, observer=None):
+    """Alg. 1.  Returns a dict: seeds, steps (list of dicts), M (final registers), blk, build_sweeps, build_visits.
+
+    observer (optional) is called as observer(k, M, blk, step, trace_live, trace_edges) with numpy views
+    of the oracle's own buffers (valid during the call only): k = 0 once after the build (M = the build's
+    registers, trace_live[t] = |L_t| for t = 0..sweeps, trace_edges[t] = visits of sweep t, blk and step
+    None), then k = 1..K after each step, before its rebuild (M = registers the step used, blk = blocked
+    pairs after it, step = its record as a dict): the final state of a run with K = k.  A true return value
+    ends the run; the result then holds the steps done ("stopped_after").
+    """
     xadj, adj = _csr(graph)
     n = graph.n
     if not (1 <= K <= n):
@@ -198,11 +215,29 @@ def greedy(graph, thr: np.ndarray, J: int, K: int, seed: int = 0, eps_g: float =
     bs = ctypes.c_int64()
     bv = ctypes.c_int64()
     thr = np.ascontiguousarray(thr, dtype=np.uint32)
-    rc = _load().orc_greedy(n, _p(xadj), _p(adj), _p(thr), J, seed & 0xFFFFFFFF, K, eps_g, eps_l, eps_c, _p(M),
-                            _p(blk), ctypes.cast(steps, ctypes.c_void_p), ctypes.byref(bs), ctypes.byref(bv))
-    if rc != 0:
+    last = [0]
+
+    def _obs(k, pM, pblk, pst, sweeps, ptl, pte, user):
+        def view(ptr, count, dt):
+            return np.ctypeslib.as_array(ctypes.cast(ptr, ctypes.POINTER(dt)), shape=(count,))
+        Mv = view(pM, n * J, ctypes.c_uint8).reshape(n, J)
+        last[0] = k
+        if k == 0:
+            tl = view(ptl, sweeps + 1, ctypes.c_int64).copy()
+            te = view(pte, max(sweeps, 1), ctypes.c_int64)[:sweeps].copy()
+            return int(bool(observer(0, Mv, None, None, tl, te)))
+        st = ctypes.cast(pst, ctypes.POINTER(Step)).contents
+        rec = {f: getattr(st, f) for f, _ in Step._fields_}
+        return int(bool(observer(k, Mv, view(pblk, n * J, ctypes.c_uint8).reshape(n, J), rec, None, None)))
+
+    cb = _OBSERVER(_obs) if observer is not None else _OBSERVER()
+    rc = _load().orc_greedy_observed(n, _p(xadj), _p(adj), _p(thr), J, seed & 0xFFFFFFFF, K, eps_g, eps_l, eps_c,
+                                     _p(M), _p(blk), ctypes.cast(steps, ctypes.c_void_p), ctypes.byref(bs),
+                                     ctypes.byref(bv), cb, None)
+    if rc < 0:
         raise MemoryError("oracle greedy")
-    recs = [{f: getattr(s, f) for f, _ in Step._fields_} for s in steps]
+    done = K if rc == 0 else last[0]
+    recs = [{f: getattr(s, f) for f, _ in Step._fields_} for s in steps[:done]]
     return {
         "seeds": [r["seed"] for r in recs],
         "steps": recs,
@@ -210,4 +245,5 @@ def greedy(graph, thr: np.ndarray, J: int, K: int, seed: int = 0, eps_g: float =
         "blk": blk,
         "build_sweeps": bs.value,
         "build_visits": bv.value,
+        "stopped_after": None if rc == 0 else done,
     }

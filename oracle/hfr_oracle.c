@@ -327,6 +327,18 @@ typedef struct {
 } orc_step;
 
 /*
+ * Observer of a greedy run, for recording expected values of long runs.  It is
+ * called once after the build's Simulate (k = 0: M holds the build's registers,
+ * sweeps and the two traces describe that Simulate, blk and st are NULL) and once
+ * after every step k >= 1, when that step's record is complete and before its
+ * rebuild (if any) starts: M then holds the registers the step used and blk the
+ * blocked pairs after it, which is exactly the final state of a run with K = k
+ * (no rebuild follows the last step, reading R9).  A nonzero return ends the run.
+ */
+typedef int (*orc_observer)(int32_t k, const uint8_t* M, const uint8_t* blk, const orc_step* st, int64_t sweeps,
+                            const int64_t* trace_live, const int64_t* trace_edges, void* user);
+
+/*
  * Alg. 1 (HyperFuseR) with the readings R1-R10:
  *
  *   M = Simulate(no blocks); M_S' = 0; varsigma = 0; S = {}
@@ -343,11 +355,13 @@ typedef struct {
  * delta = (R - R_at_last_rebuild) / J.  M (n*J bytes) holds the final
  * registers on return; blk (n*J bytes) the final blocked pairs (may be NULL
  * for an internal buffer).  build_sweeps/build_visits describe the initial
- * Simulate.  Returns 0, or -1 on allocation failure.
+ * Simulate.  obs (may be NULL) is called as described above.  Returns 0, 1 if
+ * the observer ended the run early, or -1 on allocation failure.
  */
-int orc_greedy(int64_t n, const int64_t* xadj, const int32_t* adj, const uint32_t* thr_edge, int32_t J, uint32_t seed,
-               int32_t K, double eps_g, double eps_l, double eps_c, uint8_t* M, uint8_t* blk_out, orc_step* steps,
-               int64_t* build_sweeps, int64_t* build_visits) {
+int orc_greedy_observed(int64_t n, const int64_t* xadj, const int32_t* adj, const uint32_t* thr_edge, int32_t J,
+                        uint32_t seed, int32_t K, double eps_g, double eps_l, double eps_c, uint8_t* M,
+                        uint8_t* blk_out, orc_step* steps, int64_t* build_sweeps, int64_t* build_visits,
+                        orc_observer obs, void* user) {
     uint8_t* blk = blk_out ? blk_out : calloc((size_t)(n * J > 0 ? n * J : 1), 1);
     uint8_t* inS = calloc((size_t)(n > 0 ? n : 1), 1);
     uint8_t* MS = calloc((size_t)J, 1);
@@ -357,15 +371,17 @@ int orc_greedy(int64_t n, const int64_t* xadj, const int32_t* adj, const uint32_
     int64_t* te = malloc(sizeof(int64_t) * (size_t)cap);
     if (!blk || !inS || !MS || !merged || !tl || !te) return -1;
     if (blk_out) memset(blk, 0, (size_t)(n * J));
+    int rc = 0;
 
     int64_t sw = orc_simulate(n, xadj, adj, thr_edge, J, seed, NULL, eps_c, -1, M, tl, te, cap);
     int64_t vis = 0;
     for (int64_t t = 0; t < sw && t < cap; ++t) vis += te[t];
     *build_sweeps = sw;
     *build_visits = vis;
+    if (obs && obs(0, M, NULL, NULL, sw, tl, te, user)) rc = 1;
 
     int64_t R = 0, R_rebuild = 0;
-    for (int32_t k = 1; k <= K; ++k) {
+    for (int32_t k = 1; k <= K && rc == 0; ++k) {
         int64_t best = -1;
         int32_t s = -1;
         for (int64_t v = 0; v < n; ++v) {
@@ -399,7 +415,8 @@ int orc_greedy(int64_t n, const int64_t* xadj, const int32_t* adj, const uint32_
         st->rebuilt = 0;
         st->sweeps = 0;
         st->visits = 0;
-        if (k < K) {
+        if (obs && obs(k, M, blk, st, 0, NULL, NULL, user)) rc = 1;
+        if (k < K && rc == 0) {
             if (fresh) {
                 memcpy(MS, merged, (size_t)J);
             } else {
@@ -420,5 +437,13 @@ int orc_greedy(int64_t n, const int64_t* xadj, const int32_t* adj, const uint32_
     free(merged);
     free(tl);
     free(te);
-    return 0;
+    return rc;
+}
+
+/* Alg. 1 without an observer. */
+int orc_greedy(int64_t n, const int64_t* xadj, const int32_t* adj, const uint32_t* thr_edge, int32_t J, uint32_t seed,
+               int32_t K, double eps_g, double eps_l, double eps_c, uint8_t* M, uint8_t* blk_out, orc_step* steps,
+               int64_t* build_sweeps, int64_t* build_visits) {
+    return orc_greedy_observed(n, xadj, adj, thr_edge, J, seed, K, eps_g, eps_l, eps_c, M, blk_out, steps,
+                               build_sweeps, build_visits, NULL, NULL);
 }

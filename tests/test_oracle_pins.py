@@ -246,6 +246,79 @@ def test_sweep_states_counts_and_traces(gi):
     assert sweeps <= dmax + 1
 
 
+def _bf_blocked_trace(g, gs, rk, blocked):
+    """Sweep count, |L_t| and edge-visit traces of Simulate on the residual graph, from the brute-force
+    sweep states: L_0 = V, L_t = rows changed by sweep t-1, and sweep t visits the edges (u, v) with v in
+    L_t whose source u is not blocked in every sample (reading 11: such a row holds zeros and cannot
+    change, so its edges are not visited)."""
+    J = len(gs)
+    full = np.array([all(u in blocked[j] for j in range(J)) for u in range(g.n)])
+    states = [bf.hop_state(gs, rk, 0, blocked)]
+    while True:
+        states.append(bf.hop_state(gs, rk, len(states), blocked))
+        if np.array_equal(states[-1], states[-2]):
+            break
+    sweeps = len(states) - 1  # the last sweep changes nothing and detects the fixed point
+    L = [np.ones(g.n, bool)] + [(states[t] != states[t - 1]).any(axis=1) for t in range(1, sweeps + 1)]
+    src = np.repeat(np.arange(g.n), np.diff(g.xadj))
+    te = [int((L[t][g.adj] & ~full[src]).sum()) for t in range(sweeps)]
+    return sweeps, [int(x.sum()) for x in L], te, states[-1]
+
+
+@pytest.mark.parametrize("gi", [0, 2, 4, 5])
+def test_edge_trace_under_blocking(gi):
+    """Reading 11 on Simulate(blocked): with (a) the reach of a seed set, whose seeds are blocked in every
+    sample, and (b) an arbitrary pattern with some vertices blocked in every sample, the sweep count, the
+    |L_t| trace and the per-sweep edge visits equal their definitions on the brute-force sweep states."""
+    g = _tiny_graphs()[gi]
+    J = 8
+    thr = oracle.edge_thresholds(g, "const", f32(0.45))
+    gs = bf.sample_graphs(g, thr, J)
+    rk = bf.ranks(g.n, J)
+    rng = np.random.default_rng(50 + gi)
+    S = [int(x) for x in rng.choice(g.n, 2, replace=False)]
+    arb = [set(int(x) for x in np.nonzero(rng.random(g.n) < 0.25)[0]) for _ in range(J)]
+    everywhere = [int(x) for x in rng.choice(g.n, 3, replace=False)]
+    for b in arb:
+        b.update(everywhere)
+    for blocked in (bf.reach_sets(gs, S), arb):
+        blk = np.zeros((g.n, J), dtype=np.uint8)
+        for j, b in enumerate(blocked):
+            for v in b:
+                blk[v, j] = 1
+        assert blk.all(axis=1).any()  # reading 11 is exercised
+        M, sweeps, tl, te = oracle.simulate(g, thr, J, blk=blk)
+        bsw, btl, bte, bM = _bf_blocked_trace(g, gs, rk, blocked)
+        assert sweeps == bsw
+        assert list(tl) == btl
+        assert list(te) == bte
+        assert np.array_equal(M.astype(np.int64), bM)
+        # the unblocked count differs whenever a fully blocked row has an out-edge into L_0 = V
+        src_full = blk.all(axis=1)[np.repeat(np.arange(g.n), np.diff(g.xadj))]
+        if src_full.any():
+            assert te[0] == g.m - int(src_full.sum())
+
+
+@pytest.mark.parametrize("gi,model,p", [(1, "const", 0.3), (4, "const", 0.2), (2, "wc", 0.0)])
+def test_rebuild_visits_and_sweeps(gi, model, p):
+    """Always-rebuild greedy: each step's rebuild runs Simulate on the residual graph of the seeds so far;
+    its sweep count and its edge visits (summed over its sweeps, reading 11) equal the brute-force ones."""
+    g = _tiny_graphs()[gi]
+    J, K = 8, 5
+    thr = oracle.edge_thresholds(g, model, f32(p))
+    gs = bf.sample_graphs(g, thr, J)
+    rk = bf.ranks(g.n, J)
+    res = oracle.greedy(g, thr, J, K, eps_g=0.0, eps_l=0.0)
+    _, bsw0, _, bte0, _ = (None,) + _bf_blocked_trace(g, gs, rk, [set() for _ in range(J)])
+    assert res["build_sweeps"] == bsw0 and res["build_visits"] == sum(bte0)
+    for k in range(K - 1):
+        st = res["steps"][k]
+        bsw, _, bte, _ = _bf_blocked_trace(g, gs, rk, bf.reach_sets(gs, res["seeds"][: k + 1]))
+        assert st["rebuilt"] == 1
+        assert st["sweeps"] == bsw, k
+        assert st["visits"] == sum(bte), k
+
+
 def test_early_exit_threshold():
     # eps_c: stop as soon as |L| <= eps_c * n (Sec. 3.2).
     g = _tiny_graphs()[5]
