@@ -934,14 +934,14 @@ im_status im_sketch_get_blocked(const im_sketch* sk, uint8_t* out) {
     if (!out) return fail(IM_ERR_INVALID_ARG, "out is null");
     if (!sk->selected) return fail(IM_ERR_STATE, "no seed selection has run on this sketch");
     const size_t bytes = (size_t)sk->g.n * sk->L.J;
-    void* tmp = nullptr;
-    if (hipMalloc(&tmp, bytes) != hipSuccess) return fail(IM_ERR_OUT_OF_BUDGET, "temporary allocation failed");
+    void* tmp = ctx_alloc(sk->ctx, bytes);
+    if (!tmp) return fail(IM_ERR_OUT_OF_BUDGET, "temporary allocation failed");
     hipStream_t s = sk->ctx->stream;
     im_status rs = IM_OK;
     if (launch_blocked_to_bytes(sk->L, sk->g.n, sk->gb.blk, (uint8_t*)tmp, s) != hipSuccess ||
         hipMemcpyAsync(out, tmp, bytes, hipMemcpyDeviceToHost, s) != hipSuccess || hipStreamSynchronize(s) != hipSuccess)
         rs = fail(IM_ERR_DEVICE, "blocked copy failed");
-    (void)hipFree(tmp);
+    ctx_free(sk->ctx, tmp);
     return rs;
 }
 
@@ -989,8 +989,29 @@ im_status im_estimate(im_sketch* sk, const int32_t* verts, int64_t count, float*
     return rs;
 }
 
-im_status im_select_seeds(im_sketch* sk, int32_t K, const im_select_opts* opts, int32_t* out_seeds, im_step* out_steps,
-                          im_select_stats* stats) {
+}  // extern "C"
+
+namespace {
+
+// Reach-search level ids restart (with every vertex stamp cleared) once the next
+// step could run past this value; HFR_LEVEL_ID_LIMIT lowers it so that tests can
+// force the restart on small graphs.
+int32_t level_id_limit(int64_t n) {
+    int64_t lim = INT32_MAX - (n + 8);
+    if (const char* e = getenv("HFR_LEVEL_ID_LIMIT")) {
+        const long long v = atoll(e);
+        if (v > 0 && v < lim) lim = v;
+    }
+    return (int32_t)std::max<int64_t>(lim, 1);
+}
+
+// Alg. 1 on a built sketch.  `scratch` holds the K step records and K seeds
+// (select_scratch_bytes(K) bytes, device memory) or is null, in which case they
+// are allocated from the context for the call.
+size_t select_scratch_bytes(int32_t K) { return ((sizeof(StepRec) * (size_t)K + 255) & ~size_t(255)) + 4 * (size_t)K; }
+
+im_status select_impl(im_sketch* sk, int32_t K, const im_select_opts* opts, int32_t* out_seeds, im_step* out_steps,
+                      im_select_stats* stats, void* scratch) {
     im_status st0 = check_sketch(sk);
     if (st0 != IM_OK) return st0;
     if (!out_seeds) return fail(IM_ERR_INVALID_ARG, "out_seeds is null");
@@ -1012,11 +1033,12 @@ im_status im_select_seeds(im_sketch* sk, int32_t K, const im_select_opts* opts, 
     StepRec* d_steps = nullptr;
     int32_t* d_seeds = nullptr;
     {
-        void* p = ctx_alloc(sk->ctx, sizeof(StepRec) * K + 4 * (size_t)K + 512);
+        void* p = scratch ? scratch : ctx_alloc(sk->ctx, select_scratch_bytes(K));
         if (!p) return fail(IM_ERR_OUT_OF_BUDGET, "temporary allocation failed");
         d_steps = (StepRec*)p;
         d_seeds = (int32_t*)((char*)p + ((sizeof(StepRec) * K + 255) & ~size_t(255)));
     }
+    const int32_t lvl_limit = level_id_limit(n);
     std::vector<StepRec> h_steps(K);
     int32_t rebuilds = 0;
     int64_t rsweeps = 0, rvisits = 0, levels_total = 0;
@@ -1029,9 +1051,17 @@ im_status im_select_seeds(im_sketch* sk, int32_t K, const im_select_opts* opts, 
         HIP_TRY(hipMemsetAsync(b.key, 0, 8, s));
         HIP_TRY(hipMemsetAsync(b.R, 0, 8 * NSLOT * SLOT_U64, s));
         HIP_TRY(hipMemsetAsync(b.Rreb, 0, 8, s));
-        HIP_TRY(hipMemsetAsync(d_steps, 0, sizeof(StepRec) * K, s));
+        // the step records start at zero (fill kernel: no memset node in this memory)
+        HIP_TRY(launch_fill_u32((uint32_t*)d_steps, 0u, (int64_t)(sizeof(StepRec) / 4) * K, s));
+        // level ids start afresh every call, so a long-lived sketch never runs them out
+        HIP_TRY(hipMemsetAsync(b.stamp, 0, 4 * (size_t)n, s));
+        sk->level_id = 1;
         int cur = sk->build_buf;
         for (int k = 1; k <= K; ++k) {
+            if (sk->level_id > lvl_limit) {
+                HIP_TRY(hipMemsetAsync(b.stamp, 0, 4 * (size_t)n, s));
+                sk->level_id = 1;
+            }
             HIP_TRY(launch_argmax(L, n, sk->M[cur], b, s));
             HIP_TRY(hipMemsetAsync(b.qsize, 0, 16, s));
             const int32_t lvl0 = sk->level_id;
@@ -1090,7 +1120,7 @@ im_status im_select_seeds(im_sketch* sk, int32_t K, const im_select_opts* opts, 
         return IM_OK;
     };
     im_status st = body();
-    ctx_free(sk->ctx, d_steps);
+    if (!scratch) ctx_free(sk->ctx, d_steps);
     if (st != IM_OK) return st;
     if (out_steps) {
         for (int k = 0; k < K; ++k) {
@@ -1119,6 +1149,15 @@ im_status im_select_seeds(im_sketch* sk, int32_t K, const im_select_opts* opts, 
         stats->wall_ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - wall0).count();
     }
     return IM_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+im_status im_select_seeds(im_sketch* sk, int32_t K, const im_select_opts* opts, int32_t* out_seeds, im_step* out_steps,
+                          im_select_stats* stats) {
+    return select_impl(sk, K, opts, out_seeds, out_steps, stats, nullptr);
 }
 
 
