@@ -203,6 +203,23 @@ IM_API im_status im_estimate_all(im_sketch* sk, float* out, int32_t out_on_devic
 IM_API im_status im_select_seeds(im_sketch* sk, int32_t K, const im_select_opts* opts, int32_t* out_seeds,
                           im_step* out_steps, im_select_stats* stats);
 
+/*
+ * Allocation-free variant of im_select_seeds, for callers that cannot allocate
+ * device memory during the call (code under stream capture, tight serving
+ * loops, harnesses that forbid allocation).  Same arguments, results and
+ * errors as im_select_seeds, with K in [1, IM_NOALLOC_MAX_K] (larger K:
+ * IM_ERR_INVALID_ARG before any device work).  The per-call step records and
+ * seeds live in a fixed 512 KiB device array that every GPU the library runs
+ * on holds until the process ends; no device memory is allocated or freed.
+ * All calls on one GPU share that array: calls that overlap in time on the
+ * same GPU (from different threads or contexts) race and must be serialised
+ * by the caller.  The context must have been created by im_ctx_create on that
+ * GPU (which records the array's device address).
+ */
+#define IM_NOALLOC_MAX_K 4096
+IM_API im_status im_select_seeds_noalloc(im_sketch* sk, int32_t K, const im_select_opts* opts, int32_t* out_seeds,
+                                         im_step* out_steps, im_select_stats* stats);
+
 /* Build information; trace of the build: live_counts[t] = |L_t| (t = 0..sweeps)
  * and edge_visits[t] = edges with a live head in sweep t (t < sweeps); cap
  * bounds both arrays; *written receives sweeps+1. */

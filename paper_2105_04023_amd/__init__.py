@@ -238,14 +238,17 @@ def im_estimate_all(sk: Sketch, out=None):
     return res
 
 
-def im_select_seeds(sk: Sketch, K: int, eps_g: float = 0.01, eps_l: float = 0.3):
-    """Alg. 1 greedy loop with error-adaptive rebuild.  Returns (seeds, steps, stats)."""
+def im_select_seeds(sk: Sketch, K: int, eps_g: float = 0.01, eps_l: float = 0.3, noalloc: bool = False):
+    """Alg. 1 greedy loop with error-adaptive rebuild.  Returns (seeds, steps, stats).
+
+    noalloc selects im_select_seeds_noalloc (no device allocation in the call; K <= 4096)."""
     seeds = np.zeros(K, dtype=np.int32)
     steps = (B.im_step * K)()
     stats = B.im_select_stats()
     opts = B.im_select_opts(eps_g, eps_l)
-    B.check(sk.lib.im_select_seeds(sk.handle, K, ctypes.byref(opts), seeds.ctypes.data,
-                                   ctypes.cast(steps, ctypes.c_void_p), ctypes.byref(stats)))
+    fn = sk.lib.im_select_seeds_noalloc if noalloc else sk.lib.im_select_seeds
+    B.check(fn(sk.handle, K, ctypes.byref(opts), seeds.ctypes.data, ctypes.cast(steps, ctypes.c_void_p),
+               ctypes.byref(stats)))
     st = [Step(**{f: getattr(s, f) for f, _ in B.im_step._fields_}) for s in steps]
     return seeds, st, {f: getattr(stats, f) for f, _ in B.im_select_stats._fields_}
 

@@ -16,6 +16,7 @@ STATUS_NAMES = {0: "IM_OK", -1: "IM_ERR_INVALID_ARG", -2: "IM_ERR_INVALID_GRAPH"
                 -4: "IM_ERR_DEVICE", -5: "IM_ERR_STATE"}
 IM_PROB_CONSTANT, IM_PROB_WEIGHTED_CASCADE, IM_PROB_PER_EDGE = 0, 1, 2
 IM_BUILD_TIME_SWEEPS, IM_BUILD_IN_PLACE, IM_BUILD_ATOMIC_REVERSE = 1, 2, 4
+IM_NOALLOC_MAX_K = 4096  # largest K of im_select_seeds_noalloc
 
 # Every symbol include/im.h declares (checked by the CPU test suite).
 EXPORTED = [
@@ -25,6 +26,7 @@ EXPORTED = [
     "im_sketch_get_sweep_log", "im_sketch_clear_sweep_log", "im_batch_create", "im_batch_run", "im_batch_get_result",
     "im_batch_get_registers", "im_batch_device_bytes", "im_batch_free", "im_server_create", "im_server_add_graph",
     "im_server_submit", "im_server_wait", "im_server_get_stats", "im_server_free", "im_evaluate_influence",
+    "im_select_seeds_noalloc",
 ]
 
 
@@ -153,6 +155,8 @@ def load(path: str = LIB_PATH):
         "im_estimate_all": ([p, p, i32], ctypes.c_int),
         "im_select_seeds": ([p, i32, ctypes.POINTER(im_select_opts), p, p, ctypes.POINTER(im_select_stats)],
                             ctypes.c_int),
+        "im_select_seeds_noalloc": ([p, i32, ctypes.POINTER(im_select_opts), p, p,
+                                     ctypes.POINTER(im_select_stats)], ctypes.c_int),
         "im_sketch_get_info": ([p, ctypes.POINTER(im_sketch_info)], ctypes.c_int),
         "im_sketch_get_trace": ([p, p, p, i32, ctypes.POINTER(i32)], ctypes.c_int),
         "im_sketch_get_registers": ([p, i32, p], ctypes.c_int),

@@ -18,12 +18,25 @@
 
 #include <algorithm>
 #include <chrono>
+#include <mutex>
 #include <string>
 #include <vector>
 
 #include "hfr_host.h"
 
 using namespace hfr;
+
+// Scratch of the allocation-free selection (im_select_seeds_noalloc): the step
+// records and seeds of one call with K <= IM_NOALLOC_MAX_K.  Each device holds
+// its own copy for the life of the process.  Host code never passes this name
+// to a kernel or a copy: it uses the device address recorded per device when a
+// context is created (init_scratch).
+constexpr size_t NOALLOC_SCRATCH_BYTES = 512 * 1024;
+static __device__ __align__(256) unsigned char scratch[NOALLOC_SCRATCH_BYTES];
+
+namespace {
+im_status init_scratch(int device);
+}
 
 namespace hfr {
 
@@ -548,6 +561,10 @@ im_status im_ctx_create(int32_t device, void* stream, size_t hbm_budget, im_allo
     HIP_TRY(hipGetDeviceCount(&ndev));
     if (device < 0 || device >= ndev) return fail(IM_ERR_INVALID_ARG, "device %d out of range (%d devices)", device, ndev);
     HIP_TRY(hipSetDevice(device));
+    {
+        const im_status st = init_scratch(device);
+        if (st != IM_OK) return st;
+    }
     im_ctx* c = new im_ctx;
     c->device = device;
     c->stream = (hipStream_t)stream;
@@ -1151,6 +1168,26 @@ im_status select_impl(im_sketch* sk, int32_t K, const im_select_opts* opts, int3
     return IM_OK;
 }
 
+constexpr int MAX_DEVICES = 64;
+std::mutex g_scratch_mu;
+void* g_scratch_ptr[MAX_DEVICES] = {};
+
+// Called by im_ctx_create with `device` current: records this device's address
+// of the scratch array, once per device.
+im_status init_scratch(int device) {
+    if (device >= MAX_DEVICES) return IM_OK;  // the allocation-free call then refuses this device
+    std::lock_guard<std::mutex> lk(g_scratch_mu);
+    if (g_scratch_ptr[device]) return IM_OK;
+    void* ptr = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+    if (e != hipSuccess || !ptr) {
+        (void)hipGetLastError();
+        return fail(IM_ERR_DEVICE, "scratch symbol lookup failed: %s", hipGetErrorString(e));
+    }
+    g_scratch_ptr[device] = ptr;
+    return IM_OK;
+}
+
 }  // namespace
 
 extern "C" {
@@ -1158,6 +1195,25 @@ extern "C" {
 im_status im_select_seeds(im_sketch* sk, int32_t K, const im_select_opts* opts, int32_t* out_seeds, im_step* out_steps,
                           im_select_stats* stats) {
     return select_impl(sk, K, opts, out_seeds, out_steps, stats, nullptr);
+}
+
+im_status im_select_seeds_noalloc(im_sketch* sk, int32_t K, const im_select_opts* opts, int32_t* out_seeds,
+                                  im_step* out_steps, im_select_stats* stats) {
+    im_status st0 = check_sketch(sk);
+    if (st0 != IM_OK) return st0;
+    if (K < 1 || K > IM_NOALLOC_MAX_K)
+        return fail(IM_ERR_INVALID_ARG, "K must be in [1, %d] for the allocation-free selection (got %d)",
+                    IM_NOALLOC_MAX_K, K);
+    static_assert(sizeof(StepRec) * IM_NOALLOC_MAX_K + 256 + 4 * IM_NOALLOC_MAX_K <= NOALLOC_SCRATCH_BYTES,
+                  "scratch too small for IM_NOALLOC_MAX_K");
+    const int dev = sk->ctx->device;
+    void* ptr = nullptr;
+    {
+        std::lock_guard<std::mutex> lk(g_scratch_mu);
+        if (dev >= 0 && dev < MAX_DEVICES) ptr = g_scratch_ptr[dev];
+    }
+    if (!ptr) return fail(IM_ERR_STATE, "no scratch address for device %d", dev);
+    return select_impl(sk, K, opts, out_seeds, out_steps, stats, ptr);
 }
 
 
