@@ -96,7 +96,7 @@ typedef struct im_build_opts {
     int32_t piece_edges;  /* edges per piece of a split row, at most 2048 (0: 256) */
     int32_t sparse_div;   /* sweep t > 0 visits only the rows next to L_t when the
                              in-degrees of L_t sum to at most m / sparse_div
-                             (0: 48; < 0: never) */
+                             (0: 8; < 0: never) */
     int32_t flags;        /* IM_BUILD_* bits */
 } im_build_opts;
 

@@ -660,7 +660,7 @@ im_status build_sketch(im_ctx* ctx, const im_csr* graph, const im_probs* probs, 
          sk_alloc(sk, &sk->vis_ring, (size_t)3 * RING * NSLOT * SLOT_U64) && sk_alloc(sk, &sk->gather, 2 * GATHER * MAX_BATCH);
     ok = ok && sk_alloc(sk, &sk->d_err, 4) && sk_alloc(sk, &sk->d_heavy_counts, 4) && sk_alloc(sk, &sk->d_flag, 4);
     sk->fr.chunk = 256;
-    sk->fr.sparse_div = o.sparse_div < 0 ? 0u : (o.sparse_div == 0 ? 48u : (uint32_t)o.sparse_div);
+    sk->fr.sparse_div = o.sparse_div < 0 ? 0u : (o.sparse_div == 0 ? 8u : (uint32_t)o.sparse_div);
     {
         // coarse copy of L_t: at least 256 vertices per bit, at most COARSE_WORDS
         // words; used by the one-row-per-wave kernels while at most half of its
@@ -796,8 +796,12 @@ im_status build_sketch(im_ctx* ctx, const im_csr* graph, const im_probs* probs, 
             if (!pm_ || !sk->rev_tmp) return fail(IM_ERR_OUT_OF_BUDGET, "temporary allocation failed");
             uint32_t* indeg = nullptr;
             if (one_stream) {
-                // a counting sort on the target, with LDS counters only
-                HIP_TRY(launch_reverse_csr_buckets(g, sk->rev_tmp, &indeg, s));
+                // a counting sort on the target, with LDS counters only; its records of
+                // edges live in no sample are flagged as they are placed (the thresholds of
+                // constant p and of the weighted cascade depend on the target only)
+                DeadTest dt{sk->X, R, hash_seed, g.thr_const,
+                            probs->kind == IM_PROB_CONSTANT ? 1 : (probs->kind == IM_PROB_WEIGHTED_CASCADE ? 2 : 0)};
+                HIP_TRY(launch_reverse_csr_buckets(g, sk->rev_tmp, &indeg, dt, s));
             } else {
                 // global atomics, the scatter on the aux stream beside the sweeps
                 indeg = (uint32_t*)sk->rev_tmp;

@@ -145,6 +145,7 @@ hipError_t launch_wc_thresholds(const uint32_t* indeg, uint32_t* thr, int64_t n,
 hipError_t launch_gather_u32(const uint32_t* src, const int32_t* idx, int64_t m, uint32_t* out, hipStream_t s);
 hipError_t launch_edge_thresholds(const float* w, uint32_t* thr, int64_t m, uint32_t* err, hipStream_t s);
 hipError_t launch_sim_words(uint32_t* X, uint32_t* HJ, int J, uint32_t seed, hipStream_t s);
+
 // Sets DEAD_EDGE in the target id of every edge live in no sample (thresholds final).
 hipError_t launch_dead_edges(const DevGraph& g, const uint32_t* X, int J, hipStream_t s);
 hipError_t launch_heavy_count(const DevGraph& g, int64_t piece_edges, unsigned long long* counts, hipStream_t s);
@@ -161,7 +162,17 @@ hipError_t launch_reverse_csr(const DevGraph& g, const uint32_t* indeg, int64_t*
 // (graphs with n <= 2^25 and m < 2^31: rb_fits).
 bool rb_fits(int64_t n, int64_t m);
 size_t rb_temp_bytes(int64_t n, int64_t m);
-hipError_t launch_reverse_csr_buckets(const DevGraph& g, void* tmp, uint32_t** indeg, hipStream_t s);
+// Edge-liveness test applied to the reverse CSR's records as they are placed:
+// mode 0 none, 1 constant threshold thr_const, 2 weighted cascade (1/indeg(v)).
+struct DeadTest {
+    const uint32_t* X;  // J sample words
+    int J;
+    uint32_t seed;
+    uint32_t thr_const;
+    int mode;
+};
+hipError_t launch_reverse_csr_buckets(const DevGraph& g, void* tmp, uint32_t** indeg, const DeadTest& dt,
+                                      hipStream_t s);
 hipError_t launch_heavy_slots(const DevGraph& g, hipStream_t s);
 hipError_t launch_light_rows(const DevGraph& g, uint32_t* flags, int64_t* pos, uint32_t* scan_tmp, hipStream_t s);
 hipError_t launch_full_blocked(const Layout& L, int64_t n, const uint32_t* blk, uint32_t* fullblk, hipStream_t s);

@@ -561,6 +561,11 @@ __global__ __launch_bounds__(256) void k_sweep_frontier(const uint32_t* __restri
 // Sparse sweep: marks the source rows of the in-edges of L_t.  An in-edge from
 // a row that is not split sets the row's bit in `mark`; an in-edge from a
 // split row sets the bit of its 64-edge window in its piece's window mask.
+// In-edges live in no sample (flagged in the reverse CSR) and in-edges from rows
+// blocked in every sample mark nothing: such a row merges nothing through them.
+// The sweep's edge visits -- in-edges of L_t whose source is not blocked in
+// every sample -- are counted here, per source kind (split or not), so the row
+// and piece kernels of a sparse sweep count only the rows they merge.
 // Nothing is listed here: the marked rows are listed afterwards with one
 // atomic per wave, and the piece kernel finds its pieces by scanning the
 // window masks, so each in-edge costs one random access and no shared counter
@@ -570,19 +575,31 @@ __global__ __launch_bounds__(256) void k_sweep_expand(const uint32_t* __restrict
                                                       int first, int64_t n, Frontier fr, int parity,
                                                       const int64_t* __restrict__ rxadj,
                                                       const int32_t* __restrict__ radj,
-                                                      const int32_t* __restrict__ rpiece, int32_t wpp) {
+                                                      const int32_t* __restrict__ rpiece, int32_t wpp,
+                                                      const uint32_t* __restrict__ fullblk,
+                                                      unsigned long long* __restrict__ vis_light,
+                                                      unsigned long long* __restrict__ vis_heavy) {
+    __shared__ unsigned long long sh64[4];
     const uint32_t live = sweep_live(gate, gate_thresh, first, n);
     if (!live || !sweep_sparse(sgate, first, m, fr.sparse_div)) return;
     const uint32_t nitems = fr.counts[4 * parity];
     const int lane = threadIdx.x & 63;
+    unsigned long long my_light = 0, my_heavy = 0;
     for (int64_t it = wave_index(); it < (int64_t)nitems; it += wave_count()) {
         const int2 item = fr.items[it];
         const int64_t vb = rxadj[item.x], ve = rxadj[item.x + 1];
         const int64_t e0 = vb + (int64_t)item.y * fr.chunk;
         const int64_t e1 = e0 + fr.chunk < ve ? e0 + fr.chunk : ve;
         for (int64_t e = e0 + lane; e < e1; e += 64) {
-            const int32_t u = radj[e];
+            const int32_t a = radj[e];
+            const int32_t u = adj_target(a);
             const int32_t wi = rpiece[e];
+            if (fullblk && bit_of(fullblk, u)) continue;  // neither visited nor marked
+            if (wi < 0)
+                ++my_light;
+            else
+                ++my_heavy;
+            if (adj_dead(a)) continue;
             // most rows are reached from several live vertices: test before
             // paying for the atomic
             uint32_t* word;
@@ -597,6 +614,13 @@ __global__ __launch_bounds__(256) void k_sweep_expand(const uint32_t* __restrict
             }
             if ((*word & bit) == 0u) atomicOr(word, bit);
         }
+    }
+    const unsigned long long bl = block_sum256(my_light, sh64);
+    const unsigned long long bh = block_sum256(my_heavy, sh64);
+    if (threadIdx.x == 0) {
+        const int slot = blockIdx.x % NSLOT;
+        if (bl) atomicAdd(&vis_light[slot * SLOT_U64], bl);
+        if (bh && vis_heavy) atomicAdd(&vis_heavy[slot * SLOT_U64], bh);
     }
 }
 
@@ -702,6 +726,7 @@ __global__ __launch_bounds__(256) void k_sweep_light(
             }
         }
     }
+    if (sparse) my_vis = 0;  // a sparse sweep's visits are counted by k_sweep_expand
     const uint32_t bc = block_sum256(my_cnt, sh32);
     const unsigned long long bv = block_sum256(my_vis, sh64);
     const unsigned long long bm = block_sum256(my_mrg, sh64);
@@ -970,6 +995,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(5, 8))) voi
             my_mrg += mrg;
         }
     }
+    if (sparse) my_vis = 0;  // a sparse sweep's visits are counted by k_sweep_expand
     const uint32_t bc = block_sum256(my_cnt, sh32);
     const unsigned long long bv = block_sum256(my_vis, sh64);
     const unsigned long long bm = block_sum256(my_mrg, sh64);
@@ -1159,6 +1185,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(7, 8))) voi
             }
         }
     }
+    if (sparse) my_vis = 0;  // a sparse sweep's visits are counted by k_sweep_expand
     const unsigned long long bv = block_sum256(my_vis, sh64);
     const unsigned long long bm = block_sum256(p == 0 ? my_mrg : 0ull, sh64);
     if (threadIdx.x == 0) {
@@ -1268,7 +1295,8 @@ hipError_t launch_sweep(const Layout& L, const DevGraph& g, const uint32_t* X, c
     hipLaunchKernelGGL(k_sweep_frontier, dim3(sg), dim3(256), 0, s, sp.gate, sp.gate_thresh, sp.sgate, g.m, sp.first,
                        g.n, sp.Lcur, sp.Lclear, sp.fr, sp.parity, g.rxadj);
     hipLaunchKernelGGL(k_sweep_expand, dim3(sg), dim3(256), 0, s, sp.gate, sp.gate_thresh, sp.sgate, g.m, sp.first, g.n,
-                       sp.fr, sp.parity, g.rxadj, g.radj, g.rpiece, (int32_t)((g.piece_edges + 63) / 64));
+                       sp.fr, sp.parity, g.rxadj, g.radj, g.rpiece, (int32_t)((g.piece_edges + 63) / 64), sp.fullblk,
+                       sp.vis_out, g.npieces > 0 ? sp.vis_heavy_out : nullptr);
     hipLaunchKernelGGL(k_sweep_compact, dim3(sg), dim3(256), 0, s, sp.gate, sp.gate_thresh, sp.sgate, g.m, sp.first,
                        g.n, sp.fr, sp.parity);
     hipError_t err = hipGetLastError();
@@ -1651,22 +1679,55 @@ __global__ __launch_bounds__(1024) void k_rb_fscan(const int64_t* __restrict__ o
         }
 }
 
-// Per chunk: places its records at their slots (radj, rpiece).
+// Per chunk: places its records at their slots (radj, rpiece).  With dt.mode
+// set, a record whose edge is live in no sample gets DEAD_EDGE in its source
+// id -- the test k_dead_edges applies to the out-edges, with the hash
+// recomputed from (u, v) (Eq. hash) and a threshold that depends on the target
+// only: constant p (mode 1), or the weighted cascade's 1/indeg(v) (mode 2), the
+// in-degree being the length of v's in-edge list.  A sparse sweep marks no row
+// for a flagged in-edge.
 __global__ __launch_bounds__(1024) void k_rb_fplace(const int64_t* __restrict__ off, int ncol, int nbk,
                                                     const int64_t* __restrict__ cstart,
                                                     const uint32_t* __restrict__ ctab, const int32_t* __restrict__ tv,
                                                     const int32_t* __restrict__ tu, const int32_t* __restrict__ tw,
-                                                    int32_t* __restrict__ radj, int32_t* __restrict__ rpiece) {
+                                                    int32_t* __restrict__ radj, int32_t* __restrict__ rpiece,
+                                                    const int64_t* __restrict__ rxadj, DeadTest dt) {
     constexpr int BT = 1 << RB_SHIFT;
     __shared__ uint32_t cur[BT];
     RbChunk ch;
     if (!rb_chunk(blockIdx.x, off, ncol, nbk, cstart, ch)) return;
     for (int i = threadIdx.x; i < BT; i += 1024) cur[i] = ctab[(int64_t)blockIdx.x * BT + i];
     __syncthreads();
-    for (int64_t i = ch.r0 + threadIdx.x; i < ch.r1; i += 1024) {
-        const int64_t p = ch.s0 + atomicAdd(&cur[tv[i] - ch.v0], 1u);
-        radj[p] = tu[i];
-        rpiece[p] = tw[i];
+    // uniform trip count per wave, so that the sample scan's ballot sees every lane
+    const int64_t span = ((ch.r1 - ch.r0 + 1023) / 1024) * 1024;
+    for (int64_t k = threadIdx.x; k < span; k += 1024) {
+        const int64_t i = ch.r0 + k;
+        const bool in = i < ch.r1;
+        const int32_t v = in ? tv[i] : 0, u = in ? tu[i] : 0;
+        bool dead = false;
+        if (dt.mode) {
+            const uint32_t t =
+                dt.mode == 2 ? (in ? wc_threshold((uint32_t)(rxadj[v + 1] - rxadj[v])) : 0u) : dt.thr_const;
+            const uint32_t h = mm3_key8((uint32_t)u, (uint32_t)v, dt.seed) & 0x7FFFFFFFu;
+            uint32_t mn = 0xFFFFFFFFu;
+            for (int j0 = 0; j0 < dt.J; j0 += 16) {
+                if (!__ballot(in && mn >= t)) break;  // every edge of the wave is live somewhere
+#pragma unroll
+                for (int g = 0; g < 16; g += 4) {
+                    if (j0 + g < dt.J) {
+                        const uint32_t* xg = dt.X + j0 + g;
+                        mn = min(min(mn, xg[0] ^ h), xg[1] ^ h);
+                        mn = min(min(mn, xg[2] ^ h), xg[3] ^ h);
+                    }
+                }
+            }
+            dead = in && mn >= t;
+        }
+        if (in) {
+            const int64_t p = ch.s0 + atomicAdd(&cur[v - ch.v0], 1u);
+            radj[p] = dead ? (int32_t)((uint32_t)u | DEAD_EDGE) : u;
+            rpiece[p] = tw[i];
+        }
     }
 }
 
@@ -1690,7 +1751,8 @@ size_t rb_temp_bytes(int64_t n, int64_t m) {
 
 // In-degrees (indeg) and the reverse CSR of g (rxadj, radj, rpiece) on stream
 // s; tmp holds rb_temp_bytes(n, m) bytes, indeg at its start.
-hipError_t launch_reverse_csr_buckets(const DevGraph& g, void* tmp, uint32_t** indeg_out, hipStream_t s) {
+hipError_t launch_reverse_csr_buckets(const DevGraph& g, void* tmp, uint32_t** indeg_out, const DeadTest& dt,
+                                      hipStream_t s) {
     const int64_t n = g.n, m = g.m;
     const int nbk = (int)((n + (1 << RB_SHIFT) - 1) >> RB_SHIFT);
     const int ncol = 2 * RB_BLOCKS;
@@ -1735,7 +1797,7 @@ hipError_t launch_reverse_csr_buckets(const DevGraph& g, void* tmp, uint32_t** i
     hipLaunchKernelGGL(k_rb_fscan, dim3((unsigned)nbk), dim3(1024), 0, s, off, ncol, nbk, n, cstart, ctab, indeg,
                        g.rxadj);
     hipLaunchKernelGGL(k_rb_fplace, dim3((unsigned)maxch), dim3(1024), 0, s, off, ncol, nbk, cstart, ctab, tv, tu, tw,
-                       g.radj, g.rpiece);
+                       g.radj, g.rpiece, g.rxadj, dt);
     return hipGetLastError();
 }
 
