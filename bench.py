@@ -58,6 +58,18 @@ def heavy_launch_bytes(rec, J, wc, m_heavy, npieces):
     return b
 
 
+def heavy_launch_visit_bytes(rec, J, wc, m_heavy, npieces):
+    """The same launch priced by the per-sweep formula of the measurement plan, which charges the
+    neighbour's row, hash and threshold for EVERY visited edge (E_t * J + ...), live in some sample or
+    not.  The kernel reads nothing for an edge live in no sample, so this fraction can exceed 1."""
+    if not rec["ran"]:
+        return 0
+    hv = rec["visits"] - rec["light_visits"]
+    b = hv * (J + 4 + (4 if wc else 0))
+    b += 4 * hv if rec["sparse"] else 4 * m_heavy + 20 * npieces
+    return b
+
+
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "k_sweep_heavy__rmat24_wc_J256_K50__traffic.md")
 KERNEL_SOURCES = ["paper_2105_04023_amd/csrc/hfr_kernels.hip", "paper_2105_04023_amd/csrc/hfr_device.h",
                   "paper_2105_04023_amd/csrc/hfr_internal.h", "paper_2105_04023_amd/csrc/hfr_api.hip"]
@@ -140,21 +152,79 @@ def summarize_pmc(fetch_dir: str, write_dir: str, command: str):
     return "\n".join(lines) + "\n"
 
 
-def cpu_baseline(seconds_hint: float = 15.0):
-    """The oracle's Simulate, single-threaded, on a bounded sample: the same R-MAT recipe at scale 16."""
+def host_cpu() -> dict:
+    """CPU model and the cores this process may run on."""
+    model = platform.processor() or platform.machine()
+    try:
+        with open("/proc/cpuinfo") as fh:
+            for line in fh:
+                if line.startswith("model name"):
+                    model = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    try:
+        usable = len(os.sched_getaffinity(0))
+    except (AttributeError, OSError):
+        usable = os.cpu_count()
+    return {"host_cpu": model, "host_nproc": os.cpu_count(), "host_usable_cores": usable}
+
+
+def recorded_oracle_runs() -> list:
+    """Wall times of the oracle's full runs on the configured workloads, as recorded (with the host's CPU
+    model) when tests/golden/make_goldens.py wrote the expected values: one core per run."""
+    out = []
+    gdir = os.path.join(ROOT, "tests", "golden")
+    for name in ("er_n1000_m10000_p0.1_J64_K10", "rmat20_p0.01_J256_K50", "rmat24_wc_J256_K50"):
+        try:
+            rec = json.load(open(os.path.join(gdir, f"oracle_{name}.json")))
+        except (OSError, ValueError):
+            continue
+        b = rec.get("build")
+        if not b:
+            continue
+        J = rec["J"]
+        item = {"workload": name, "host_cpu": rec.get("host_cpu"), "cores": 1,
+                "build_s": b["wall_s"], "build_visits": b["visits"] * J,
+                "build_visits_per_s": b["visits"] * J / b["wall_s"] if b["wall_s"] > 0 else None,
+                "greedy_steps_done": rec["K_done"], "K": rec["K"], "total_s": rec.get("oracle_wall_s")}
+        out.append(item)
+    try:
+        rec = json.load(open(os.path.join(gdir, "oracle_batch64_rmat_J128_K20.json")))
+        out.append({"workload": rec["name"], "host_cpu": rec.get("host_cpu"), "cores": rec.get("procs"),
+                    "jobs": len(rec["jobs"]), "total_s": rec.get("oracle_wall_s"),
+                    "job_s_sum": sum(j.get("oracle_wall_s", 0.0) for j in rec["jobs"])})
+    except (OSError, ValueError, KeyError):
+        pass
+    return out
+
+
+def cpu_baseline(max_sweeps: int = 1):
+    """The oracle, single-threaded, on a bounded sample of the configured workloads: the 2^20-vertex IC
+    workload's build Simulate for its first `max_sweeps` sweeps (the full build is ~200 s on one core),
+    and the 1000-vertex ER workload's whole run (build and K = 10 greedy steps)."""
     import oracle
     import synth
 
-    g = synth.rmat(16, 16 << 16, seed=3)
-    thr = oracle.edge_thresholds(g, "wc")
+    w = synth.workload_rmat20()
+    g = w.graph
+    thr = oracle.edge_thresholds(g, w.model, w.p)
     t0 = time.perf_counter()
-    M, sweeps, tl, te = oracle.simulate(g, thr, 256)
+    M, sweeps, tl, te = oracle.simulate(g, thr, w.J, max_sweeps=max_sweeps)
     dt = time.perf_counter() - t0
-    visits = int(te.sum()) * 256
-    return {"value": visits / dt, "unit": "edge*sim visits/s", "cores": 1, "kind": "oracle",
-            "sample": f"R-MAT scale 16 (n=65536, m={g.m}), weighted cascade, R=256: full Simulate to the fixed "
-                      f"point ({sweeps} sweeps, {visits} visits) in {dt:.1f} s on one host core",
-            "host_cpu": platform.processor() or platform.machine(), "host_nproc": os.cpu_count()}
+    visits = int(te.sum()) * w.J
+    e = synth.workload_er_small()
+    ethr = oracle.edge_thresholds(e.graph, e.model, e.p)
+    t1 = time.perf_counter()
+    res = oracle.greedy(e.graph, ethr, e.J, e.K)
+    dt_er = time.perf_counter() - t1
+    out = {"value": visits / dt, "unit": "edge·simulation visits/s", "cores": 1, "kind": "oracle",
+           "sample": f"{w.name} (n={g.n}, m={g.m}): the build Simulate's first {sweeps} sweeps ({visits} visits) "
+                     f"in {dt:.1f} s on one host core",
+           "er1000_whole_run_s": dt_er, "er1000_build_visits": res["build_visits"] * e.J,
+           "recorded_full_runs": recorded_oracle_runs()}
+    out.update(host_cpu())
+    return out
 
 
 def batch_leg(hf, ctx, steps: int, warmup: int):
@@ -433,6 +503,9 @@ def main():
     npieces = results[-1]["info"]["heavy_pieces"]
     assert results[-1]["info"]["heavy_rows"] == int((deg > heavy_deg).sum()), "split threshold mismatch"
     tot_bytes = sum(heavy_launch_bytes(rec, J, wc, m_heavy, npieces) for rec in recs)
+    tot_visit_bytes = sum(heavy_launch_visit_bytes(rec, J, wc, m_heavy, npieces) for rec in recs)
+    heavy_visits = sum(rec["visits"] - rec["light_visits"] for rec in recs if rec["ran"])
+    heavy_merged = sum(rec["merged"] - rec["light_merged"] for rec in recs if rec["ran"])
     tot_ms = sum(rec["heavy_ms"] for rec in recs)
     nlaunch = len(recs)
     achieved = tot_bytes / (tot_ms * 1e-3) / 1e9 if tot_ms > 0 else 0.0
@@ -440,9 +513,9 @@ def main():
     row_bytes = sum(rec["light_visits"] * 4 + rec["light_merged"] * (J + 4 + (4 if wc else 0))
                     for rec in recs if rec["ran"])
     out = {
-        "metric": "edge*simulation visits/s in sketch build (+ K-seed IM time; batched vs plain in 'batched')",
+        "metric": "edge\u00b7simulation visits/s in sketch build + K=50 IM time, batched vs plain",
         "value": visits / build_s,
-        "unit": "edge*sim visits/s",
+        "unit": "edge\u00b7simulation visits/s",
         "n_gpus": 1,
         "steps": args.steps,
         "warmup": args.warmup,
@@ -468,7 +541,13 @@ def main():
                      "frac": achieved / HBM_PEAK_GBS, "traffic": measured_traffic(), "traffic_unit": "bytes/launch",
                      "kernel": "k_sweep_heavy",
                      "launches": nlaunch, "avg_launch_ms": tot_ms / max(nlaunch, 1),
-                     "algorithmic_bytes_per_launch": tot_bytes / max(nlaunch, 1)},
+                     "algorithmic_bytes_per_launch": tot_bytes / max(nlaunch, 1),
+                     # the same launches priced per visited edge (every visit's row charged)
+                     "visit_model_bytes_per_launch": tot_visit_bytes / max(nlaunch, 1),
+                     "frac_visit_model": (tot_visit_bytes / (tot_ms * 1e-3) / 1e9 / HBM_PEAK_GBS
+                                          if tot_ms > 0 else 0.0),
+                     "heavy_edge_visits_per_step": heavy_visits // args.steps,
+                     "heavy_edges_merged_per_step": heavy_merged // args.steps},
         "row_kernel": {"kernel": "k_sweep_rows64", "ms": row_ms,
                        "visit_bytes_GBs": row_bytes / (row_ms * 1e-3) / 1e9 if row_ms > 0 else 0.0},
     }

@@ -162,7 +162,8 @@ def serve_sample(pool, stream, limit=400):
 def _serve_job(args):
     i, (t, gi, model, p, R, K), (scale, draws, gseed) = args
     g = synth.rmat(scale, draws, seed=gseed)
-    meta = {"name": f"request{i}", "request": i, "graph": gi, "scale": scale, "draws": draws, "graph_seed": gseed}
+    meta = {"name": f"request{i}", "request": i, "pool_graph": gi, "scale": scale, "draws": draws,
+            "graph_seed": gseed}
     return solve(g, model, p, R, K, meta=meta)
 
 

@@ -1,0 +1,197 @@
+"""Parity of the GPU library with the CPU oracle at the full sizes of the benchmark workloads.
+
+The expected values were written by ``tests/golden/make_goldens.py``, which runs the oracle only
+(Alg. 1 with Alg. 2, one core) on the same seeded inputs.  Each file holds the input's fingerprint,
+the build (sweep count, |L_t| and edge-visit traces, sha256 of all n x R registers, explicit rows of
+the largest in- and out-degree vertices and a random sample) and every greedy step's record with
+sha256 of the registers in force and of the blocked pairs after it.  The library runs in the
+benchmark's configuration (default build options) and every integer and FP64 field must be equal.
+
+* ER n = 1000 (IC p = 0.1, R = 64, K = 10) and R-MAT 2^20 (IC p = 0.01, R = 256, K = 50): the whole
+  run -- build, all K steps (seeds, scores, reach, e, sigma, delta, err_l, err_g, fresh, rebuilds and
+  their sweep and visit counts), final registers and blocked pairs.
+* The 64-job batch (R = 128, K = 20), solved in one autotuned launch: every job's seeds, step
+  records, build counters and build and final registers.
+* A sample of the serving stream's requests (every (graph size, model, p, R) class on the pool's
+  graphs of at most 2^15 vertices, and IC p = 0.01 on its 2^18-vertex graph), served together over
+  several slots: every request's seeds.
+"""
+from __future__ import annotations
+
+import hashlib
+import json
+import os
+
+import numpy as np
+import pytest
+
+import synth
+
+pytestmark = [pytest.mark.gpu, pytest.mark.timeout(900)]
+
+GOLDEN = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden")
+STEP_FIELDS = ("seed", "rebuilt", "fresh", "sweeps", "score", "reach", "e", "sigma", "delta", "err_l", "err_g",
+               "visits")
+
+
+def _load(name):
+    with open(os.path.join(GOLDEN, f"oracle_{name}.json")) as fh:
+        return json.load(fh)
+
+
+def sha(a: np.ndarray) -> str:
+    return hashlib.sha256(np.ascontiguousarray(a).data).hexdigest()
+
+
+def _check_graph(g, rec):
+    gg = rec["graph"]
+    assert (g.n, g.m) == (gg["n"], gg["m"])
+    assert sha(g.xadj) == gg["xadj_sha256"] and sha(g.adj[: g.m]) == gg["adj_sha256"], "input differs from the oracle's"
+
+
+def _check_registers(M, ref_sha, chunks=None, rows=None, what=""):
+    if sha(M) == ref_sha:
+        return
+    # name the first differing part before failing
+    msg = f"{what}: registers differ from the oracle's"
+    if rows:
+        for v, hx in rows.items():
+            if M[int(v)].tobytes().hex() != hx:
+                msg += f"; row {v} differs"
+                break
+    if chunks:
+        n = M.shape[0]
+        for c, d in enumerate(chunks):
+            lo, hi = c * n // len(chunks), (c + 1) * n // len(chunks)
+            if sha(M[lo:hi])[:16] != d:
+                msg += f"; first differing vertex block [{lo}, {hi})"
+                break
+    raise AssertionError(msg)
+
+
+def _check_steps(steps, ref_steps):
+    assert len(steps) == len(ref_steps)
+    for k, (s, r) in enumerate(zip(steps, ref_steps)):
+        got = tuple(getattr(s, f) for f in STEP_FIELDS)
+        exp = tuple(r[f] for f in STEP_FIELDS)
+        assert got == exp, f"step {k + 1}: {dict(zip(STEP_FIELDS, got))} != {dict(zip(STEP_FIELDS, exp))}"
+
+
+@pytest.fixture(scope="module")
+def hf():
+    import torch
+
+    assert torch.cuda.is_available(), "the GPU tests need a visible MI355X"
+    import paper_2105_04023_amd as hf
+
+    hf._binding.load()
+    return hf
+
+
+def _single_graph(hf, w, rec):
+    """Build + select on the device-resident CSR (the benchmark's configuration), against the record."""
+    import torch
+
+    g = w.graph
+    _check_graph(g, rec)
+    b = rec["build"]
+    K = rec["K_done"]
+    print(f"[golden] {rec['name']}: n={g.n} m={g.m} R={rec['J']} K'={K}", flush=True)
+    ctx = hf.Context(0)
+    xd, ad = torch.from_numpy(g.xadj).cuda(), torch.from_numpy(g.adj).cuda()
+    sk = hf.im_build_sketches(ctx, xd, ad, g.n, rec["J"], model=rec["model"], p=w.p, hash_seed=rec["hash_seed"])
+    try:
+        info = sk.info()
+        live, vis = sk.trace()
+        assert info["sweeps"] == b["sweeps"] and info["visits"] == b["visits"]
+        assert list(live) == b["live_trace"] and list(vis) == b["visit_trace"]
+        M0 = sk.registers(0)
+        _check_registers(M0, b["M_sha256"], b["M_chunks"], b["rows"], "build")
+        del M0
+        if K == 0:
+            return
+        seeds, steps, stats = hf.im_select_seeds(sk, K, eps_g=rec["eps_g"], eps_l=rec["eps_l"])
+        assert list(map(int, seeds)) == [s["seed"] for s in rec["steps"][:K]]
+        # the K-th step of a K-step run never rebuilds; the oracle's record of that step in a
+        # longer run may have (its rebuild then follows, outside the prefix)
+        ref = [dict(s) for s in rec["steps"][:K]]
+        ref[-1].update(rebuilt=0, sweeps=0, visits=0)
+        _check_steps(steps, ref)
+        M1 = sk.registers(1)
+        _check_registers(M1, rec["steps"][K - 1]["M_sha256"], what=f"after step {K}")
+        del M1
+        assert sha(sk.blocked()) == rec["steps"][K - 1]["blk_sha256"], "blocked pairs differ from the oracle's"
+    finally:
+        sk.free()
+        ctx.close()
+
+
+def test_er1000_whole_run(hf):
+    _single_graph(hf, synth.workload_er_small(), _load("er_n1000_m10000_p0.1_J64_K10"))
+
+
+def test_rmat20_whole_run(hf):
+    rec = _load("rmat20_p0.01_J256_K50")
+    assert rec["K_done"] == 50
+    _single_graph(hf, synth.workload_rmat20(), rec)
+
+
+def test_batch64_every_job(hf):
+    import torch
+
+    rec = _load("batch64_rmat_J128_K20")
+    jobs = rec["jobs"]
+    recipe = synth.batch_recipe()
+    assert len(jobs) == len(recipe) == 64
+    dev, bjobs = [], []
+    for (scale, draws, p, seed), jr in zip(recipe, jobs):
+        g = synth.rmat(scale, draws, seed=seed)
+        _check_graph(g, jr)
+        x, a = torch.from_numpy(g.xadj).cuda(), torch.from_numpy(g.adj).cuda()
+        dev.append((x, a, g))
+        bjobs.append(hf.BatchJob(x, a, g.n, jr["J"], jr["K"], model="const", p=p, eps_g=jr["eps_g"],
+                                 eps_l=jr["eps_l"]))
+    ctx = hf.Context(0)
+    print("[golden] batch64: autotuned create", flush=True)
+    b = hf.im_batch_create(ctx, bjobs, autotune=True)
+    try:
+        b.run()
+        for i, jr in enumerate(jobs):
+            seeds, steps, cnt = b.result(i)
+            assert list(map(int, seeds)) == jr["seeds"], f"job {i}"
+            _check_steps(steps, jr["steps"])
+            assert cnt["build_sweeps"] == jr["build"]["sweeps"] and cnt["build_visits"] == jr["build"]["visits"]
+            assert cnt["rebuilds"] == sum(s["rebuilt"] for s in jr["steps"])
+            assert cnt["rebuild_visits"] == sum(s["visits"] for s in jr["steps"])
+            _check_registers(b.registers(i, 0), jr["build"]["M_sha256"], jr["build"]["M_chunks"], jr["build"]["rows"],
+                             f"job {i} build")
+            _check_registers(b.registers(i, 1), jr["steps"][-1]["M_sha256"], what=f"job {i} final")
+    finally:
+        b.free()
+        ctx.close()
+
+
+def test_serving_sample_requests(hf):
+    rec = _load("serve_sample")
+    pool, stream = synth.serving_recipe()
+    jobs = rec["jobs"]
+    used = sorted({stream[jr["request"]][1] for jr in jobs})
+    sv = hf.Server(0, slots=4, hbm_budget=200 << 30)
+    try:
+        gid = {}
+        for gi in used:
+            scale, draws, gseed = pool[gi]
+            g = synth.rmat(scale, draws, seed=gseed)
+            gid[gi] = sv.add_graph(g.xadj, g.adj, g.n)
+        print(f"[golden] serving: {len(jobs)} requests on {len(used)} graphs", flush=True)
+        tickets = []
+        for jr in jobs:  # submitted together, in arrival order: they overlap on the slots
+            t, gi, model, p, R, K = stream[jr["request"]]
+            assert (model, R, K) == (jr["model"], jr["J"], jr["K"])
+            tickets.append((jr, sv.submit(gid[gi], R, K, model=model, p=p)))
+        for jr, tk in tickets:
+            seeds, resp = sv.wait(tk)
+            assert list(map(int, seeds)) == jr["seeds"], f"request {jr['request']}"
+            assert resp["rebuilds"] == sum(s["rebuilt"] for s in jr["steps"]), f"request {jr['request']}"
+    finally:
+        sv.close()
