@@ -37,9 +37,10 @@ WORKLOADS = {
 def heavy_launch_bytes(rec, J, wc, m_heavy, npieces):
     """Algorithmic HBM bytes of one launch of the split-row piece kernel (k_sweep_heavy).
 
-    Per merged edge (a visited edge live in some sample): the neighbour's row (J bytes),
-    the edge hash (4) and, for the weighted cascade, the edge's threshold (4); an edge live
-    in no sample is known to be so from its id (flag bit), which costs nothing more.  Edge
+    Per merged edge (a visited edge live in some sample): the neighbour's row (J bytes) and,
+    for the weighted cascade, the edge's threshold (4); the edge's hash is recomputed from
+    its two ids, and an edge live in no sample is known to be so from its id (flag bit),
+    which costs nothing more.  Edge
     ids: a dense launch reads every split-row out-edge id (4 m_heavy) and the piece table
     (20 B per piece), a sparse launch the ids of the edges it visits (4 each).  The partial
     rows and flags written (J + 4 bytes per run of a row's pieces with a live edge) are not
@@ -50,7 +51,7 @@ def heavy_launch_bytes(rec, J, wc, m_heavy, npieces):
         return 0
     hv = rec["visits"] - rec["light_visits"]
     hm = rec["merged"] - rec["light_merged"]
-    b = hm * (J + 4 + (4 if wc else 0))
+    b = hm * (J + (4 if wc else 0))
     if rec["sparse"]:
         b += 4 * hv
     else:
@@ -60,12 +61,12 @@ def heavy_launch_bytes(rec, J, wc, m_heavy, npieces):
 
 def heavy_launch_visit_bytes(rec, J, wc, m_heavy, npieces):
     """The same launch priced by the per-sweep formula of the measurement plan, which charges the
-    neighbour's row, hash and threshold for EVERY visited edge (E_t * J + ...), live in some sample or
+    neighbour's row (and threshold) for EVERY visited edge (E_t * J + ...), live in some sample or
     not.  The kernel reads nothing for an edge live in no sample, so this fraction can exceed 1."""
     if not rec["ran"]:
         return 0
     hv = rec["visits"] - rec["light_visits"]
-    b = hv * (J + 4 + (4 if wc else 0))
+    b = hv * (J + (4 if wc else 0))
     b += 4 * hv if rec["sparse"] else 4 * m_heavy + 20 * npieces
     return b
 
@@ -510,7 +511,7 @@ def main():
     nlaunch = len(recs)
     achieved = tot_bytes / (tot_ms * 1e-3) / 1e9 if tot_ms > 0 else 0.0
     row_ms = sum(rec["kernel_ms"] for rec in recs)
-    row_bytes = sum(rec["light_visits"] * 4 + rec["light_merged"] * (J + 4 + (4 if wc else 0))
+    row_bytes = sum(rec["light_visits"] * 4 + rec["light_merged"] * (J + (4 if wc else 0))
                     for rec in recs if rec["ran"])
     out = {
         "metric": "edge\u00b7simulation visits/s in sketch build + K=50 IM time, batched vs plain",

@@ -137,6 +137,7 @@ struct im_sketch {
     bool rev_ready = false;
     void* rev_tmp = nullptr;  // in-degrees and cursors of the reverse CSR build
     void* list_tmp = nullptr; // a preparation temporary (per-edge weights, light-row list build)
+    void* hash_tmp = nullptr; // the edge hashes, held until the edges live in no sample are flagged
     std::vector<hipEvent_t> sweep_ev;
     bool time_sweeps = false;
     bool in_place = false;  // sweeps read and write one register buffer
@@ -184,6 +185,7 @@ void sk_release(im_sketch* sk) {
     if (sk->h_small) (void)hipHostFree(sk->h_small);
     if (sk->rev_tmp && sk->ctx) ctx_free(sk->ctx, sk->rev_tmp);
     if (sk->list_tmp && sk->ctx) ctx_free(sk->ctx, sk->list_tmp);
+    if (sk->hash_tmp && sk->ctx) ctx_free(sk->ctx, sk->hash_tmp);
     for (hipEvent_t e : {sk->ev_a, sk->ev_b, sk->ev_batch[0], sk->ev_batch[1], sk->ev_indeg, sk->ev_rev})
         if (e) (void)hipEventDestroy(e);
     if (sk->aux) (void)hipStreamDestroy(sk->aux);
@@ -646,7 +648,12 @@ im_status build_sketch(im_ctx* ctx, const im_csr* graph, const im_probs* probs, 
     g.m = m;
     const Layout& L = sk->L;
     bool ok = true;
-    ok = ok && sk_alloc(sk, &g.xadj, n + 1) && sk_alloc(sk, &g.adj, m) && sk_alloc(sk, &g.eh, m);
+    ok = ok && sk_alloc(sk, &g.xadj, n + 1) && sk_alloc(sk, &g.adj, m);
+    // the edge hashes are a preparation temporary: once the edges live in no sample are
+    // flagged, every kernel recomputes the hash of (u, v) instead of loading it
+    g.hseed = hash_seed;
+    ok = ok && (sk->hash_tmp = ctx_alloc(ctx, 4 * (size_t)(m > 0 ? m : 1))) != nullptr;
+    g.eh = (uint32_t*)sk->hash_tmp;
     ok = ok && sk_alloc(sk, &sk->X, R) && sk_alloc(sk, &sk->HJ, R) && sk_alloc(sk, &sk->T, R);
     for (int i = 0; i < 3 && ok && simulate; ++i) ok = sk_alloc(sk, &sk->M[i], (size_t)n * L.P);
     const int64_t words = (n + 31) / 32 + 1;
@@ -823,6 +830,10 @@ im_status build_sketch(im_ctx* ctx, const im_csr* graph, const im_probs* probs, 
             }
             // samples and thresholds are final: flag the edges live in no sample
             HIP_TRY(launch_dead_edges(g, sk->X, R, s));
+            HIP_TRY(hipStreamSynchronize(s));
+            ctx_free(ctx, sk->hash_tmp);
+            sk->hash_tmp = nullptr;
+            g.eh = nullptr;
             // the row kernel's list of rows with 1..heavy_deg out-edges
             uint32_t* lflags = (uint32_t*)pm_;
             int64_t* lpos = (int64_t*)((char*)pm_ + a4n);

@@ -342,7 +342,8 @@ DEVI void tile_rows(const BJob& jb, BCtl* c, const BDesc& d, int tile) {
             const int64_t u = u0 + grp;
             bool ch = false;
             if (u < wend)
-                ch = sweep_row<G, DW, KIND>(u, jb.xadj, jb.adj, jb.eh, jb.thr, ntv, x, A, B, Lcur, Lnext, blk, nullptr,
+                ch = sweep_row<G, DW, KIND>(u, jb.xadj, jb.adj, EdgeHashes{jb.eh, jb.seed}, jb.thr, ntv, x, A, B, Lcur,
+                                            Lnext, blk, nullptr,
                                             jb.heavy_deg, jb.P, jb.PW, first, true, lane, p, my_vis);
             const uint64_t bal = __ballot(ch && p == 0);
 #pragma unroll
@@ -395,8 +396,8 @@ DEVI void tile_pieces(const BJob& jb, BCtl* c, const BDesc& d, int ptile) {
         for (int i = 0; i < DW; ++i) acc[i].e = acc[i].o = 0u;
         uint32_t vis = 0;
         if (!skip)
-            vis = merge_edges<G, DW, KIND>(jb.pe0[pc], jb.pe1[pc], jb.adj, jb.eh, jb.thr, ntv, A, Lcur, first, P, lane,
-                                           p, x, acc);
+            vis = merge_edges<G, DW, KIND>(jb.pe0[pc], jb.pe1[pc], (uint32_t)u, jb.adj, EdgeHashes{jb.eh, jb.seed},
+                                           jb.thr, ntv, A, Lcur, first, P, lane, p, x, acc);
         if (vis > 0) {
 #pragma unroll
             for (int i = 0; i < DW; ++i) {
@@ -459,7 +460,8 @@ DEVI void tile_bfs(const BJob& jb, BCtl* c, const BDesc& d, int tile) {
     const uint32_t ntv = to_vgpr(0u - jb.thr_const);
     const int cur = d.level & 1;
     unsigned long long my_new = bfs_expand_entries<G, DW, KIND>(
-        b0, b1, RPW, jb.xadj, jb.adj, jb.eh, jb.thr, ntv, x, jb.F[cur], jb.F[cur ^ 1], jb.Q[cur], jb.Q[cur ^ 1],
+        b0, b1, RPW, jb.xadj, jb.adj, EdgeHashes{jb.eh, jb.seed}, jb.thr, ntv, x, jb.F[cur], jb.F[cur ^ 1], jb.Q[cur],
+        jb.Q[cur ^ 1],
         &c->qnext, jb.blk, jb.stamp, d.level_id + d.level + 1, BFS_CHUNK_B, jb.P, jb.PW);
     my_new = wave_sum(my_new);
     if ((threadIdx.x & 63) == 0 && my_new) atomicAdd(&c->R, my_new);

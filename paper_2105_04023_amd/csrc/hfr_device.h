@@ -38,6 +38,18 @@ DEVI uint32_t mm3_tail(uint32_t h, uint32_t len) {
 DEVI uint32_t mm3_key4(uint32_t a, uint32_t seed) { return mm3_tail(mm3_round(seed, a), 4u); }
 DEVI uint32_t mm3_key8(uint32_t a, uint32_t b, uint32_t seed) { return mm3_tail(mm3_round(mm3_round(seed, a), b), 8u); }
 
+// The 31-bit hash of edge e = (u, v) (Eq. hash): read from a precomputed array,
+// or -- with eh null -- recomputed from the two ids (two Murmur3 rounds and the
+// finaliser, about twenty integer instructions), which saves the 4-byte load
+// and the cache line it costs a merged edge whose neighbours are not merged.
+struct EdgeHashes {
+    const uint32_t* eh;
+    uint32_t seed;
+};
+DEVI uint32_t edge_hash_of(const EdgeHashes& H, int64_t e, uint32_t u, uint32_t v) {
+    return H.eh ? H.eh[e] : (mm3_key8(u, v, H.seed) & 0x7FFFFFFFu);
+}
+
 DEVI uint32_t lead_zeros(uint32_t x) { return x == 0u ? 32u : (uint32_t)__builtin_clz(x); }
 
 // ----------------------------------------------------------------------------
@@ -203,20 +215,20 @@ DEVI double estimate_from_sum(uint32_t s, int J, const double* __restrict__ T) {
 // ----------------------------------------------------------------------------
 constexpr int UB = 8;  // neighbour rows in flight per wave (twice that with one dword per lane)
 
-// G = 64: merges one window of up to 64 out-edges, lane l holding edge e (in:
-// the edge exists) with head v, `mask` the lanes whose head is in L_t (not
+// G = 64: merges one window of up to 64 out-edges of row u, lane l holding edge
+// e (in: the edge exists) with head v, `mask` the lanes whose head is in L_t (not
 // empty, edges live in no sample already dropped).  The rows of up to UB heads
 // are loaded back-to-back before they are merged.  Returns the number of rows
 // merged.
 template <int DW, int KIND>
-DEVI uint32_t merge_window64(uint64_t mask, int64_t e, bool in, int32_t v, const uint32_t* __restrict__ eh,
+DEVI uint32_t merge_window64(uint64_t mask, int64_t e, bool in, int32_t v, uint32_t u, const EdgeHashes& H,
                              const uint32_t* __restrict__ thr, uint32_t ntv, const uint32_t* __restrict__ A, int P,
                          int lane, const uint32_t (&x)[DW][4], Acc (&acc)[DW]) {
     // hashes and thresholds of the merged edges only: a sparse mask then
     // fetches only the cache lines it needs
     const uint32_t merged = (uint32_t)__builtin_popcountll(mask);
     const bool mine = ((mask >> lane) & 1ull) != 0ull;
-    const uint32_t hh = mine ? eh[e] : 0u;
+    const uint32_t hh = mine ? edge_hash_of(H, e, u, (uint32_t)v) : 0u;
     uint32_t ntt = 0u;  // negated threshold
     if constexpr (KIND == THR_TARGET) ntt = 0u - (mine ? thr[v] : 0u);
     if constexpr (KIND == THR_EDGE) ntt = 0u - (mine ? thr[e] : 0u);
@@ -281,8 +293,8 @@ DEVI uint32_t merge_window64(uint64_t mask, int64_t e, bool in, int32_t v, const
 // of edges with a live head.
 constexpr int NW = 4;
 template <int DW, int KIND>
-DEVI uint32_t merge_edges64(int64_t eb, int64_t ee, const int32_t* __restrict__ adj, const uint32_t* __restrict__ eh,
-                            const uint32_t* __restrict__ thr, uint32_t ntv, const uint32_t* __restrict__ A,
+DEVI uint32_t merge_edges64(int64_t eb, int64_t ee, uint32_t u, const int32_t* __restrict__ adj,
+                            const EdgeHashes& H, const uint32_t* __restrict__ thr, uint32_t ntv, const uint32_t* __restrict__ A,
                             const uint32_t* __restrict__ Lcur, int first, int P, int lane,
                             const uint32_t (&x)[DW][4], Acc (&acc)[DW], const uint32_t* cl = nullptr, int cs = 0,
                             unsigned long long* mrg = nullptr) {
@@ -308,7 +320,7 @@ DEVI uint32_t merge_edges64(int64_t eb, int64_t ee, const int32_t* __restrict__ 
             const uint64_t mm = mw[w] & ~dm[w];  // edges live in no sample merge nothing
             if (!mm) continue;
             const uint32_t mg =
-                merge_window64<DW, KIND>(mm, c0 + 64 * w + lane, inw[w], vw[w], eh, thr, ntv, A, P, lane, x, acc);
+                merge_window64<DW, KIND>(mm, c0 + 64 * w + lane, inw[w], vw[w], u, H, thr, ntv, A, P, lane, x, acc);
             if (mrg) *mrg += mg;
         }
     }
@@ -319,8 +331,8 @@ DEVI uint32_t merge_edges64(int64_t eb, int64_t ee, const int32_t* __restrict__ 
 // (window i starts at eb + 64 i), NW of them at a time with their loads and
 // L_t tests issued together.  Returns the number of edges with a live head.
 template <int DW, int KIND>
-DEVI uint32_t merge_marked_windows64(int64_t eb, int64_t ee, uint32_t wm, const int32_t* __restrict__ adj,
-                                     const uint32_t* __restrict__ eh, const uint32_t* __restrict__ thr, uint32_t ntv,
+DEVI uint32_t merge_marked_windows64(int64_t eb, int64_t ee, uint32_t wm, uint32_t u, const int32_t* __restrict__ adj,
+                                     const EdgeHashes& H, const uint32_t* __restrict__ thr, uint32_t ntv,
                                      const uint32_t* __restrict__ A, const uint32_t* __restrict__ Lcur, int first,
                                      int P, int lane, const uint32_t (&x)[DW][4], Acc (&acc)[DW],
                                      const uint32_t* cl = nullptr, int cs = 0, unsigned long long* mrg = nullptr) {
@@ -353,7 +365,7 @@ DEVI uint32_t merge_marked_windows64(int64_t eb, int64_t ee, uint32_t wm, const 
             const uint64_t mm = mw[w] & ~dm[w];  // edges live in no sample merge nothing
             if (!mm) continue;
             const uint32_t mg =
-                merge_window64<DW, KIND>(mm, w0[w] + lane, inw[w], vw[w], eh, thr, ntv, A, P, lane, x, acc);
+                merge_window64<DW, KIND>(mm, w0[w] + lane, inw[w], vw[w], u, H, thr, ntv, A, P, lane, x, acc);
             if (mrg) *mrg += mg;
         }
     }
@@ -365,8 +377,8 @@ DEVI uint32_t merge_marked_windows64(int64_t eb, int64_t ee, uint32_t wm, const 
 // up to UB live heads per batch of loads.  Groups may diverge; shuffles only
 // read lanes of the caller's own group.
 template <int G, int DW, int KIND>
-DEVI uint32_t merge_edges_grp(int64_t eb, int64_t ee, const int32_t* __restrict__ adj,
-                              const uint32_t* __restrict__ eh, const uint32_t* __restrict__ thr, uint32_t ntv,
+DEVI uint32_t merge_edges_grp(int64_t eb, int64_t ee, uint32_t u, const int32_t* __restrict__ adj,
+                              const EdgeHashes& H, const uint32_t* __restrict__ thr, uint32_t ntv,
                               const uint32_t* __restrict__ A, const uint32_t* __restrict__ Lcur, int first, int P,
                               int lane, int p, const uint32_t (&x)[DW][4], Acc (&acc)[DW],
                               unsigned long long* mrg = nullptr) {
@@ -386,7 +398,7 @@ DEVI uint32_t merge_edges_grp(int64_t eb, int64_t ee, const int32_t* __restrict_
         mask &= ~(__ballot(in && adj_dead(a)) >> gbase);  // edges live in no sample merge nothing
         if (!mask) continue;
         if (mrg) *mrg += (uint32_t)__builtin_popcountll(mask);
-        const uint32_t hh = eh[ec];
+        const uint32_t hh = edge_hash_of(H, ec, u, (uint32_t)v);
         uint32_t tt = 0u;
         if constexpr (KIND == THR_TARGET) tt = thr[v];
         if constexpr (KIND == THR_EDGE) tt = thr[ec];
@@ -440,15 +452,15 @@ DEVI uint32_t merge_edges_grp(int64_t eb, int64_t ee, const int32_t* __restrict_
 }
 
 template <int G, int DW, int KIND>
-DEVI uint32_t merge_edges(int64_t eb, int64_t ee, const int32_t* __restrict__ adj, const uint32_t* __restrict__ eh,
+DEVI uint32_t merge_edges(int64_t eb, int64_t ee, uint32_t u, const int32_t* __restrict__ adj, const EdgeHashes& H,
                           const uint32_t* __restrict__ thr, uint32_t ntv, const uint32_t* __restrict__ A,
                           const uint32_t* __restrict__ Lcur, int first, int P, int lane, int p,
                           const uint32_t (&x)[DW][4], Acc (&acc)[DW], const uint32_t* cl = nullptr, int cs = 0,
                           unsigned long long* mrg = nullptr) {
     if constexpr (G == 64)
-        return merge_edges64<DW, KIND>(eb, ee, adj, eh, thr, ntv, A, Lcur, first, P, lane, x, acc, cl, cs, mrg);
+        return merge_edges64<DW, KIND>(eb, ee, u, adj, H, thr, ntv, A, Lcur, first, P, lane, x, acc, cl, cs, mrg);
     else
-        return merge_edges_grp<G, DW, KIND>(eb, ee, adj, eh, thr, ntv, A, Lcur, first, P, lane, p, x, acc, mrg);
+        return merge_edges_grp<G, DW, KIND>(eb, ee, u, adj, H, thr, ntv, A, Lcur, first, P, lane, p, x, acc, mrg);
 }
 
 template <int G, int DW>
@@ -466,7 +478,7 @@ DEVI void load_sim_words(const uint32_t* __restrict__ X, int P, int p, uint32_t 
 // atomically.
 template <int G, int DW, int KIND>
 DEVI bool sweep_row(int64_t u, const int64_t* __restrict__ xadj, const int32_t* __restrict__ adj,
-                    const uint32_t* __restrict__ eh, const uint32_t* __restrict__ thr, uint32_t ntv,
+                    const EdgeHashes& H, const uint32_t* __restrict__ thr, uint32_t ntv,
                     const uint32_t (&x)[DW][4], const uint32_t* __restrict__ A, uint32_t* __restrict__ B,
                     const uint32_t* __restrict__ Lcur, uint32_t* __restrict__ Lnext, const uint32_t* __restrict__ blk,
                     const uint32_t* __restrict__ fullblk, int64_t heavy_deg, int P, int PW, int first,
@@ -496,7 +508,8 @@ DEVI bool sweep_row(int64_t u, const int64_t* __restrict__ xadj, const int32_t* 
     for (int i = 0; i < DW; ++i) acc[i].e = acc[i].o = 0u;
     unsigned long long mg = 0;
     const uint32_t vis =
-        merge_edges<G, DW, KIND>(eb, ee, adj, eh, thr, ntv, A, Lcur, first, P, lane, p, x, acc, nullptr, 0, &mg);
+        merge_edges<G, DW, KIND>(eb, ee, (uint32_t)u, adj, H, thr, ntv, A, Lcur, first, P, lane, p, x, acc, nullptr, 0,
+                                 &mg);
     if (p == 0) {
         my_vis += vis;
         if (my_mrg) *my_mrg += mg;
@@ -763,7 +776,7 @@ DEVI int decide_step(unsigned long long R, unsigned long long R0, int J, int k, 
 // bounds).  Returns the number of newly blocked pairs found by this lane.
 template <int G, int DW, int KIND>
 DEVI unsigned long long bfs_expand_entries(int64_t b0, int64_t b1, int64_t bstep, const int64_t* __restrict__ xadj,
-                                           const int32_t* __restrict__ adj, const uint32_t* __restrict__ eh,
+                                           const int32_t* __restrict__ adj, const EdgeHashes& H,
                                            const uint32_t* __restrict__ thr, uint32_t ntv, const uint32_t (&x)[DW][4],
                                            const uint32_t* __restrict__ Fc, uint32_t* Fn, const int2* __restrict__ Qc,
                                            int2* Qn, uint32_t* qn, uint32_t* blk, int32_t* stamp,
@@ -781,12 +794,14 @@ DEVI unsigned long long bfs_expand_entries(int64_t b0, int64_t b1, int64_t bstep
         const int64_t ent = base + grp;
         const bool ok = ent < b1;
         int64_t e0 = 0, e1 = 0;
+        uint32_t src = 0;  // the entry's vertex: the source of its edges
         uint32_t fb[DW];  // frontier bits of this lane's registers, bit (k) of fb[i] for register 4q+k
 #pragma unroll
         for (int i = 0; i < DW; ++i) fb[i] = 0u;
         if (ok) {
             const int2 qe = Qc[ent];
             const int64_t v = qe.x;
+            src = (uint32_t)v;
             const int64_t vb = xadj[v], ve = xadj[v + 1];
             e0 = vb + (int64_t)qe.y * bfs_chunk;
             e1 = e0 + bfs_chunk < ve ? e0 + bfs_chunk : ve;
@@ -854,7 +869,7 @@ DEVI unsigned long long bfs_expand_entries(int64_t b0, int64_t b1, int64_t bstep
             const bool in = e < e1;
             const int32_t wa = in ? adj[e] : 0;
             const int32_t wv = adj_target(wa);
-            const uint32_t hh = in ? eh[e] : 0u;
+            const uint32_t hh = in ? edge_hash_of(H, e, src, (uint32_t)wv) : 0u;
             uint32_t tt = 0u;
             if constexpr (KIND == THR_TARGET) tt = in ? thr[wv] : 0u;
             if constexpr (KIND == THR_EDGE) tt = in ? thr[e] : 0u;

@@ -33,7 +33,9 @@ struct DevGraph {
     int64_t n = 0, m = 0;
     int64_t* xadj = nullptr;
     int32_t* adj = nullptr;   // the sketch's copy; DEAD_EDGE may be set once the sweeps' inputs are final
-    uint32_t* eh = nullptr;   // 31-bit edge hash per edge
+    uint32_t* eh = nullptr;   // 31-bit edge hash per edge, held during preparation only (null: the
+                              // kernels recompute the hash of (u, v) from hseed)
+    uint32_t hseed = 0;       // hash seed
     uint32_t* thr = nullptr;  // per target vertex (WC) or per edge
     uint32_t thr_const = 0;
     int kind = THR_CONST;

@@ -19,6 +19,10 @@
 
 namespace hfr {
 
+// Edge hashes of a graph for the kernels: its array while it exists (preparation),
+// else recomputed from (u, v) and the seed.
+static inline EdgeHashes hashes(const DevGraph& g) { return EdgeHashes{g.eh, g.hseed}; }
+
 // ----------------------------------------------------------------------------
 // Utilities and graph preparation.
 // ----------------------------------------------------------------------------
@@ -671,7 +675,7 @@ __global__ __launch_bounds__(64) void k_sweep_cleanup(const uint32_t* __restrict
 
 template <int G, int DW, int KIND>
 __global__ __launch_bounds__(256) void k_sweep_light(
-    const int64_t* __restrict__ xadj, const int32_t* __restrict__ adj, const uint32_t* __restrict__ eh,
+    const int64_t* __restrict__ xadj, const int32_t* __restrict__ adj, EdgeHashes H,
     const uint32_t* __restrict__ thr, uint32_t thr_const, const uint32_t* __restrict__ X,
     const uint32_t* __restrict__ A, uint32_t* __restrict__ B, const uint32_t* __restrict__ Lcur,
     uint32_t* __restrict__ Lnext, const uint32_t* __restrict__ blk, const uint32_t* __restrict__ gate,
@@ -700,7 +704,7 @@ __global__ __launch_bounds__(256) void k_sweep_light(
                 const int64_t u = c * 32 + rr + grp;
                 bool changed = false;
                 if (u < n)
-                    changed = sweep_row<G, DW, KIND>(u, xadj, adj, eh, thr, ntv, x, A, B, Lcur, Lnext, blk, fullblk,
+                    changed = sweep_row<G, DW, KIND>(u, xadj, adj, H, thr, ntv, x, A, B, Lcur, Lnext, blk, fullblk,
                                                      heavy_deg, P, PW, first, true, lane, p, my_vis, &my_mrg);
                 if (changed && p == 0) my_sum += (unsigned long long)(rxadj[u + 1] - rxadj[u]);
                 const uint64_t bal = __ballot(changed && p == 0);
@@ -718,7 +722,7 @@ __global__ __launch_bounds__(256) void k_sweep_light(
             const int64_t i = base + grp;
             bool changed = false;
             if (i < nw)
-                changed = sweep_row<G, DW, KIND>(fr.W[i], xadj, adj, eh, thr, ntv, x, A, B, Lcur, Lnext, blk,
+                changed = sweep_row<G, DW, KIND>(fr.W[i], xadj, adj, H, thr, ntv, x, A, B, Lcur, Lnext, blk,
                                                  fullblk, heavy_deg, P, PW, first, false, lane, p, my_vis, &my_mrg);
             if (changed && p == 0) {
                 my_cnt += 1;
@@ -749,7 +753,7 @@ __global__ __launch_bounds__(256) void k_sweep_light(
 // blocked bits), so finishing a row needs no extra round trip.
 template <int DW, int KIND, bool BLK>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(5, 8))) void k_sweep_rows64(
-    const int64_t* __restrict__ xadj, const int32_t* __restrict__ adj, const uint32_t* __restrict__ eh,
+    const int64_t* __restrict__ xadj, const int32_t* __restrict__ adj, EdgeHashes H,
     const uint32_t* __restrict__ thr, uint32_t thr_const, const uint32_t* __restrict__ X,
     const uint32_t* __restrict__ A, uint32_t* __restrict__ B, const uint32_t* __restrict__ Lcur,
     uint32_t* __restrict__ Lnext, const uint32_t* __restrict__ blk, const uint32_t* __restrict__ gate,
@@ -851,9 +855,10 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(5, 8))) voi
             mask &= ~dmask;  // edges live in no sample merge nothing
             if (!mask) continue;
             mrg += (uint32_t)__builtin_popcountll(mask);
-            // hashes and thresholds of the merged edges only
+            // hashes and thresholds of the merged edges only; the row of lane's edge is r
             const bool mine = ((mask >> lane) & 1ull) != 0ull;
-            const uint32_t hh = mine ? eh[e] : 0u;
+            const uint32_t su = (uint32_t)__shfl((int)u, r, 64);
+            const uint32_t hh = mine ? edge_hash_of(H, e, su, (uint32_t)v) : 0u;
             uint32_t tt = 0u;
             if constexpr (KIND == THR_TARGET) tt = mine ? thr[v] : 0u;
             if constexpr (KIND == THR_EDGE) tt = mine ? thr[e] : 0u;
@@ -1014,7 +1019,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(5, 8))) voi
 // piece's out-neighbours in L_t, written to part[piece].
 template <int G, int DW, int KIND>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(7, 8))) void k_sweep_heavy(
-    const int32_t* __restrict__ adj, const uint32_t* __restrict__ eh, const uint32_t* __restrict__ thr,
+    const int32_t* __restrict__ adj, EdgeHashes H, const uint32_t* __restrict__ thr,
     uint32_t thr_const, const uint32_t* __restrict__ X, const uint32_t* __restrict__ A,
     const uint32_t* __restrict__ Lcur, const uint32_t* __restrict__ blk, const uint32_t* __restrict__ gate,
     uint32_t gate_thresh, unsigned long long* __restrict__ vis_out, const int32_t* __restrict__ hrow,
@@ -1057,11 +1062,11 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(7, 8))) voi
             my_vis += vis;
         }
     };
-    // merges piece pc of split row r, edges [b0, b1) (uniform over the group);
-    // wm: its 64-edge windows to scan, all of them when 0; skip: the row is
-    // blocked in every sample
-    auto piece = [&](const int64_t pc, const int32_t r, const int64_t b0, const int64_t b1, const uint32_t wm,
-                     const bool skip) {
+    // merges piece pc of split row r (vertex u), edges [b0, b1) (uniform over the
+    // group); wm: its 64-edge windows to scan, all of them when 0; skip: the row
+    // is blocked in every sample
+    auto piece = [&](const int64_t pc, const int32_t r, const uint32_t u, const int64_t b0, const int64_t b1,
+                     const uint32_t wm, const bool skip) {
         Acc acc[DW];
 #pragma unroll
         for (int k = 0; k < DW; ++k) acc[k].e = acc[k].o = 0u;
@@ -1069,19 +1074,19 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(7, 8))) voi
         if (!skip) {
             if (wm) {
                 if constexpr (G == 64) {
-                    vis = merge_marked_windows64<DW, KIND>(b0, b1, wm, adj, eh, thr, ntv, A, Lcur, first, P, lane, x,
-                                                           acc, nullptr, 0, &my_mrg);
+                    vis = merge_marked_windows64<DW, KIND>(b0, b1, wm, u, adj, H, thr, ntv, A, Lcur, first, P, lane,
+                                                           x, acc, nullptr, 0, &my_mrg);
                 } else {
                     for (uint32_t left = wm; left; left &= left - 1) {
                         const int64_t w0 = b0 + 64 * (int64_t)__builtin_ctz(left);
                         const int64_t w1 = w0 + 64 < b1 ? w0 + 64 : b1;
-                        vis += merge_edges<G, DW, KIND>(w0, w1, adj, eh, thr, ntv, A, Lcur, first, P, lane, p, x, acc,
-                                                        nullptr, 0, &my_mrg);
+                        vis += merge_edges<G, DW, KIND>(w0, w1, u, adj, H, thr, ntv, A, Lcur, first, P, lane, p, x,
+                                                        acc, nullptr, 0, &my_mrg);
                     }
                 }
             } else {
-                vis = merge_edges<G, DW, KIND>(b0, b1, adj, eh, thr, ntv, A, Lcur, first, P, lane, p, x, acc, cl, cs,
-                                               &my_mrg);
+                vis = merge_edges<G, DW, KIND>(b0, b1, u, adj, H, thr, ntv, A, Lcur, first, P, lane, p, x, acc, cl,
+                                               cs, &my_mrg);
             }
         }
         finish_piece(pc, r, vis, acc);
@@ -1095,14 +1100,15 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(7, 8))) voi
         span = span < 1 ? 1 : (span > 64 ? 64 : span);
         for (int64_t base = wave_index() * span; base < npieces; base += wave_count() * span) {
             const int cnt = (int)(npieces - base < span ? npieces - base : span);
-            int32_t rl = 0;
+            int32_t rl = 0, ul = 0;
             int64_t b0l = 0, b1l = 0;
             bool skl = false;
             if (lane < cnt) {
                 rl = prow[base + lane];
                 b0l = pe0[base + lane];
                 b1l = pe1[base + lane];
-                skl = fullblk && bit_of(fullblk, hrow[rl]) != 0u;
+                ul = hrow[rl];
+                skl = fullblk && bit_of(fullblk, ul) != 0u;
             }
             const uint64_t skipm = __ballot(skl);
             Acc acc[DW];
@@ -1122,8 +1128,9 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(7, 8))) voi
                     run_r = r;
                 }
                 if (!((skipm >> j) & 1ull))
-                    vis += merge_edges<G, DW, KIND>(__shfl(b0l, j, 64), __shfl(b1l, j, 64), adj, eh, thr, ntv, A,
-                                                    Lcur, first, P, lane, p, x, acc, cl, cs, &my_mrg);
+                    vis += merge_edges<G, DW, KIND>(__shfl(b0l, j, 64), __shfl(b1l, j, 64), (uint32_t)__shfl(ul, j, 64),
+                                                    adj, H, thr, ntv, A, Lcur, first, P, lane, p, x, acc, cl, cs,
+                                                    &my_mrg);
             }
             finish_piece(base + first_j, run_r, vis, acc);
         }
@@ -1147,7 +1154,10 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(7, 8))) voi
                 b0_n = pe0[i + stride];
                 b1_n = pe1[i + stride];
             }
-            if (i < npieces) piece(i, r, b0, b1, 0u, fullblk && bit_of(fullblk, hrow[r]) != 0u);
+            if (i < npieces) {
+                const int32_t u = hrow[r];
+                piece(i, r, (uint32_t)u, b0, b1, 0u, fullblk && bit_of(fullblk, u) != 0u);
+            }
         }
     } else {
         // the pieces with a marked window: each wave scans `span` window masks
@@ -1162,14 +1172,15 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(7, 8))) voi
                 if (wm) fr.wmask[base + lane] = 0u;
             }
             // the table entries of every marked piece of the span, loaded at once
-            int32_t rl = 0;
+            int32_t rl = 0, ul = 0;
             int64_t b0l = 0, b1l = 0;
             bool skl = false;
             if (wm) {
                 rl = prow[base + lane];
                 b0l = pe0[base + lane];
                 b1l = pe1[base + lane];
-                skl = fullblk && bit_of(fullblk, hrow[rl]) != 0u;
+                ul = hrow[rl];
+                skl = fullblk && bit_of(fullblk, ul) != 0u;
             }
             for (uint64_t nz = __ballot(wm != 0u); nz;) {
                 // group grp takes the grp-th marked piece left
@@ -1178,10 +1189,11 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(7, 8))) voi
                 const int j = t ? __builtin_ctzll(t) : 0;
                 const uint32_t wj = (uint32_t)__shfl((int)wm, j, 64);
                 const int32_t r = __shfl(rl, j, 64);
+                const uint32_t u = (uint32_t)__shfl(ul, j, 64);
                 const int64_t b0 = __shfl(b0l, j, 64), b1 = __shfl(b1l, j, 64);
                 const bool sk = __shfl((int)skl, j, 64) != 0;
                 for (int k = 0; k < RPW && nz; ++k) nz &= nz - 1;
-                if (t) piece(base + j, r, b0, b1, wj, sk);
+                if (t) piece(base + j, r, u, b0, b1, wj, sk);
             }
         }
     }
@@ -1306,8 +1318,9 @@ hipError_t launch_sweep(const Layout& L, const DevGraph& g, const uint32_t* X, c
         const int rg = grid_for_rows((g.n + 31) / 32);
 #define HFR_ROWS64(BLK_)                                                                                              \
     HFR_LAYOUT_DISPATCH(L, HFR_KIND_DISPATCH(g.kind, hipLaunchKernelGGL((k_sweep_rows64<DW_, K_, BLK_>), dim3(rg),     \
-                                                                        dim3(256), 0, s, g.xadj, g.adj, g.eh, g.thr,  \
-                                                                        g.thr_const, X, sp.A, sp.B, sp.Lcur, sp.Lnext, \
+                                                                        dim3(256), 0, s, g.xadj, g.adj, hashes(g),    \
+                                                                        g.thr, g.thr_const, X, sp.A, sp.B, sp.Lcur,   \
+                                                                        sp.Lnext,                                     \
                                                                         sp.blk, sp.gate, sp.gate_thresh, sp.cnt_out,  \
                                                                         sp.vis_out, sp.sgate, sp.sum_out, g.rxadj,    \
                                                                         g.n, g.m, L.P, L.PW, g.heavy_deg, sp.first,   \
@@ -1320,8 +1333,9 @@ hipError_t launch_sweep(const Layout& L, const DevGraph& g, const uint32_t* X, c
 #undef HFR_ROWS64
     } else {
         HFR_LAYOUT_DISPATCH(L, HFR_KIND_DISPATCH(g.kind, hipLaunchKernelGGL((k_sweep_light<G_, DW_, K_>), dim3(lg),
-                                                                            dim3(256), 0, s, g.xadj, g.adj, g.eh,
-                                                                            g.thr, g.thr_const, X, sp.A, sp.B, sp.Lcur,
+                                                                            dim3(256), 0, s, g.xadj, g.adj,
+                                                                            hashes(g), g.thr, g.thr_const, X, sp.A,
+                                                                            sp.B, sp.Lcur,
                                                                             sp.Lnext, sp.blk, sp.gate, sp.gate_thresh,
                                                                             sp.cnt_out, sp.vis_out, sp.sgate,
                                                                             sp.sum_out, g.rxadj, g.n, g.m, L.P, L.PW,
@@ -1336,7 +1350,7 @@ hipError_t launch_sweep(const Layout& L, const DevGraph& g, const uint32_t* X, c
         const int rpw = 64 / L.G;
         const int hg = grid_for_rows((g.npieces + rpw - 1) / rpw);
         HFR_LAYOUT_DISPATCH(L, HFR_KIND_DISPATCH(g.kind, hipLaunchKernelGGL((k_sweep_heavy<G_, DW_, K_>), dim3(hg),
-                                                                            dim3(256), 0, s, g.adj, g.eh, g.thr,
+                                                                            dim3(256), 0, s, g.adj, hashes(g), g.thr,
                                                                             g.thr_const, X, sp.A, sp.Lcur, sp.blk,
                                                                             sp.gate, sp.gate_thresh,
                                                                             sp.vis_heavy_out, g.hrow, g.prow, g.pe0,
@@ -2033,7 +2047,7 @@ hipError_t launch_reach_start(const Layout& L, const DevGraph& g, const GreedyBu
 // One BFS level over the queue of level `cur` (see bfs_expand_entries).
 template <int G, int DW, int KIND>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(8, 8))) void k_bfs_expand(const int64_t* __restrict__ xadj, const int32_t* __restrict__ adj,
-                                                    const uint32_t* __restrict__ eh, const uint32_t* __restrict__ thr,
+                                                    EdgeHashes H, const uint32_t* __restrict__ thr,
                                                     uint32_t thr_const, const uint32_t* __restrict__ X, GreedyBufs b,
                                                     int cur, int32_t level_id_next, int P, int PW) {
     __shared__ unsigned long long sh64[4];
@@ -2045,7 +2059,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(8, 8))) voi
     load_sim_words<G, DW>(X, P, p, x);
     const uint32_t ntv = to_vgpr(0u - thr_const);
     const unsigned long long my_new = bfs_expand_entries<G, DW, KIND>(
-        wave_index() * RPW, (int64_t)size, wave_count() * RPW, xadj, adj, eh, thr, ntv, x, b.F[cur & 1],
+        wave_index() * RPW, (int64_t)size, wave_count() * RPW, xadj, adj, H, thr, ntv, x, b.F[cur & 1],
         b.F[(cur + 1) & 1], b.Q[cur & 1], b.Q[(cur + 1) & 1], &b.qsize[(cur + 1) % 3], b.blk, b.stamp, level_id_next,
         b.bfs_chunk, P, PW);
     const unsigned long long bn = block_sum256(my_new, sh64);
@@ -2073,9 +2087,9 @@ __global__ void k_bfs_cleanup(GreedyBufs b, int cur, int PW) {
 hipError_t launch_bfs_level(const Layout& L, const DevGraph& g, const uint32_t* X, const GreedyBufs& b, int level,
                             int32_t level_id_next, int grid, hipStream_t s) {
     HFR_LAYOUT_DISPATCH(L, HFR_KIND_DISPATCH(g.kind, hipLaunchKernelGGL((k_bfs_expand<G_, DW_, K_>), dim3(grid),
-                                                                        dim3(256), 0, s, g.xadj, g.adj, g.eh, g.thr,
-                                                                        g.thr_const, X, b, level, level_id_next, L.P,
-                                                                        L.PW)));
+                                                                        dim3(256), 0, s, g.xadj, g.adj, hashes(g),
+                                                                        g.thr, g.thr_const, X, b, level, level_id_next,
+                                                                        L.P, L.PW)));
     hipError_t err = hipGetLastError();
     if (err != hipSuccess) return err;
     hipLaunchKernelGGL(k_bfs_cleanup, dim3(256), dim3(256), 0, s, b, level, L.PW);

@@ -29,10 +29,10 @@ def test_heavy_launch_bytes(bench):
     idle = dict(dense, ran=0)
     # per merged row the head's row, the edge hash and (weighted cascade) the threshold; a
     # sparse launch reads the ids of the edges it visits
-    assert bench.heavy_launch_bytes(sparse, J, False, m_heavy, npieces) == 500 * 4 + 250 * (J + 4)
-    assert bench.heavy_launch_bytes(sparse, J, True, m_heavy, npieces) == 500 * 4 + 250 * (J + 8)
+    assert bench.heavy_launch_bytes(sparse, J, False, m_heavy, npieces) == 500 * 4 + 250 * J
+    assert bench.heavy_launch_bytes(sparse, J, True, m_heavy, npieces) == 500 * 4 + 250 * (J + 4)
     # a dense launch reads every split-row edge id and the piece table instead
-    assert bench.heavy_launch_bytes(dense, J, True, m_heavy, npieces) == 250 * (J + 8) + 4 * m_heavy + 20 * npieces
+    assert bench.heavy_launch_bytes(dense, J, True, m_heavy, npieces) == 250 * (J + 4) + 4 * m_heavy + 20 * npieces
     assert bench.heavy_launch_bytes(idle, J, True, m_heavy, npieces) == 0
 
 
