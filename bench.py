@@ -415,6 +415,7 @@ def main():
     ap.add_argument("--K", type=int, default=0, help="override K")
     ap.add_argument("--sparse-div", type=int, default=0)
     ap.add_argument("--heavy-degree", type=int, default=0)
+    ap.add_argument("--piece-edges", type=int, default=0)
     ap.add_argument("--dump-sweeps", default="", help="write the sweep log of the last step to this JSON file")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="start with one 1 GiB device copy (the counter calibration of the traffic summary)")
@@ -467,6 +468,7 @@ def main():
         t0 = time.perf_counter()
         sk = hf.im_build_sketches(ctx, xd, ad, g.n, w.J, model=w.model, p=w.p, eps_c=w.eps_c,
                                   sparse_div=args.sparse_div, heavy_degree=args.heavy_degree,
+                                  piece_edges=args.piece_edges,
                                   time_sweeps=timed)
         t1 = time.perf_counter()
         seeds, steps, stats = hf.im_select_seeds(sk, K, eps_g=w.eps_g, eps_l=w.eps_l)

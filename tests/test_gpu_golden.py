@@ -10,6 +10,9 @@ benchmark's configuration (default build options) and every integer and FP64 fie
 * ER n = 1000 (IC p = 0.1, R = 64, K = 10) and R-MAT 2^20 (IC p = 0.01, R = 256, K = 50): the whole
   run -- build, all K steps (seeds, scores, reach, e, sigma, delta, err_l, err_g, fresh, rebuilds and
   their sweep and visit counts), final registers and blocked pairs.
+* R-MAT 2^24, weighted cascade, R = 256: the build in full and the greedy prefix of K' steps the
+  oracle run reached (the first K' steps of K = 50 are the run with K = K'; no rebuild follows the
+  last step), with the registers and blocked pairs after step K'.
 * The 64-job batch (R = 128, K = 20), solved in one autotuned launch: every job's seeds, step
   records, build counters and build and final registers.
 * A sample of the serving stream's requests (every (graph size, model, p, R) class on the pool's
@@ -134,6 +137,12 @@ def test_rmat20_whole_run(hf):
     rec = _load("rmat20_p0.01_J256_K50")
     assert rec["K_done"] == 50
     _single_graph(hf, synth.workload_rmat20(), rec)
+
+
+def test_rmat24_wc_build_and_greedy_prefix(hf):
+    rec = _load("rmat24_wc_J256_K50")
+    assert "build" in rec
+    _single_graph(hf, synth.workload_rmat24_wc(), rec)
 
 
 def test_batch64_every_job(hf):
