@@ -149,7 +149,12 @@ struct BGlobal {
     int32_t xbeg[MAX_XCC], xend[MAX_XCC];  // pinned jobs [xbeg[x], xend[x]) run on XCD x (host-written)
     int32_t gbeg, gend;                    // jobs [gbeg, gend) run on every XCD
     alignas(128) uint32_t jobs_done;
+    uint32_t xdone[MAX_XCC];      // pinned jobs of XCD x that reached PH_DONE
+    uint32_t gdone;               // jobs served by every XCD that reached PH_DONE
     alignas(128) uint32_t abort;  // nonzero: the watchdog fired
+    // tiles completed by the waves of XCD x (slot x * 16, one 128-byte line each): the
+    // watchdog's evidence that some job, anywhere, is still moving
+    alignas(128) unsigned long long xprog[MAX_XCC * 16];
     alignas(128) unsigned long long tiles;
     unsigned long long phases;
 };
@@ -698,15 +703,22 @@ DEVI void advance(const BJob& jb, BGlobal* gl, uint32_t seq) {
         st64(&c->dsc, ((unsigned long long)(seq + 1) << 32) | ntiles);
         __hip_atomic_store(&c->claim, (unsigned long long)(seq + 1) << 32, __ATOMIC_RELEASE, JOB_SCOPE);
         atomicAdd(&gl->phases, 1ull);
-        if (phase == PH_DONE) atomicAdd(&gl->jobs_done, 1u);
+        if (phase == PH_DONE) {
+            // the wave that advances a pinned job runs on that job's XCD
+            atomicAdd(jb.pinned ? &gl->xdone[xcc_id()] : &gl->gdone, 1u);
+            atomicAdd(&gl->jobs_done, 1u);
+        }
     }
 }
 
 // The persistent solver.  Every wave loops: claim a tile of a pinned job of
 // its XCD or of a job served by all XCDs, run it, count it, and advance the
 // job when it completed the phase's last tile.  A wave that finds nothing
-// backs off (up to ~28 us) before it scans again; it raises the abort flag
-// when the claim words it scans have not changed for `timeout` ticks.
+// backs off (up to ~28 us) before it scans again.  A wave leaves once every job
+// it may serve is done (or all jobs are, or the abort flag is up).  It raises
+// the abort flag when, for `timeout` ticks, neither the claim words it scans,
+// nor the phase count, nor the tiles completed on any XCD have changed: then
+// no wave anywhere is making progress (a broken invariant only).
 template <int G, int DW>
 __global__ __launch_bounds__(256) void k_batch(const BJob* __restrict__ jobs, int njobs, BGlobal* gl,
                                                unsigned long long timeout_ticks) {
@@ -721,8 +733,12 @@ __global__ __launch_bounds__(256) void k_batch(const BJob* __restrict__ jobs, in
     int backoff = 0;
     unsigned long long idle_t0 = 0, last_sig = 0, my_tiles = 0;
     while (true) {
-        const uint32_t stop =
-            lane == 0 ? (ld32_all(&gl->abort) | (ld32_all(&gl->jobs_done) >= (uint32_t)njobs ? 1u : 0u)) : 0u;
+        uint32_t stop = 0;
+        if (lane == 0) {
+            stop = ld32_all(&gl->abort) | (ld32_all(&gl->jobs_done) >= (uint32_t)njobs ? 1u : 0u);
+            // every job this wave may serve is done: other XCDs may still be busy
+            if (ld32_all(&gl->xdone[x]) >= (uint32_t)n1 && ld32_all(&gl->gdone) >= (uint32_t)n2) stop = 1u;
+        }
         if (__builtin_amdgcn_readfirstlane(stop)) break;
         int jsel = -1;
         unsigned long long claim = 0, dsc = 0, sig = 0;
@@ -756,6 +772,12 @@ __global__ __launch_bounds__(256) void k_batch(const BJob* __restrict__ jobs, in
             }
         }
         if (jsel < 0) {
+            unsigned long long prog = 0;
+            if (lane == 0) {
+                prog = ld64(&gl->phases);
+                for (int k = 0; k < MAX_XCC; ++k) prog += ld64(&gl->xprog[k * 16]);
+            }
+            sig = sig * 0x9E3779B97F4A7C15ull + bcast64(prog);
             const unsigned long long now = wall_clock64();
             if (!idle || sig != last_sig) {  // some job moved: not stuck
                 idle = true;
@@ -778,6 +800,7 @@ __global__ __launch_bounds__(256) void k_batch(const BJob* __restrict__ jobs, in
         const BDesc d = load_desc(&c->d);
         run_tile<G, DW>(jb, c, d, (int)(uint32_t)claim);
         ++my_tiles;
+        if (lane == 0) __hip_atomic_fetch_add(&gl->xprog[x * 16], 1ull, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
         job_release(pinned);
         uint32_t prev = 0;
         if (lane == 0) prev = __hip_atomic_fetch_add(&c->done, 1u, __ATOMIC_ACQ_REL, JOB_SCOPE);
@@ -800,6 +823,11 @@ __global__ void k_batch_arm(const BJob* __restrict__ jobs, int njobs, BGlobal* g
     const int j = blockIdx.x * blockDim.x + threadIdx.x;
     if (j == 0) {  // the job ranges per XCD stay as the host wrote them
         gl->jobs_done = 0;
+        for (int k = 0; k < MAX_XCC; ++k) {
+            gl->xdone[k] = 0;
+            gl->xprog[k * 16] = 0;
+        }
+        gl->gdone = 0;
         gl->abort = 0;
         gl->tiles = 0;
         gl->phases = 0;
@@ -1175,7 +1203,13 @@ im_status im_batch_create(im_ctx* ctx, int32_t count, const im_batch_job* jobs, 
         return fail(IM_ERR_DEVICE, "device attribute query failed");
     }
     b->cus = cus > 0 ? cus : 256;
-    b->timeout_ticks = (unsigned long long)(clk_khz > 0 ? clk_khz : 100000) * 1000ull * 4ull;  // 4 s
+    // watchdog period: 4 s, or HFR_BATCH_TIMEOUT_MS (tests shorten it)
+    unsigned long long timeout_ms = 4000;
+    if (const char* e = getenv("HFR_BATCH_TIMEOUT_MS")) {
+        const long long v = atoll(e);
+        if (v > 0) timeout_ms = (unsigned long long)v;
+    }
+    b->timeout_ticks = (unsigned long long)(clk_khz > 0 ? clk_khz : 100000) * timeout_ms;
     b->cfg.G = o.lanes_per_row ? o.lanes_per_row : Gmin;
     if (o.tile_edges) b->cfg.tile_edges = o.tile_edges;
     if (o.heavy_degree) b->cfg.heavy_degree = o.heavy_degree;

@@ -260,3 +260,35 @@ def test_batch_budget(hf):
         hf.im_batch_create(small, [hf.BatchJob(g.xadj, g.adj, g.n, 64, 4)])
     assert e.value.status == -3
     assert small.bytes_in_use() == 0
+
+
+def test_uneven_pinned_batch_with_short_watchdog(hf, ctx, monkeypatch):
+    """Every job pinned to one XCD, one job far larger than the rest: the XCDs that hold only small
+    jobs finish long before the large one.  Their waves leave instead of reading the unchanged claim
+    words of finished jobs as a stall, and the waves that keep waiting see the tiles completed on
+    other XCDs; with the watchdog period forced down to 20 ms the batch still completes and every
+    job equals the single-graph path."""
+    monkeypatch.setenv("HFR_BATCH_TIMEOUT_MS", "20")
+    big = synth.rmat(15, 16 << 15, seed=61)
+    small = [synth.rmat(8, 12 << 8, seed=62 + i) for i in range(15)]
+    specs = [(big, "const", 0.05, 12)] + [(g, ("const", "wc")[i % 2], 0.1, 5) for i, g in enumerate(small)]
+    jobs, plain = [], []
+    for g, model, p, K in specs:
+        jobs.append(hf.BatchJob(g.xadj, g.adj, g.n, 128, K, model=model, p=p))
+        sk = hf.im_build_sketches(ctx, g.xadj, g.adj, g.n, 128, model=model, p=p)
+        try:
+            seeds, steps, _ = hf.im_select_seeds(sk, K)
+            plain.append((list(seeds), steps))
+        finally:
+            sk.free()
+    b = hf.im_batch_create(ctx, jobs, pin_edges=1 << 30)
+    try:
+        for _ in range(2):
+            b.run()
+            for i, (seeds, steps) in enumerate(plain):
+                bs, bsteps, _ = b.result(i)
+                assert list(bs) == seeds, i
+                for a, c in zip(bsteps, steps):
+                    assert a == c
+    finally:
+        b.free()

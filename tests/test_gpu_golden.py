@@ -13,8 +13,8 @@ benchmark's configuration (default build options) and every integer and FP64 fie
 * R-MAT 2^24, weighted cascade, R = 256: the build in full and the greedy prefix of K' steps the
   oracle run reached (the first K' steps of K = 50 are the run with K = K'; no rebuild follows the
   last step), with the registers and blocked pairs after step K'.
-* The 64-job batch (R = 128, K = 20), solved in one autotuned launch: every job's seeds, step
-  records, build counters and build and final registers.
+* The 64-job batch (R = 128, K = 20), solved in one launch, autotuned and with large tiles: every
+  job's seeds, step records, build counters and build and final registers.
 * A sample of the serving stream's requests (every (graph size, model, p, R) class on the pool's
   graphs of at most 2^15 vertices, and IC p = 0.01 on its 2^18-vertex graph), served together over
   several slots: every request's seeds.
@@ -145,7 +145,8 @@ def test_rmat24_wc_build_and_greedy_prefix(hf):
     _single_graph(hf, synth.workload_rmat24_wc(), rec)
 
 
-def test_batch64_every_job(hf):
+@pytest.mark.parametrize("decomposition", ["autotuned", "tile_edges=65536"])
+def test_batch64_every_job(hf, decomposition):
     import torch
 
     rec = _load("batch64_rmat_J128_K20")
@@ -161,8 +162,11 @@ def test_batch64_every_job(hf):
         bjobs.append(hf.BatchJob(x, a, g.n, jr["J"], jr["K"], model="const", p=p, eps_g=jr["eps_g"],
                                  eps_l=jr["eps_l"]))
     ctx = hf.Context(0)
-    print("[golden] batch64: autotuned create", flush=True)
-    b = hf.im_batch_create(ctx, bjobs, autotune=True)
+    print(f"[golden] batch64: {decomposition}", flush=True)
+    if decomposition == "autotuned":
+        b = hf.im_batch_create(ctx, bjobs, autotune=True)
+    else:  # large tiles (capped so that a phase still has hundreds of tiles)
+        b = hf.im_batch_create(ctx, bjobs, tile_edges=65536)
     try:
         b.run()
         for i, jr in enumerate(jobs):
