@@ -57,13 +57,16 @@ typedef enum im_prob_kind {
  * Requirements: n >= 1, xadj[0] = 0, xadj nondecreasing, xadj[n] = m,
  * 0 <= adj[e] < n, n < 2^31.  Duplicate edges and self-loops are accepted
  * (they do not change the registers; they do count towards in-degrees for the
- * weighted cascade). */
+ * weighted cascade).  The offsets are int64 (offset_bits 0 or 64) or int32
+ * (offset_bits 32, which needs m < 2^31); the library keeps its own int64
+ * copy either way.  Any other offset_bits is IM_ERR_INVALID_ARG. */
 typedef struct im_csr {
     int64_t n;
     int64_t m;
-    const int64_t* xadj; /* n+1 offsets */
+    const void* xadj;    /* n+1 offsets, int64_t or int32_t per offset_bits */
     const int32_t* adj;  /* m vertex ids */
     int32_t on_device;   /* 0: xadj/adj are host pointers; 1: device pointers on the context's device */
+    int32_t offset_bits; /* 0 or 64: int64 offsets; 32: int32 offsets */
 } im_csr;
 
 /* Edge probabilities w_uv in [0, 1] (Sec. 2.1).  per_edge (kind PER_EDGE)

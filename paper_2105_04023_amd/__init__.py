@@ -157,6 +157,23 @@ def _ptr_and_residency(a, dtype):
     return arr.ctypes.data, 0, arr
 
 
+def _offsets(xadj):
+    """(pointer, on_device, keepalive, offset_bits) of CSR offsets: int32 arrays and tensors are passed as
+    they are (offset_bits 32), anything else as int64."""
+    torch = _torch()
+    if isinstance(xadj, torch.Tensor):
+        if xadj.dtype == torch.int32:
+            t = xadj.contiguous()
+            return t.data_ptr(), int(t.is_cuda), t, 32
+        p, d, k = _ptr_and_residency(xadj, (np.int64, torch.int64))
+        return p, d, k, 64
+    if np.asarray(xadj).dtype == np.int32:
+        arr = np.ascontiguousarray(xadj, dtype=np.int32)
+        return arr.ctypes.data, 0, arr, 32
+    p, d, k = _ptr_and_residency(xadj, (np.int64, torch.int64))
+    return p, d, k, 64
+
+
 def im_build_sketches(ctx: Context, xadj, adj, n: int, R: int, model: str = "const", p: float = 0.0,
                       per_edge=None, hash_seed: int = 0, eps_c: float = 0.0, heavy_degree: int = 0,
                       piece_edges: int = 0, sparse_div: int = 0, time_sweeps: bool = False,
@@ -165,12 +182,12 @@ def im_build_sketches(ctx: Context, xadj, adj, n: int, R: int, model: str = "con
     in_place selects in-place sweeps (IM_BUILD_IN_PLACE) for the build and every rebuild;
     atomic_reverse the atomic reverse-CSR construction (IM_BUILD_ATOMIC_REVERSE)."""
     torch = _torch()
-    xp, xdev, xk = _ptr_and_residency(xadj, (np.int64, torch.int64))
+    xp, xdev, xk, xbits = _offsets(xadj)
     ap, adev, ak = _ptr_and_residency(adj, (np.int32, torch.int32))
     if xdev != adev:
         raise ValueError("xadj and adj must both be host arrays or both device tensors")
     m = int(len(adj)) if not isinstance(adj, torch.Tensor) else int(adj.numel())
-    g = B.im_csr(n, m, xp, ap, xdev)
+    g = B.im_csr(n, m, xp, ap, xdev, xbits)
     keep = [xk, ak]
     pe_ptr = None
     if model == "edge":
@@ -194,7 +211,7 @@ def im_evaluate_influence(ctx: Context, xadj, adj, n: int, seeds, R: int, model:
                           per_edge=None, hash_seed: int = 0):
     """Monte-Carlo influence of a seed set over R fresh samples: (sigma, reached pairs)."""
     torch = _torch()
-    xp, xdev, xk = _ptr_and_residency(xadj, (np.int64, torch.int64))
+    xp, xdev, xk, xbits = _offsets(xadj)
     ap, adev, ak = _ptr_and_residency(adj, (np.int32, torch.int32))
     if xdev != adev:
         raise ValueError("xadj and adj must both be host arrays or both device tensors")
@@ -209,7 +226,7 @@ def im_evaluate_influence(ctx: Context, xadj, adj, n: int, seeds, R: int, model:
         keep.append(pk)
     sv = np.ascontiguousarray(seeds, dtype=np.int32).ravel()
     sigma, reach = ctypes.c_double(), ctypes.c_int64()
-    B.check(ctx.lib.im_evaluate_influence(ctx.handle, ctypes.byref(B.im_csr(n, m, xp, ap, xdev)),
+    B.check(ctx.lib.im_evaluate_influence(ctx.handle, ctypes.byref(B.im_csr(n, m, xp, ap, xdev, xbits)),
                                           ctypes.byref(B.im_probs(_KIND[model], float(p), pe_ptr)), R,
                                           hash_seed & 0xFFFFFFFF, sv.ctypes.data, len(sv), ctypes.byref(sigma),
                                           ctypes.byref(reach)))
@@ -323,7 +340,7 @@ def im_batch_create(ctx: Context, jobs, autotune: bool = False, lanes_per_row: i
     arr = (B.im_batch_job * len(jobs))()
     keep = []
     for i, j in enumerate(jobs):
-        xp, xdev, xk = _ptr_and_residency(j.xadj, (np.int64, torch.int64))
+        xp, xdev, xk, xbits = _offsets(j.xadj)
         ap, adev, ak = _ptr_and_residency(j.adj, (np.int32, torch.int32))
         if xdev != adev:
             raise ValueError("xadj and adj must both be host arrays or both device tensors")
@@ -336,7 +353,7 @@ def im_batch_create(ctx: Context, jobs, autotune: bool = False, lanes_per_row: i
                 raise ValueError("per-edge probabilities must reside where the CSR resides")
             pe_ptr = pp
             keep.append(pk)
-        arr[i].graph = B.im_csr(j.n, m, xp, ap, xdev)
+        arr[i].graph = B.im_csr(j.n, m, xp, ap, xdev, xbits)
         arr[i].probs = B.im_probs(_KIND[j.model], float(j.p), pe_ptr)
         arr[i].R, arr[i].K, arr[i].hash_seed = j.R, j.K, j.hash_seed & 0xFFFFFFFF
         arr[i].eps_c, arr[i].eps_g, arr[i].eps_l = j.eps_c, j.eps_g, j.eps_l
@@ -364,13 +381,13 @@ class Server:
 
     def add_graph(self, xadj, adj, n: int) -> int:
         torch = _torch()
-        xp, xdev, xk = _ptr_and_residency(xadj, (np.int64, torch.int64))
+        xp, xdev, xk, xbits = _offsets(xadj)
         ap, adev, ak = _ptr_and_residency(adj, (np.int32, torch.int32))
         if xdev != adev:
             raise ValueError("xadj and adj must both be host arrays or both device tensors")
         m = int(len(adj)) if not isinstance(adj, torch.Tensor) else int(adj.numel())
         gid = ctypes.c_int32()
-        B.check(self.lib.im_server_add_graph(self.handle, ctypes.byref(B.im_csr(n, m, xp, ap, xdev)),
+        B.check(self.lib.im_server_add_graph(self.handle, ctypes.byref(B.im_csr(n, m, xp, ap, xdev, xbits)),
                                              ctypes.byref(gid)))
         self._ns.append(n)
         return gid.value

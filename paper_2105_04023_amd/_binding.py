@@ -12,6 +12,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "libhipfuser.so")
 
 IM_OK = 0
+IM_ERR_INVALID_ARG, IM_ERR_INVALID_GRAPH, IM_ERR_OUT_OF_BUDGET, IM_ERR_DEVICE, IM_ERR_STATE = -1, -2, -3, -4, -5
 STATUS_NAMES = {0: "IM_OK", -1: "IM_ERR_INVALID_ARG", -2: "IM_ERR_INVALID_GRAPH", -3: "IM_ERR_OUT_OF_BUDGET",
                 -4: "IM_ERR_DEVICE", -5: "IM_ERR_STATE"}
 IM_PROB_CONSTANT, IM_PROB_WEIGHTED_CASCADE, IM_PROB_PER_EDGE = 0, 1, 2
@@ -38,7 +39,7 @@ class ImError(RuntimeError):
 
 class im_csr(ctypes.Structure):
     _fields_ = [("n", ctypes.c_int64), ("m", ctypes.c_int64), ("xadj", ctypes.c_void_p), ("adj", ctypes.c_void_p),
-                ("on_device", ctypes.c_int32)]
+                ("on_device", ctypes.c_int32), ("offset_bits", ctypes.c_int32)]
 
 
 class im_probs(ctypes.Structure):

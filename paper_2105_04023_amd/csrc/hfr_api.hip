@@ -73,6 +73,58 @@ void ctx_free(im_ctx* c, void* p) {
         (void)hipFree(p);
 }
 
+im_status csr_offsets_check(const im_csr* g) {
+    if (g->offset_bits != 0 && g->offset_bits != 32 && g->offset_bits != 64)
+        return fail(IM_ERR_INVALID_ARG, "offset_bits must be 0, 32 or 64 (got %d)", g->offset_bits);
+    if (g->offset_bits == 32 && g->m >= (1ll << 31)) return fail(IM_ERR_INVALID_GRAPH, "int32 offsets need m < 2^31");
+    return IM_OK;
+}
+
+int64_t csr_offset_at(const im_csr* g, int64_t i) {
+    if (g->offset_bits == 32) {
+        int32_t v = 0;
+        const int32_t* p = static_cast<const int32_t*>(g->xadj) + i;
+        if (g->on_device) {
+            if (hipMemcpy(&v, p, 4, hipMemcpyDeviceToHost) != hipSuccess) return -1;
+        } else {
+            v = *p;
+        }
+        return v;
+    }
+    int64_t v = 0;
+    const int64_t* p = static_cast<const int64_t*>(g->xadj) + i;
+    if (g->on_device) {
+        if (hipMemcpy(&v, p, 8, hipMemcpyDeviceToHost) != hipSuccess) return -1;
+    } else {
+        v = *p;
+    }
+    return v;
+}
+
+hipError_t csr_copy_offsets(const im_csr* g, int64_t* dst, hipStream_t s) {
+    const int64_t cnt = g->n + 1;
+    if (g->offset_bits != 32)
+        return hipMemcpyAsync(dst, g->xadj, 8 * cnt, g->on_device ? hipMemcpyDeviceToDevice : hipMemcpyHostToDevice, s);
+    const int32_t* src = static_cast<const int32_t*>(g->xadj);
+    if (g->on_device) return launch_widen_offsets(src, dst, cnt, s);
+    std::vector<int64_t> wide(src, src + cnt);
+    const hipError_t e = hipMemcpyAsync(dst, wide.data(), 8 * cnt, hipMemcpyHostToDevice, s);
+    if (e != hipSuccess) return e;
+    return hipStreamSynchronize(s);  // the staging vector goes out of scope
+}
+
+hipError_t csr_offsets_to_host(const im_csr* g, int64_t* dst) {
+    const int64_t cnt = g->n + 1;
+    if (g->offset_bits != 32)
+        return hipMemcpy(dst, g->xadj, 8 * cnt, g->on_device ? hipMemcpyDeviceToHost : hipMemcpyHostToHost);
+    std::vector<int32_t> narrow(cnt);
+    const hipError_t e =
+        hipMemcpy(narrow.data(), g->xadj, 4 * cnt, g->on_device ? hipMemcpyDeviceToHost : hipMemcpyHostToHost);
+    if (e != hipSuccess) return e;
+    for (int64_t i = 0; i < cnt; ++i) dst[i] = narrow[i];
+    return hipSuccess;
+}
+
 }  // namespace hfr
 
 namespace {
@@ -604,6 +656,7 @@ im_status build_sketch(im_ctx* ctx, const im_csr* graph, const im_probs* probs, 
     if (n < 1 || n >= (1ll << 31)) return fail(IM_ERR_INVALID_GRAPH, "n must be in [1, 2^31) (got %lld)", (long long)n);
     if (m < 0 || m >= (1ll << 40)) return fail(IM_ERR_INVALID_GRAPH, "m out of range (got %lld)", (long long)m);
     if (!graph->xadj || (m > 0 && !graph->adj)) return fail(IM_ERR_INVALID_GRAPH, "null CSR array");
+    if (const im_status oc = csr_offsets_check(graph); oc != IM_OK) return oc;
     if (probs->kind != IM_PROB_CONSTANT && probs->kind != IM_PROB_WEIGHTED_CASCADE && probs->kind != IM_PROB_PER_EDGE)
         return fail(IM_ERR_INVALID_ARG, "unknown probability kind %d", (int)probs->kind);
     if (probs->kind == IM_PROB_CONSTANT && live_threshold(probs->p) == 0xFFFFFFFFu)
@@ -625,15 +678,9 @@ im_status build_sketch(im_ctx* ctx, const im_csr* graph, const im_probs* probs, 
     if (hipSetDevice(ctx->device) != hipSuccess) return fail(IM_ERR_DEVICE, "hipSetDevice failed");
 
     // host-side offset checks that need no device pass
-    int64_t x0 = 0, xn = 0;
-    if (graph->on_device) {
-        if (hipMemcpy(&x0, graph->xadj, 8, hipMemcpyDeviceToHost) != hipSuccess ||
-            hipMemcpy(&xn, graph->xadj + n, 8, hipMemcpyDeviceToHost) != hipSuccess)
-            return fail(IM_ERR_DEVICE, "reading device xadj failed");
-    } else {
-        x0 = graph->xadj[0];
-        xn = graph->xadj[n];
-    }
+    const int64_t x0 = csr_offset_at(graph, 0), xn = csr_offset_at(graph, n);
+    if (graph->on_device && (x0 < 0 || xn < 0) && hipGetLastError() != hipSuccess)
+        return fail(IM_ERR_DEVICE, "reading device xadj failed");
     if (x0 != 0 || xn != m) return fail(IM_ERR_INVALID_GRAPH, "xadj[0] must be 0 and xadj[n] must equal m");
 
     sk = new im_sketch;
@@ -714,7 +761,7 @@ im_status build_sketch(im_ctx* ctx, const im_csr* graph, const im_probs* probs, 
     auto body = [&]() -> im_status {
         const hipMemcpyKind kind = graph->on_device ? hipMemcpyDeviceToDevice : hipMemcpyHostToDevice;
         HIP_TRY(hipEventRecord(sk->ev_a, s));
-        HIP_TRY(hipMemcpyAsync(g.xadj, graph->xadj, 8 * (n + 1), kind, s));
+        HIP_TRY(csr_copy_offsets(graph, g.xadj, s));
         if (m > 0) HIP_TRY(hipMemcpyAsync(g.adj, graph->adj, 4 * m, kind, s));
         HIP_TRY(launch_fill_u32(sk->d_err, 0u, 1, s));
         HIP_TRY(launch_validate(g, sk->d_err, s));

@@ -1178,6 +1178,7 @@ im_status im_batch_create(im_ctx* ctx, int32_t count, const im_batch_job* jobs, 
         if (n < 1 || n >= (1ll << 31)) return fail(IM_ERR_INVALID_GRAPH, "job %d: n must be in [1, 2^31)", i);
         if (m < 0 || m >= (1ll << 40)) return fail(IM_ERR_INVALID_GRAPH, "job %d: m out of range", i);
         if (!j.graph.xadj || (m > 0 && !j.graph.adj)) return fail(IM_ERR_INVALID_GRAPH, "job %d: null CSR array", i);
+        if (const im_status oc = csr_offsets_check(&j.graph); oc != IM_OK) return oc;
         if (j.K < 1 || j.K > n) return fail(IM_ERR_INVALID_ARG, "job %d: K must be in [1, n]", i);
         const im_prob_kind pk = j.probs.kind;
         if (pk != IM_PROB_CONSTANT && pk != IM_PROB_WEIGHTED_CASCADE && pk != IM_PROB_PER_EDGE)
@@ -1242,7 +1243,7 @@ im_status im_batch_create(im_ctx* ctx, int32_t count, const im_batch_job* jobs, 
         h.xadj.resize(h.n + 1);
         h.adj.resize(h.m);
         const hipMemcpyKind kind = j.graph.on_device ? hipMemcpyDeviceToHost : hipMemcpyHostToHost;
-        if (hipMemcpy(h.xadj.data(), j.graph.xadj, 8 * (h.n + 1), kind) != hipSuccess ||
+        if (csr_offsets_to_host(&j.graph, h.xadj.data()) != hipSuccess ||
             (h.m > 0 && hipMemcpy(h.adj.data(), j.graph.adj, 4 * h.m, kind) != hipSuccess))
             return bail(fail(IM_ERR_DEVICE, "job %d: reading the CSR failed", i));
         if (h.xadj[0] != 0 || h.xadj[h.n] != h.m)

@@ -32,4 +32,14 @@ im_status fail(im_status st, const char* fmt, ...);
 void* ctx_alloc(im_ctx* c, size_t bytes);
 void ctx_free(im_ctx* c, void* p);
 
+// Offsets of a caller's CSR, int64 or int32 per im_csr.offset_bits.
+// csr_offsets_check: IM_OK, or the error (with its message) of an invalid offset_bits.
+im_status csr_offsets_check(const im_csr* g);
+// Offset i (host read, or a small device-to-host copy for device arrays); -1 on a copy failure.
+int64_t csr_offset_at(const im_csr* g, int64_t i);
+// All n+1 offsets as int64 into device memory dst (widened on the device for int32 inputs).
+hipError_t csr_copy_offsets(const im_csr* g, int64_t* dst, hipStream_t s);
+// All n+1 offsets as int64 into host memory.
+hipError_t csr_offsets_to_host(const im_csr* g, int64_t* dst);
+
 }  // namespace hfr

@@ -147,6 +147,7 @@ hipError_t launch_wc_thresholds(const uint32_t* indeg, uint32_t* thr, int64_t n,
 hipError_t launch_gather_u32(const uint32_t* src, const int32_t* idx, int64_t m, uint32_t* out, hipStream_t s);
 hipError_t launch_edge_thresholds(const float* w, uint32_t* thr, int64_t m, uint32_t* err, hipStream_t s);
 hipError_t launch_sim_words(uint32_t* X, uint32_t* HJ, int J, uint32_t seed, hipStream_t s);
+hipError_t launch_widen_offsets(const int32_t* src, int64_t* dst, int64_t count, hipStream_t s);
 
 // Sets DEAD_EDGE in the target id of every edge live in no sample (thresholds final).
 hipError_t launch_dead_edges(const DevGraph& g, const uint32_t* X, int J, hipStream_t s);

@@ -216,6 +216,20 @@ __global__ void k_sim_words(uint32_t* X, uint32_t* HJ, int J, uint32_t seed) {
     }
 }
 
+// int32 CSR offsets widened to the library's int64 copy.
+__global__ void k_widen_offsets(const int32_t* __restrict__ src, int64_t* __restrict__ dst, int64_t count) {
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < count; i += (int64_t)gridDim.x * blockDim.x)
+        dst[i] = (int64_t)src[i];
+}
+
+hipError_t launch_widen_offsets(const int32_t* src, int64_t* dst, int64_t count, hipStream_t s) {
+    int64_t blocks = (count + 255) / 256;
+    if (blocks > 8192) blocks = 8192;
+    if (blocks < 1) blocks = 1;
+    hipLaunchKernelGGL(k_widen_offsets, dim3((unsigned)blocks), dim3(256), 0, s, src, dst, count);
+    return hipGetLastError();
+}
+
 hipError_t launch_sim_words(uint32_t* X, uint32_t* HJ, int J, uint32_t seed, hipStream_t s) {
     hipLaunchKernelGGL(k_sim_words, dim3((J + 255) / 256), dim3(256), 0, s, X, HJ, J, seed);
     return hipGetLastError();

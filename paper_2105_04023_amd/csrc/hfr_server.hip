@@ -261,6 +261,7 @@ im_status im_server_add_graph(im_server* sv, const im_csr* graph, int32_t* out_g
     const int64_t n = graph->n, m = graph->m;
     if (n < 1 || n >= (1ll << 31) || m < 0 || !graph->xadj || (m > 0 && !graph->adj))
         return hfr::fail(IM_ERR_INVALID_GRAPH, "malformed CSR");
+    if (const im_status oc = hfr::csr_offsets_check(graph); oc != IM_OK) return oc;
     if (hipSetDevice(sv->device) != hipSuccess) return hfr::fail(IM_ERR_DEVICE, "hipSetDevice failed");
     GraphRes g;
     g.n = n;
@@ -272,7 +273,7 @@ im_status im_server_add_graph(im_server* sv, const im_csr* graph, int32_t* out_g
         return hfr::fail(IM_ERR_OUT_OF_BUDGET, "the graph pool exceeds the budget");
     const hipMemcpyKind kind = graph->on_device ? hipMemcpyDeviceToDevice : hipMemcpyHostToDevice;
     if (hipMalloc(&g.xadj, 8 * (n + 1)) != hipSuccess || (hipMalloc(&g.adj, 4 * (m ? m : 1)) != hipSuccess) ||
-        hipMemcpy(g.xadj, graph->xadj, 8 * (n + 1), kind) != hipSuccess ||
+        hfr::csr_copy_offsets(graph, g.xadj, nullptr) != hipSuccess || hipDeviceSynchronize() != hipSuccess ||
         (m > 0 && hipMemcpy(g.adj, graph->adj, 4 * m, kind) != hipSuccess)) {
         if (g.xadj) (void)hipFree(g.xadj);
         if (g.adj) (void)hipFree(g.adj);

@@ -91,8 +91,10 @@ def hf():
     return hf
 
 
-def _single_graph(hf, w, rec):
-    """Build + select on the device-resident CSR (the benchmark's configuration), against the record."""
+def _single_graph(hf, w, rec, offset_bits=64):
+    """Build + select on the device-resident CSR (the benchmark's configuration), against the record.
+    offset_bits 32 passes the offsets as int32 (the 1000-vertex and 2^20-vertex workloads are stated
+    with int32 CSRs)."""
     import torch
 
     g = w.graph
@@ -101,7 +103,8 @@ def _single_graph(hf, w, rec):
     K = rec["K_done"]
     print(f"[golden] {rec['name']}: n={g.n} m={g.m} R={rec['J']} K'={K}", flush=True)
     ctx = hf.Context(0)
-    xd, ad = torch.from_numpy(g.xadj).cuda(), torch.from_numpy(g.adj).cuda()
+    xadj = g.xadj.astype(np.int32) if offset_bits == 32 else g.xadj
+    xd, ad = torch.from_numpy(xadj).cuda(), torch.from_numpy(g.adj).cuda()
     sk = hf.im_build_sketches(ctx, xd, ad, g.n, rec["J"], model=rec["model"], p=w.p, hash_seed=rec["hash_seed"])
     try:
         info = sk.info()
@@ -130,13 +133,13 @@ def _single_graph(hf, w, rec):
 
 
 def test_er1000_whole_run(hf):
-    _single_graph(hf, synth.workload_er_small(), _load("er_n1000_m10000_p0.1_J64_K10"))
+    _single_graph(hf, synth.workload_er_small(), _load("er_n1000_m10000_p0.1_J64_K10"), offset_bits=32)
 
 
 def test_rmat20_whole_run(hf):
     rec = _load("rmat20_p0.01_J256_K50")
     assert rec["K_done"] == 50
-    _single_graph(hf, synth.workload_rmat20(), rec)
+    _single_graph(hf, synth.workload_rmat20(), rec, offset_bits=32)
 
 
 def test_rmat24_wc_build_and_greedy_prefix(hf):
