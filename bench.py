@@ -410,7 +410,9 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-batch", action="store_true", help="skip the batched-vs-plain comparison")
     ap.add_argument("--no-quality", action="store_true", help="skip the rebuild-policy quality comparison")
-    ap.add_argument("--serve-requests", type=int, default=400,
+    ap.add_argument("--serve-slots", type=int, default=4, help="concurrent slots of the serving engine")
+    ap.add_argument("--serve-only", action="store_true", help="run only the serving leg and print its object")
+    ap.add_argument("--serve-requests", type=int, default=2000,
                     help="requests of the serving leg (the full stream has 2000; 0 skips the leg)")
     ap.add_argument("--K", type=int, default=0, help="override K")
     ap.add_argument("--sparse-div", type=int, default=0)
@@ -442,6 +444,9 @@ def main():
 
     if args.batch_only:
         print(json.dumps({"batched": batch_leg(hf, hf.Context(0), args.steps, args.warmup)}), flush=True)
+        return
+    if args.serve_only:
+        print(json.dumps({"serving": serve_leg(hf, args.serve_requests, slots=args.serve_slots)}), flush=True)
         return
     import synth
 
@@ -557,7 +562,7 @@ def main():
     if not args.no_batch:
         out["batched"] = batch_leg(hf, ctx, args.steps, args.warmup)
     if args.serve_requests > 0:
-        out["serving"] = serve_leg(hf, args.serve_requests)
+        out["serving"] = serve_leg(hf, args.serve_requests, slots=args.serve_slots)
     if not args.no_quality:
         out["quality"] = quality_leg(hf, ctx)
     if args.dump_sweeps:

@@ -373,20 +373,23 @@ IM_API void im_batch_free(im_batch* b);
  * ---------------------------------------------------------------------------
  * Serving: requests (graph, edge model, R, K) over a pool of resident graphs,
  * answered by `slots` concurrent slots.  Each slot has its own host thread and
- * HIP stream, so requests of different slots overlap on the device; requests
- * that arrive while the slots are busy wait in a queue and start as soon as
- * their slot is free.  A slot keeps the sketches it built resident and reuses
- * them for later requests with the same (graph, model, p, R, hash seed,
- * eps_c); every request runs its own greedy selection, so its result equals
- * im_build_sketches + im_select_seeds run alone.  hbm_budget (0 = none) bounds
- * the device memory of the resident graphs plus all sketches; each slot holds
- * at most an equal share of what the graphs leave and evicts its least
- * recently used idle sketches to admit a new build.
+ * HIP stream, so requests of different slots overlap on the device.  Requests
+ * wait in one queue; each free slot takes the oldest request it can start now,
+ * so a request is admitted as soon as any slot and the memory it needs are
+ * free.  Sketches stay resident in one pool and are reused, on whichever slot
+ * runs the request, by later requests with the same (graph, model, p, R, hash
+ * seed, eps_c); a sketch serves one request at a time, and a key whose copies
+ * are all busy may get a second copy.  Every request runs its own greedy
+ * selection, so its result equals im_build_sketches + im_select_seeds run
+ * alone.  hbm_budget (0 = none) bounds the device memory of the resident graphs
+ * plus all sketches: a build evicts idle sketches, least recently used first,
+ * until it fits, and a request whose sketch cannot fit even alone fails with
+ * IM_ERR_OUT_OF_BUDGET without evicting anything.
  * ---------------------------------------------------------------------------
  */
 typedef struct im_server_opts {
     int32_t slots;      /* concurrent requests, in [1, 64] */
-    int32_t reserved;
+    int32_t max_copies; /* resident copies one sketch key may have, in [1, 64] (0: 2) */
     size_t hbm_budget;  /* device bytes for graphs and sketches; 0 = no bound */
 } im_server_opts;
 
@@ -403,7 +406,7 @@ typedef struct im_request {
 
 typedef struct im_response {
     int32_t status;        /* IM_OK, or the error of this request */
-    int32_t slot;          /* slot that served it */
+    int32_t slot;          /* slot that served it (-1: it never ran) */
     int32_t sketch_reused; /* 1 if its sketches were resident already */
     int32_t rebuilds;      /* rebuilds of its greedy selection */
     double queue_ms;       /* submit to start */
@@ -429,6 +432,10 @@ IM_API im_status im_server_add_graph(im_server* sv, const im_csr* graph, int32_t
 IM_API im_status im_server_submit(im_server* sv, const im_request* rq, int32_t* out_seeds, int64_t* out_ticket);
 /* Blocks until the request is done; fills *out (may be NULL) and returns its status. */
 IM_API im_status im_server_wait(im_server* sv, int64_t ticket, im_response* out);
+/* Cancels a request that has not started: IM_OK, after which im_server_wait
+ * returns IM_ERR_STATE for it (its out_seeds are not written); IM_ERR_STATE if
+ * it already started, finished or the ticket is unknown.  Thread-safe. */
+IM_API im_status im_server_cancel(im_server* sv, int64_t ticket);
 IM_API im_status im_server_get_stats(im_server* sv, im_server_stats* out);
 /* Finishes the queued requests, then frees every resource of the server. */
 IM_API void im_server_free(im_server* sv);

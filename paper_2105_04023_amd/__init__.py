@@ -370,10 +370,10 @@ class Server:
     """Serving engine of the library (im_server_*): resident graphs, concurrent slots, sketch reuse,
     admission by an HBM budget.  submit() returns a ticket; wait() blocks for its seeds and response."""
 
-    def __init__(self, device: int = 0, slots: int = 4, hbm_budget: int = 0):
+    def __init__(self, device: int = 0, slots: int = 4, hbm_budget: int = 0, max_copies: int = 0):
         self.lib = B.load()
         h = ctypes.c_void_p()
-        B.check(self.lib.im_server_create(device, ctypes.byref(B.im_server_opts(slots, 0, hbm_budget)),
+        B.check(self.lib.im_server_create(device, ctypes.byref(B.im_server_opts(slots, max_copies, hbm_budget)),
                                           ctypes.byref(h)))
         self.handle = h
         self._ns = []
@@ -410,6 +410,15 @@ class Server:
         seeds = self._pending.pop(ticket)
         B.check(st)
         return seeds, {f: getattr(resp, f) for f, _ in B.im_response._fields_}
+
+    def cancel(self, ticket: int) -> bool:
+        """Cancels a request that has not started; False if it started, finished or is unknown."""
+        st = self.lib.im_server_cancel(self.handle, ticket)
+        if st == B.IM_OK:
+            return True
+        if st == B.IM_ERR_STATE:
+            return False
+        B.check(st)
 
     def stats(self) -> dict:
         s = B.im_server_stats()

@@ -27,7 +27,7 @@ EXPORTED = [
     "im_sketch_get_sweep_log", "im_sketch_clear_sweep_log", "im_batch_create", "im_batch_run", "im_batch_get_result",
     "im_batch_get_registers", "im_batch_device_bytes", "im_batch_free", "im_server_create", "im_server_add_graph",
     "im_server_submit", "im_server_wait", "im_server_get_stats", "im_server_free", "im_evaluate_influence",
-    "im_select_seeds_noalloc",
+    "im_select_seeds_noalloc", "im_server_cancel",
 ]
 
 
@@ -109,7 +109,7 @@ class im_batch_stats(ctypes.Structure):
 
 
 class im_server_opts(ctypes.Structure):
-    _fields_ = [("slots", ctypes.c_int32), ("reserved", ctypes.c_int32), ("hbm_budget", ctypes.c_size_t)]
+    _fields_ = [("slots", ctypes.c_int32), ("max_copies", ctypes.c_int32), ("hbm_budget", ctypes.c_size_t)]
 
 
 class im_request(ctypes.Structure):
@@ -177,6 +177,7 @@ def load(path: str = LIB_PATH):
         "im_server_add_graph": ([p, ctypes.POINTER(im_csr), ctypes.POINTER(i32)], ctypes.c_int),
         "im_server_submit": ([p, ctypes.POINTER(im_request), p, ctypes.POINTER(i64)], ctypes.c_int),
         "im_server_wait": ([p, i64, ctypes.POINTER(im_response)], ctypes.c_int),
+        "im_server_cancel": ([p, i64], ctypes.c_int),
         "im_server_get_stats": ([p, ctypes.POINTER(im_server_stats)], ctypes.c_int),
         "im_server_free": ([p], None),
         "im_evaluate_influence": ([p, ctypes.POINTER(im_csr), ctypes.POINTER(im_probs), i32, ctypes.c_uint32, p, i32,

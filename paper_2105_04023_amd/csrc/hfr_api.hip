@@ -600,6 +600,17 @@ im_status check_sketch(const im_sketch* sk) {
 
 }  // namespace
 
+namespace hfr {
+
+void sketch_rebind(im_sketch* sk, im_ctx* ctx) {
+    if (!sk || !ctx || sk->ctx == ctx) return;
+    sk->ctx->in_use -= sk->bytes;
+    ctx->in_use += sk->bytes;
+    sk->ctx = ctx;
+}
+
+}  // namespace hfr
+
 extern "C" {
 
 const char* im_last_error(void) { return hfr::g_last_error.c_str(); }
@@ -632,7 +643,7 @@ im_status im_ctx_create(int32_t device, void* stream, size_t hbm_budget, im_allo
 
 void im_ctx_free(im_ctx* ctx) { delete ctx; }
 
-size_t im_ctx_bytes_in_use(const im_ctx* ctx) { return ctx ? ctx->in_use : 0; }
+size_t im_ctx_bytes_in_use(const im_ctx* ctx) { return ctx ? ctx->in_use.load() : 0; }
 
 size_t im_sketch_bytes_needed(int64_t n, int64_t m, int32_t R, im_prob_kind kind) {
     if (n < 1 || m < 0 || R < 4 || R > 1024 || R % 4) return 0;
@@ -672,7 +683,7 @@ im_status build_sketch(im_ctx* ctx, const im_csr* graph, const im_probs* probs, 
         return fail(IM_ERR_INVALID_ARG, "unknown build flag");
     const size_t need = bytes_needed(n, m, R, probs->kind);
     if (ctx->budget && ctx->in_use + need > ctx->budget)
-        return fail(IM_ERR_OUT_OF_BUDGET, "sketch needs %zu bytes, %zu of %zu in use", need, ctx->in_use, ctx->budget);
+        return fail(IM_ERR_OUT_OF_BUDGET, "sketch needs %zu bytes, %zu of %zu in use", need, ctx->in_use.load(), ctx->budget);
 
     hipStream_t s = ctx->stream;
     if (hipSetDevice(ctx->device) != hipSuccess) return fail(IM_ERR_DEVICE, "hipSetDevice failed");

@@ -5,6 +5,7 @@
 #include <hip/hip_runtime.h>
 #include <stddef.h>
 
+#include <atomic>
 #include <string>
 
 #include "../../include/im.h"
@@ -14,7 +15,7 @@ struct im_ctx {
     int device = 0;
     hipStream_t stream = nullptr;
     size_t budget = 0;  // bytes all handles of the context may hold (0 = no bound)
-    size_t in_use = 0;
+    std::atomic<size_t> in_use{0};  // sketches of several threads may be released into one context
     im_alloc_fn af = nullptr;
     im_free_fn ff = nullptr;
     void* user = nullptr;
@@ -41,5 +42,10 @@ int64_t csr_offset_at(const im_csr* g, int64_t i);
 hipError_t csr_copy_offsets(const im_csr* g, int64_t* dst, hipStream_t s);
 // All n+1 offsets as int64 into host memory.
 hipError_t csr_offsets_to_host(const im_csr* g, int64_t* dst);
+
+// Moves an idle sketch (no work of it in flight) to another context of the same
+// device: its later calls run on that context's stream and count against that
+// context's bytes in use.  Both contexts must use the same allocator.
+void sketch_rebind(im_sketch* sk, im_ctx* ctx);
 
 }  // namespace hfr

@@ -1,42 +1,30 @@
 // Serving engine: influence-maximisation requests over a pool of resident
-// graphs, answered by concurrent slots.
+// graphs, answered by concurrent slots (the scheduling is hfr_sched.h's).
 //
 // Each slot is one host thread with its own HIP stream and its own context,
-// so the requests of different slots overlap on the device; a request that
-// arrives while others run is queued and admitted as soon as its slot is
-// free.  Sketches (the build of Alg. 1 + Alg. 2 for one graph, edge model, R
-// and hash seed) stay resident in the slot that built them and are reused by
-// later requests with the same key; every request runs its own greedy
-// selection (im_select_seeds starts from the build's registers each time).
-// Device memory is admitted by budget: the resident graphs and every slot's
-// sketches share hbm_budget, each slot holding at most an equal share of what
-// the graphs leave; a slot evicts its least recently used idle sketches until
-// a new build fits.  A request routes to the slot that holds (or is about to
-// build) its sketch, else to the slot with the least queued work.
+// so the requests of different slots overlap on the device.  Requests wait in
+// one shared queue and each free slot takes the oldest one it can start now,
+// so a request is admitted as soon as any slot and the memory it needs are
+// free.  Sketches (the build of Alg. 1 + Alg. 2 for one graph, edge model, p,
+// R, hash seed and eps_c) form one pool: a later request with the same key
+// reuses an idle copy on whichever slot runs it (the sketch is moved to that
+// slot's stream), and a key with every copy busy may get a second copy.
+// Every request runs its own greedy selection (im_select_seeds starts from the
+// build's registers each time), so a served result equals
+// im_build_sketches + im_select_seeds run alone.  The resident graphs and all
+// sketches share hbm_budget; a build evicts idle sketches least recently used
+// first until it fits, and a build that cannot fit even alone is refused.
 #include <hip/hip_runtime.h>
 #include <string.h>
 
-#include <algorithm>
-#include <chrono>
-#include <condition_variable>
-#include <deque>
-#include <map>
 #include <memory>
 #include <mutex>
-#include <string>
-#include <thread>
-#include <tuple>
 #include <vector>
 
 #include "hfr_host.h"
+#include "hfr_sched.h"
 
 namespace {
-
-using Clock = std::chrono::steady_clock;
-
-double ms_between(Clock::time_point a, Clock::time_point b) {
-    return std::chrono::duration<double, std::milli>(b - a).count();
-}
 
 struct GraphRes {
     int64_t n = 0, m = 0;
@@ -45,35 +33,59 @@ struct GraphRes {
     size_t bytes = 0;
 };
 
-// (graph, kind, p bits, R, hash seed, eps_c bits)
-using Key = std::tuple<int32_t, int32_t, uint32_t, int32_t, uint32_t, uint64_t>;
-
-struct Request {
-    int64_t ticket = 0;
+struct Payload {
     im_request rq{};
-    Key key;
+    GraphRes g;
     int32_t* out_seeds = nullptr;
-    double work = 0.0;
-    Clock::time_point t_submit, t_start, t_end;
-    im_response resp{};
-    std::string error;
-    bool done = false;
 };
 
-struct CachedSketch {
-    im_sketch* sk = nullptr;
-    size_t bytes = 0;
-    uint64_t last_use = 0;
-};
-
-struct Slot {
-    int index = 0;
+struct SlotRes {
     hipStream_t stream = nullptr;
     im_ctx* ctx = nullptr;
-    std::thread thread;
-    std::deque<std::shared_ptr<Request>> queue;
-    double queued_work = 0.0;
-    std::map<Key, CachedSketch> cache;
+};
+
+// The HIP path behind the scheduler: build and select through the C ABI on the
+// slot's context.
+struct HipBackend final : hfr::sched::Backend<Payload> {
+    int device = 0;
+    std::vector<SlotRes> slots;
+
+    im_status build(int slot, const Payload& p, void** handle, size_t* bytes, std::string* err) override {
+        (void)hipSetDevice(device);
+        const im_request& q = p.rq;
+        im_csr csr{p.g.n, p.g.m, p.g.xadj, p.g.adj, 1, 64};
+        im_probs pr{(im_prob_kind)q.kind, q.p, nullptr};
+        im_build_opts bo{};
+        bo.eps_c = q.eps_c;
+        im_sketch* sk = nullptr;
+        const im_status st = im_build_sketches(slots[slot].ctx, &csr, &pr, q.R, q.hash_seed, &bo, &sk);
+        if (st != IM_OK) {
+            *err = im_last_error();
+            return st;
+        }
+        im_sketch_info info{};
+        *bytes = im_sketch_get_info(sk, &info) == IM_OK ? info.device_bytes : 0;
+        *handle = sk;
+        return IM_OK;
+    }
+    void adopt(int slot, void* handle) override {
+        (void)hipSetDevice(device);
+        hfr::sketch_rebind(static_cast<im_sketch*>(handle), slots[slot].ctx);
+    }
+    im_status select(int slot, void* handle, const Payload& p, int32_t* rebuilds, std::string* err) override {
+        (void)slot;
+        (void)hipSetDevice(device);
+        im_select_opts so{p.rq.eps_g, p.rq.eps_l};
+        im_select_stats ss{};
+        const im_status st = im_select_seeds(static_cast<im_sketch*>(handle), p.rq.K, &so, p.out_seeds, nullptr, &ss);
+        *rebuilds = ss.rebuilds;
+        if (st != IM_OK) *err = im_last_error();
+        return st;
+    }
+    void release(void* handle) override {
+        (void)hipSetDevice(device);
+        im_sketch_free(static_cast<im_sketch*>(handle));
+    }
 };
 
 }  // namespace
@@ -81,141 +93,23 @@ struct Slot {
 struct im_server {
     int device = 0;
     size_t budget = 0;
+    std::mutex mu;                 // guards graphs, graph_bytes, started
+    std::vector<GraphRes> graphs;  // fixed once the first request is submitted
     size_t graph_bytes = 0;
-    size_t slot_budget = 0;
-    std::vector<GraphRes> graphs;
-    std::vector<std::unique_ptr<Slot>> slots;
-    std::map<Key, int> route;  // key -> slot holding or building its sketch
-    std::map<int64_t, std::shared_ptr<Request>> requests;
-    std::mutex mu;
-    std::condition_variable cv_work, cv_done;
-    bool stopping = false;
-    bool started = false;  // a request was submitted: the graph pool is fixed
-    int64_t next_ticket = 1;
-    uint64_t use_clock = 0;
-    im_server_stats stats{};
+    bool started = false;
+    HipBackend backend;
+    std::unique_ptr<hfr::sched::Scheduler<Payload>> sched;
 };
 
 namespace {
 
-// Runs one request on its slot (slot thread, server lock not held).
-void serve(im_server* sv, Slot* sl, Request* r) {
-    const im_request& q = r->rq;
-    const GraphRes& g = sv->graphs[q.graph];
-    im_status st = IM_OK;
-    im_sketch* sk = nullptr;
-    bool reused = false;
-    double build_ms = 0.0;
-    {
-        std::lock_guard<std::mutex> lk(sv->mu);
-        auto it = sl->cache.find(r->key);
-        if (it != sl->cache.end()) {
-            sk = it->second.sk;
-            it->second.last_use = ++sv->use_clock;
-            reused = true;
-        }
-    }
-    if (!sk) {
-        im_csr csr{g.n, g.m, g.xadj, g.adj, 1};
-        im_probs pr{(im_prob_kind)q.kind, q.p, nullptr};
-        im_build_opts bo{};
-        bo.eps_c = q.eps_c;
-        const auto t0 = Clock::now();
-        st = im_build_sketches(sl->ctx, &csr, &pr, q.R, q.hash_seed, &bo, &sk);
-        if (st == IM_ERR_OUT_OF_BUDGET) {
-            // evict idle sketches of this slot, least recently used first
-            while (st == IM_ERR_OUT_OF_BUDGET) {
-                im_sketch* victim = nullptr;
-                {
-                    std::lock_guard<std::mutex> lk(sv->mu);
-                    auto best = sl->cache.end();
-                    for (auto it = sl->cache.begin(); it != sl->cache.end(); ++it)
-                        if (best == sl->cache.end() || it->second.last_use < best->second.last_use) best = it;
-                    if (best != sl->cache.end()) {
-                        victim = best->second.sk;
-                        sv->route.erase(best->first);
-                        sl->cache.erase(best);
-                        sv->stats.evictions += 1;
-                    }
-                }
-                if (!victim) break;
-                im_sketch_free(victim);
-                st = im_build_sketches(sl->ctx, &csr, &pr, q.R, q.hash_seed, &bo, &sk);
-            }
-        }
-        build_ms = ms_between(t0, Clock::now());
-        if (st == IM_OK) {
-            std::lock_guard<std::mutex> lk(sv->mu);
-            CachedSketch cs;
-            im_sketch_info info{};
-            cs.sk = sk;
-            if (im_sketch_get_info(sk, &info) == IM_OK) cs.bytes = info.device_bytes;
-            cs.last_use = ++sv->use_clock;
-            sl->cache[r->key] = cs;
-            sv->stats.sketches_built += 1;
-        } else {
-            r->error = im_last_error();
-        }
-    }
-    int32_t rebuilds = 0;
-    double select_ms = 0.0;
-    if (st == IM_OK) {
-        im_select_opts so{q.eps_g, q.eps_l};
-        im_select_stats ss{};
-        const auto t0 = Clock::now();
-        st = im_select_seeds(sk, q.K, &so, r->out_seeds, nullptr, &ss);
-        select_ms = ms_between(t0, Clock::now());
-        rebuilds = ss.rebuilds;
-        if (st != IM_OK) r->error = im_last_error();
-    }
-    r->resp.status = st;
-    r->resp.slot = sl->index;
-    r->resp.sketch_reused = reused ? 1 : 0;
-    r->resp.rebuilds = rebuilds;
-    r->resp.build_ms = build_ms;
-    r->resp.select_ms = select_ms;
-}
-
-void slot_main(im_server* sv, Slot* sl) {
-    (void)hipSetDevice(sv->device);
-    while (true) {
-        std::shared_ptr<Request> r;
-        {
-            std::unique_lock<std::mutex> lk(sv->mu);
-            sv->cv_work.wait(lk, [&] { return sv->stopping || !sl->queue.empty(); });
-            if (sl->queue.empty()) return;  // stopping and drained
-            r = sl->queue.front();
-            sl->queue.pop_front();
-            r->t_start = Clock::now();
-        }
-        serve(sv, sl, r.get());
-        {
-            std::lock_guard<std::mutex> lk(sv->mu);
-            r->t_end = Clock::now();
-            r->resp.queue_ms = ms_between(r->t_submit, r->t_start);
-            r->resp.latency_ms = ms_between(r->t_submit, r->t_end);
-            r->done = true;
-            sl->queued_work -= r->work;
-            sv->stats.completed += 1;
-            if (r->resp.status != IM_OK) sv->stats.failed += 1;
-        }
-        sv->cv_done.notify_all();
-    }
-}
-
 void server_release(im_server* sv) {
     if (!sv) return;
-    {
-        std::lock_guard<std::mutex> lk(sv->mu);
-        sv->stopping = true;
-    }
-    sv->cv_work.notify_all();
-    for (auto& sl : sv->slots)
-        if (sl->thread.joinable()) sl->thread.join();
-    for (auto& sl : sv->slots) {
-        for (auto& kv : sl->cache) im_sketch_free(kv.second.sk);
-        if (sl->ctx) im_ctx_free(sl->ctx);
-        if (sl->stream) (void)hipStreamDestroy(sl->stream);
+    if (sv->sched) sv->sched->stop();  // finishes queued requests, frees every sketch
+    sv->sched.reset();
+    for (auto& sl : sv->backend.slots) {
+        if (sl.ctx) im_ctx_free(sl.ctx);
+        if (sl.stream) (void)hipStreamDestroy(sl.stream);
     }
     for (auto& g : sv->graphs) {
         if (g.xadj) (void)hipFree(g.xadj);
@@ -231,6 +125,8 @@ extern "C" {
 im_status im_server_create(int32_t device, const im_server_opts* opts, im_server** out) {
     if (!opts || !out) return hfr::fail(IM_ERR_INVALID_ARG, "null argument");
     if (opts->slots < 1 || opts->slots > 64) return hfr::fail(IM_ERR_INVALID_ARG, "slots must be in [1, 64]");
+    if (opts->max_copies < 0 || opts->max_copies > 64)
+        return hfr::fail(IM_ERR_INVALID_ARG, "max_copies must be in [0, 64]");
     int ndev = 0;
     if (hipGetDeviceCount(&ndev) != hipSuccess || device < 0 || device >= ndev)
         return hfr::fail(IM_ERR_INVALID_ARG, "device %d out of range", device);
@@ -238,20 +134,24 @@ im_status im_server_create(int32_t device, const im_server_opts* opts, im_server
     im_server* sv = new im_server;
     sv->device = device;
     sv->budget = opts->hbm_budget;
+    sv->backend.device = device;
     for (int i = 0; i < opts->slots; ++i) {
-        auto sl = std::make_unique<Slot>();
-        sl->index = i;
-        if (hipStreamCreateWithFlags(&sl->stream, hipStreamNonBlocking) != hipSuccess) {
+        SlotRes sl;
+        if (hipStreamCreateWithFlags(&sl.stream, hipStreamNonBlocking) != hipSuccess) {
             server_release(sv);
             return hfr::fail(IM_ERR_DEVICE, "stream creation failed");
         }
-        if (im_ctx_create(device, sl->stream, 0, nullptr, nullptr, nullptr, &sl->ctx) != IM_OK) {
+        // no per-context bound: the scheduler admits builds by the server's budget
+        if (im_ctx_create(device, sl.stream, 0, nullptr, nullptr, nullptr, &sl.ctx) != IM_OK) {
+            (void)hipStreamDestroy(sl.stream);
             server_release(sv);
             return IM_ERR_DEVICE;
         }
-        sv->slots.push_back(std::move(sl));
+        sv->backend.slots.push_back(sl);
     }
-    for (auto& sl : sv->slots) sl->thread = std::thread(slot_main, sv, sl.get());
+    sv->sched = std::make_unique<hfr::sched::Scheduler<Payload>>(opts->slots, opts->hbm_budget, &sv->backend,
+                                                                 opts->max_copies ? opts->max_copies : 2);
+    sv->sched->start();
     *out = sv;
     return IM_OK;
 }
@@ -281,93 +181,73 @@ im_status im_server_add_graph(im_server* sv, const im_csr* graph, int32_t* out_g
     }
     sv->graph_bytes += g.bytes;
     sv->graphs.push_back(g);
-    // every slot may hold an equal share of what the graphs leave
-    const size_t left = sv->budget ? sv->budget - sv->graph_bytes : 0;
-    sv->slot_budget = sv->budget ? std::max<size_t>(left / sv->slots.size(), 1) : 0;
-    for (auto& sl : sv->slots) sl->ctx->budget = sv->slot_budget;
+    sv->sched->set_fixed_bytes(sv->graph_bytes);
     *out_graph = (int32_t)sv->graphs.size() - 1;
     return IM_OK;
 }
 
 im_status im_server_submit(im_server* sv, const im_request* rq, int32_t* out_seeds, int64_t* out_ticket) {
     if (!sv || !rq || !out_seeds || !out_ticket) return hfr::fail(IM_ERR_INVALID_ARG, "null argument");
-    if (rq->graph < 0 || rq->graph >= (int32_t)sv->graphs.size())
-        return hfr::fail(IM_ERR_INVALID_ARG, "unknown graph %d", rq->graph);
     if (rq->kind != IM_PROB_CONSTANT && rq->kind != IM_PROB_WEIGHTED_CASCADE)
         return hfr::fail(IM_ERR_INVALID_ARG, "requests take a constant probability or the weighted cascade");
     if (rq->kind == IM_PROB_CONSTANT && hfr::live_threshold(rq->p) == 0xFFFFFFFFu)
         return hfr::fail(IM_ERR_INVALID_ARG, "probability must be in [0, 1]");
     if (rq->R < 4 || rq->R > 1024 || rq->R % 4) return hfr::fail(IM_ERR_INVALID_ARG, "R must be a multiple of 4 in [4, 1024]");
-    const GraphRes& g = sv->graphs[rq->graph];
-    if (rq->K < 1 || rq->K > g.n) return hfr::fail(IM_ERR_INVALID_ARG, "K must be in [1, n]");
     if (!(rq->eps_c >= 0.0) || !(rq->eps_g >= 0.0) || !(rq->eps_l >= 0.0))
         return hfr::fail(IM_ERR_INVALID_ARG, "thresholds must be >= 0");
-    auto r = std::make_shared<Request>();
-    r->rq = *rq;
+    Payload p;
+    {
+        // the graph table is read under the lock that add_graph takes
+        std::lock_guard<std::mutex> lk(sv->mu);
+        if (rq->graph < 0 || rq->graph >= (int32_t)sv->graphs.size())
+            return hfr::fail(IM_ERR_INVALID_ARG, "unknown graph %d", rq->graph);
+        p.g = sv->graphs[rq->graph];
+        sv->started = true;
+    }
+    if (rq->K < 1 || rq->K > p.g.n) return hfr::fail(IM_ERR_INVALID_ARG, "K must be in [1, n]");
+    p.rq = *rq;
+    p.out_seeds = out_seeds;
     uint32_t pbits = 0;
     if (rq->kind == IM_PROB_CONSTANT) memcpy(&pbits, &rq->p, 4);
     uint64_t ebits = 0;
     memcpy(&ebits, &rq->eps_c, 8);
-    r->key = Key(rq->graph, rq->kind, pbits, rq->R, rq->hash_seed, ebits);
-    r->out_seeds = out_seeds;
-    r->work = (double)(g.n + g.m) * (double)rq->R * (1.0 + 0.02 * rq->K);
-    {
-        std::lock_guard<std::mutex> lk(sv->mu);
-        sv->started = true;
-        r->ticket = sv->next_ticket++;
-        r->t_submit = Clock::now();
-        int s = -1;
-        auto it = sv->route.find(r->key);
-        if (it != sv->route.end()) {
-            s = it->second;
-        } else {
-            double best = 0.0;
-            for (auto& sl : sv->slots)
-                if (s < 0 || sl->queued_work < best) {
-                    best = sl->queued_work;
-                    s = sl->index;
-                }
-            sv->route[r->key] = s;
-        }
-        Slot* sl = sv->slots[s].get();
-        sl->queue.push_back(r);
-        sl->queued_work += r->work;
-        sv->requests[r->ticket] = r;
-        sv->stats.submitted += 1;
-        *out_ticket = r->ticket;
-    }
-    sv->cv_work.notify_all();
+    const hfr::sched::SketchKey key(rq->graph, rq->kind, pbits, rq->R, rq->hash_seed, ebits);
+    const size_t need = im_sketch_bytes_needed(p.g.n, p.g.m, rq->R, (im_prob_kind)rq->kind);
+    *out_ticket = sv->sched->submit(key, need, p);
+    return IM_OK;
+}
+
+im_status im_server_cancel(im_server* sv, int64_t ticket) {
+    if (!sv) return hfr::fail(IM_ERR_INVALID_ARG, "null server");
+    if (sv->sched->cancel(ticket) != IM_OK)
+        return hfr::fail(IM_ERR_STATE, "ticket %lld is unknown, running or finished", (long long)ticket);
     return IM_OK;
 }
 
 im_status im_server_wait(im_server* sv, int64_t ticket, im_response* out) {
     if (!sv) return hfr::fail(IM_ERR_INVALID_ARG, "null server");
-    std::shared_ptr<Request> r;
-    {
-        std::unique_lock<std::mutex> lk(sv->mu);
-        auto it = sv->requests.find(ticket);
-        if (it == sv->requests.end()) return hfr::fail(IM_ERR_INVALID_ARG, "unknown ticket %lld", (long long)ticket);
-        r = it->second;
-        sv->cv_done.wait(lk, [&] { return r->done; });
-        sv->requests.erase(ticket);
-    }
-    if (out) *out = r->resp;
-    if (r->resp.status != IM_OK) return hfr::fail((im_status)r->resp.status, "%s", r->error.c_str());
+    hfr::sched::Outcome o;
+    if (!sv->sched->wait(ticket, &o)) return hfr::fail(IM_ERR_INVALID_ARG, "unknown ticket %lld", (long long)ticket);
+    if (out) *out = o.resp;
+    if (o.resp.status != IM_OK) return hfr::fail((im_status)o.resp.status, "%s", o.error.c_str());
     return IM_OK;
 }
 
 im_status im_server_get_stats(im_server* sv, im_server_stats* out) {
     if (!sv || !out) return hfr::fail(IM_ERR_INVALID_ARG, "null argument");
-    std::lock_guard<std::mutex> lk(sv->mu);
-    *out = sv->stats;
-    size_t used = sv->graph_bytes;
-    int64_t resident = 0;
-    for (auto& sl : sv->slots) {
-        used += im_ctx_bytes_in_use(sl->ctx);
-        resident += (int64_t)sl->cache.size();
+    const hfr::sched::Stats s = sv->sched->stats();
+    size_t gb = 0;
+    {
+        std::lock_guard<std::mutex> lk(sv->mu);
+        gb = sv->graph_bytes;
     }
-    out->device_bytes = used;
-    out->resident_sketches = resident;
+    out->submitted = s.submitted;
+    out->completed = s.completed;
+    out->failed = s.failed;
+    out->sketches_built = s.sketches_built;
+    out->evictions = s.evictions;
+    out->resident_sketches = s.resident_sketches;
+    out->device_bytes = gb + s.sketch_bytes;
     return IM_OK;
 }
 

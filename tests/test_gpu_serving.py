@@ -66,16 +66,17 @@ def test_alone_results_match_oracle(alone):
         assert alone[req] == ref["seeds"]
 
 
-def _server(hf, slots=3, budget=0):
-    sv = hf.Server(0, slots=slots, hbm_budget=budget)
+def _server(hf, slots=3, budget=0, max_copies=0):
+    sv = hf.Server(0, slots=slots, hbm_budget=budget, max_copies=max_copies)
     for g in GRAPHS:
         sv.add_graph(g.xadj, g.adj, g.n)
     return sv
 
 
 def test_mix_equals_alone(hf, alone):
-    """All requests submitted at once over 3 slots: they overlap, and each equals its result alone."""
-    sv = _server(hf)
+    """All requests submitted at once over 3 slots, one copy per sketch: they overlap, each equals its
+    result alone, and the second round reuses every sketch of the first (on whichever slot runs it)."""
+    sv = _server(hf, max_copies=1)
     try:
         tickets = [(r, sv.submit(r[0], r[3], r[4], model=r[1], p=r[2], hash_seed=r[5])) for r in REQS * 2]
         slots = set()
@@ -153,5 +154,68 @@ def test_invalid_requests(hf):
             sv.submit(0, 64, 3, p=2.0)   # p outside [0, 1]
         with pytest.raises(ValueError):
             sv.submit(0, 64, 3, model="edge")
+    finally:
+        sv.close()
+
+
+def test_second_copies_under_contention(hf, alone):
+    """Many requests of two keys at once over 4 slots with up to 2 copies per key: more than one copy
+    of a key may be built, never more than 2, and every result equals the request alone."""
+    sv = _server(hf, slots=4, max_copies=2)
+    try:
+        reqs = [REQS[1], REQS[3]] * 6
+        tickets = [(r, sv.submit(r[0], r[3], r[4], model=r[1], p=r[2], hash_seed=r[5])) for r in reqs]
+        for req, t in tickets:
+            seeds, _ = sv.wait(t)
+            assert list(map(int, seeds)) == alone[req]
+        st = sv.stats()
+        assert 2 <= st["sketches_built"] <= 4 and st["resident_sketches"] == st["sketches_built"]
+    finally:
+        sv.close()
+
+
+def test_cancel_queued_requests(hf, alone):
+    """One slot: requests queue behind the first; cancelled ones report IM_ERR_STATE and never run,
+    and the results of the others are unchanged."""
+    sv = _server(hf, slots=1)
+    try:
+        order = [REQS[5], REQS[0], REQS[2], REQS[4], REQS[7], REQS[1]]
+        tickets = [(r, sv.submit(r[0], r[3], r[4], model=r[1], p=r[2], hash_seed=r[5])) for r in order]
+        cancelled = {tickets[2][1], tickets[4][1]}
+        assert all(sv.cancel(t) for t in cancelled)
+        for req, t in tickets:
+            if t in cancelled:
+                with pytest.raises(hf.ImError) as e:
+                    sv.wait(t)
+                assert e.value.status == -5
+            else:
+                seeds, resp = sv.wait(t)
+                assert list(map(int, seeds)) == alone[req]
+                assert not sv.cancel(t)  # finished
+        assert sv.stats()["completed"] == len(order)
+    finally:
+        sv.close()
+
+
+def test_oversized_request_evicts_nothing(hf, alone):
+    """A request whose sketch cannot fit the budget even alone fails at once and leaves the resident
+    sketches in place; a failed request does not change the results of the others."""
+    ctx = hf.Context(0)
+    graphs = sum(8 * (x.n + 1) + 4 * x.m for x in GRAPHS)
+    small = ctx.bytes_needed(GRAPHS[0].n, GRAPHS[0].m, 64)
+    big = ctx.bytes_needed(GRAPHS[2].n, GRAPHS[2].m, 1024)
+    assert big > 2 * small
+    sv = _server(hf, slots=2, budget=graphs + 2 * small)
+    try:
+        req = REQS[0]
+        s1, _ = sv.wait(sv.submit(req[0], req[3], req[4], model=req[1], p=req[2], hash_seed=req[5]))
+        assert sv.stats()["resident_sketches"] == 1
+        with pytest.raises(hf.ImError) as e:
+            sv.wait(sv.submit(2, 1024, 5, model="const", p=0.1))
+        assert e.value.status == -3
+        st = sv.stats()
+        assert st["resident_sketches"] == 1 and st["evictions"] == 0
+        s2, r2 = sv.wait(sv.submit(req[0], req[3], req[4], model=req[1], p=req[2], hash_seed=req[5]))
+        assert r2["sketch_reused"] == 1 and list(map(int, s1)) == list(map(int, s2)) == alone[req]
     finally:
         sv.close()
