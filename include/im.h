@@ -311,8 +311,10 @@ typedef struct im_batch_job {
 
 /* Work decomposition of the persistent solver.  Zero selects the default.
  * autotune = 1: im_batch_create solves the batch once per candidate
- * decomposition (lanes per row, tile size, grid), keeps the fastest, and
- * fails with IM_ERR_DEVICE if any two candidates disagree on a seed. */
+ * decomposition (lanes per row: the smallest power of two covering a row and
+ * twice that; tile size; XCD pinning; grid), keeps the fastest, and fails with
+ * IM_ERR_DEVICE if any two candidates disagree on a seed.  Fields set to
+ * nonzero values are not varied. */
 typedef struct im_batch_opts {
     int32_t autotune;
     int32_t lanes_per_row; /* power of two in [max(4, R_max/4), 64]; default the smallest */

@@ -1406,20 +1406,26 @@ im_status im_batch_create(im_ctx* ctx, int32_t count, const im_batch_job* jobs, 
     if (o.autotune) {
         // every candidate decomposition solves the batch once; the fastest is
         // kept and all of them must agree on every seed
+        // lanes per row (registers per lane): the smallest power of two covering a
+        // row, and twice that (fewer registers per lane, fewer rows per wave)
         std::vector<BatchCfg> cands;
-        std::vector<int> tiles = o.tile_edges ? std::vector<int>{o.tile_edges} : std::vector<int>{2048, 4096, 8192};
+        std::vector<int> lanes = o.lanes_per_row ? std::vector<int>{o.lanes_per_row} : std::vector<int>{Gmin};
+        if (!o.lanes_per_row && 2 * Gmin <= 64) lanes.push_back(2 * Gmin);
+        std::vector<int> tiles = o.tile_edges ? std::vector<int>{o.tile_edges} : std::vector<int>{4096, 8192};
         std::vector<int64_t> pins = o.pin_edges ? std::vector<int64_t>{b->cfg.pin_edges}
                                                 : std::vector<int64_t>{b->cfg.pin_edges, -1};
         std::vector<int> wgs = o.workgroups ? std::vector<int>{o.workgroups} : std::vector<int>{2 * b->cus, 4 * b->cus};
-        for (int te : tiles)
-            for (int64_t pe : pins)
-                for (int wg : wgs) {
-                    BatchCfg c = b->cfg;
-                    c.tile_edges = te;
-                    c.pin_edges = pe;
-                    c.workgroups = wg;
-                    cands.push_back(c);
-                }
+        for (int G : lanes)
+            for (int te : tiles)
+                for (int64_t pe : pins)
+                    for (int wg : wgs) {
+                        BatchCfg c = b->cfg;
+                        c.G = G;
+                        c.tile_edges = te;
+                        c.pin_edges = pe;
+                        c.workgroups = wg;
+                        cands.push_back(c);
+                    }
         float best = 1e30f;
         BatchCfg best_cfg = b->cfg;
         std::vector<int32_t> ref, cur;
