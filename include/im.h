@@ -207,6 +207,24 @@ IM_API im_status im_select_seeds(im_sketch* sk, int32_t K, const im_select_opts*
                           im_step* out_steps, im_select_stats* stats);
 
 /*
+ * Greedy seed selection (Alg. 1) that reuses the sketch's last selection.
+ * Every successful im_select_seeds, im_select_seeds_noalloc or
+ * im_select_seeds_resume call on a sketch records its greedy run (K steps,
+ * host memory).  When the thresholds equal that run's, this call answers K up
+ * to its length from the record, with no device work (the first K steps of a
+ * run are the run with K seeds: Alg. 1 rebuilds nothing after the last step),
+ * and a larger K continues the run from its last step (whose rebuild decision
+ * is taken again, now that a step follows) instead of starting from the
+ * build.  Other thresholds, or no recorded run, start from the build as
+ * im_select_seeds does.  Outputs are those im_select_seeds returns for the
+ * same K and thresholds, bit for bit; stats->device_ms counts only this call's
+ * device work (0 when answered from the record).  A failed call drops the
+ * record.  Same arguments and errors as im_select_seeds.
+ */
+IM_API im_status im_select_seeds_resume(im_sketch* sk, int32_t K, const im_select_opts* opts, int32_t* out_seeds,
+                                        im_step* out_steps, im_select_stats* stats);
+
+/*
  * Allocation-free variant of im_select_seeds, for callers that cannot allocate
  * device memory during the call (code under stream capture, tight serving
  * loops, harnesses that forbid allocation).  Same arguments, results and
@@ -263,11 +281,14 @@ IM_API void im_sketch_clear_sweep_log(im_sketch* sk);
 
 /* Copies registers to the host, n*R bytes, vertex-major (R registers of a
  * vertex adjacent).  which = 0: registers of the build; which = 1: registers
- * in force at the end of the last im_select_seeds. */
+ * in force at the end of the greedy run the sketch holds (that of the last
+ * selection call, or, after an im_select_seeds_resume answered from its
+ * record, the recorded run's). */
 IM_API im_status im_sketch_get_registers(const im_sketch* sk, int32_t which, uint8_t* out);
 
-/* Copies the blocked pairs of the last im_select_seeds (the reach of S in
- * every sample) to the host as n*R bytes (1 = blocked). */
+/* Copies the blocked pairs of the greedy run the sketch holds (the reach of
+ * its S in every sample; which run: as for im_sketch_get_registers, which = 1)
+ * to the host as n*R bytes (1 = blocked). */
 IM_API im_status im_sketch_get_blocked(const im_sketch* sk, uint8_t* out);
 
 IM_API void im_sketch_free(im_sketch* sk);
@@ -381,9 +402,10 @@ IM_API void im_batch_free(im_batch* b);
  * free.  Sketches stay resident in one pool and are reused, on whichever slot
  * runs the request, by later requests with the same (graph, model, p, R, hash
  * seed, eps_c); a sketch serves one request at a time, and a key whose copies
- * are all busy may get a second copy.  Every request runs its own greedy
- * selection, so its result equals im_build_sketches + im_select_seeds run
- * alone.  hbm_budget (0 = none) bounds the device memory of the resident graphs
+ * are all busy may get a second copy.  Selections go through
+ * im_select_seeds_resume, so a request whose sketch copy last served the same
+ * thresholds reuses or continues that greedy run; its result still equals
+ * im_build_sketches + im_select_seeds run alone.  hbm_budget (0 = none) bounds the device memory of the resident graphs
  * plus all sketches: a build evicts idle sketches, least recently used first,
  * until it fits, and a request whose sketch cannot fit even alone fails with
  * IM_ERR_OUT_OF_BUDGET without evicting anything.

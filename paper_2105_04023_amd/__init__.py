@@ -255,15 +255,20 @@ def im_estimate_all(sk: Sketch, out=None):
     return res
 
 
-def im_select_seeds(sk: Sketch, K: int, eps_g: float = 0.01, eps_l: float = 0.3, noalloc: bool = False):
+def im_select_seeds(sk: Sketch, K: int, eps_g: float = 0.01, eps_l: float = 0.3, noalloc: bool = False,
+                    resume: bool = False):
     """Alg. 1 greedy loop with error-adaptive rebuild.  Returns (seeds, steps, stats).
 
-    noalloc selects im_select_seeds_noalloc (no device allocation in the call; K <= 4096)."""
+    noalloc selects im_select_seeds_noalloc (no device allocation in the call; K <= 4096);
+    resume selects im_select_seeds_resume (reuses or continues the sketch's last run)."""
+    if noalloc and resume:
+        raise ValueError("noalloc and resume select different entry points")
     seeds = np.zeros(K, dtype=np.int32)
     steps = (B.im_step * K)()
     stats = B.im_select_stats()
     opts = B.im_select_opts(eps_g, eps_l)
-    fn = sk.lib.im_select_seeds_noalloc if noalloc else sk.lib.im_select_seeds
+    fn = (sk.lib.im_select_seeds_noalloc if noalloc else
+          sk.lib.im_select_seeds_resume if resume else sk.lib.im_select_seeds)
     B.check(fn(sk.handle, K, ctypes.byref(opts), seeds.ctypes.data, ctypes.cast(steps, ctypes.c_void_p),
                ctypes.byref(stats)))
     st = [Step(**{f: getattr(s, f) for f, _ in B.im_step._fields_}) for s in steps]

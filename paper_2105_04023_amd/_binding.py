@@ -27,7 +27,7 @@ EXPORTED = [
     "im_sketch_get_sweep_log", "im_sketch_clear_sweep_log", "im_batch_create", "im_batch_run", "im_batch_get_result",
     "im_batch_get_registers", "im_batch_device_bytes", "im_batch_free", "im_server_create", "im_server_add_graph",
     "im_server_submit", "im_server_wait", "im_server_get_stats", "im_server_free", "im_evaluate_influence",
-    "im_select_seeds_noalloc", "im_server_cancel",
+    "im_select_seeds_noalloc", "im_server_cancel", "im_select_seeds_resume",
 ]
 
 
@@ -158,6 +158,8 @@ def load(path: str = LIB_PATH):
                             ctypes.c_int),
         "im_select_seeds_noalloc": ([p, i32, ctypes.POINTER(im_select_opts), p, p,
                                      ctypes.POINTER(im_select_stats)], ctypes.c_int),
+        "im_select_seeds_resume": ([p, i32, ctypes.POINTER(im_select_opts), p, p,
+                                    ctypes.POINTER(im_select_stats)], ctypes.c_int),
         "im_sketch_get_info": ([p, ctypes.POINTER(im_sketch_info)], ctypes.c_int),
         "im_sketch_get_trace": ([p, p, p, i32, ctypes.POINTER(i32)], ctypes.c_int),
         "im_sketch_get_registers": ([p, i32, p], ctypes.c_int),

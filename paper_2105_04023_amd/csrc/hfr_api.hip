@@ -204,6 +204,13 @@ struct im_sketch {
     int64_t sweep_hint = 0;  // sweeps of the last Simulate: rebuilds batch their sweeps by it
     int32_t level_id = 1;
     bool selected = false;
+    // the greedy run of the last selection (steps 1..sel_K, before step sel_K's
+    // rebuild decision took effect), for continuing it (select_resumable)
+    int32_t sel_K = 0;
+    double sel_eps_g = 0.0, sel_eps_l = 0.0;
+    std::vector<StepRec> sel_recs;
+    std::vector<int32_t> sel_seeds;
+    std::vector<int64_t> sel_levels;  // reach levels with work, per step
     bool has_registers = true;
 };
 
@@ -1100,8 +1107,12 @@ int32_t level_id_limit(int64_t n) {
 // are allocated from the context for the call.
 size_t select_scratch_bytes(int32_t K) { return ((sizeof(StepRec) * (size_t)K + 255) & ~size_t(255)) + 4 * (size_t)K; }
 
+// resume: a run recorded by an earlier call with the same thresholds is reused --
+// K up to its length is answered from the record (its first K steps are the run
+// with K seeds: no rebuild follows the last step), and a longer K continues it
+// from its last step (whose decision is taken again, now with a step after it).
 im_status select_impl(im_sketch* sk, int32_t K, const im_select_opts* opts, int32_t* out_seeds, im_step* out_steps,
-                      im_select_stats* stats, void* scratch) {
+                      im_select_stats* stats, void* scratch, bool resume = false) {
     im_status st0 = check_sketch(sk);
     if (st0 != IM_OK) return st0;
     if (!out_seeds) return fail(IM_ERR_INVALID_ARG, "out_seeds is null");
@@ -1118,10 +1129,57 @@ im_status select_impl(im_sketch* sk, int32_t K, const im_select_opts* opts, int3
     const Layout& L = sk->L;
     GreedyBufs& b = sk->gb;
     const size_t W = 4 * (size_t)L.PW;
+    const bool same = resume && sk->sel_K > 0 && sk->sel_eps_g == eps_g && sk->sel_eps_l == eps_l;
+    // writes the outputs of steps 1..K from a complete record h (step K rebuilding nothing)
+    auto emit = [&](const std::vector<StepRec>& h, const std::vector<int64_t>& lv, double device_ms) {
+        int32_t rb = 0;
+        int64_t rs = 0, rv = 0, lt = 0;
+        for (int k = 0; k < K; ++k) {
+            StepRec r = h[k];
+            if (k == K - 1) r.rebuilt = 0, r.sweeps = 0, r.visits = 0;
+            out_seeds[k] = r.seed;
+            rb += r.rebuilt;
+            rs += r.sweeps;
+            rv += r.visits;
+            lt += lv[k];
+            if (out_steps) {
+                im_step& o = out_steps[k];
+                o.seed = r.seed;
+                o.rebuilt = r.rebuilt;
+                o.fresh = r.fresh;
+                o.sweeps = r.sweeps;
+                o.score = r.score;
+                o.reach = r.reach;
+                o.e = r.e;
+                o.sigma = r.sigma;
+                o.delta = r.delta;
+                o.err_l = r.err_l;
+                o.err_g = r.err_g;
+                o.visits = r.visits;
+            }
+        }
+        if (stats) {
+            stats->rebuilds = rb;
+            stats->reserved = 0;
+            stats->rebuild_sweeps = rs;
+            stats->rebuild_visits = rv;
+            stats->bfs_levels = lt;
+            stats->device_ms = device_ms;
+            stats->wall_ms =
+                std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - wall0).count();
+        }
+    };
+    if (same && K <= sk->sel_K) {  // a prefix of the recorded run: no device work
+        emit(sk->sel_recs, sk->sel_levels, 0.0);
+        return IM_OK;
+    }
+    const int k0 = same ? sk->sel_K : 0;  // steps already taken
+    sk->sel_K = 0;                        // the record is valid again only once this call completes
 
     // per-call buffers for K records and seeds
     StepRec* d_steps = nullptr;
     int32_t* d_seeds = nullptr;
+    double device_ms = 0.0;
     {
         void* p = scratch ? scratch : ctx_alloc(sk->ctx, select_scratch_bytes(K));
         if (!p) return fail(IM_ERR_OUT_OF_BUDGET, "temporary allocation failed");
@@ -1130,24 +1188,56 @@ im_status select_impl(im_sketch* sk, int32_t K, const im_select_opts* opts, int3
     }
     const int32_t lvl_limit = level_id_limit(n);
     std::vector<StepRec> h_steps(K);
-    int32_t rebuilds = 0;
-    int64_t rsweeps = 0, rvisits = 0, levels_total = 0;
+    std::vector<int64_t> h_levels(K, 0);
+    for (int k = 0; k < k0; ++k) {
+        h_steps[k] = sk->sel_recs[k];
+        h_levels[k] = sk->sel_levels[k];
+    }
 
+    // a rebuild after step k (1-based) on the register buffers not holding the build
+    auto rebuild_after = [&](int k, int* cur) -> im_status {
+        int ia = (*cur + 1) % 3, ib = (*cur + 2) % 3;
+        if (ia == sk->build_buf) ia = (ia + 1) % 3;
+        if (ib == sk->build_buf || ib == ia) ib = 3 - sk->build_buf - ia;
+        SimResult r;
+        im_status rs = run_simulate(sk, ia, ib, b.blk, &r);
+        if (rs != IM_OK) return rs;
+        *cur = r.buf;
+        h_steps[k - 1].sweeps = r.sweeps;
+        h_steps[k - 1].visits = r.visits;
+        return IM_OK;
+    };
     auto body = [&]() -> im_status {
         HIP_TRY(hipEventRecord(sk->ev_a, s));
-        HIP_TRY(hipMemsetAsync(b.blk, 0, 4 * n * W, s));
-        HIP_TRY(hipMemsetAsync(b.inS, 0, n, s));
-        HIP_TRY(hipMemsetAsync(b.MS, 0, 4 * L.P, s));
-        HIP_TRY(hipMemsetAsync(b.key, 0, 8, s));
-        HIP_TRY(hipMemsetAsync(b.R, 0, 8 * NSLOT * SLOT_U64, s));
-        HIP_TRY(hipMemsetAsync(b.Rreb, 0, 8, s));
         // the step records start at zero (fill kernel: no memset node in this memory)
         HIP_TRY(launch_fill_u32((uint32_t*)d_steps, 0u, (int64_t)(sizeof(StepRec) / 4) * K, s));
-        // level ids start afresh every call, so a long-lived sketch never runs them out
-        HIP_TRY(hipMemsetAsync(b.stamp, 0, 4 * (size_t)n, s));
-        sk->level_id = 1;
         int cur = sk->build_buf;
-        for (int k = 1; k <= K; ++k) {
+        if (k0 == 0) {
+            HIP_TRY(hipMemsetAsync(b.blk, 0, 4 * n * W, s));
+            HIP_TRY(hipMemsetAsync(b.inS, 0, n, s));
+            HIP_TRY(hipMemsetAsync(b.MS, 0, 4 * L.P, s));
+            HIP_TRY(hipMemsetAsync(b.key, 0, 8, s));
+            HIP_TRY(hipMemsetAsync(b.R, 0, 8 * NSLOT * SLOT_U64, s));
+            HIP_TRY(hipMemsetAsync(b.Rreb, 0, 8, s));
+            // level ids start afresh every call, so a long-lived sketch never runs them out
+            HIP_TRY(hipMemsetAsync(b.stamp, 0, 4 * (size_t)n, s));
+            sk->level_id = 1;
+        } else {
+            // continue the recorded run: its device state is the one after step k0, before
+            // step k0's decision took effect; take that decision again with steps to follow
+            cur = sk->sel_buf;
+            HIP_TRY(hipMemcpyAsync(d_steps, sk->sel_recs.data(), sizeof(StepRec) * k0, hipMemcpyHostToDevice, s));
+            HIP_TRY(hipMemcpyAsync(d_seeds, sk->sel_seeds.data(), 4 * (size_t)k0, hipMemcpyHostToDevice, s));
+            int32_t flag = -1;
+            HIP_TRY(launch_decide(L, b, d_steps + (k0 - 1), k0, K, eps_g, eps_l, sk->d_flag, s));
+            HIP_TRY(hipMemcpyAsync(&flag, sk->d_flag, 4, hipMemcpyDeviceToHost, s));
+            HIP_TRY(hipStreamSynchronize(s));
+            if (flag == 1) {
+                const im_status rs = rebuild_after(k0, &cur);
+                if (rs != IM_OK) return rs;
+            }
+        }
+        for (int k = k0 + 1; k <= K; ++k) {
             if (sk->level_id > lvl_limit) {
                 HIP_TRY(hipMemsetAsync(b.stamp, 0, 4 * (size_t)n, s));
                 sk->level_id = 1;
@@ -1159,8 +1249,10 @@ im_status select_impl(im_sketch* sk, int32_t K, const im_select_opts* opts, int3
             int32_t flag = -1;
             int level = 0;
             {
-                const im_status rs = run_reach(sk, lvl0, &level, &levels_total);
+                int64_t with_work = 0;
+                const im_status rs = run_reach(sk, lvl0, &level, &with_work);
                 if (rs != IM_OK) return rs;
+                h_levels[k - 1] = with_work;
             }
             sk->level_id = lvl0 + level + 2;
             {
@@ -1176,18 +1268,8 @@ im_status select_impl(im_sketch* sk, int32_t K, const im_select_opts* opts, int3
             HIP_TRY(hipMemcpyAsync(&flag, sk->d_flag, 4, hipMemcpyDeviceToHost, s));
             HIP_TRY(hipStreamSynchronize(s));
             if (flag == 1) {
-                int ia = (cur + 1) % 3, ib = (cur + 2) % 3;
-                if (ia == sk->build_buf) ia = (ia + 1) % 3;
-                if (ib == sk->build_buf || ib == ia) ib = 3 - sk->build_buf - ia;
-                SimResult r;
-                im_status rs = run_simulate(sk, ia, ib, b.blk, &r);
+                const im_status rs = rebuild_after(k, &cur);
                 if (rs != IM_OK) return rs;
-                cur = r.buf;
-                ++rebuilds;
-                rsweeps += r.sweeps;
-                rvisits += r.visits;
-                h_steps[k - 1].sweeps = r.sweeps;
-                h_steps[k - 1].visits = r.visits;
             }
         }
         HIP_TRY(hipEventRecord(sk->ev_b, s));
@@ -1196,6 +1278,7 @@ im_status select_impl(im_sketch* sk, int32_t K, const im_select_opts* opts, int3
         HIP_TRY(hipMemcpyAsync(out_seeds, d_seeds, 4 * (size_t)K, hipMemcpyDeviceToHost, s));
         HIP_TRY(hipStreamSynchronize(s));
         for (int k = 0; k < K; ++k) {
+            // the host holds the sweep and visit counts of rebuilds (steps before k0 kept theirs)
             const int32_t sw = h_steps[k].sweeps;
             const int64_t vi = h_steps[k].visits;
             h_steps[k] = dev[k];
@@ -1206,38 +1289,19 @@ im_status select_impl(im_sketch* sk, int32_t K, const im_select_opts* opts, int3
         sk->selected = true;
         float ms = 0.f;
         HIP_TRY(hipEventElapsedTime(&ms, sk->ev_a, sk->ev_b));
-        if (stats) stats->device_ms = ms;
+        device_ms = ms;
         return IM_OK;
     };
     im_status st = body();
     if (!scratch) ctx_free(sk->ctx, d_steps);
     if (st != IM_OK) return st;
-    if (out_steps) {
-        for (int k = 0; k < K; ++k) {
-            const StepRec& r = h_steps[k];
-            im_step& o = out_steps[k];
-            o.seed = r.seed;
-            o.rebuilt = r.rebuilt;
-            o.fresh = r.fresh;
-            o.sweeps = r.sweeps;
-            o.score = r.score;
-            o.reach = r.reach;
-            o.e = r.e;
-            o.sigma = r.sigma;
-            o.delta = r.delta;
-            o.err_l = r.err_l;
-            o.err_g = r.err_g;
-            o.visits = r.visits;
-        }
-    }
-    if (stats) {
-        stats->rebuilds = rebuilds;
-        stats->reserved = 0;
-        stats->rebuild_sweeps = rsweeps;
-        stats->rebuild_visits = rvisits;
-        stats->bfs_levels = levels_total;
-        stats->wall_ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - wall0).count();
-    }
+    sk->sel_recs = h_steps;
+    sk->sel_seeds.assign(out_seeds, out_seeds + K);
+    sk->sel_levels = h_levels;
+    sk->sel_eps_g = eps_g;
+    sk->sel_eps_l = eps_l;
+    sk->sel_K = K;
+    emit(h_steps, h_levels, device_ms);
     return IM_OK;
 }
 
@@ -1268,6 +1332,11 @@ extern "C" {
 im_status im_select_seeds(im_sketch* sk, int32_t K, const im_select_opts* opts, int32_t* out_seeds, im_step* out_steps,
                           im_select_stats* stats) {
     return select_impl(sk, K, opts, out_seeds, out_steps, stats, nullptr);
+}
+
+im_status im_select_seeds_resume(im_sketch* sk, int32_t K, const im_select_opts* opts, int32_t* out_seeds,
+                                 im_step* out_steps, im_select_stats* stats) {
+    return select_impl(sk, K, opts, out_seeds, out_steps, stats, nullptr, true);
 }
 
 im_status im_select_seeds_noalloc(im_sketch* sk, int32_t K, const im_select_opts* opts, int32_t* out_seeds,

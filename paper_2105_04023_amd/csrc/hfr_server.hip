@@ -9,8 +9,11 @@
 // R, hash seed and eps_c) form one pool: a later request with the same key
 // reuses an idle copy on whichever slot runs it (the sketch is moved to that
 // slot's stream), and a key with every copy busy may get a second copy.
-// Every request runs its own greedy selection (im_select_seeds starts from the
-// build's registers each time), so a served result equals
+// A request's selection goes through im_select_seeds_resume: a sketch keeps the
+// greedy run of its last request, a request with the same thresholds and a K
+// no larger is answered from that run and a larger K continues it, so
+// repeated and growing K on one key cost only the steps not yet taken.  The
+// outputs are those of im_select_seeds, so a served result equals
 // im_build_sketches + im_select_seeds run alone.  The resident graphs and all
 // sketches share hbm_budget; a build evicts idle sketches least recently used
 // first until it fits, and a build that cannot fit even alone is refused.
@@ -77,7 +80,8 @@ struct HipBackend final : hfr::sched::Backend<Payload> {
         (void)hipSetDevice(device);
         im_select_opts so{p.rq.eps_g, p.rq.eps_l};
         im_select_stats ss{};
-        const im_status st = im_select_seeds(static_cast<im_sketch*>(handle), p.rq.K, &so, p.out_seeds, nullptr, &ss);
+        const im_status st =
+            im_select_seeds_resume(static_cast<im_sketch*>(handle), p.rq.K, &so, p.out_seeds, nullptr, &ss);
         *rebuilds = ss.rebuilds;
         if (st != IM_OK) *err = im_last_error();
         return st;

@@ -13,6 +13,8 @@ benchmark's configuration (default build options) and every integer and FP64 fie
 * R-MAT 2^24, weighted cascade, R = 256: the build in full and the greedy prefix of K' steps the
   oracle run reached (the first K' steps of K = 50 are the run with K = K'; no rebuild follows the
   last step), with the registers and blocked pairs after step K'.
+* Resumed selection (im_select_seeds_resume) on the ER and 2^20 records: a sequence of K answered
+  from, or continuing, the run the sketch holds, each answer against the oracle's run with that K.
 * The 64-job batch (R = 128, K = 20), solved in one launch, autotuned and with large tiles: every
   job's seeds, step records, build counters and build and final registers.
 * A sample of the serving stream's requests (every (graph size, model, p, R) class on the pool's
@@ -146,6 +148,56 @@ def test_rmat24_wc_build_and_greedy_prefix(hf):
     rec = _load("rmat24_wc_J256_K50")
     assert "build" in rec
     _single_graph(hf, synth.workload_rmat24_wc(), rec)
+
+
+@pytest.mark.parametrize("name,make,ks", [
+    ("er_n1000_m10000_p0.1_J64_K10", synth.workload_er_small, [3, 3, 7, 5, 10, 1, 10]),
+    ("rmat20_p0.01_J256_K50", synth.workload_rmat20, [10, 25, 20, 50, 50]),
+])
+def test_resumed_selection(hf, name, make, ks):
+    """im_select_seeds_resume on one sketch over a sequence of K: a K no larger than the run the
+    sketch holds is answered from its record (no device work), a larger K continues that run.  Every
+    answer is the oracle's run with that K (the first K steps of the record, no rebuild after the
+    last); after each continued run the registers in force and the blocked pairs are the oracle's
+    after step K; the stats equal those of a run from the build."""
+    import torch
+
+    rec = _load(name)
+    w = make()
+    g = w.graph
+    _check_graph(g, rec)
+    eg, el = rec["eps_g"], rec["eps_l"]
+    print(f"[golden] resumed selection on {name}: K sequence {ks}", flush=True)
+    ctx = hf.Context(0)
+    xd, ad = torch.from_numpy(g.xadj).cuda(), torch.from_numpy(g.adj).cuda()
+    sk = hf.im_build_sketches(ctx, xd, ad, g.n, rec["J"], model=rec["model"], p=w.p, hash_seed=rec["hash_seed"])
+    try:
+        fresh = {K: hf.im_select_seeds(sk, K, eps_g=eg, eps_l=el)[2] for K in sorted(set(ks))}
+        hf.im_select_seeds(sk, 1, eps_g=eg, eps_l=el)  # the sketch now holds the run with K = 1
+        held = 1
+        for K in ks:
+            seeds, steps, stats = hf.im_select_seeds(sk, K, eps_g=eg, eps_l=el, resume=True)
+            ref = [dict(s) for s in rec["steps"][:K]]
+            ref[-1].update(rebuilt=0, sweeps=0, visits=0)
+            assert list(map(int, seeds)) == [s["seed"] for s in ref], K
+            _check_steps(steps, ref)
+            for f in ("rebuilds", "rebuild_sweeps", "rebuild_visits", "bfs_levels"):
+                assert stats[f] == fresh[K][f], (K, f)
+            if K <= held:
+                assert stats["device_ms"] == 0.0, K
+            else:
+                held = K
+                assert sha(sk.registers(1)) == rec["steps"][K - 1]["M_sha256"], K
+                assert sha(sk.blocked()) == rec["steps"][K - 1]["blk_sha256"], K
+        # other thresholds start from the build, as a plain call does
+        a = hf.im_select_seeds(sk, 5, eps_g=eg * 2, eps_l=el, resume=True)
+        b = hf.im_select_seeds(sk, 5, eps_g=eg * 2, eps_l=el)
+        assert list(a[0]) == list(b[0])
+        assert [tuple(getattr(s, f) for f in STEP_FIELDS) for s in a[1]] == \
+            [tuple(getattr(s, f) for f in STEP_FIELDS) for s in b[1]]
+    finally:
+        sk.free()
+        ctx.close()
 
 
 @pytest.mark.parametrize("decomposition", ["autotuned", "tile_edges=65536"])

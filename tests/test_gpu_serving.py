@@ -110,6 +110,29 @@ def test_sketch_reuse_and_prefixes(hf, alone):
         sv.close()
 
 
+def test_growing_and_repeated_K_on_one_sketch(hf):
+    """One slot, one copy: requests of one key with K growing, shrinking and repeated are answered
+    from, or continue, the greedy run the sketch holds; each equals the same K run alone."""
+    gi, model, p, R, _, seed = REQS[2]
+    g = GRAPHS[gi]
+    ks = [5, 20, 12, 35, 35, 3, 40]
+    ctx = hf.Context(0)
+    sk = hf.im_build_sketches(ctx, g.xadj, g.adj, g.n, R, model=model, p=p, hash_seed=seed)
+    try:
+        ref = {K: (list(map(int, r[0])), r[2]["rebuilds"]) for K in set(ks)
+               for r in [hf.im_select_seeds(sk, K)]}
+    finally:
+        sk.free()
+    sv = _server(hf, slots=1, max_copies=1)
+    try:
+        for K in ks:
+            seeds, resp = sv.wait(sv.submit(gi, R, K, model=model, p=p, hash_seed=seed))
+            assert (list(map(int, seeds)), resp["rebuilds"]) == ref[K], K
+        assert sv.stats()["sketches_built"] == 1
+    finally:
+        sv.close()
+
+
 def test_budget_evicts_and_rejects(hf, alone):
     ctx = hf.Context(0)
     g = GRAPHS[2]
