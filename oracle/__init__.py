@@ -202,7 +202,8 @@ def greedy(graph, thr: np.ndarray, J: int, K: int, seed: int = 0, eps_g: float =
     of the oracle's own buffers (valid during the call only): k = 0 once after the build (M = the build's
     registers, trace_live[t] = |L_t| for t = 0..sweeps, trace_edges[t] = visits of sweep t, blk and step
     None), then k = 1..K after each step, before its rebuild (M = registers the step used, blk = blocked
-    pairs after it, step = its record as a dict): the final state of a run with K = k.  A true return value
+    pairs after it, step = its record as a dict, with, for k >= 2, the completed record of step k - 1 under
+    "previous": its rebuild, if any, has ended): the final state of a run with K = k.  A true return value
     ends the run; the result then holds the steps done ("stopped_after").
     """
     xadj, adj = _csr(graph)
@@ -228,6 +229,8 @@ def greedy(graph, thr: np.ndarray, J: int, K: int, seed: int = 0, eps_g: float =
             return int(bool(observer(0, Mv, None, None, tl, te)))
         st = ctypes.cast(pst, ctypes.POINTER(Step)).contents
         rec = {f: getattr(st, f) for f, _ in Step._fields_}
+        if k >= 2:
+            rec["previous"] = {f: getattr(steps[k - 2], f) for f, _ in Step._fields_}
         return int(bool(observer(k, Mv, view(pblk, n * J, ctypes.c_uint8).reshape(n, J), rec, None, None)))
 
     cb = _OBSERVER(_obs) if observer is not None else _OBSERVER()

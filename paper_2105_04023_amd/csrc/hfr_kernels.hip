@@ -764,9 +764,12 @@ __global__ __launch_bounds__(256) void k_sweep_light(
 // one flat sequence, 64 per window, each lane finding its row by binary search
 // over the rows' prefix offsets in LDS.  Live heads are merged in batches of UB
 // row loads; the first load of a row also fetches the row itself (and its
-// blocked bits), so finishing a row needs no extra round trip.
+// blocked bits), so finishing a row needs no extra round trip.  At one dword
+// per lane (R = 256) the kernel runs at 7 waves per SIMD, a few spilled
+// registers included (measured on the 2^24 weighted-cascade graph: 7% less
+// row-kernel time than at 5 waves); wider rows keep 5.
 template <int DW, int KIND, bool BLK>
-__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(5, 8))) void k_sweep_rows64(
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(DW == 1 ? 7 : 5, 8))) void k_sweep_rows64(
     const int64_t* __restrict__ xadj, const int32_t* __restrict__ adj, EdgeHashes H,
     const uint32_t* __restrict__ thr, uint32_t thr_const, const uint32_t* __restrict__ X,
     const uint32_t* __restrict__ A, uint32_t* __restrict__ B, const uint32_t* __restrict__ Lcur,
@@ -783,6 +786,13 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(5, 8))) voi
     const uint32_t live = sweep_live(gate, gate_thresh, first, n);
     if (!live) return;
     const bool sparse = sweep_sparse(sgate, first, m, fr.sparse_div);
+    // dense: every row with 1..heavy_deg out-edges (rows without out-edges never
+    // change and are never in L_t); sparse: the listed rows
+    const int64_t nrows = sparse ? (int64_t)fr.counts[4 * parity + 1] : nlight;
+    const int64_t nbatch = (nrows + 31) >> 5;
+    // a workgroup none of whose waves has a batch leaves before any other load
+    // (sparse sweeps late in a Simulate list a few rows for the whole grid)
+    if ((int64_t)blockIdx.x * (blockDim.x >> 6) >= nbatch) return;
     const uint32_t* cl = load_coarse(sweep_coarse(live, first, sparse, fr), fr, s_coarse);
     const int cs = fr.coarse_shift;
     const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
@@ -791,10 +801,6 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(5, 8))) voi
     const uint32_t ntv = to_vgpr(0u - thr_const);
     uint32_t my_cnt = 0;
     unsigned long long my_vis = 0, my_sum = 0, my_mrg = 0;
-    // dense: every row with 1..heavy_deg out-edges (rows without out-edges never
-    // change and are never in L_t); sparse: the listed rows
-    const int64_t nrows = sparse ? (int64_t)fr.counts[4 * parity + 1] : nlight;
-    const int64_t nbatch = (nrows + 31) >> 5;
     for (int64_t c = wave_index(); c < nbatch; c += wave_count()) {
         // ---- the batch's rows: one per lane i < 32 (ascending in a dense sweep)
         int64_t u = -1;

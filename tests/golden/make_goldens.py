@@ -98,6 +98,10 @@ def solve(g, model, p, J, K, eps_g=0.01, eps_l=0.3, eps_c=0.0, hash_seed=0, out_
                             "wall_s": round(time.time() - t0, 1)}
         else:
             st = dict(st)
+            prev = st.pop("previous", None)
+            if prev is not None:  # the rebuild after step k - 1 has ended: complete its record
+                for f in ("rebuilt", "sweeps", "visits"):
+                    rec["steps"][-1][f] = prev[f]
             st["M_sha256"] = sha(M)
             st["blk_sha256"] = sha(blk)
             st["wall_s"] = round(time.time() - t0, 1)

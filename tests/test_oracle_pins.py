@@ -529,3 +529,31 @@ def test_greedy_error_adaptive_decisions():
             if k < K - 1:
                 MS = merged
     assert any(s["rebuilt"] for s in res["steps"]) and any(s["fresh"] for s in res["steps"][:-1])
+
+
+def test_greedy_observer_sees_completed_previous_steps():
+    """The observer of a run gets, from step 2 on, the record of the step before as the finished
+    run reports it (rebuild flag, sweep and visit counts included), and each step's own record
+    before its rebuild; a run stopped by the observer after step k reports the first k steps of
+    the full run, the last without a rebuild."""
+    g = synth.erdos_renyi(50, 250, seed=14)
+    J, K = 16, 8
+    thr = oracle.edge_thresholds(g, "const", f32(0.4))
+    full = oracle.greedy(g, thr, J, K, eps_g=0.01, eps_l=0.3)
+    assert any(s["rebuilt"] for s in full["steps"][:-1])
+    seen = {}
+
+    def obs(k, M, blk, st, tl, te):
+        if k >= 1:
+            seen[k] = dict(st)
+        return k == 5
+
+    part = oracle.greedy(g, thr, J, K, eps_g=0.01, eps_l=0.3, observer=obs)
+    assert part["stopped_after"] == 5
+    for k in range(2, 6):
+        assert seen[k]["previous"] == full["steps"][k - 2], k
+    for k in range(1, 6):
+        own = {f: v for f, v in seen[k].items() if f != "previous"}
+        assert own == dict(full["steps"][k - 1], rebuilt=0, sweeps=0, visits=0), k
+    assert part["steps"][:4] == full["steps"][:4]
+    assert part["steps"][4] == dict(full["steps"][4], rebuilt=0, sweeps=0, visits=0)
