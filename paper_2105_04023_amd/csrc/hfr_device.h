@@ -171,6 +171,13 @@ DEVI uint32_t wave_excl_scan(uint32_t c, uint32_t* total) {
     return x - c;
 }
 
+// Lane j's value of x (j wave-uniform), as a scalar.
+DEVI int64_t readlane64(int64_t x, int j) {
+    const uint32_t lo = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)x, j);
+    const uint32_t hi = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)((uint64_t)x >> 32), j);
+    return (int64_t)(((uint64_t)hi << 32) | lo);
+}
+
 DEVI int64_t wave_index() { return __builtin_amdgcn_readfirstlane((int)((blockIdx.x * blockDim.x + threadIdx.x) >> 6)); }
 DEVI int64_t wave_count() { return (int64_t)(gridDim.x * blockDim.x) >> 6; }
 

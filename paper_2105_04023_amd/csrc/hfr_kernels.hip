@@ -1037,6 +1037,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(DW == 1 ? 7
 
 // One G-lane group per piece of a split row: merge of the live rows of the
 // piece's out-neighbours in L_t, written to part[piece].
+constexpr int NSP = 2;  // marked pieces whose first windows a sparse sweep loads together
 template <int G, int DW, int KIND>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(7, 8))) void k_sweep_heavy(
     const int32_t* __restrict__ adj, EdgeHashes H, const uint32_t* __restrict__ thr,
@@ -1202,18 +1203,77 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(7, 8))) voi
                 ul = hrow[rl];
                 skl = fullblk && bit_of(fullblk, ul) != 0u;
             }
-            for (uint64_t nz = __ballot(wm != 0u); nz;) {
-                // group grp takes the grp-th marked piece left
-                uint64_t t = nz;
-                for (int k = 0; k < grp && t; ++k) t &= t - 1;
-                const int j = t ? __builtin_ctzll(t) : 0;
-                const uint32_t wj = (uint32_t)__shfl((int)wm, j, 64);
-                const int32_t r = __shfl(rl, j, 64);
-                const uint32_t u = (uint32_t)__shfl(ul, j, 64);
-                const int64_t b0 = __shfl(b0l, j, 64), b1 = __shfl(b1l, j, 64);
-                const bool sk = __shfl((int)skl, j, 64) != 0;
-                for (int k = 0; k < RPW && nz; ++k) nz &= nz - 1;
-                if (t) piece(base + j, r, u, b0, b1, wj, sk);
+            if constexpr (G == 64) {
+                // NSP marked pieces at a time: the edge ids of each one's first marked
+                // window are loaded, and their heads tested against L_t, together, so
+                // that the pieces share those round trips; then each piece is merged
+                // (its other marked windows, rare in a sparse sweep, after the first)
+                for (uint64_t nz = __ballot(wm != 0u); nz;) {
+                    // per slot: the piece's lane in the span, its table entry (wave-uniform,
+                    // read from that lane) and the first marked window's edge ids
+                    int js[NSP];
+                    uint32_t wj[NSP], uq[NSP];
+                    int32_t rq[NSP], vw[NSP];
+                    int64_t w0[NSP], e1q[NSP];
+                    bool val[NSP];
+                    uint64_t dm[NSP], mw[NSP];
+#pragma unroll
+                    for (int q = 0; q < NSP; ++q) {
+                        val[q] = nz != 0ull;
+                        js[q] = val[q] ? __builtin_ctzll(nz) : 0;
+                        nz &= nz - 1;
+                        const int j = js[q];
+                        wj[q] = (uint32_t)__builtin_amdgcn_readlane((int)wm, j);
+                        rq[q] = __builtin_amdgcn_readlane(rl, j);
+                        uq[q] = (uint32_t)__builtin_amdgcn_readlane(ul, j);
+                        const int64_t b0q = readlane64(b0l, j);
+                        e1q[q] = readlane64(b1l, j);
+                        const bool skip = !val[q] || __builtin_amdgcn_readlane((int)skl, j) != 0;
+                        w0[q] = skip || wj[q] == 0u ? e1q[q] : b0q + 64 * (int64_t)__builtin_ctz(wj[q]);
+                        const bool in = w0[q] + lane < e1q[q];
+                        const int32_t a = in ? adj[w0[q] + lane] : 0;
+                        vw[q] = adj_target(a);
+                        dm[q] = __ballot(adj_dead(a));
+                    }
+#pragma unroll
+                    for (int q = 0; q < NSP; ++q) mw[q] = __ballot(w0[q] + lane < e1q[q] && bit_of(Lcur, vw[q]) != 0u);
+#pragma unroll
+                    for (int q = 0; q < NSP; ++q) {
+                        if (!val[q]) continue;
+                        Acc acc[DW];
+#pragma unroll
+                        for (int k = 0; k < DW; ++k) acc[k].e = acc[k].o = 0u;
+                        uint32_t vis = 0;
+                        if (w0[q] < e1q[q]) {  // not skipped (a window is never empty)
+                            vis = (uint32_t)__builtin_popcountll(mw[q]);
+                            const uint64_t mm = mw[q] & ~dm[q];  // edges live in no sample merge nothing
+                            if (mm)
+                                my_mrg += merge_window64<DW, KIND>(mm, w0[q] + lane, w0[q] + lane < e1q[q], vw[q],
+                                                                   uq[q], H, thr, ntv, A, P, lane, x, acc);
+                            const uint32_t rest = wj[q] & (wj[q] - 1u);
+                            if (rest)
+                                vis += merge_marked_windows64<DW, KIND>(w0[q] - 64 * (int64_t)__builtin_ctz(wj[q]),
+                                                                        e1q[q], rest, uq[q], adj, H, thr, ntv, A,
+                                                                        Lcur, first, P, lane, x, acc, nullptr, 0,
+                                                                        &my_mrg);
+                        }
+                        finish_piece(base + js[q], rq[q], vis, acc);
+                    }
+                }
+            } else {
+                for (uint64_t nz = __ballot(wm != 0u); nz;) {
+                    // group grp takes the grp-th marked piece left
+                    uint64_t t = nz;
+                    for (int k = 0; k < grp && t; ++k) t &= t - 1;
+                    const int j = t ? __builtin_ctzll(t) : 0;
+                    const uint32_t wj = (uint32_t)__shfl((int)wm, j, 64);
+                    const int32_t r = __shfl(rl, j, 64);
+                    const uint32_t u = (uint32_t)__shfl(ul, j, 64);
+                    const int64_t b0 = __shfl(b0l, j, 64), b1 = __shfl(b1l, j, 64);
+                    const bool sk = __shfl((int)skl, j, 64) != 0;
+                    for (int k = 0; k < RPW && nz; ++k) nz &= nz - 1;
+                    if (t) piece(base + j, r, u, b0, b1, wj, sk);
+                }
             }
         }
     }
