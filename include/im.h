@@ -88,6 +88,10 @@ typedef struct im_probs {
                                   sweeps; registers, estimates and seeds equal those of synchronous
                                   sweeps when eps_c = 0, while sweep and visit counts depend on the
                                   schedule (not reproducible). */
+#define IM_BUILD_TIME_PIECES 8 /* record the sweep log with HIP-event timings of the split-row
+                                  piece kernel only (heavy_ms; kernel_ms and sweep_ms are 0): two
+                                  events per sweep instead of six, so the timing costs the sweeps
+                                  less.  IM_BUILD_TIME_SWEEPS includes it. */
 #define IM_BUILD_ATOMIC_REVERSE 4 /* build the reverse CSR (in-edges, for sparse sweeps) with global
                                      atomics on an auxiliary stream beside the first sweeps, the
                                      method used anyway when n > 2^25 or m >= 2^31; otherwise it
@@ -249,7 +253,7 @@ IM_API im_status im_sketch_get_trace(const im_sketch* sk, int64_t* live_counts, 
                               int32_t* written);
 
 /* One sweep, recorded when the build was asked to time sweeps
- * (IM_BUILD_TIME_SWEEPS): kernel_ms is the device time of the row
+ * (IM_BUILD_TIME_SWEEPS, or IM_BUILD_TIME_PIECES for heavy_ms alone): kernel_ms is the device time of the row
  * kernel, heavy_ms that of the split-row piece kernel, sweep_ms that of all
  * kernels of the sweep, from HIP events on the context stream; light_visits the edges
  * with a live head the row kernel visited, visits those of the whole sweep, live_next

@@ -114,7 +114,7 @@ class Sketch:
         return live[: w.value], vis[: w.value - 1]
 
     def sweep_log(self, clear: bool = False) -> list:
-        """Timed launches of the row sweep kernel (needs time_sweeps=True at build)."""
+        """One record per launched sweep (needs time_sweeps at build)."""
         cap = 1 << 16
         buf = (B.im_sweep_rec * cap)()
         k = self.lib.im_sketch_get_sweep_log(self.handle, ctypes.cast(buf, ctypes.c_void_p), cap)
@@ -176,11 +176,15 @@ def _offsets(xadj):
 
 def im_build_sketches(ctx: Context, xadj, adj, n: int, R: int, model: str = "const", p: float = 0.0,
                       per_edge=None, hash_seed: int = 0, eps_c: float = 0.0, heavy_degree: int = 0,
-                      piece_edges: int = 0, sparse_div: int = 0, time_sweeps: bool = False,
+                      piece_edges: int = 0, sparse_div: int = 0, time_sweeps=False,
                       in_place: bool = False, atomic_reverse: bool = False) -> Sketch:
     """Alg. 1 initialisation + Alg. 2: builds the per-vertex rank registers of R samples.
+    time_sweeps: True times every kernel of every sweep (IM_BUILD_TIME_SWEEPS), "pieces" the
+    split-row piece kernel only (IM_BUILD_TIME_PIECES);
     in_place selects in-place sweeps (IM_BUILD_IN_PLACE) for the build and every rebuild;
     atomic_reverse the atomic reverse-CSR construction (IM_BUILD_ATOMIC_REVERSE)."""
+    if time_sweeps not in (False, True, "pieces"):
+        raise ValueError("time_sweeps must be False, True or 'pieces'")
     torch = _torch()
     xp, xdev, xk, xbits = _offsets(xadj)
     ap, adev, ak = _ptr_and_residency(adj, (np.int32, torch.int32))
@@ -197,7 +201,9 @@ def im_build_sketches(ctx: Context, xadj, adj, n: int, R: int, model: str = "con
         pe_ptr = pp
         keep.append(pk)
     probs = B.im_probs(_KIND[model], float(p), pe_ptr)
-    flags = ((B.IM_BUILD_TIME_SWEEPS if time_sweeps else 0) | (B.IM_BUILD_IN_PLACE if in_place else 0) |
+    timing = (B.IM_BUILD_TIME_PIECES if time_sweeps == "pieces" else
+              B.IM_BUILD_TIME_SWEEPS if time_sweeps else 0)
+    flags = (timing | (B.IM_BUILD_IN_PLACE if in_place else 0) |
              (B.IM_BUILD_ATOMIC_REVERSE if atomic_reverse else 0))
     opts = B.im_build_opts(eps_c, heavy_degree, piece_edges, sparse_div, flags)
     h = ctypes.c_void_p()

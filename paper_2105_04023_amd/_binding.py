@@ -16,7 +16,7 @@ IM_ERR_INVALID_ARG, IM_ERR_INVALID_GRAPH, IM_ERR_OUT_OF_BUDGET, IM_ERR_DEVICE, I
 STATUS_NAMES = {0: "IM_OK", -1: "IM_ERR_INVALID_ARG", -2: "IM_ERR_INVALID_GRAPH", -3: "IM_ERR_OUT_OF_BUDGET",
                 -4: "IM_ERR_DEVICE", -5: "IM_ERR_STATE"}
 IM_PROB_CONSTANT, IM_PROB_WEIGHTED_CASCADE, IM_PROB_PER_EDGE = 0, 1, 2
-IM_BUILD_TIME_SWEEPS, IM_BUILD_IN_PLACE, IM_BUILD_ATOMIC_REVERSE = 1, 2, 4
+IM_BUILD_TIME_SWEEPS, IM_BUILD_IN_PLACE, IM_BUILD_ATOMIC_REVERSE, IM_BUILD_TIME_PIECES = 1, 2, 4, 8
 IM_NOALLOC_MAX_K = 4096  # largest K of im_select_seeds_noalloc
 
 # Every symbol include/im.h declares (checked by the CPU test suite).

@@ -191,7 +191,8 @@ struct im_sketch {
     void* list_tmp = nullptr; // a preparation temporary (per-edge weights, light-row list build)
     void* hash_tmp = nullptr; // the edge hashes, held until the edges live in no sample are flagged
     std::vector<hipEvent_t> sweep_ev;
-    bool time_sweeps = false;
+    bool time_sweeps = false;  // sweep log recorded (either timing flag)
+    bool time_all = false;     // every kernel of a sweep timed, not only the piece kernel
     bool in_place = false;  // sweeps read and write one register buffer
 
     // build statistics
@@ -503,10 +504,12 @@ im_status run_simulate(im_sketch* sk, int ia, int ib, const uint32_t* blk, SimRe
             sp.first = st == 0;
             hipEvent_t e0 = nullptr, e1 = nullptr, ea = nullptr, eb = nullptr, e2 = nullptr, e3 = nullptr;
             if (sk->time_sweeps && timer_idx + 5 < (int)sk->sweep_ev.size()) {
-                e0 = sk->sweep_ev[timer_idx];
-                e1 = sk->sweep_ev[timer_idx + 1];
-                ea = sk->sweep_ev[timer_idx + 2];
-                eb = sk->sweep_ev[timer_idx + 3];
+                if (sk->time_all) {
+                    e0 = sk->sweep_ev[timer_idx];
+                    e1 = sk->sweep_ev[timer_idx + 1];
+                    ea = sk->sweep_ev[timer_idx + 2];
+                    eb = sk->sweep_ev[timer_idx + 3];
+                }
                 e2 = sk->sweep_ev[timer_idx + 4];
                 e3 = sk->sweep_ev[timer_idx + 5];
                 timer_idx += 6;
@@ -573,8 +576,10 @@ im_status run_simulate(im_sketch* sk, int ia, int ib, const uint32_t* blk, SimRe
         // stopping rule that returned at once
         for (int i = 0; i + 5 < timer_idx; i += 6) {
             float km = 0.f, wm = 0.f, hm = 0.f;
-            HIP_TRY(hipEventElapsedTime(&km, sk->sweep_ev[i], sk->sweep_ev[i + 1]));
-            HIP_TRY(hipEventElapsedTime(&wm, sk->sweep_ev[i + 2], sk->sweep_ev[i + 3]));
+            if (sk->time_all) {
+                HIP_TRY(hipEventElapsedTime(&km, sk->sweep_ev[i], sk->sweep_ev[i + 1]));
+                HIP_TRY(hipEventElapsedTime(&wm, sk->sweep_ev[i + 2], sk->sweep_ev[i + 3]));
+            }
             HIP_TRY(hipEventElapsedTime(&hm, sk->sweep_ev[i + 4], sk->sweep_ev[i + 5]));
             const int t = i / 6;
             im_sweep_rec rec{};
@@ -686,7 +691,7 @@ im_status build_sketch(im_ctx* ctx, const im_csr* graph, const im_probs* probs, 
     if (!(o.eps_c >= 0.0)) return fail(IM_ERR_INVALID_ARG, "eps_c must be >= 0");
     if (o.heavy_degree < 0 || o.piece_edges < 0) return fail(IM_ERR_INVALID_ARG, "negative tuning value");
     if (o.piece_edges > 2048) return fail(IM_ERR_INVALID_ARG, "piece_edges must be at most 2048");
-    if (o.flags & ~(IM_BUILD_TIME_SWEEPS | IM_BUILD_IN_PLACE | IM_BUILD_ATOMIC_REVERSE))
+    if (o.flags & ~(IM_BUILD_TIME_SWEEPS | IM_BUILD_IN_PLACE | IM_BUILD_ATOMIC_REVERSE | IM_BUILD_TIME_PIECES))
         return fail(IM_ERR_INVALID_ARG, "unknown build flag");
     const size_t need = bytes_needed(n, m, R, probs->kind);
     if (ctx->budget && ctx->in_use + need > ctx->budget)
@@ -706,7 +711,8 @@ im_status build_sketch(im_ctx* ctx, const im_csr* graph, const im_probs* probs, 
     sk->L = make_layout(R);
     sk->seed = hash_seed;
     sk->eps_c = o.eps_c;
-    sk->time_sweeps = (o.flags & IM_BUILD_TIME_SWEEPS) != 0;
+    sk->time_all = (o.flags & IM_BUILD_TIME_SWEEPS) != 0;
+    sk->time_sweeps = sk->time_all || (o.flags & IM_BUILD_TIME_PIECES) != 0;
     sk->in_place = (o.flags & IM_BUILD_IN_PLACE) != 0;
     DevGraph& g = sk->g;
     g.n = n;

@@ -395,3 +395,28 @@ def test_first_sweep_merges_the_edges_live_somewhere(hf, ctx, model, p, J, heavy
     M_or, _, _, te = oracle.simulate(g, thr, J)
     assert np.array_equal(M, M_or)
     assert [r["visits"] for r in log] == [int(v) for v in te]
+
+
+def test_piece_kernel_timing_only(hf, ctx):
+    """IM_BUILD_TIME_PIECES: the sweep log holds the same sweeps and counts as with every kernel
+    timed, with heavy_ms only (kernel_ms and sweep_ms 0), and the registers do not change."""
+    g = synth.rmat(12, 40000, seed=7)
+    logs, regs = {}, {}
+    for mode in (True, "pieces"):
+        sk = hf.im_build_sketches(ctx, g.xadj, g.adj, g.n, 256, model="wc", heavy_degree=8, piece_edges=64,
+                                  time_sweeps=mode)
+        try:
+            logs[mode] = sk.sweep_log()
+            regs[mode] = sk.registers(0)
+        finally:
+            sk.free()
+    assert np.array_equal(regs[True], regs["pieces"])
+    full, pieces = logs[True], logs["pieces"]
+    assert len(full) == len(pieces) > 0
+    keys = ("simulate", "sweep", "ran", "visits", "light_visits", "merged", "light_merged", "live", "live_next",
+            "sparse")
+    assert [[r[k] for k in keys] for r in full] == [[r[k] for k in keys] for r in pieces]
+    assert all(r["kernel_ms"] == 0.0 and r["sweep_ms"] == 0.0 for r in pieces)
+    assert any(r["heavy_ms"] > 0.0 for r in pieces if r["ran"])
+    with pytest.raises(ValueError):
+        hf.im_build_sketches(ctx, g.xadj, g.adj, g.n, 64, time_sweeps="rows")
