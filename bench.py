@@ -418,7 +418,8 @@ def main():
     ap.add_argument("--sparse-div", type=int, default=0)
     ap.add_argument("--heavy-degree", type=int, default=0)
     ap.add_argument("--piece-edges", type=int, default=0)
-    ap.add_argument("--dump-sweeps", default="", help="write the sweep log of the last step to this JSON file")
+    ap.add_argument("--dump-sweeps", default="",
+                    help="write the sweep log of the last warm-up step (every kernel timed) to this JSON file")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="start with one 1 GiB device copy (the counter calibration of the traffic summary)")
     ap.add_argument("--summarize-pmc", nargs=2, metavar=("FETCH_DIR", "WRITE_DIR"),
