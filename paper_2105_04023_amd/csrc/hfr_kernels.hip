@@ -1792,35 +1792,57 @@ __global__ __launch_bounds__(1024) void k_rb_fplace(const int64_t* __restrict__ 
     if (!rb_chunk(blockIdx.x, off, ncol, nbk, cstart, ch)) return;
     for (int i = threadIdx.x; i < BT; i += 1024) cur[i] = ctab[(int64_t)blockIdx.x * BT + i];
     __syncthreads();
-    // uniform trip count per wave, so that the sample scan's ballot sees every lane
-    const int64_t span = ((ch.r1 - ch.r0 + 1023) / 1024) * 1024;
-    for (int64_t k = threadIdx.x; k < span; k += 1024) {
-        const int64_t i = ch.r0 + k;
-        const bool in = i < ch.r1;
-        const int32_t v = in ? tv[i] : 0, u = in ? tu[i] : 0;
-        bool dead = false;
+    // RPT records per thread (k0 + 1024 r), so that one load of sample words serves
+    // RPT records; uniform trip count per wave, so that the sample scan's ballot
+    // sees every lane
+    constexpr int RPT = 4;
+    const int64_t span = ((ch.r1 - ch.r0 + 1024 * RPT - 1) / (1024 * RPT)) * (1024 * RPT);
+    for (int64_t k0 = threadIdx.x; k0 < span; k0 += 1024 * RPT) {
+        int32_t v[RPT], u[RPT];
+        bool in[RPT];
+        uint32_t t[RPT], h[RPT], mn[RPT];
+#pragma unroll
+        for (int r = 0; r < RPT; ++r) {
+            const int64_t i = ch.r0 + k0 + 1024 * r;
+            in[r] = i < ch.r1;
+            v[r] = in[r] ? tv[i] : 0;
+            u[r] = in[r] ? tu[i] : 0;
+            mn[r] = 0xFFFFFFFFu;
+            t[r] = 0u;
+            h[r] = 0u;
+            if (dt.mode) {
+                t[r] = dt.mode == 2 ? (in[r] ? wc_threshold((uint32_t)(rxadj[v[r] + 1] - rxadj[v[r]])) : 0u)
+                                    : dt.thr_const;
+                h[r] = mm3_key8((uint32_t)u[r], (uint32_t)v[r], dt.seed) & 0x7FFFFFFFu;
+            }
+        }
         if (dt.mode) {
-            const uint32_t t =
-                dt.mode == 2 ? (in ? wc_threshold((uint32_t)(rxadj[v + 1] - rxadj[v])) : 0u) : dt.thr_const;
-            const uint32_t h = mm3_key8((uint32_t)u, (uint32_t)v, dt.seed) & 0x7FFFFFFFu;
-            uint32_t mn = 0xFFFFFFFFu;
             for (int j0 = 0; j0 < dt.J; j0 += 16) {
-                if (!__ballot(in && mn >= t)) break;  // every edge of the wave is live somewhere
+                bool open = false;
+#pragma unroll
+                for (int r = 0; r < RPT; ++r) open = open || (in[r] && mn[r] >= t[r]);
+                if (!__ballot(open)) break;  // every record of the wave is live somewhere
 #pragma unroll
                 for (int g = 0; g < 16; g += 4) {
                     if (j0 + g < dt.J) {
                         const uint32_t* xg = dt.X + j0 + g;
-                        mn = min(min(mn, xg[0] ^ h), xg[1] ^ h);
-                        mn = min(min(mn, xg[2] ^ h), xg[3] ^ h);
+                        const uint32_t x0 = xg[0], x1 = xg[1], x2 = xg[2], x3 = xg[3];
+#pragma unroll
+                        for (int r = 0; r < RPT; ++r) {
+                            mn[r] = min(min(mn[r], x0 ^ h[r]), x1 ^ h[r]);
+                            mn[r] = min(min(mn[r], x2 ^ h[r]), x3 ^ h[r]);
+                        }
                     }
                 }
             }
-            dead = in && mn >= t;
         }
-        if (in) {
-            const int64_t p = ch.s0 + atomicAdd(&cur[v - ch.v0], 1u);
-            radj[p] = dead ? (int32_t)((uint32_t)u | DEAD_EDGE) : u;
-            rpiece[p] = tw[i];
+#pragma unroll
+        for (int r = 0; r < RPT; ++r) {
+            if (!in[r]) continue;
+            const bool dead = dt.mode && mn[r] >= t[r];
+            const int64_t p = ch.s0 + atomicAdd(&cur[v[r] - ch.v0], 1u);
+            radj[p] = dead ? (int32_t)((uint32_t)u[r] | DEAD_EDGE) : u[r];
+            rpiece[p] = tw[ch.r0 + k0 + 1024 * r];
         }
     }
 }
