@@ -268,7 +268,11 @@ struct Sizes {
     size_t total;
 };
 
-int64_t qcap_for(int64_t n, int64_t m) { return n + (m + BFS_CHUNK - 1) / BFS_CHUNK + 64; }
+// a level's entries (each vertex once, in chunks of BFS_CHUNK out-edges), plus the
+// slots the waves of a reach level may reserve and leave unfilled
+int64_t qcap_for(int64_t n, int64_t m) {
+    return n + (m + BFS_CHUNK - 1) / BFS_CHUNK + 64 + (int64_t)BFS_WAVES * BFS_RESV;
+}
 
 size_t bytes_needed(int64_t n, int64_t m, int32_t R, im_prob_kind kind) {
     const Layout L = make_layout(R);
@@ -379,7 +383,7 @@ im_status run_reach(im_sketch* sk, int32_t lvl0, int* levels, int64_t* with_work
     GreedyBufs& b = sk->gb;
     int level = 0, nb = 4;
     while (true) {
-        const int64_t bfs_grid = 2048;
+        const int64_t bfs_grid = BFS_GRID;
         for (int i = 0; i < nb; ++i, ++level)
             HIP_TRY(launch_bfs_level(sk->L, sk->g, sk->X, b, level, lvl0 + level + 1, (int)bfs_grid, s));
         HIP_TRY(hipMemcpyAsync(sk->h_small, b.qsize, 16, hipMemcpyDeviceToHost, s));

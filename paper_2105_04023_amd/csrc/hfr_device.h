@@ -781,7 +781,14 @@ DEVI int decide_step(unsigned long long R, unsigned long long R0, int J, int k, 
 // words of G / (4 PW) edges at once (8 edges at R = 256).  The wave serves
 // entries base + (lane / G) for base = b0, b0 + bstep, ... below b1 (uniform
 // bounds).  Returns the number of newly blocked pairs found by this lane.
-template <int G, int DW, int KIND>
+//
+// RESV (G = 64): a wave takes next-queue slots from the shared counter qn
+// BFS_RESV at a time (or as many as one flush needs) instead of once per flush,
+// so that the counter is not the level's serialisation point; the slots a wave
+// reserved and did not fill become holes (vertex -1), which the next level and
+// the cleanup skip.  The queue then needs BFS_RESV slots per wave of the launch
+// beyond its entries.
+template <int G, int DW, int KIND, bool RESV = false>
 DEVI unsigned long long bfs_expand_entries(int64_t b0, int64_t b1, int64_t bstep, const int64_t* __restrict__ xadj,
                                            const int32_t* __restrict__ adj, const EdgeHashes& H,
                                            const uint32_t* __restrict__ thr, uint32_t ntv, const uint32_t (&x)[DW][4],
@@ -797,16 +804,17 @@ DEVI unsigned long long bfs_expand_entries(int64_t b0, int64_t b1, int64_t bstep
     const uint64_t gmask = G == 64 ? ~0ull : ((1ull << G) - 1ull);
     const uint64_t wmask = W >= 64 ? ~0ull : ((1ull << W) - 1ull);
     unsigned long long my_new = 0;
+    uint32_t rpos = 0, rend = 0;  // RESV: the wave's reserved slots not yet filled
     for (int64_t base = b0; base < b1; base += bstep) {
         const int64_t ent = base + grp;
-        const bool ok = ent < b1;
+        const int2 qe = ent < b1 ? Qc[ent] : make_int2(-1, 0);
+        const bool ok = qe.x >= 0;  // past b1, or a hole
         int64_t e0 = 0, e1 = 0;
         uint32_t src = 0;  // the entry's vertex: the source of its edges
         uint32_t fb[DW];  // frontier bits of this lane's registers, bit (k) of fb[i] for register 4q+k
 #pragma unroll
         for (int i = 0; i < DW; ++i) fb[i] = 0u;
         if (ok) {
-            const int2 qe = Qc[ent];
             const int64_t v = qe.x;
             src = (uint32_t)v;
             const int64_t vb = xadj[v], ve = xadj[v + 1];
@@ -854,7 +862,29 @@ DEVI unsigned long long bfs_expand_entries(int64_t b0, int64_t b1, int64_t bstep
                     nch = (uint32_t)((mywdeg + bfs_chunk - 1) / bfs_chunk);
                 uint32_t tot;
                 const uint32_t off = wave_excl_scan(nch, &tot);
-                if (tot) {
+                if (tot && RESV) {
+                    // the first `have` of the flush's entries fill the reserved slots, the
+                    // rest a new block taken from the counter
+                    const uint32_t have = rend - rpos;
+                    uint32_t nb = rend, nend = rend;
+                    if (tot > have) {
+                        const uint32_t take = tot - have > (uint32_t)BFS_RESV ? tot - have : (uint32_t)BFS_RESV;
+                        uint32_t blk0 = 0;
+                        if (lane == 0) blk0 = atomicAdd(qn, take);
+                        nb = __shfl(blk0, 0, 64);
+                        nend = nb + take;
+                    }
+                    for (uint32_t c = 0; c < nch; ++c) {
+                        const uint32_t i = off + c;
+                        Qn[i < have ? rpos + i : nb + (i - have)] = make_int2((int)myw, (int)c);
+                    }
+                    if (tot > have) {
+                        rpos = nb + (tot - have);
+                        rend = nend;
+                    } else {
+                        rpos += tot;
+                    }
+                } else if (tot) {
                     uint32_t pos = 0;
                     if (lane == 0) pos = atomicAdd(qn, tot);
                     pos = __shfl(pos, 0, 64) + off;
@@ -936,6 +966,8 @@ DEVI unsigned long long bfs_expand_entries(int64_t b0, int64_t b1, int64_t bstep
         }
         if (nb > 0) flush();
     }
+    if constexpr (RESV && G == 64)
+        for (uint32_t h = rpos + lane; h < rend; h += 64) Qn[h] = make_int2(-1, 0);  // holes
     return my_new;
 }
 

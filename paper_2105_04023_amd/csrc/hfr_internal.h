@@ -68,6 +68,11 @@ __host__ __device__ inline int32_t adj_target(int32_t a) { return a & 0x7FFFFFFF
 __host__ __device__ inline bool adj_dead(int32_t a) { return a < 0; }
 
 constexpr int COARSE_WORDS = 2048;  // coarse copy of L_t: 8 KiB of LDS per workgroup
+// Reach levels: workgroups of 256 per launch, and the queue slots a wave reserves at
+// a time (the queue holds up to BFS_WAVES * BFS_RESV slots beyond its entries).
+constexpr int BFS_GRID = 2048;
+constexpr int BFS_WAVES = BFS_GRID * 4;
+constexpr int BFS_RESV = 64;
 
 // Work lists of a sparse sweep.  Counters come in two sets selected by the
 // sweep parity; a sweep zeroes the other set for the next sweep.

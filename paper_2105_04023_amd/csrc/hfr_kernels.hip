@@ -2160,7 +2160,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(8, 8))) voi
     uint32_t x[DW][4];
     load_sim_words<G, DW>(X, P, p, x);
     const uint32_t ntv = to_vgpr(0u - thr_const);
-    const unsigned long long my_new = bfs_expand_entries<G, DW, KIND>(
+    const unsigned long long my_new = bfs_expand_entries<G, DW, KIND, true>(
         wave_index() * RPW, (int64_t)size, wave_count() * RPW, xadj, adj, H, thr, ntv, x, b.F[cur & 1],
         b.F[(cur + 1) & 1], b.Q[cur & 1], b.Q[(cur + 1) & 1], &b.qsize[(cur + 1) % 3], b.blk, b.stamp, level_id_next,
         b.bfs_chunk, P, PW);
@@ -2181,13 +2181,15 @@ __global__ void k_bfs_cleanup(GreedyBufs b, int cur, int PW) {
          i += (int64_t)gridDim.x * blockDim.x) {
         const int64_t ent = i / W;
         const int2 qe = Qc[ent];
-        if (qe.y == 0) Fc[(int64_t)qe.x * W + (i % W)] = 0u;
+        if (qe.y == 0 && qe.x >= 0) Fc[(int64_t)qe.x * W + (i % W)] = 0u;  // holes have vertex -1
     }
     if (blockIdx.x == 0 && threadIdx.x == 0) b.qsize[3] += 1u;
 }
 
 hipError_t launch_bfs_level(const Layout& L, const DevGraph& g, const uint32_t* X, const GreedyBufs& b, int level,
                             int32_t level_id_next, int grid, hipStream_t s) {
+    // the queues hold BFS_RESV slots per wave of at most BFS_GRID workgroups beyond their entries
+    if (grid < 1 || grid > BFS_GRID) return hipErrorInvalidValue;
     HFR_LAYOUT_DISPATCH(L, HFR_KIND_DISPATCH(g.kind, hipLaunchKernelGGL((k_bfs_expand<G_, DW_, K_>), dim3(grid),
                                                                         dim3(256), 0, s, g.xadj, g.adj, hashes(g),
                                                                         g.thr, g.thr_const, X, b, level, level_id_next,
