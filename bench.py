@@ -298,12 +298,12 @@ def batch_leg(hf, ctx, steps: int, warmup: int):
     }
 
 
-def _replay(hf, graphs, stream, slots: int, budget_gb: int):
+def _replay(hf, graphs, stream, slots: int, budget_gb: int, max_copies: int = 0):
     """Replays a request stream in real time against a fresh serving engine; latency is
     submit-to-completion and service time build + selection, as the engine measures them."""
     import numpy as np
 
-    sv = hf.Server(0, slots=slots, hbm_budget=budget_gb << 30)
+    sv = hf.Server(0, slots=slots, hbm_budget=budget_gb << 30, max_copies=max_copies)
     try:
         for g in graphs:
             sv.add_graph(g.xadj, g.adj, g.n)
@@ -341,8 +341,8 @@ def _replay(hf, graphs, stream, slots: int, budget_gb: int):
     }
 
 
-def serve_leg(hf, n_requests: int, slots: int = 4, budget_gb: int = 200, low_rate: float = 3.0,
-              low_requests: int = 60):
+def serve_leg(hf, n_requests: int, slots: int = 8, budget_gb: int = 200, low_rate: float = 3.0,
+              low_requests: int = 60, max_copies: int = 0):
     """Poisson stream (mean 200 requests/s, seed 5) over 16 resident R-MAT graphs (log2 n in 14..22,
     degree 16); each request: IC p=0.01, IC p=0.1 or weighted cascade, R in {64, 256}, K in 10..100.
     The stream is replayed in real time against the library's serving engine under a 200 GB budget.
@@ -357,12 +357,12 @@ def serve_leg(hf, n_requests: int, slots: int = 4, budget_gb: int = 200, low_rat
     log(f"serving workload: {len(graphs)} graphs (n={sum(g.n for g in graphs)}, m={sum(g.m for g in graphs)}), "
         f"{len(stream)} requests over {stream[-1][0]:.1f} s, generated in {time.perf_counter() - t:.1f} s")
     out = {"workload": "serve_16rmat_log2n14-22_deg16_poisson200_" + str(n_requests), "slots": slots,
-           "hbm_budget_gb": budget_gb}
-    out.update(_replay(hf, graphs, stream, slots, budget_gb))
+           "max_copies": max_copies or 1, "hbm_budget_gb": budget_gb}
+    out.update(_replay(hf, graphs, stream, slots, budget_gb, max_copies))
     if low_requests > 0:
         _, low = synth.serving_recipe(requests=low_requests, rate=low_rate)
         log(f"serving at low load: {len(low)} requests over {low[-1][0]:.1f} s")
-        r = _replay(hf, graphs, low, slots, budget_gb)
+        r = _replay(hf, graphs, low, slots, budget_gb, max_copies)
         out["low_load"] = {k: r[k] for k in ("requests", "offered_req_s", "throughput_req_s", "latency_ms_p50",
                                              "latency_ms_p99", "service_ms_p50", "service_ms_p99",
                                              "sketch_reuse_frac")}
@@ -410,8 +410,10 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-batch", action="store_true", help="skip the batched-vs-plain comparison")
     ap.add_argument("--no-quality", action="store_true", help="skip the rebuild-policy quality comparison")
-    ap.add_argument("--serve-slots", type=int, default=4, help="concurrent slots of the serving engine")
+    ap.add_argument("--serve-slots", type=int, default=8, help="concurrent slots of the serving engine")
     ap.add_argument("--serve-only", action="store_true", help="run only the serving leg and print its object")
+    ap.add_argument("--serve-max-copies", type=int, default=0,
+                    help="resident copies one sketch key may have in the serving leg (0: the library's default, 1)")
     ap.add_argument("--serve-requests", type=int, default=2000,
                     help="requests of the serving leg (the full stream has 2000; 0 skips the leg)")
     ap.add_argument("--K", type=int, default=0, help="override K")
@@ -447,7 +449,8 @@ def main():
         print(json.dumps({"batched": batch_leg(hf, hf.Context(0), args.steps, args.warmup)}), flush=True)
         return
     if args.serve_only:
-        print(json.dumps({"serving": serve_leg(hf, args.serve_requests, slots=args.serve_slots)}), flush=True)
+        print(json.dumps({"serving": serve_leg(hf, args.serve_requests, slots=args.serve_slots,
+                                               max_copies=args.serve_max_copies)}), flush=True)
         return
     import synth
 
@@ -568,7 +571,7 @@ def main():
     if not args.no_batch:
         out["batched"] = batch_leg(hf, ctx, args.steps, args.warmup)
     if args.serve_requests > 0:
-        out["serving"] = serve_leg(hf, args.serve_requests, slots=args.serve_slots)
+        out["serving"] = serve_leg(hf, args.serve_requests, slots=args.serve_slots, max_copies=args.serve_max_copies)
     if not args.no_quality:
         out["quality"] = quality_leg(hf, ctx)
     if args.dump_sweeps:

@@ -406,7 +406,7 @@ IM_API void im_batch_free(im_batch* b);
  * free.  Sketches stay resident in one pool and are reused, on whichever slot
  * runs the request, by later requests with the same (graph, model, p, R, hash
  * seed, eps_c); a sketch serves one request at a time, and a key whose copies
- * are all busy may get a second copy.  Selections go through
+ * are all busy may get another copy, up to max_copies.  Selections go through
  * im_select_seeds_resume, so a request whose sketch copy last served the same
  * thresholds reuses or continues that greedy run; its result still equals
  * im_build_sketches + im_select_seeds run alone.  hbm_budget (0 = none) bounds the device memory of the resident graphs
@@ -417,7 +417,10 @@ IM_API void im_batch_free(im_batch* b);
  */
 typedef struct im_server_opts {
     int32_t slots;      /* concurrent requests, in [1, 64] */
-    int32_t max_copies; /* resident copies one sketch key may have, in [1, 64] (0: 2) */
+    int32_t max_copies; /* resident copies one sketch key may have, in [1, 64] (0: 1).  With
+                           resumed selection a key's requests mostly need no device work, so a
+                           second copy (a second build) pays only when requests of one key that
+                           need new greedy steps overlap. */
     size_t hbm_budget;  /* device bytes for graphs and sketches; 0 = no bound */
 } im_server_opts;
 

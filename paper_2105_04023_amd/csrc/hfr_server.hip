@@ -8,7 +8,8 @@
 // free.  Sketches (the build of Alg. 1 + Alg. 2 for one graph, edge model, p,
 // R, hash seed and eps_c) form one pool: a later request with the same key
 // reuses an idle copy on whichever slot runs it (the sketch is moved to that
-// slot's stream), and a key with every copy busy may get a second copy.
+// slot's stream), and a key with every copy busy may get another copy (up to
+// max_copies, default 1).
 // A request's selection goes through im_select_seeds_resume: a sketch keeps the
 // greedy run of its last request, a request with the same thresholds and a K
 // no larger is answered from that run and a larger K continues it, so
@@ -154,7 +155,7 @@ im_status im_server_create(int32_t device, const im_server_opts* opts, im_server
         sv->backend.slots.push_back(sl);
     }
     sv->sched = std::make_unique<hfr::sched::Scheduler<Payload>>(opts->slots, opts->hbm_budget, &sv->backend,
-                                                                 opts->max_copies ? opts->max_copies : 2);
+                                                                 opts->max_copies ? opts->max_copies : 1);
     sv->sched->start();
     *out = sv;
     return IM_OK;
