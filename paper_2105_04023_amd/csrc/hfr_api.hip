@@ -206,7 +206,7 @@ struct im_sketch {
     int32_t level_id = 1;
     bool selected = false;
     // the greedy run of the last selection (steps 1..sel_K, before step sel_K's
-    // rebuild decision took effect), for continuing it (select_resumable)
+    // rebuild decision took effect), which im_select_seeds_resume reuses or continues
     int32_t sel_K = 0;
     double sel_eps_g = 0.0, sel_eps_l = 0.0;
     std::vector<StepRec> sel_recs;
