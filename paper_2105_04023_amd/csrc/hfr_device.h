@@ -788,7 +788,7 @@ DEVI int decide_step(unsigned long long R, unsigned long long R0, int J, int k, 
 // reserved and did not fill become holes (vertex -1), which the next level and
 // the cleanup skip.  The queue then needs BFS_RESV slots per wave of the launch
 // beyond its entries.
-template <int G, int DW, int KIND, bool RESV = false>
+template <int G, int DW, int KIND, bool RESV = false, int NE = 1>
 DEVI unsigned long long bfs_expand_entries(int64_t b0, int64_t b1, int64_t bstep, const int64_t* __restrict__ xadj,
                                            const int32_t* __restrict__ adj, const EdgeHashes& H,
                                            const uint32_t* __restrict__ thr, uint32_t ntv, const uint32_t (&x)[DW][4],
@@ -805,30 +805,42 @@ DEVI unsigned long long bfs_expand_entries(int64_t b0, int64_t b1, int64_t bstep
     const uint64_t wmask = W >= 64 ? ~0ull : ((1ull << W) - 1ull);
     unsigned long long my_new = 0;
     uint32_t rpos = 0, rend = 0;  // RESV: the wave's reserved slots not yet filled
-    for (int64_t base = b0; base < b1; base += bstep) {
-        const int64_t ent = base + grp;
-        const int2 qe = ent < b1 ? Qc[ent] : make_int2(-1, 0);
-        const bool ok = qe.x >= 0;  // past b1, or a hole
-        int64_t e0 = 0, e1 = 0;
-        uint32_t src = 0;  // the entry's vertex: the source of its edges
-        uint32_t fb[DW];  // frontier bits of this lane's registers, bit (k) of fb[i] for register 4q+k
+    static_assert(NE == 1 || G == 64, "several entries per step need one entry per wave");
+    // NE entries per step (base, base + bstep, ...): their records, edge ranges,
+    // frontier bits and first windows of edges are loaded together, so that the
+    // entries' round trips overlap; their candidate edges share the flush batches
+    for (int64_t base = b0; base < b1; base += NE * bstep) {
+        int2 qe[NE];
 #pragma unroll
-        for (int i = 0; i < DW; ++i) fb[i] = 0u;
-        if (ok) {
-            const int64_t v = qe.x;
-            src = (uint32_t)v;
-            const int64_t vb = xadj[v], ve = xadj[v + 1];
-            e0 = vb + (int64_t)qe.y * bfs_chunk;
-            e1 = e0 + bfs_chunk < ve ? e0 + bfs_chunk : ve;
+        for (int t = 0; t < NE; ++t) {
+            const int64_t ent = base + t * bstep + grp;
+            qe[t] = ent < b1 ? Qc[ent] : make_int2(-1, 0);
+        }
+        int64_t e0[NE], e1[NE];
+        uint32_t src[NE];     // the entry's vertex: the source of its edges
+        uint32_t fb[NE][DW];  // frontier bits of this lane's registers, bit (k) of fb[t][i] for register 4q+k
 #pragma unroll
-            for (int i = 0; i < DW; ++i) {
-                const int q = i * G + p;
-                uint32_t f = 0;
-                if (q < P) {
+        for (int t = 0; t < NE; ++t) {
+            e0[t] = e1[t] = 0;
+            src[t] = 0;
 #pragma unroll
-                    for (int k = 0; k < 4; ++k) f |= ((Fc[v * W + k * PW + (q >> 5)] >> (q & 31)) & 1u) << k;
+            for (int i = 0; i < DW; ++i) fb[t][i] = 0u;
+            if (qe[t].x >= 0) {  // not past b1, nor a hole
+                const int64_t v = qe[t].x;
+                src[t] = (uint32_t)v;
+                const int64_t vb = xadj[v], ve = xadj[v + 1];
+                e0[t] = vb + (int64_t)qe[t].y * bfs_chunk;
+                e1[t] = e0[t] + bfs_chunk < ve ? e0[t] + bfs_chunk : ve;
+#pragma unroll
+                for (int i = 0; i < DW; ++i) {
+                    const int q = i * G + p;
+                    uint32_t f = 0;
+                    if (q < P) {
+#pragma unroll
+                        for (int k = 0; k < 4; ++k) f |= ((Fc[v * W + k * PW + (q >> 5)] >> (q & 31)) & 1u) << k;
+                    }
+                    fb[t][i] = f;
                 }
-                fb[i] = f;
             }
         }
         uint32_t myval = 0;
@@ -901,20 +913,9 @@ DEVI unsigned long long bfs_expand_entries(int64_t b0, int64_t b1, int64_t bstep
             myval = 0;
             myslot = false;
         };
-        for (int64_t w0 = e0; w0 < e1; w0 += G) {
-            const int64_t e = w0 + p;
-            const bool in = e < e1;
-            const int32_t wa = in ? adj[e] : 0;
-            const int32_t wv = adj_target(wa);
-            const uint32_t hh = in ? edge_hash_of(H, e, src, (uint32_t)wv) : 0u;
-            uint32_t tt = 0u;
-            if constexpr (KIND == THR_TARGET) tt = in ? thr[wv] : 0u;
-            if constexpr (KIND == THR_EDGE) tt = in ? thr[e] : 0u;
-            const int nwin = (int)(e1 - w0 < G ? e1 - w0 : G);
-            // G = 64: only the window's edges live in some sample (an edge live in
-            // none reaches nothing); groups scan their whole window
-            uint64_t todo = 0;
-            if constexpr (G == 64) todo = __ballot(in && !adj_dead(wa));
+        // the serial pass over one window's edges (lane p holds edge w0 + p with
+        // head wv, hash hh and threshold tt; fbe: the entry's frontier bits)
+        auto scan = [&](uint64_t todo, int nwin, uint32_t hh, uint32_t tt, int32_t wv, const uint32_t (&fbe)[DW]) {
             for (int jj = 0; G == 64 ? todo != 0ull : jj < nwin; ++jj) {
                 int j = jj;
                 if constexpr (G == 64) {
@@ -938,7 +939,7 @@ DEVI unsigned long long bfs_expand_entries(int64_t b0, int64_t b1, int64_t bstep
                 for (int i = 0; i < DW; ++i) {
 #pragma unroll
                     for (int k = 0; k < 4; ++k) {
-                        const bool c = (int32_t)((x[i][k] ^ hb) + nt) < 0 && ((fb[i] >> k) & 1u);
+                        const bool c = (int32_t)((x[i][k] ^ hb) + nt) < 0 && ((fbe[i] >> k) & 1u);
                         const uint64_t bal = __ballot(c);
                         if constexpr (G == 64) {
                             const uint32_t lo = (uint32_t)bal, hi = (uint32_t)(bal >> 32);
@@ -962,6 +963,44 @@ DEVI unsigned long long bfs_expand_entries(int64_t b0, int64_t b1, int64_t bstep
                     flush();
                     nb = 0;
                 }
+            }
+        };
+        // window [w0, w0 + G) of entry t: edge ids, heads, hashes and thresholds
+        auto load_window = [&](int t, int64_t w0, bool& in, int32_t& wa, int32_t& wv, uint32_t& hh, uint32_t& tt) {
+            const int64_t e = w0 + p;
+            in = e < e1[t];
+            wa = in ? adj[e] : 0;
+            wv = adj_target(wa);
+            hh = in ? edge_hash_of(H, e, src[t], (uint32_t)wv) : 0u;
+            tt = 0u;
+            if constexpr (KIND == THR_TARGET) tt = in ? thr[wv] : 0u;
+            if constexpr (KIND == THR_EDGE) tt = in ? thr[e] : 0u;
+        };
+        // G = 64: only the window's edges live in some sample (an edge live in
+        // none reaches nothing); groups scan their whole window
+        auto todo_of = [&](bool in, int32_t wa) -> uint64_t {
+            if constexpr (G == 64) return __ballot(in && !adj_dead(wa));
+            return 0ull;
+        };
+        {
+            bool in[NE];
+            int32_t wa[NE], wv[NE];
+            uint32_t hh[NE], tt[NE];
+#pragma unroll
+            for (int t = 0; t < NE; ++t) load_window(t, e0[t], in[t], wa[t], wv[t], hh[t], tt[t]);
+#pragma unroll
+            for (int t = 0; t < NE; ++t)
+                scan(todo_of(in[t], wa[t]), (int)(e1[t] - e0[t] < G ? e1[t] - e0[t] : G), hh[t], tt[t], wv[t],
+                     fb[t]);
+        }
+#pragma unroll
+        for (int t = 0; t < NE; ++t) {
+            for (int64_t w0 = e0[t] + G; w0 < e1[t]; w0 += G) {
+                bool in;
+                int32_t wa, wv;
+                uint32_t hh, tt;
+                load_window(t, w0, in, wa, wv, hh, tt);
+                scan(todo_of(in, wa), (int)(e1[t] - w0 < G ? e1[t] - w0 : G), hh, tt, wv, fb[t]);
             }
         }
         if (nb > 0) flush();

@@ -2160,7 +2160,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(8, 8))) voi
     uint32_t x[DW][4];
     load_sim_words<G, DW>(X, P, p, x);
     const uint32_t ntv = to_vgpr(0u - thr_const);
-    const unsigned long long my_new = bfs_expand_entries<G, DW, KIND, true>(
+    const unsigned long long my_new = bfs_expand_entries<G, DW, KIND, true, G == 64 ? 2 : 1>(
         wave_index() * RPW, (int64_t)size, wave_count() * RPW, xadj, adj, H, thr, ntv, x, b.F[cur & 1],
         b.F[(cur + 1) & 1], b.Q[cur & 1], b.Q[(cur + 1) & 1], &b.qsize[(cur + 1) % 3], b.blk, b.stamp, level_id_next,
         b.bfs_chunk, P, PW);
