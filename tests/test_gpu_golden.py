@@ -207,6 +207,13 @@ def test_resumed_selection(hf, name, make, ks):
                 held = K
                 assert sha(sk.registers(1)) == rec["steps"][K - 1]["M_sha256"], K
                 assert sha(sk.blocked()) == rec["steps"][K - 1]["blk_sha256"], K
+        # a run recorded by the allocation-free entry point is continued the same way
+        hf.im_select_seeds(sk, 2, eps_g=eg, eps_l=el, noalloc=True)
+        seeds, steps, stats = hf.im_select_seeds(sk, ks[-1], eps_g=eg, eps_l=el, resume=True)
+        ref, complete = _prefix_reference(rec, ks[-1])
+        assert list(map(int, seeds)) == [s["seed"] for s in ref]
+        _check_steps(steps, ref, rebuild_counts=complete)
+        assert stats["device_ms"] > 0.0
         # other thresholds start from the build, as a plain call does
         a = hf.im_select_seeds(sk, 5, eps_g=eg * 2, eps_l=el, resume=True)
         b = hf.im_select_seeds(sk, 5, eps_g=eg * 2, eps_l=el)
