@@ -734,7 +734,7 @@ im_status build_sketch(im_ctx* ctx, const im_csr* graph, const im_probs* probs, 
     const int64_t words = (n + 31) / 32 + 1;
     ok = ok && sk_alloc(sk, &sk->Lbm[0], words) && sk_alloc(sk, &sk->Lbm[1], words) &&
          sk_alloc(sk, &sk->Lbm[2], words);
-    ok = ok && sk_alloc(sk, &g.rxadj, n + 1) && sk_alloc(sk, &g.radj, m) && sk_alloc(sk, &g.rpiece, m) &&
+    ok = ok && sk_alloc(sk, &g.rxadj, n + 1) && sk_alloc(sk, &g.rrec, m) &&
          sk_alloc(sk, &g.hslot, n) && sk_alloc(sk, &g.lrows, n);
     ok = ok && sk_alloc(sk, &sk->fr.mark, words) && sk_alloc(sk, &sk->fr.items, n + m / 256 + 64) &&
          sk_alloc(sk, &sk->fr.W, n) && sk_alloc(sk, &sk->fr.counts, 8);

@@ -50,10 +50,11 @@ struct DevGraph {
     int64_t* pe1 = nullptr;     // one past the last edge of each piece
     // in-edges (reverse CSR), for sweeps that start from the live vertices
     int64_t* rxadj = nullptr;   // [n + 1]
-    int32_t* radj = nullptr;    // [m]
+    int2* rrec = nullptr;       // [m] per in-edge: x = source id (DEAD_EDGE set when the edge is live
+                                // in no sample), y = for a split source row its 64-edge window,
+                                // piece * wpp + window in the piece (wpp = ceil(piece_edges / 64)),
+                                // -1 otherwise; one 8-byte record, written once and read together
     int32_t* hslot = nullptr;   // heavy slot of each row, -1 for rows processed whole [n]
-    int32_t* rpiece = nullptr;  // per in-edge of a split source row: its 64-edge window, piece * wpp +
-                                // window in the piece (wpp = ceil(piece_edges / 64)); -1 otherwise [m]
     int32_t* lrows = nullptr;   // rows with 1..heavy_deg out-edges, ascending [nlight]
     int64_t nlight = 0;
     int64_t piece_edges = 256;

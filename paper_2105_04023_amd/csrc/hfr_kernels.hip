@@ -592,8 +592,7 @@ __global__ __launch_bounds__(256) void k_sweep_expand(const uint32_t* __restrict
                                                       const unsigned long long* __restrict__ sgate, int64_t m,
                                                       int first, int64_t n, Frontier fr, int parity,
                                                       const int64_t* __restrict__ rxadj,
-                                                      const int32_t* __restrict__ radj,
-                                                      const int32_t* __restrict__ rpiece, int32_t wpp,
+                                                      const int2* __restrict__ rrec, int32_t wpp,
                                                       const uint32_t* __restrict__ fullblk,
                                                       unsigned long long* __restrict__ vis_light,
                                                       unsigned long long* __restrict__ vis_heavy) {
@@ -609,9 +608,10 @@ __global__ __launch_bounds__(256) void k_sweep_expand(const uint32_t* __restrict
         const int64_t e0 = vb + (int64_t)item.y * fr.chunk;
         const int64_t e1 = e0 + fr.chunk < ve ? e0 + fr.chunk : ve;
         for (int64_t e = e0 + lane; e < e1; e += 64) {
-            const int32_t a = radj[e];
+            const int2 rc = rrec[e];
+            const int32_t a = rc.x;
             const int32_t u = adj_target(a);
-            const int32_t wi = rpiece[e];
+            const int32_t wi = rc.y;
             if (fullblk && bit_of(fullblk, u)) continue;  // neither visited nor marked
             if (wi < 0)
                 ++my_light;
@@ -1387,7 +1387,7 @@ hipError_t launch_sweep(const Layout& L, const DevGraph& g, const uint32_t* X, c
     hipLaunchKernelGGL(k_sweep_frontier, dim3(sg), dim3(256), 0, s, sp.gate, sp.gate_thresh, sp.sgate, g.m, sp.first,
                        g.n, sp.Lcur, sp.Lclear, sp.fr, sp.parity, g.rxadj);
     hipLaunchKernelGGL(k_sweep_expand, dim3(sg), dim3(256), 0, s, sp.gate, sp.gate_thresh, sp.sgate, g.m, sp.first, g.n,
-                       sp.fr, sp.parity, g.rxadj, g.radj, g.rpiece, (int32_t)((g.piece_edges + 63) / 64), sp.fullblk,
+                       sp.fr, sp.parity, g.rxadj, g.rrec, (int32_t)((g.piece_edges + 63) / 64), sp.fullblk,
                        sp.vis_out, g.npieces > 0 ? sp.vis_heavy_out : nullptr);
     hipLaunchKernelGGL(k_sweep_compact, dim3(sg), dim3(256), 0, s, sp.gate, sp.gate_thresh, sp.sgate, g.m, sp.first,
                        g.n, sp.fr, sp.parity);
@@ -1536,11 +1536,11 @@ __global__ __launch_bounds__(256) void k_scan_apply(const uint32_t* __restrict__
     if (blockIdx.x == nb - 1 && threadIdx.x == 0) out[n] = sums[nb];
 }
 
-// radj[cursor[v]++] = u for every edge (u, v); the order inside an in-row
+// rrec[cursor[v]++] = (u, window) for every edge (u, v); the order inside an in-row
 // depends on scheduling, the set does not (graphs too large for the counting
 // sort below).
 __global__ void k_rev_scatter(const int64_t* __restrict__ xadj, const int32_t* __restrict__ adj, int64_t n,
-                              int64_t* cursor, int32_t* radj, int32_t* rpiece, const int32_t* __restrict__ hslot,
+                              int64_t* cursor, int2* rrec, const int32_t* __restrict__ hslot,
                               const int64_t* __restrict__ hpb, int64_t piece, int32_t wpp) {
     const int lane = threadIdx.x & 63;
     for (int64_t u = wave_index(); u < n; u += wave_count()) {
@@ -1550,10 +1550,10 @@ __global__ void k_rev_scatter(const int64_t* __restrict__ xadj, const int32_t* _
         for (int64_t e = eb + lane; e < ee; e += 64) {
             const int32_t v = adj_target(adj[e]);  // may run beside the flagging of dead edges
             const unsigned long long pos = atomicAdd((unsigned long long*)&cursor[v], 1ull);
-            radj[pos] = (int32_t)u;
             // 64-edge window of the edge within its piece (windows of piece c are
             // c * wpp .. c * wpp + wpp - 1)
-            rpiece[pos] = r >= 0 ? (int32_t)((base + (e - eb) / piece) * wpp + ((e - eb) % piece) / 64) : -1;
+            rrec[pos] = make_int2((int32_t)u,
+                                  r >= 0 ? (int32_t)((base + (e - eb) / piece) * wpp + ((e - eb) % piece) / 64) : -1);
         }
     }
 }
@@ -1573,7 +1573,7 @@ hipError_t launch_reverse_csr(const DevGraph& g, const uint32_t* indeg, int64_t*
     hipLaunchKernelGGL(k_scan_apply, dim3((unsigned)nb), dim3(256), 0, s, indeg, n, sums, g.rxadj);
     hipLaunchKernelGGL(k_copy_i64, dim3(4096), dim3(256), 0, s, g.rxadj, cursor, n);
     if (g.m > 0)
-        hipLaunchKernelGGL(k_rev_scatter, dim3(8192), dim3(256), 0, s, g.xadj, g.adj, n, cursor, g.radj, g.rpiece,
+        hipLaunchKernelGGL(k_rev_scatter, dim3(8192), dim3(256), 0, s, g.xadj, g.adj, n, cursor, g.rrec,
                            g.hslot, g.hpb, g.piece_edges, (int32_t)((g.piece_edges + 63) / 64));
     return hipGetLastError();
 }
@@ -1773,7 +1773,7 @@ __global__ __launch_bounds__(1024) void k_rb_fscan(const int64_t* __restrict__ o
         }
 }
 
-// Per chunk: places its records at their slots (radj, rpiece).  With dt.mode
+// Per chunk: places its records at their slots (rrec).  With dt.mode
 // set, a record whose edge is live in no sample gets DEAD_EDGE in its source
 // id -- the test k_dead_edges applies to the out-edges, with the hash
 // recomputed from (u, v) (Eq. hash) and a threshold that depends on the target
@@ -1784,7 +1784,7 @@ __global__ __launch_bounds__(1024) void k_rb_fplace(const int64_t* __restrict__ 
                                                     const int64_t* __restrict__ cstart,
                                                     const uint32_t* __restrict__ ctab, const int32_t* __restrict__ tv,
                                                     const int32_t* __restrict__ tu, const int32_t* __restrict__ tw,
-                                                    int32_t* __restrict__ radj, int32_t* __restrict__ rpiece,
+                                                    int2* __restrict__ rrec,
                                                     const int64_t* __restrict__ rxadj, DeadTest dt) {
     constexpr int BT = 1 << RB_SHIFT;
     __shared__ uint32_t cur[BT];
@@ -1841,8 +1841,7 @@ __global__ __launch_bounds__(1024) void k_rb_fplace(const int64_t* __restrict__ 
             if (!in[r]) continue;
             const bool dead = dt.mode && mn[r] >= t[r];
             const int64_t p = ch.s0 + atomicAdd(&cur[v[r] - ch.v0], 1u);
-            radj[p] = dead ? (int32_t)((uint32_t)u[r] | DEAD_EDGE) : u[r];
-            rpiece[p] = tw[ch.r0 + k0 + 1024 * r];
+            rrec[p] = make_int2(dead ? (int32_t)((uint32_t)u[r] | DEAD_EDGE) : u[r], tw[ch.r0 + k0 + 1024 * r]);
         }
     }
 }
@@ -1865,7 +1864,7 @@ size_t rb_temp_bytes(int64_t n, int64_t m) {
            al(8 * (nbk + 1)) + al(4 * rb_max_chunks(n, m) * (1 << RB_SHIFT));
 }
 
-// In-degrees (indeg) and the reverse CSR of g (rxadj, radj, rpiece) on stream
+// In-degrees (indeg) and the reverse CSR of g (rxadj, rrec) on stream
 // s; tmp holds rb_temp_bytes(n, m) bytes, indeg at its start.
 hipError_t launch_reverse_csr_buckets(const DevGraph& g, void* tmp, uint32_t** indeg_out, const DeadTest& dt,
                                       hipStream_t s) {
@@ -1913,7 +1912,7 @@ hipError_t launch_reverse_csr_buckets(const DevGraph& g, void* tmp, uint32_t** i
     hipLaunchKernelGGL(k_rb_fscan, dim3((unsigned)nbk), dim3(1024), 0, s, off, ncol, nbk, n, cstart, ctab, indeg,
                        g.rxadj);
     hipLaunchKernelGGL(k_rb_fplace, dim3((unsigned)maxch), dim3(1024), 0, s, off, ncol, nbk, cstart, ctab, tv, tu, tw,
-                       g.radj, g.rpiece, g.rxadj, dt);
+                       g.rrec, g.rxadj, dt);
     return hipGetLastError();
 }
 
