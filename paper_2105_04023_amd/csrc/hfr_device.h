@@ -639,6 +639,101 @@ DEVI bool fix_row(int64_t r, int64_t u, const uint32_t* __restrict__ A, uint32_t
     return changed;
 }
 
+// G = 64: fix_row for two split rows at once (val[t]: row t exists), their
+// loads interleaved so that the two rows share their round trips: row words,
+// blocked masks and piece ranges, then the piece flags 64 at a time and the
+// flagged partial rows in batches of up to 8 per row.  A batch slot without a
+// flagged piece re-reads the row's own registers, which the max leaves as they
+// are.  changed[t] as fix_row returns it.
+template <int DW>
+DEVI void fix_rows2(const int64_t (&r)[2], const int64_t (&u)[2], const bool (&val)[2],
+                    const uint32_t* __restrict__ A, uint32_t* __restrict__ B, const uint32_t* __restrict__ Lcur,
+                    const uint32_t* __restrict__ blk, const int64_t* __restrict__ hpb,
+                    const int64_t* __restrict__ hpn, const uint32_t* __restrict__ part,
+                    const uint32_t* __restrict__ part_any, uint32_t stamp, int P, int PW, int first, int lane,
+                    bool (&changed)[2]) {
+    bool inL[2], any[2];
+    uint32_t ub[2][DW], a[2][DW], acc[2][DW];
+    int64_t pb[2], np[2];
+#pragma unroll
+    for (int t = 0; t < 2; ++t) {
+        inL[t] = val[t] && !first && bit_of(Lcur, u[t]) != 0;
+        any[t] = false;
+        pb[t] = val[t] ? hpb[r[t]] : 0;
+        np[t] = val[t] ? hpn[r[t]] : 0;
+#pragma unroll
+        for (int k = 0; k < DW; ++k) {
+            const int q = k * 64 + lane;
+            const int qc = q < P ? q : P - 1;
+            ub[t][k] = (blk && q < P) ? unblocked_mask(blk, u[t], q, PW) : 0xFFFFFFFFu;
+            a[t][k] = A[u[t] * P + qc];
+            acc[t][k] = 0u;
+        }
+    }
+    const int64_t npm = np[0] > np[1] ? np[0] : np[1];
+    for (int64_t c0 = 0; c0 < npm; c0 += 64) {
+        uint64_t mask[2];
+#pragma unroll
+        for (int t = 0; t < 2; ++t) {
+            const bool hit = c0 + lane < np[t] && part_any[pb[t] + c0 + lane] == stamp;
+            mask[t] = __ballot(hit);
+            any[t] = any[t] || mask[t] != 0ull;
+        }
+        while (mask[0] | mask[1]) {
+            uint32_t pv[2][8][DW];
+#pragma unroll
+            for (int t = 0; t < 2; ++t) {
+#pragma unroll
+                for (int b = 0; b < 8; ++b) {
+                    // a flagged partial row, or (none left) the row's own registers
+                    const uint32_t* src = A + u[t] * P;
+                    if (mask[t]) {
+                        const int j = __builtin_ctzll(mask[t]);
+                        mask[t] &= mask[t] - 1;
+                        src = part + (pb[t] + c0 + j) * P;
+                    }
+#pragma unroll
+                    for (int k = 0; k < DW; ++k) {
+                        const int q = k * 64 + lane;
+                        pv[t][b][k] = src[q < P ? q : P - 1];
+                    }
+                }
+            }
+            __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+            for (int t = 0; t < 2; ++t)
+#pragma unroll
+                for (int b = 0; b < 8; ++b)
+#pragma unroll
+                    for (int k = 0; k < DW; ++k) acc[t][k] = byte_max(acc[t][k], pv[t][b][k]);
+        }
+    }
+#pragma unroll
+    for (int t = 0; t < 2; ++t) {
+        changed[t] = false;
+        if (!val[t] || (!any[t] && !inL[t])) continue;
+        bool ch = false;
+        uint32_t nw[DW];
+#pragma unroll
+        for (int k = 0; k < DW; ++k) {
+            const int q = k * 64 + lane;
+            nw[k] = 0;
+            if (q < P) {
+                nw[k] = byte_max(a[t][k], acc[t][k]) & ub[t][k];
+                ch = ch || nw[k] != a[t][k];
+            }
+        }
+        changed[t] = __ballot(ch) != 0ull;
+        if (changed[t] || inL[t]) {
+#pragma unroll
+            for (int k = 0; k < DW; ++k) {
+                const int q = k * 64 + lane;
+                if (q < P) B[u[t] * P + q] = nw[k];
+            }
+        }
+    }
+}
+
 // Greedy score (Alg. 1): score(u) = sum_j max(M_S'[j], M_u[j]) for u not in
 // S, as the key score << 32 | (2^32 - 1 - u) so that the maximum key is the
 // highest score with the lowest id.  The wave scores rows base + (lane / G)

@@ -1328,17 +1328,26 @@ __global__ __launch_bounds__(256) void k_sweep_heavy_fix(
                 u = hrow[r];
                 need = needs(r, u);
             }
-            for (uint64_t mask = __ballot(need); mask; mask &= mask - 1) {
-                const int j = __builtin_ctzll(mask);
-                const int64_t rr = __builtin_amdgcn_readlane((int)r, j);
-                const int64_t uu = __builtin_amdgcn_readlane((int)u, j);
-                const bool changed =
-                    fix_row<G, DW>(rr, uu, A, B, Lcur, blk, hpb, hpn, part, part_any, stamp, P, PW, first, lane, p);
-                if (changed && lane == 0) {
-                    atomicOr(&Lnext[uu >> 5], 1u << (uu & 31));
-                    my_cnt += 1;
-                    my_sum += (unsigned long long)(rxadj[uu + 1] - rxadj[uu]);
+            // the rows that need work, two at a time (their loads interleaved)
+            for (uint64_t mask = __ballot(need); mask;) {
+                int64_t rr[2], uu[2];
+                bool vv[2], ch[2];
+#pragma unroll
+                for (int t = 0; t < 2; ++t) {
+                    vv[t] = mask != 0ull;
+                    const int j = vv[t] ? __builtin_ctzll(mask) : 0;
+                    mask &= mask - 1;
+                    rr[t] = __builtin_amdgcn_readlane((int)r, j);
+                    uu[t] = __builtin_amdgcn_readlane((int)u, j);
                 }
+                fix_rows2<DW>(rr, uu, vv, A, B, Lcur, blk, hpb, hpn, part, part_any, stamp, P, PW, first, lane, ch);
+#pragma unroll
+                for (int t = 0; t < 2; ++t)
+                    if (vv[t] && ch[t] && lane == 0) {
+                        atomicOr(&Lnext[uu[t] >> 5], 1u << (uu[t] & 31));
+                        my_cnt += 1;
+                        my_sum += (unsigned long long)(rxadj[uu[t] + 1] - rxadj[uu[t]]);
+                    }
             }
         }
     } else {
